@@ -1,0 +1,224 @@
+/*
+ * dcm.h -- C ABI of the MI355X (gfx950) dynamic cutoff method library.
+ *
+ * The library runs the per-step hot path of the dynamic cutoff method (DCM)
+ * of Springer, Ismail and Bientinesi, "A Scalable, Linear-Time Dynamic
+ * Cutoff Algorithm for Molecular Dynamics":
+ *
+ *   interface detection on a density grid      (Section 2.1, Fig. 4, Eq. 4)
+ *   cutoff-limited fast-sweeping distances     (Section 2.2, Algorithm 2.1)
+ *   per-particle cutoffs from the distances    (Section 2.2)
+ *   linked-cell binning with small cells       (Section 2.3, Algorithm 2.2)
+ *   dynamic-cutoff Lennard-Jones forces        (Section 2.4, Algorithm 2.3, Eqs. 2-3)
+ *   velocity Verlet integration                (Section 2, Fig. 3 box 5)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array arguments are DEVICE pointers owned by the caller, contiguous,
+ *   structure-of-arrays, in the caller's particle order (outputs too: the
+ *   library undoes its internal spatial ordering).  Positions are in the
+ *   periodic box [0, L_a); inputs outside it are wrapped on the fly.
+ * - Every call is asynchronous on the context's HIP stream.  Scalar outputs
+ *   (energies, virials, counters) are device scalars.  No call synchronises
+ *   the stream except dcm_sync_status, dcm_create and dcm_destroy.
+ * - Scratch memory (grid buffers, cells, sorted copies, partial sums) is owned
+ *   by the context and grown on demand; growing it allocates device memory,
+ *   so call each entry point once with its largest sizes before capturing it
+ *   in a HIP graph.
+ * - Return value: DCM_OK, or an error detected on the host (bad arguments,
+ *   HIP launch failure) -- then nothing was enqueued.  Conditions only the
+ *   device can see (non-finite input or output, a distance sweep that did not
+ *   converge, a single-phase density field) raise a sticky device flag that
+ *   dcm_sync_status reports and clears.
+ * - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef DCM_H
+#define DCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dcm_status;
+#define DCM_OK 0
+#define DCM_ERR_INVALID 1       /* null pointer, negative size, non-positive length ... */
+#define DCM_ERR_RANGE 2         /* rc_max >= L_a/2 (breaks the minimum image), size limits */
+#define DCM_ERR_NOT_CONVERGED 3 /* distance sweep hit its wave limit */
+#define DCM_ERR_DEGENERATE 4    /* the density field holds a single phase */
+#define DCM_ERR_NONFINITE 5     /* NaN/Inf position or force */
+#define DCM_ERR_HIP 6           /* HIP runtime error */
+#define DCM_ERR_NOMEM 7         /* device allocation failed */
+
+typedef struct dcm_ctx dcm_ctx;
+
+/* Orthorhombic periodic box, edges L[0..2] > 0 (Section 2: the domain
+ * L = L_x x L_y x L_z). */
+typedef struct { double L[3]; } dcm_box;
+
+/* Lennard-Jones 12-6 parameters, truncated and unshifted (Eq. 3). */
+typedef struct { double epsilon, sigma; } dcm_lj;
+
+/* Cutoff as a function of the particle-interface distance delta
+ * (Section 2.2): rc = rc_max - (rc_max - rc_min) * min(delta/ramp, 1), i.e.
+ * rc_max at the interface and in the low-density phase, rc_min at distance
+ * >= ramp inside the high-density phase.  Requires 0 < rc_min <= rc_max,
+ * ramp > 0. */
+typedef struct { double rc_min, rc_max, ramp; } dcm_rule;
+
+/* Density grid (Section 2.1, footnote 2): n[a] voxels of edge h[a] = L_a/n[a]
+ * along each axis; voxel v = (k*n[1] + j)*n[0] + i. */
+typedef struct { int32_t n[3]; double h[3]; } dcm_grid;
+
+/* Arithmetic of the pair kernel.
+ * DCM_FP64: all FP64.
+ * DCM_FP32_MIXED: separations and r^2 in FP64 (so the pair-inclusion test is
+ * exact), the Lennard-Jones terms in FP32, per-particle force sums and the
+ * global energy/virial in FP64. */
+enum { DCM_FP64 = 0, DCM_FP32_MIXED = 1 };
+
+/* Which pairs interact.
+ * DCM_PAIR_OWN (Algorithm 2.3): j acts on i iff r_ij < rc_i; Newton's third
+ * law is not applied (Section 2.4), so sum_i F_i need not vanish.
+ * DCM_PAIR_MAX: j and i interact iff r_ij <= max(rc_i, rc_j) (symmetric). */
+enum { DCM_PAIR_OWN = 0, DCM_PAIR_MAX = 1 };
+
+/* Optional outputs of dcm_forces. */
+enum { DCM_EV_ENERGY = 1, DCM_EV_VIRIAL = 2, DCM_EV_COUNTS = 4 };
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to `hip_stream` (a hipStream_t; NULL = the default
+ * stream) on the current device.  *out receives the context. */
+dcm_status dcm_create(dcm_ctx **out, void *hip_stream);
+
+/* Synchronise and free the context and all of its scratch memory. */
+dcm_status dcm_destroy(dcm_ctx *ctx);
+
+/* Rebind the context to another stream of the same device. */
+dcm_status dcm_set_stream(dcm_ctx *ctx, void *hip_stream);
+
+/* Synchronise the stream, then return (and clear) the sticky device status:
+ * DCM_ERR_NONFINITE, DCM_ERR_NOT_CONVERGED, DCM_ERR_RANGE or
+ * DCM_ERR_DEGENERATE in that priority order, else DCM_OK. */
+dcm_status dcm_sync_status(dcm_ctx *ctx);
+
+/* Text of the last error raised on this context ("" if none).  The string is
+ * owned by the context and valid until the next call on it. */
+const char *dcm_last_error(const dcm_ctx *ctx);
+
+/* Host helper: grid with n[a] = max(1, round(L_a/h)) and h[a] = L_a/n[a]
+ * (the voxel edge h is chosen once per run, Section 2.1 footnote 2). */
+dcm_status dcm_make_grid(dcm_box box, double h, dcm_grid *out);
+
+/* ------------------------------------------------------------- hot path */
+
+/* Interface detection (Section 2.1, Fig. 4, Eq. 4).
+ * Bins the n particles (x, y, z) into the grid (counts, optional, uint32
+ * [N_v]), takes each voxel's gray value as the particle count of its periodic
+ * 3x3x3 window, splits the volume into high (1) and low (0) density phases
+ * and regularises the split, then marks interface voxels: high-density voxels
+ * with a low-density face neighbour.
+ *   split <= 0: the threshold minimises the two-phase piecewise-constant
+ *               energy with no length term (the 2-means split of the gray
+ *               values); a density contrast below 2 flags DCM_ERR_DEGENERATE
+ *               and classifies the whole volume as high density.
+ *   split  > 0: fixed threshold, phase 1 iff gray value >= split.
+ * Regularisation: synchronous 27-neighbour majority vote (>= 14 of 27),
+ * repeated to a fixed point or a 2-cycle, at most 16 passes.
+ * seg (uint8 [N_v], S of Eq. 4) and iface (uint8 [N_v]) are required;
+ * threshold_out (int32 device scalar) is optional.
+ * Limits: N_v < 2^31; gray values must stay below 4096 (else DCM_ERR_RANGE
+ * via dcm_sync_status). */
+dcm_status dcm_detect_interface(dcm_ctx *ctx, const double *x, const double *y,
+                                const double *z, int64_t n, dcm_box box, dcm_grid grid,
+                                double split, uint32_t *counts, uint8_t *seg,
+                                uint8_t *iface, int32_t *threshold_out);
+
+/* Box-interface distances (Section 2.2, Algorithm 2.1).  Interface and
+ * low-density voxels start at 0, the rest at +infinity; the first-order
+ * Godunov upwind update of |grad d| = 1 is applied to every voxel in
+ * synchronous waves, accepting only values <= rc_grid, until a wave changes
+ * nothing (at most max_waves waves, else DCM_ERR_NOT_CONVERGED via
+ * dcm_sync_status).  dist (double [N_v]) receives min(D, rc_grid);
+ * waves_out (int32 device scalar, optional) the number of waves run. */
+dcm_status dcm_sweep_distance(dcm_ctx *ctx, const uint8_t *seg, const uint8_t *iface,
+                              dcm_grid grid, double rc_grid, int32_t max_waves,
+                              double *dist, int32_t *waves_out);
+
+/* Cutoff assignment (Section 2.2): delta_i = periodic trilinear interpolation
+ * of the voxel-centred distances at x_i; rc_i from the rule.  delta (double
+ * [n]) is optional, rc (double [n]) required. */
+dcm_status dcm_assign_cutoffs(dcm_ctx *ctx, const double *x, const double *y,
+                              const double *z, int64_t n, dcm_box box, dcm_grid grid,
+                              const double *dist, dcm_rule rule, double *delta,
+                              double *rc);
+
+/* Linked cells (Section 2.3).  Cells of edge L_a/n_a with
+ * n_a = floor(L_a/cell_edge) (cell_edge <= 0 picks rc_min-sized cells from the
+ * cutoffs), cell c = (c_z*n_y + c_y)*n_x + c_x.  Particles are sorted by cell
+ * (stable: ascending caller index within a cell) into context-owned copies of
+ * (x, y, z, rc) that dcm_forces reads.  cell_of (int32 [n]) and cell_start
+ * (int32 [n_cells + 1], exclusive prefix of per-cell counts) are optional
+ * copies for the caller; dcm_cell_dims gives n_cells.  prec selects the
+ * layout of the sorted copy for the later dcm_forces call.  The positions
+ * and cutoffs are read during this call only. */
+dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                           const double *rc, int64_t n, dcm_box box, double cell_edge,
+                           int prec, int32_t *cell_of, int32_t *cell_start);
+
+/* Host query: cell counts per axis and cell edge lengths of the last
+ * dcm_build_cells call on this context. */
+dcm_status dcm_cell_dims(const dcm_ctx *ctx, int32_t n_cells[3], double cell_len[3]);
+
+/* Dynamic-cutoff Lennard-Jones forces (Algorithm 2.3, Eqs. 2-3) on the cells
+ * of the last dcm_build_cells call.  For every i, F_i sums
+ * f_ij = 24 eps s6 (2 s6 - 1) / r^2 * (x_i - x_j), s6 = (sigma/r)^6, over the
+ * interacting j (pair_rule), with minimum-image separations.
+ * fx, fy, fz (double [n], caller order) are required.  With ev_flags:
+ *   DCM_EV_ENERGY: *energy = sum over interacting ordered pairs of U/2,
+ *                  U = 4 eps s6 (s6 - 1);
+ *   DCM_EV_VIRIAL: virial[6] = xx yy zz xy xz yz of sum of d_a f_b / 2;
+ *   DCM_EV_COUNTS: nnbr[i] = number of j acting on i (int32 [n]), *npairs =
+ *                  number of interacting ordered pairs (uint64).
+ * Pointers for unrequested outputs may be NULL.  energy/virial/npairs are
+ * device scalars.  The energy and virial sums are deterministic. */
+dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_flags,
+                      double *fx, double *fy, double *fz, double *energy, double *virial,
+                      int32_t *nnbr, uint64_t *npairs);
+
+/* Velocity-Verlet MD with the whole DCM pipeline (Fig. 3).
+ * nsteps == 0: compute forces at the current positions (detection, distances,
+ * cutoffs, cells, forces) into fx, fy, fz.
+ * nsteps  > 0: fx, fy, fz must hold the forces at the current positions; each
+ * step does v += dt/(2m) F; x += dt v (wrapped); re-detect the interface and
+ * re-sweep the distances when (step0 + s + 1) % redetect_every == 0 or no
+ * distance field exists yet; re-assign cutoffs and rebuild cells (every
+ * step); recompute F; v += dt/(2m) F.
+ * energy_series (double [2*nsteps], optional): potential and kinetic energy
+ * after each step.  delta/rc (double [n], optional) receive the last
+ * distances and cutoffs. */
+dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,
+                    double *vz, double *fx, double *fy, double *fz, int64_t n, double mass,
+                    dcm_box box, dcm_lj lj, dcm_rule rule, dcm_grid grid, double rc_grid,
+                    int pair_rule, int prec, double dt, int32_t nsteps,
+                    int32_t redetect_every, int64_t step0, double *energy_series,
+                    double *delta, double *rc);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Record HIP events around every launch of the named kernel family
+ * ("pair", "cells", "detect", "sweep", "cutoffs", "verlet") when enabled. */
+dcm_status dcm_set_profiling(dcm_ctx *ctx, int enable);
+
+/* Synchronise, then return the summed event time (ms) and launch count of a
+ * kernel family since profiling was enabled, and reset them. */
+dcm_status dcm_kernel_time(dcm_ctx *ctx, const char *family, double *total_ms,
+                           int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCM_H */

@@ -1,0 +1,564 @@
+// Host side of the C ABI declared in include/dcm.h: argument validation,
+// context-owned scratch memory, and the order in which each entry point
+// enqueues its kernels on the context's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "dcm_internal.hpp"
+
+using namespace dcm;
+
+namespace dcm {
+
+dcm_status fail(dcm_ctx *ctx, dcm_status code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+dcm_status ensure(dcm_ctx *ctx, DevBuf &b, size_t bytes) {
+  if (bytes < 256) bytes = 256;
+  if (b.cap >= bytes) return DCM_OK;
+  if (b.p) {
+    hipStreamSynchronize(ctx->stream);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t sz = (bytes + 4095) & ~size_t(4095);
+  hipError_t e = hipMalloc(&b.p, sz);
+  if (e != hipSuccess) {
+    hipGetLastError();
+    b.p = nullptr;
+    return fail(ctx, DCM_ERR_NOMEM,
+                std::string("device allocation of ") + std::to_string(sz) + " bytes failed");
+  }
+  b.cap = sz;
+  return DCM_OK;
+}
+
+dcm_status check_launch(dcm_ctx *ctx, const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(ctx, DCM_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return DCM_OK;
+}
+
+void timer_begin(dcm_ctx *ctx, const char *family, hipEvent_t *ev) {
+  (void)family;
+  *ev = nullptr;
+  if (!ctx->profile) return;
+  if (hipEventCreate(ev) != hipSuccess) {
+    *ev = nullptr;
+    return;
+  }
+  hipEventRecord(*ev, ctx->stream);
+}
+
+void timer_end(dcm_ctx *ctx, const char *family, hipEvent_t ev) {
+  if (!ev) return;
+  hipEvent_t e2;
+  if (hipEventCreate(&e2) != hipSuccess) return;
+  hipEventRecord(e2, ctx->stream);
+  ctx->timers[family].pending.push_back({ev, e2});
+}
+
+}  // namespace dcm
+
+namespace {
+
+template <typename T>
+T *ptr(const DevBuf &b) {
+  return static_cast<T *>(b.p);
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+dcm_status check_box(dcm_ctx *ctx, const dcm_box &box) {
+  for (int a = 0; a < 3; ++a)
+    if (!finite_pos(box.L[a])) return fail(ctx, DCM_ERR_INVALID, "box lengths must be > 0");
+  return DCM_OK;
+}
+
+dcm_status check_grid(dcm_ctx *ctx, const dcm_grid &g, int64_t *nvox) {
+  int64_t v = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (g.n[a] < 1 || !finite_pos(g.h[a]))
+      return fail(ctx, DCM_ERR_INVALID, "grid needs n >= 1 and h > 0 on every axis");
+    v *= g.n[a];
+    if (v >= (int64_t(1) << 31)) return fail(ctx, DCM_ERR_RANGE, "grid has 2^31 or more voxels");
+  }
+  *nvox = v;
+  return DCM_OK;
+}
+
+dcm_status check_n(dcm_ctx *ctx, int64_t n) {
+  if (n < 0) return fail(ctx, DCM_ERR_INVALID, "particle count must be >= 0");
+  if (n >= (int64_t(1) << 31) - 1) return fail(ctx, DCM_ERR_RANGE, "particle count >= 2^31 - 1");
+  return DCM_OK;
+}
+
+#define DCM_TRY(expr)                  \
+  do {                                 \
+    dcm_status st_ = (expr);           \
+    if (st_ != DCM_OK) return st_;     \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
+  if (!out) return DCM_ERR_INVALID;
+  *out = nullptr;
+  dcm_ctx *ctx = new (std::nothrow) dcm_ctx();
+  if (!ctx) return DCM_ERR_NOMEM;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    hipGetLastError();
+    delete ctx;
+    return DCM_ERR_HIP;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, 256) != hipSuccess) {
+    hipGetLastError();
+    delete ctx;
+    return DCM_ERR_NOMEM;
+  }
+  ctx->d_status = static_cast<uint32_t *>(p);
+  if (hipMalloc(&p, sizeof(Ctl)) != hipSuccess) {
+    hipGetLastError();
+    hipFree(ctx->d_status);
+    delete ctx;
+    return DCM_ERR_NOMEM;
+  }
+  ctx->ctl = static_cast<Ctl *>(p);
+  if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) {
+    hipGetLastError();
+    hipFree(ctx->d_status);
+    hipFree(ctx->ctl);
+    delete ctx;
+    return DCM_ERR_NOMEM;
+  }
+  ctx->h_status = static_cast<uint32_t *>(p);
+  launch_clear_status(ctx->stream, ctx->d_status);
+  launch_reset_ctl(ctx->stream, ctx->ctl);
+  dcm_status st = check_launch(ctx, "dcm_create");
+  if (st == DCM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = DCM_ERR_HIP;
+  if (st != DCM_OK) {
+    hipFree(ctx->d_status);
+    hipFree(ctx->ctl);
+    hipHostFree(ctx->h_status);
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return DCM_OK;
+}
+
+dcm_status dcm_destroy(dcm_ctx *ctx) {
+  if (!ctx) return DCM_ERR_INVALID;
+  hipStreamSynchronize(ctx->stream);
+  DevBuf *bufs[] = {&ctx->fsm_chg,  &ctx->counts,   &ctx->gray,      &ctx->hist,      &ctx->seg_a,
+                    &ctx->seg_b,    &ctx->seg,       &ctx->iface,     &ctx->dA,
+                    &ctx->dB,       &ctx->dist,      &ctx->delta,     &ctx->rc,
+                    &ctx->partials, &ctx->ke,        &ctx->cell_of,   &ctx->cell_count,
+                    &ctx->cell_start, &ctx->cell_fill, &ctx->perm,    &ctx->sorted,
+                    &ctx->scan_tmp, &ctx->scalars};
+  for (DevBuf *b : bufs)
+    if (b->p) hipFree(b->p);
+  for (auto &kv : ctx->timers)
+    for (auto &pr : kv.second.pending) {
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+  hipFree(ctx->d_status);
+  hipFree(ctx->ctl);
+  hipHostFree(ctx->h_status);
+  delete ctx;
+  return DCM_OK;
+}
+
+dcm_status dcm_set_stream(dcm_ctx *ctx, void *hip_stream) {
+  if (!ctx) return DCM_ERR_INVALID;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return DCM_OK;
+}
+
+dcm_status dcm_sync_status(dcm_ctx *ctx) {
+  if (!ctx) return DCM_ERR_INVALID;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return fail(ctx, DCM_ERR_HIP, std::string("stream error: ") +
+                                      hipGetErrorString(hipGetLastError()));
+  if (hipMemcpy(ctx->h_status, ctx->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return fail(ctx, DCM_ERR_HIP, "status read failed");
+  uint32_t st = *ctx->h_status;
+  launch_clear_status(ctx->stream, ctx->d_status);
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return DCM_ERR_HIP;
+  if (st & (ST_NONFINITE_POS | ST_NONFINITE_FORCE))
+    return fail(ctx, DCM_ERR_NONFINITE, "non-finite position or force");
+  if (st & ST_NOT_CONVERGED)
+    return fail(ctx, DCM_ERR_NOT_CONVERGED, "distance sweep reached its wave limit");
+  if (st & (ST_HIST_RANGE | ST_RC_RANGE))
+    return fail(ctx, DCM_ERR_RANGE, "gray value >= 4096 or cutoff outside [0, L/2)");
+  if (st & ST_DEGENERATE)
+    return fail(ctx, DCM_ERR_DEGENERATE, "density field holds a single phase");
+  return DCM_OK;
+}
+
+const char *dcm_last_error(const dcm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+dcm_status dcm_make_grid(dcm_box box, double h, dcm_grid *out) {
+  if (!out || !finite_pos(h)) return DCM_ERR_INVALID;
+  for (int a = 0; a < 3; ++a)
+    if (!finite_pos(box.L[a])) return DCM_ERR_INVALID;
+  for (int a = 0; a < 3; ++a) {
+    double r = std::round(box.L[a] / h);
+    if (r > 2147483647.0) return DCM_ERR_RANGE;
+    int32_t k = (int32_t)r;
+    if (k < 1) k = 1;
+    out->n[a] = k;
+    out->h[a] = box.L[a] / (double)k;
+  }
+  return DCM_OK;
+}
+
+dcm_status dcm_detect_interface(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                                int64_t n, dcm_box box, dcm_grid grid, double split,
+                                uint32_t *counts, uint8_t *seg, uint8_t *iface,
+                                int32_t *threshold_out) {
+  if (!ctx) return DCM_ERR_INVALID;
+  int64_t nvox = 0;
+  DCM_TRY(check_n(ctx, n));
+  DCM_TRY(check_box(ctx, box));
+  DCM_TRY(check_grid(ctx, grid, &nvox));
+  if ((n > 0 && (!x || !y || !z)) || !seg || !iface)
+    return fail(ctx, DCM_ERR_INVALID, "dcm_detect_interface: null pointer");
+  if (!std::isfinite(split)) return fail(ctx, DCM_ERR_INVALID, "split must be finite");
+  DCM_TRY(ensure(ctx, ctx->gray, nvox * sizeof(uint32_t)));
+  DCM_TRY(ensure(ctx, ctx->hist, kHistBins * sizeof(uint32_t)));
+  DCM_TRY(ensure(ctx, ctx->seg_a, nvox));
+  DCM_TRY(ensure(ctx, ctx->seg_b, nvox));
+  if (!counts) {
+    DCM_TRY(ensure(ctx, ctx->counts, nvox * sizeof(uint32_t)));
+    counts = ptr<uint32_t>(ctx->counts);
+  }
+  const double sc[3] = {(double)grid.n[0] / box.L[0], (double)grid.n[1] / box.L[1],
+                        (double)grid.n[2] / box.L[2]};
+  hipStream_t s = ctx->stream;
+  hipEvent_t ev;
+  timer_begin(ctx, "detect", &ev);
+  launch_fill_u32(s, counts, 0u, nvox);
+  launch_fill_u32(s, ptr<uint32_t>(ctx->hist), 0u, kHistBins);
+  launch_bin_density(s, x, y, z, n, box.L, grid.n, sc, counts, ctx->d_status);
+  launch_gray(s, counts, ptr<uint32_t>(ctx->gray), grid.n);
+  launch_hist(s, ptr<uint32_t>(ctx->gray), nvox, ptr<uint32_t>(ctx->hist), ctx->d_status);
+  if (split <= 0.0)
+    launch_otsu(s, ptr<uint32_t>(ctx->hist), nvox, ctx->ctl, threshold_out, ctx->d_status);
+  launch_threshold(s, ptr<uint32_t>(ctx->gray), nvox, split, ctx->ctl, ptr<uint8_t>(ctx->seg_a),
+                   threshold_out);
+  for (int p = 1; p <= kMajorityMaxPasses; ++p)
+    launch_majority_pass(s, ptr<uint8_t>(ctx->seg_a), ptr<uint8_t>(ctx->seg_b), grid.n, p,
+                         kMajorityMaxPasses, ctx->ctl);
+  launch_interface(s, ptr<uint8_t>(ctx->seg_a), ptr<uint8_t>(ctx->seg_b), grid.n, ctx->ctl, seg,
+                   iface);
+  timer_end(ctx, "detect", ev);
+  return check_launch(ctx, "dcm_detect_interface");
+}
+
+dcm_status dcm_sweep_distance(dcm_ctx *ctx, const uint8_t *seg, const uint8_t *iface,
+                              dcm_grid grid, double rc_grid, int32_t max_waves, double *dist,
+                              int32_t *waves_out) {
+  if (!ctx) return DCM_ERR_INVALID;
+  int64_t nvox = 0;
+  DCM_TRY(check_grid(ctx, grid, &nvox));
+  if (!seg || !iface || !dist) return fail(ctx, DCM_ERR_INVALID, "dcm_sweep_distance: null pointer");
+  if (!finite_pos(rc_grid)) return fail(ctx, DCM_ERR_INVALID, "rc_grid must be > 0");
+  if (max_waves < 1 || max_waves > 100000)
+    return fail(ctx, DCM_ERR_INVALID, "max_waves must be in [1, 100000]");
+  DCM_TRY(ensure(ctx, ctx->dA, nvox * sizeof(double)));
+  DCM_TRY(ensure(ctx, ctx->dB, nvox * sizeof(double)));
+  const int64_t ntiles = fsm_tile_count(grid.n);
+  DCM_TRY(ensure(ctx, ctx->fsm_chg, 2 * ntiles));
+  uint8_t *chg0 = ptr<uint8_t>(ctx->fsm_chg), *chg1 = chg0 + ntiles;
+  hipStream_t s = ctx->stream;
+  hipEvent_t ev;
+  timer_begin(ctx, "sweep", &ev);
+  launch_fsm_init(s, seg, iface, nvox, ptr<double>(ctx->dA), ptr<double>(ctx->dB), ctx->ctl);
+  for (int w = 1; w <= max_waves; ++w)
+    launch_fsm_step(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), chg0, chg1, grid.n, grid.h,
+                    rc_grid, w, max_waves, ctx->ctl, ctx->d_status);
+  launch_fsm_final(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), nvox, rc_grid, ctx->ctl, dist,
+                   waves_out);
+  timer_end(ctx, "sweep", ev);
+  return check_launch(ctx, "dcm_sweep_distance");
+}
+
+dcm_status dcm_assign_cutoffs(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                              int64_t n, dcm_box box, dcm_grid grid, const double *dist,
+                              dcm_rule rule, double *delta, double *rc) {
+  if (!ctx) return DCM_ERR_INVALID;
+  int64_t nvox = 0;
+  DCM_TRY(check_n(ctx, n));
+  DCM_TRY(check_box(ctx, box));
+  DCM_TRY(check_grid(ctx, grid, &nvox));
+  if (n > 0 && (!x || !y || !z || !dist || !rc))
+    return fail(ctx, DCM_ERR_INVALID, "dcm_assign_cutoffs: null pointer");
+  if (!finite_pos(rule.rc_min) || !finite_pos(rule.rc_max) || !finite_pos(rule.ramp) ||
+      rule.rc_min > rule.rc_max)
+    return fail(ctx, DCM_ERR_INVALID, "rule needs 0 < rc_min <= rc_max and ramp > 0");
+  const double sc[3] = {(double)grid.n[0] / box.L[0], (double)grid.n[1] / box.L[1],
+                        (double)grid.n[2] / box.L[2]};
+  hipEvent_t ev;
+  timer_begin(ctx, "cutoffs", &ev);
+  launch_assign_cutoffs(ctx->stream, x, y, z, n, box.L, grid.n, sc, dist, rule, delta, rc);
+  timer_end(ctx, "cutoffs", ev);
+  return check_launch(ctx, "dcm_assign_cutoffs");
+}
+
+dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                           const double *rc, int64_t n, dcm_box box, double cell_edge, int prec,
+                           int32_t *cell_of, int32_t *cell_start) {
+  if (!ctx) return DCM_ERR_INVALID;
+  DCM_TRY(check_n(ctx, n));
+  DCM_TRY(check_box(ctx, box));
+  if (n > 0 && (!x || !y || !z || !rc))
+    return fail(ctx, DCM_ERR_INVALID, "dcm_build_cells: null pointer");
+  if (prec != DCM_FP64 && prec != DCM_FP32_MIXED)
+    return fail(ctx, DCM_ERR_INVALID, "unknown precision");
+  if (!std::isfinite(cell_edge)) return fail(ctx, DCM_ERR_INVALID, "cell_edge must be finite");
+  double edge = cell_edge;
+  if (edge <= 0.0) {
+    // about two particles per cell at the mean density
+    double vol = box.L[0] * box.L[1] * box.L[2];
+    edge = std::cbrt(2.0 * vol / (double)std::max<int64_t>(n, 1));
+  }
+  int32_t nc[3];
+  int64_t ncell = 1;
+  for (int a = 0; a < 3; ++a) {
+    double k = std::floor(box.L[a] / edge);
+    if (k < 1.0) k = 1.0;
+    if (k > 65536.0) return fail(ctx, DCM_ERR_RANGE, "more than 65536 cells along an axis");
+    nc[a] = (int32_t)k;
+    ncell *= nc[a];
+  }
+  if (ncell >= (int64_t(1) << 30)) return fail(ctx, DCM_ERR_RANGE, "too many cells");
+  DCM_TRY(ensure(ctx, ctx->cell_count, ncell * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->cell_fill, ncell * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->cell_start, (ncell + 1) * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_elems(ncell) * sizeof(int32_t)));
+  if (n >= (int64_t(1) << 24))
+    return fail(ctx, DCM_ERR_RANGE, "the pair kernel supports fewer than 2^24 particles");
+  DCM_TRY(ensure(ctx, ctx->perm, n * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->sorted, n * sizeof(double4)));
+  int32_t *cof = cell_of;
+  if (!cof) {
+    DCM_TRY(ensure(ctx, ctx->cell_of, n * sizeof(int32_t)));
+    cof = ptr<int32_t>(ctx->cell_of);
+  }
+  const double sc[3] = {(double)nc[0] / box.L[0], (double)nc[1] / box.L[1],
+                        (double)nc[2] / box.L[2]};
+  const double rc_cap = 0.5 * std::min(box.L[0], std::min(box.L[1], box.L[2]));
+  hipStream_t s = ctx->stream;
+  hipEvent_t ev;
+  timer_begin(ctx, "cells", &ev);
+  launch_fill_i32(s, ptr<int32_t>(ctx->cell_count), 0, ncell);
+  launch_cell_count(s, x, y, z, rc, n, box.L, nc, sc, rc_cap, cof, ptr<int32_t>(ctx->cell_count),
+                    ctx->ctl, ctx->d_status);
+  launch_exclusive_scan(s, ptr<int32_t>(ctx->cell_count), ptr<int32_t>(ctx->cell_start), ncell,
+                        ptr<int32_t>(ctx->scan_tmp));
+  launch_fill_i32(s, ptr<int32_t>(ctx->cell_fill), 0, ncell);
+  launch_cell_scatter(s, cof, n, ptr<int32_t>(ctx->cell_start), ptr<int32_t>(ctx->cell_fill),
+                      ptr<int32_t>(ctx->perm));
+  launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, ptr<int32_t>(ctx->perm));
+  launch_gather(s, x, y, z, rc, ptr<int32_t>(ctx->perm), n, box.L, rc_cap,
+                ptr<double4>(ctx->sorted));
+  if (cell_start)
+    hipMemcpyAsync(cell_start, ctx->cell_start.p, (ncell + 1) * sizeof(int32_t),
+                   hipMemcpyDeviceToDevice, s);
+  timer_end(ctx, "cells", ev);
+  for (int a = 0; a < 3; ++a) {
+    ctx->nc[a] = nc[a];
+    ctx->cell_len[a] = box.L[a] / (double)nc[a];
+    ctx->cell_scale[a] = sc[a];
+    ctx->cell_box.L[a] = box.L[a];
+  }
+  ctx->cell_n = n;
+  ctx->cell_prec = prec;
+  return check_launch(ctx, "dcm_build_cells");
+}
+
+dcm_status dcm_cell_dims(const dcm_ctx *ctx, int32_t n_cells[3], double cell_len[3]) {
+  if (!ctx || !n_cells) return DCM_ERR_INVALID;
+  if (ctx->cell_n < 0) return DCM_ERR_INVALID;
+  for (int a = 0; a < 3; ++a) {
+    n_cells[a] = ctx->nc[a];
+    if (cell_len) cell_len[a] = ctx->cell_len[a];
+  }
+  return DCM_OK;
+}
+
+dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_flags,
+                      double *fx, double *fy, double *fz, double *energy, double *virial,
+                      int32_t *nnbr, uint64_t *npairs) {
+  if (!ctx) return DCM_ERR_INVALID;
+  if (ctx->cell_n < 0) return fail(ctx, DCM_ERR_INVALID, "dcm_forces before dcm_build_cells");
+  const int64_t n = ctx->cell_n;
+  if (n > 0 && (!fx || !fy || !fz)) return fail(ctx, DCM_ERR_INVALID, "dcm_forces: null force");
+  if (pair_rule != DCM_PAIR_OWN && pair_rule != DCM_PAIR_MAX)
+    return fail(ctx, DCM_ERR_INVALID, "unknown pair rule");
+  if (prec != DCM_FP64 && prec != DCM_FP32_MIXED)
+    return fail(ctx, DCM_ERR_INVALID, "unknown precision");
+  if (!finite_pos(lj.epsilon) || !finite_pos(lj.sigma))
+    return fail(ctx, DCM_ERR_INVALID, "LJ epsilon and sigma must be > 0");
+  if ((ev_flags & DCM_EV_ENERGY) && !energy)
+    return fail(ctx, DCM_ERR_INVALID, "energy requested without a pointer");
+  if ((ev_flags & DCM_EV_VIRIAL) && !virial)
+    return fail(ctx, DCM_ERR_INVALID, "virial requested without a pointer");
+  const int64_t blocks = std::max<int64_t>(1, ceil_div(n, pair_block_size()));
+  DCM_TRY(ensure(ctx, ctx->partials, blocks * kPartialSlots * sizeof(double)));
+  PairArgs a;
+  a.pos = ptr<double4>(ctx->sorted);
+  a.cell_start = ptr<int32_t>(ctx->cell_start);
+  a.perm = ptr<int32_t>(ctx->perm);
+  a.n = n;
+  for (int k = 0; k < 3; ++k) {
+    a.nc[k] = ctx->nc[k];
+    a.len[k] = ctx->cell_len[k];
+    a.sc[k] = ctx->cell_scale[k];
+    a.L[k] = ctx->cell_box.L[k];
+    a.invL[k] = 1.0 / ctx->cell_box.L[k];
+  }
+  a.eps = lj.epsilon;
+  a.sigma = lj.sigma;
+  a.ev_flags = ev_flags;
+  a.ctl = ctx->ctl;
+  a.fx = fx;
+  a.fy = fy;
+  a.fz = fz;
+  a.nnbr = (ev_flags & DCM_EV_COUNTS) ? nnbr : nullptr;
+  a.partials = ptr<double>(ctx->partials);
+  a.status = ctx->d_status;
+  hipEvent_t ev;
+  timer_begin(ctx, "pair", &ev);
+  launch_pair(ctx->stream, a, pair_rule, prec);
+  timer_end(ctx, "pair", ev);
+  if (ev_flags & (DCM_EV_ENERGY | DCM_EV_VIRIAL | DCM_EV_COUNTS))
+    launch_reduce_partials(ctx->stream, a.partials, blocks, lj.epsilon, ev_flags, energy, virial,
+                           npairs);
+  return check_launch(ctx, "dcm_forces");
+}
+
+dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,
+                    double *vz, double *fx, double *fy, double *fz, int64_t n, double mass,
+                    dcm_box box, dcm_lj lj, dcm_rule rule, dcm_grid grid, double rc_grid,
+                    int pair_rule, int prec, double dt, int32_t nsteps, int32_t redetect_every,
+                    int64_t step0, double *energy_series, double *delta, double *rc) {
+  if (!ctx) return DCM_ERR_INVALID;
+  int64_t nvox = 0;
+  DCM_TRY(check_n(ctx, n));
+  DCM_TRY(check_box(ctx, box));
+  DCM_TRY(check_grid(ctx, grid, &nvox));
+  if (n > 0 && (!x || !y || !z || !fx || !fy || !fz))
+    return fail(ctx, DCM_ERR_INVALID, "dcm_step: null pointer");
+  if (nsteps > 0 && n > 0 && (!vx || !vy || !vz))
+    return fail(ctx, DCM_ERR_INVALID, "dcm_step: null velocity");
+  if (nsteps < 0 || redetect_every < 1 || !finite_pos(mass) || !std::isfinite(dt) ||
+      !finite_pos(rc_grid))
+    return fail(ctx, DCM_ERR_INVALID, "dcm_step: bad nsteps/redetect_every/mass/dt/rc_grid");
+  if (!finite_pos(rule.rc_min) || !finite_pos(rule.rc_max) || !finite_pos(rule.ramp) ||
+      rule.rc_min > rule.rc_max)
+    return fail(ctx, DCM_ERR_INVALID, "rule needs 0 < rc_min <= rc_max and ramp > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!(rule.rc_max < 0.5 * box.L[a]))
+      return fail(ctx, DCM_ERR_RANGE, "rc_max must be below half of every box length");
+  DCM_TRY(ensure(ctx, ctx->seg, nvox));
+  DCM_TRY(ensure(ctx, ctx->iface, nvox));
+  DCM_TRY(ensure(ctx, ctx->dist, nvox * sizeof(double)));
+  DCM_TRY(ensure(ctx, ctx->scalars, 16 * sizeof(double)));
+  DCM_TRY(ensure(ctx, ctx->ke, kinetic_blocks(n) * sizeof(double)));
+  if (!rc) {
+    DCM_TRY(ensure(ctx, ctx->rc, n * sizeof(double)));
+    rc = ptr<double>(ctx->rc);
+  }
+  if (ctx->field_n[0] != grid.n[0] || ctx->field_n[1] != grid.n[1] ||
+      ctx->field_n[2] != grid.n[2])
+    ctx->have_field = false;
+  // sweep passes stop early once one changes nothing; the cap only bounds
+  // the launches.  A tiled pass settles whole 16x8x8 tiles, so a front
+  // crosses at least a tile per pass; a plain pass advances one voxel.
+  double hmin = std::min(grid.h[0], std::min(grid.h[1], grid.h[2]));
+  int32_t max_waves = fsm_tiled(grid.n)
+                          ? std::max<int32_t>(12, (int32_t)std::ceil(2.0 * rc_grid / (8.0 * hmin)) + 8)
+                          : std::max<int32_t>(64, (int32_t)std::ceil(4.0 * rc_grid / hmin) + 8);
+  double *scal = ptr<double>(ctx->scalars);
+  auto detect = [&]() -> dcm_status {
+    DCM_TRY(dcm_detect_interface(ctx, x, y, z, n, box, grid, 0.0, nullptr, ptr<uint8_t>(ctx->seg),
+                                 ptr<uint8_t>(ctx->iface), nullptr));
+    DCM_TRY(dcm_sweep_distance(ctx, ptr<uint8_t>(ctx->seg), ptr<uint8_t>(ctx->iface), grid,
+                               rc_grid, max_waves, ptr<double>(ctx->dist), nullptr));
+    ctx->have_field = true;
+    for (int a = 0; a < 3; ++a) ctx->field_n[a] = grid.n[a];
+    return DCM_OK;
+  };
+  auto forces = [&](double *e_out) -> dcm_status {
+    DCM_TRY(dcm_assign_cutoffs(ctx, x, y, z, n, box, grid, ptr<double>(ctx->dist), rule, delta,
+                               rc));
+    DCM_TRY(dcm_build_cells(ctx, x, y, z, rc, n, box, 0.0, prec, nullptr, nullptr));
+    return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, fx, fy, fz, e_out ? e_out : scal,
+                      nullptr, nullptr, nullptr);
+  };
+  if (nsteps == 0) {
+    DCM_TRY(detect());
+    return forces(nullptr);
+  }
+  const double c = (0.5 * dt) / mass;
+  for (int32_t st = 0; st < nsteps; ++st) {
+    hipEvent_t ev;
+    timer_begin(ctx, "verlet", &ev);
+    launch_kick_drift(ctx->stream, x, y, z, vx, vy, vz, fx, fy, fz, n, c, dt, box.L);
+    timer_end(ctx, "verlet", ev);
+    if (!ctx->have_field || (step0 + st + 1) % redetect_every == 0) DCM_TRY(detect());
+    DCM_TRY(forces(energy_series ? energy_series + 2 * (int64_t)st : nullptr));
+    timer_begin(ctx, "verlet", &ev);
+    launch_kick(ctx->stream, vx, vy, vz, fx, fy, fz, n, c);
+    timer_end(ctx, "verlet", ev);
+    if (energy_series)
+      launch_kinetic(ctx->stream, vx, vy, vz, n, mass, ptr<double>(ctx->ke), kinetic_blocks(n),
+                     energy_series + 2 * (int64_t)st + 1);
+    DCM_TRY(check_launch(ctx, "dcm_step"));
+  }
+  return DCM_OK;
+}
+
+dcm_status dcm_set_profiling(dcm_ctx *ctx, int enable) {
+  if (!ctx) return DCM_ERR_INVALID;
+  ctx->profile = enable != 0;
+  return DCM_OK;
+}
+
+dcm_status dcm_kernel_time(dcm_ctx *ctx, const char *family, double *total_ms,
+                           int64_t *launches) {
+  if (!ctx || !family) return DCM_ERR_INVALID;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return DCM_ERR_HIP;
+  Timer &t = ctx->timers[family];
+  for (auto &pr : t.pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      t.ms += ms;
+      t.launches += 1;
+    }
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  t.pending.clear();
+  if (total_ms) *total_ms = t.ms;
+  if (launches) *launches = t.launches;
+  t.ms = 0.0;
+  t.launches = 0;
+  return DCM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Device-side helpers shared by the library's kernels.  Every operation whose
+// bits matter for an exact comparison (wrap, voxel/cell index, trilinear
+// weights) is written as one fixed sequence of correctly rounded IEEE
+// operations; the library is compiled with -ffp-contract=off so nothing is
+// fused unless fma() is written explicitly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dcm {
+
+// Periodic wrap into [0, L): w = x - L*floor(x/L), folding a result that
+// rounds below 0 or up to L.
+__device__ __forceinline__ double wrap_coord(double x, double L) {
+  double q = floor(x / L);
+  double w = x - L * q;
+  if (w < 0.0) w = w + L;
+  if (w >= L) w = 0.0;
+  return w;
+}
+
+// Index of the slab [c*L/n, (c+1)*L/n) holding a wrapped coordinate;
+// scale = n/L (computed once on the host).  Clamped so that a NaN or an
+// out-of-range input can never index outside [0, n).
+__device__ __forceinline__ int slab_index(double w, double scale, int n) {
+  double f = floor(w * scale);
+  int c = (f >= 0.0) ? ((f < (double)n) ? (int)f : n - 1) : 0;
+  return c;
+}
+
+__device__ __forceinline__ int wrap_index(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ bool finite3(double a, double b, double c) {
+  return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+// Sum of a value over the 64 lanes of a wavefront (fixed butterfly order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Add 1 to hist[key] for every valid lane with one atomic per distinct key in
+// the wavefront.  Must be reached by all lanes of the wavefront together.
+template <typename Counter>
+__device__ __forceinline__ void wave_aggregated_add(Counter *hist, uint32_t key, bool valid) {
+  unsigned long long pending = __ballot(valid);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t k = __shfl(key, leader, 64);
+    const unsigned long long same = __ballot(valid && key == k);
+    if ((int)(threadIdx.x & 63) == leader) atomicAdd(&hist[k], (Counter)__popcll(same));
+    pending &= ~same;
+  }
+}
+
+// Reserve one slot per valid lane in fill[key] (lanes with equal keys share
+// one atomic and take consecutive slots in lane order); returns the slot.
+__device__ __forceinline__ int wave_aggregated_slot(int32_t *fill, uint32_t key, bool valid) {
+  const int lane = (int)(threadIdx.x & 63);
+  unsigned long long pending = __ballot(valid);
+  int slot = 0;
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t k = __shfl(key, leader, 64);
+    const unsigned long long same = __ballot(valid && key == k);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&fill[k], (int32_t)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if (valid && key == k)
+      slot = base + (int)__popcll(same & ((1ull << lane) - 1ull));
+    pending &= ~same;
+  }
+  return slot;
+}
+
+}  // namespace dcm

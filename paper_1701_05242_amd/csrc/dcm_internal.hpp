@@ -1,0 +1,190 @@
+// Internal declarations of the gfx950 DCM library: the context, device
+// control block, status bits and the host-side launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dcm.h"
+
+namespace dcm {
+
+// Sticky device status bits (OR-ed by kernels, read by dcm_sync_status).
+enum : uint32_t {
+  ST_NONFINITE_POS = 1u << 0,
+  ST_HIST_RANGE = 1u << 1,
+  ST_DEGENERATE = 1u << 2,
+  ST_NOT_CONVERGED = 1u << 3,
+  ST_NONFINITE_FORCE = 1u << 4,
+  ST_RC_RANGE = 1u << 5,
+};
+
+constexpr int kHistBins = 4096;       // gray values (27-window counts) must stay below this
+constexpr int kMajorityMaxPasses = 16;
+constexpr int kPartialSlots = 8;      // per-block partial sums: E, W[6], pair count
+
+// Device-resident control block: scalars produced and consumed on the device
+// so that no stage needs a host round trip.
+struct Ctl {
+  // interface detection
+  int32_t threshold;
+  int32_t degenerate;
+  double c0, c1;
+  uint32_t maj_passes, maj_done, maj_result, maj_blocks;
+  unsigned long long maj_chg1, maj_chg2;
+  // distance sweep
+  uint32_t fsm_waves, fsm_done, fsm_result, fsm_blocks;
+  unsigned long long fsm_changed;
+  // cells: largest cutoff seen (bit pattern of a non-negative double)
+  unsigned long long rc_max_bits;
+  // reductions
+  uint32_t red_blocks;
+  uint32_t pad;
+};
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+struct Timer {
+  double ms = 0.0;
+  int64_t launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
+}  // namespace dcm
+
+struct dcm_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  uint32_t *d_status = nullptr;
+  uint32_t *h_status = nullptr;  // pinned
+  dcm::Ctl *ctl = nullptr;       // device control block
+  // grid scratch
+  dcm::DevBuf counts, gray, hist, seg_a, seg_b, seg, iface, dA, dB, dist, fsm_chg;
+  // particle scratch
+  dcm::DevBuf delta, rc, partials, ke, scalars;
+  // cells
+  dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp;
+  int32_t nc[3] = {0, 0, 0};
+  double cell_len[3] = {0, 0, 0};
+  double cell_scale[3] = {0, 0, 0};
+  dcm_box cell_box = {{0, 0, 0}};
+  int64_t cell_n = -1;
+  int cell_prec = 0;
+  // last distance field kept for dcm_step
+  bool have_field = false;
+  int32_t field_n[3] = {0, 0, 0};
+  // profiling
+  bool profile = false;
+  std::map<std::string, dcm::Timer> timers;
+};
+
+namespace dcm {
+
+// ---- context helpers (dcm_api.cpp)
+dcm_status fail(dcm_ctx *ctx, dcm_status code, const std::string &msg);
+dcm_status ensure(dcm_ctx *ctx, DevBuf &b, size_t bytes);
+dcm_status check_launch(dcm_ctx *ctx, const char *what);
+void timer_begin(dcm_ctx *ctx, const char *family, hipEvent_t *ev);
+void timer_end(dcm_ctx *ctx, const char *family, hipEvent_t ev);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---- launchers (one per kernel family; all enqueue on ctx->stream)
+// k_common.hip
+void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n);
+void launch_fill_i32(hipStream_t s, int32_t *p, int32_t v, int64_t n);
+void launch_reset_ctl(hipStream_t s, Ctl *ctl);
+void launch_clear_status(hipStream_t s, uint32_t *st);
+
+// k_grid.hip
+void launch_bin_density(hipStream_t s, const double *x, const double *y, const double *z,
+                        int64_t n, const double L[3], const int32_t nv[3], const double sc[3],
+                        uint32_t *counts, uint32_t *status);
+void launch_gray(hipStream_t s, const uint32_t *counts, uint32_t *gray, const int32_t nv[3]);
+void launch_hist(hipStream_t s, const uint32_t *gray, int64_t nvox, uint32_t *hist,
+                 uint32_t *status);
+void launch_otsu(hipStream_t s, const uint32_t *hist, int64_t nvox, Ctl *ctl, int32_t *t_out,
+                 uint32_t *status);
+void launch_threshold(hipStream_t s, const uint32_t *gray, int64_t nvox, double split,
+                      const Ctl *ctl, uint8_t *seg0, int32_t *t_out);
+void launch_majority_pass(hipStream_t s, uint8_t *buf0, uint8_t *buf1, const int32_t nv[3],
+                          int pass, int max_passes, Ctl *ctl);
+void launch_interface(hipStream_t s, const uint8_t *buf0, const uint8_t *buf1,
+                      const int32_t nv[3], const Ctl *ctl, uint8_t *seg, uint8_t *iface);
+
+// k_fsm.hip
+void launch_fsm_init(hipStream_t s, const uint8_t *seg, const uint8_t *iface, int64_t nvox,
+                     double *dA, double *dB, Ctl *ctl);
+// one launch of the sweep: a temporally blocked tile pass when fsm_tiled(nv),
+// else one synchronous wave; chg0/chg1 hold one flag per tile
+bool fsm_tiled(const int32_t nv[3]);
+int64_t fsm_tile_count(const int32_t nv[3]);
+void launch_fsm_step(hipStream_t s, double *dA, double *dB, uint8_t *chg0, uint8_t *chg1,
+                     const int32_t nv[3], const double h[3], double rc_grid, int step,
+                     int max_steps, Ctl *ctl, uint32_t *status);
+void launch_fsm_final(hipStream_t s, const double *dA, const double *dB, int64_t nvox,
+                      double rc_grid, const Ctl *ctl, double *dist, int32_t *waves_out);
+
+// k_cells.hip
+void launch_assign_cutoffs(hipStream_t s, const double *x, const double *y, const double *z,
+                           int64_t n, const double L[3], const int32_t nv[3],
+                           const double sc[3], const double *dist, dcm_rule rule,
+                           double *delta, double *rc);
+void launch_cell_count(hipStream_t s, const double *x, const double *y, const double *z,
+                       const double *rc, int64_t n, const double L[3], const int32_t nc[3],
+                       const double sc[3], double rc_cap, int32_t *cell_of, int32_t *cell_count,
+                       Ctl *ctl, uint32_t *status);
+void launch_exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64_t n,
+                           int32_t *tmp);
+int64_t scan_tmp_elems(int64_t n);
+void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
+                         const int32_t *cell_start, int32_t *cell_fill, int32_t *perm);
+void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell, int32_t *perm);
+void launch_gather(hipStream_t s, const double *x, const double *y, const double *z,
+                   const double *rc, const int32_t *perm, int64_t n, const double L[3],
+                   double rc_cap, double4 *sorted);
+
+// k_pair.hip
+struct PairArgs {
+  const double4 *pos;        // sorted (x, y, z, rc), wrapped into the box
+  const int32_t *cell_start; // [ncell + 1]
+  const int32_t *perm;       // sorted -> caller index
+  int64_t n;
+  int32_t nc[3];
+  double len[3];             // cell edge per axis = L/n
+  double sc[3];              // n/L
+  double L[3];
+  double invL[3];
+  double eps, sigma;
+  int ev_flags;
+  const Ctl *ctl;
+  double *fx, *fy, *fz;
+  int32_t *nnbr;
+  double *partials;          // [blocks * kPartialSlots]
+  uint32_t *status;
+};
+int pair_block_size();
+void launch_pair(hipStream_t s, const PairArgs &a, int rule, int prec);
+void launch_reduce_partials(hipStream_t s, const double *partials, int64_t blocks, double eps,
+                            int ev_flags, double *energy, double *virial, uint64_t *npairs);
+
+// k_verlet.hip
+void launch_kick(hipStream_t s, double *vx, double *vy, double *vz, const double *fx,
+                 const double *fy, const double *fz, int64_t n, double c);
+void launch_kick_drift(hipStream_t s, double *x, double *y, double *z, double *vx, double *vy,
+                       double *vz, const double *fx, const double *fy, const double *fz,
+                       int64_t n, double c, double dt, const double L[3]);
+void launch_kinetic(hipStream_t s, const double *vx, const double *vy, const double *vz,
+                    int64_t n, double mass, double *partials, int64_t blocks, double *out);
+int64_t kinetic_blocks(int64_t n);
+
+}  // namespace dcm

@@ -1,0 +1,431 @@
+// Interface detection on the density grid (Section 2.1, Fig. 4, Eq. 4):
+// binning -> gray value -> histogram -> two-phase threshold -> majority
+// regularisation -> interface marking.  All stages are integer stencils or
+// exact integer sums, so their results are bit-for-bit deterministic.
+//
+// The 27-point stencils run on 3-D tiles staged in LDS (64 x 4 x 4 outputs
+// per workgroup, one-voxel periodic halo) and sum separably: along x into LDS,
+// then over the 3 x 3 (y, z) window, so each output costs 3 + 9 LDS reads.
+#include "dcm_device.hpp"
+#include "dcm_internal.hpp"
+
+namespace dcm {
+
+constexpr int SX = 64, SY = 4, SZ = 4;                 // stencil tile (outputs)
+constexpr int HX = SX + 2, HY = SY + 2, HZ = SZ + 2;   // with halo
+
+// periodic index for a coordinate within one period of [0, n)
+__device__ __forceinline__ int wrap_near(int i, int n) {
+  if (i < 0) i += n;
+  if (i >= n) i -= n;
+  if (i < 0 || i >= n) i = wrap_index(i, n);  // grids thinner than the halo
+  return i;
+}
+
+// ------------------------------------------------------------ binning (Fig. 4a)
+__global__ __launch_bounds__(256) void k_bin_density(const double *__restrict__ x,
+                                                     const double *__restrict__ y,
+                                                     const double *__restrict__ z, int64_t n,
+                                                     double Lx, double Ly, double Lz, int nx,
+                                                     int ny, int nz, double sx, double sy,
+                                                     double sz, uint32_t *counts,
+                                                     uint32_t *status) {
+  // grid-stride loop with a uniform trip count so every lane reaches the
+  // wave-aggregated atomic together
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+    const int64_t i = base + threadIdx.x;
+    bool valid = i < n;
+    uint32_t v = 0;
+    if (valid) {
+      double px = x[i], py = y[i], pz = z[i];
+      if (!finite3(px, py, pz)) {
+        atomicOr(status, ST_NONFINITE_POS);
+        valid = false;
+      } else {
+        int vx = slab_index(wrap_coord(px, Lx), sx, nx);
+        int vy = slab_index(wrap_coord(py, Ly), sy, ny);
+        int vz = slab_index(wrap_coord(pz, Lz), sz, nz);
+        v = (uint32_t)(((int64_t)vz * ny + vy) * nx + vx);
+      }
+    }
+    wave_aggregated_add(counts, v, valid);
+  }
+}
+
+void launch_bin_density(hipStream_t s, const double *x, const double *y, const double *z,
+                        int64_t n, const double L[3], const int32_t nv[3], const double sc[3],
+                        uint32_t *counts, uint32_t *status) {
+  if (n <= 0) return;
+  int64_t b = ceil_div(n, 256);
+  if (b > 8192) b = 8192;
+  hipLaunchKernelGGL(k_bin_density, dim3((unsigned)b), dim3(256), 0, s, x, y, z, n, L[0], L[1],
+                     L[2], nv[0], nv[1], nv[2], sc[0], sc[1], sc[2], counts, status);
+}
+
+static dim3 stencil_grid(const int32_t nv[3]) {
+  return dim3((unsigned)ceil_div(nv[0], SX), (unsigned)ceil_div(nv[1], SY),
+              (unsigned)ceil_div(nv[2], SZ));
+}
+
+// Stage the haloed tile of `src` (periodic) into LDS.
+template <typename T, typename S>
+__device__ __forceinline__ void load_tile(S (&tile)[HZ][HY][HX], const T *__restrict__ src,
+                                          int x0, int y0, int z0, int nx, int ny, int nz) {
+  const int tid = threadIdx.y * SX + threadIdx.x;
+  for (int e = tid; e < HZ * HY * HX; e += SX * SY) {
+    const int lz = e / (HY * HX);
+    const int r = e - lz * (HY * HX);
+    const int ly = r / HX;
+    const int lx = r - ly * HX;
+    const int gx = wrap_near(x0 + lx - 1, nx);
+    const int gy = wrap_near(y0 + ly - 1, ny);
+    const int gz = wrap_near(z0 + lz - 1, nz);
+    tile[lz][ly][lx] = (S)src[((int64_t)gz * ny + gy) * nx + gx];
+  }
+}
+
+// 27-window sum at output (lx, ly, lz) of the tile from the x-summed plane.
+template <typename S>
+__device__ __forceinline__ S sum_yz(const S (&sx)[HZ][HY][SX], int lx, int ly, int lz) {
+  S s = 0;
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) s += sx[lz + dz][ly + dy][lx];
+  return s;
+}
+
+template <typename S>
+__device__ __forceinline__ void sum_x(S (&sx)[HZ][HY][SX], const S (&tile)[HZ][HY][HX]) {
+  const int tid = threadIdx.y * SX + threadIdx.x;
+  for (int e = tid; e < HZ * HY * SX; e += SX * SY) {
+    const int lz = e / (HY * SX);
+    const int r = e - lz * (HY * SX);
+    const int ly = r / SX;
+    const int lx = r - ly * SX;
+    sx[lz][ly][lx] = tile[lz][ly][lx] + tile[lz][ly][lx + 1] + tile[lz][ly][lx + 2];
+  }
+}
+
+// --------------------------------------------------- gray value (Fig. 4b)
+// gray[v] = sum of counts over the periodic 3x3x3 window of v.
+__global__ __launch_bounds__(256) void k_gray(const uint32_t *__restrict__ counts,
+                                              uint32_t *__restrict__ gray, int nx, int ny,
+                                              int nz) {
+  __shared__ uint32_t tile[HZ][HY][HX];
+  __shared__ uint32_t sx[HZ][HY][SX];
+  const int x0 = blockIdx.x * SX, y0 = blockIdx.y * SY, z0 = blockIdx.z * SZ;
+  load_tile(tile, counts, x0, y0, z0, nx, ny, nz);
+  __syncthreads();
+  sum_x(sx, tile);
+  __syncthreads();
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int gx = x0 + lx, gy = y0 + ly;
+  if (gx >= nx || gy >= ny) return;
+#pragma unroll
+  for (int lz = 0; lz < SZ; ++lz) {
+    const int gz = z0 + lz;
+    if (gz < nz) gray[((int64_t)gz * ny + gy) * nx + gx] = sum_yz(sx, lx, ly, lz);
+  }
+}
+
+void launch_gray(hipStream_t s, const uint32_t *counts, uint32_t *gray, const int32_t nv[3]) {
+  hipLaunchKernelGGL(k_gray, stencil_grid(nv), dim3(SX, SY), 0, s, counts, gray, nv[0], nv[1],
+                     nv[2]);
+}
+
+// Histogram of the gray values: a private LDS histogram per workgroup,
+// filled with wave-aggregated atomics, merged once into the global one.
+__global__ __launch_bounds__(256) void k_hist(const uint32_t *__restrict__ gray, int64_t nvox,
+                                              uint32_t *hist, uint32_t *status) {
+  __shared__ uint32_t lh[kHistBins];
+  for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) lh[b] = 0u;
+  __syncthreads();
+  bool over = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < nvox; base += stride) {
+    const int64_t v = base + threadIdx.x;
+    uint32_t g = v < nvox ? gray[v] : 0u;
+    bool valid = v < nvox && g < (uint32_t)kHistBins;
+    over |= (v < nvox) && !valid;
+    wave_aggregated_add(lh, g, valid);
+  }
+  if (over) atomicOr(status, ST_HIST_RANGE);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kHistBins; b += blockDim.x)
+    if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
+void launch_hist(hipStream_t s, const uint32_t *gray, int64_t nvox, uint32_t *hist,
+                 uint32_t *status) {
+  int64_t b = ceil_div(nvox, 256 * 16);
+  if (b < 1) b = 1;
+  if (b > 512) b = 512;
+  hipLaunchKernelGGL(k_hist, dim3((unsigned)b), dim3(256), 0, s, gray, nvox, hist, status);
+}
+
+// ------------------------------ two-phase split of the gray values (Eq. 4)
+// For threshold t the phases are {g >= t} and {g < t}.  The piecewise-
+// constant two-phase energy with no length term is smallest where
+// S0^2/n0 + S1^2/n1 is largest (S, n: exact integer sum and count of each
+// phase); ties go to the smallest t.  One workgroup of 1024 threads owns 4
+// consecutive histogram bins each.
+__global__ __launch_bounds__(1024) void k_otsu(const uint32_t *__restrict__ hist, Ctl *ctl,
+                                               int32_t *t_out, uint32_t *status) {
+  __shared__ long long sc[1024];
+  __shared__ long long ss[1024];
+  __shared__ double bscore[1024];
+  __shared__ int bt[1024];
+  __shared__ long long best_n1, best_s1;
+  const int tid = threadIdx.x;
+  const int t0 = tid * 4;
+  long long c[4], sm[4];
+  long long lc = 0, ls = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    c[q] = (long long)hist[t0 + q];
+    sm[q] = c[q] * (long long)(t0 + q);
+    lc += c[q];
+    ls += sm[q];
+  }
+  sc[tid] = lc;
+  ss[tid] = ls;
+  __syncthreads();
+  // inclusive suffix scan over threads: sc[tid] = sum over threads u >= tid
+  for (int off = 1; off < 1024; off <<= 1) {
+    long long vc = (tid + off < 1024) ? sc[tid + off] : 0;
+    long long vs = (tid + off < 1024) ? ss[tid + off] : 0;
+    __syncthreads();
+    sc[tid] += vc;
+    ss[tid] += vs;
+    __syncthreads();
+  }
+  const long long total_n = sc[0], total_s = ss[0];
+  long long above_n = (tid + 1 < 1024) ? sc[tid + 1] : 0;
+  long long above_s = (tid + 1 < 1024) ? ss[tid + 1] : 0;
+  double best = -1.0;
+  int best_t = -1;
+  long long n1q[4], s1q[4];
+  // n1/S1 at t = t0+q: every bin >= t
+  for (int q = 3; q >= 0; --q) {
+    above_n += c[q];
+    above_s += sm[q];
+    n1q[q] = above_n;
+    s1q[q] = above_s;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int t = t0 + q;
+    if (t < 1) continue;
+    long long nn1 = n1q[q], ss1 = s1q[q];
+    long long nn0 = total_n - nn1, ss0 = total_s - ss1;
+    if (nn0 == 0 || nn1 == 0) continue;
+    double S0 = (double)ss0, S1 = (double)ss1;
+    double score = (S0 * S0) / (double)nn0 + (S1 * S1) / (double)nn1;
+    if (score > best) {
+      best = score;
+      best_t = t;
+    }
+  }
+  bscore[tid] = best;
+  bt[tid] = best_t;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (tid < off) {
+      double o = bscore[tid + off];
+      int ot = bt[tid + off];
+      bool take = (ot >= 0) && (bt[tid] < 0 || o > bscore[tid] ||
+                                (o == bscore[tid] && ot < bt[tid]));
+      if (take) {
+        bscore[tid] = o;
+        bt[tid] = ot;
+      }
+    }
+    __syncthreads();
+  }
+  const int T = bt[0];
+  if (T >= 0 && T >= t0 && T < t0 + 4) {
+    best_n1 = n1q[T - t0];
+    best_s1 = s1q[T - t0];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int degenerate = 1;
+    double c0 = 0.0, c1 = 0.0;
+    if (T >= 0) {
+      long long nn1 = best_n1, ss1 = best_s1;
+      long long nn0 = total_n - nn1, ss0 = total_s - ss1;
+      c0 = (double)ss0 / (double)nn0;
+      c1 = (double)ss1 / (double)nn1;
+      degenerate = ((c1 + 3.0) / (c0 + 3.0) < 2.0) ? 1 : 0;
+    }
+    ctl->threshold = T;
+    ctl->degenerate = degenerate;
+    ctl->c0 = c0;
+    ctl->c1 = c1;
+    if (degenerate) atomicOr(status, ST_DEGENERATE);
+    if (t_out) *t_out = T;
+  }
+}
+
+void launch_otsu(hipStream_t s, const uint32_t *hist, int64_t nvox, Ctl *ctl, int32_t *t_out,
+                 uint32_t *status) {
+  (void)nvox;
+  hipLaunchKernelGGL(k_otsu, dim3(1), dim3(1024), 0, s, hist, ctl, t_out, status);
+}
+
+// Initial phase map s0 = [g >= T] (or [g >= split] for a fixed split); a
+// single-phase volume is all high density.  Also resets the majority-pass
+// state for the passes that follow.
+__global__ __launch_bounds__(256) void k_threshold(const uint32_t *__restrict__ gray,
+                                                   int64_t nvox, double split, Ctl *ctl,
+                                                   uint8_t *seg0, int32_t *t_out) {
+  const bool fixed = split > 0.0;
+  const int T = ctl->threshold;
+  const bool deg = !fixed && ctl->degenerate;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t g = gray[v];
+    uint8_t s;
+    if (fixed)
+      s = ((double)g >= split) ? 1 : 0;
+    else
+      s = deg ? 1 : ((int64_t)g >= (int64_t)T ? 1 : 0);
+    seg0[v] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->maj_passes = 0;
+    ctl->maj_done = 0;
+    ctl->maj_result = 0;
+    ctl->maj_blocks = 0;
+    ctl->maj_chg1 = 0;
+    ctl->maj_chg2 = 0;
+    if (fixed) {
+      ctl->threshold = (int32_t)ceil(split);
+      ctl->degenerate = 0;
+      if (t_out) *t_out = (int32_t)ceil(split);
+    }
+  }
+}
+
+static unsigned flat_grid(int64_t nvox) {
+  int64_t b = ceil_div(nvox, 256 * 4);
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (unsigned)b;
+}
+
+void launch_threshold(hipStream_t s, const uint32_t *gray, int64_t nvox, double split,
+                      const Ctl *ctl, uint8_t *seg0, int32_t *t_out) {
+  hipLaunchKernelGGL(k_threshold, dim3(flat_grid(nvox)), dim3(256), 0, s, gray, nvox, split,
+                     const_cast<Ctl *>(ctl), seg0, t_out);
+}
+
+// ---------------------------------------- majority regularisation (4b)
+// Pass p reads state p-1 from buf[(p-1)&1] and writes state p to buf[p&1],
+// counting voxels that differ from state p-1 (no change: fixed point) and
+// from the overwritten state p-2 (no change: 2-cycle).  The last workgroup to
+// finish decides whether later passes run.
+__global__ __launch_bounds__(256) void k_majority(uint8_t *buf0, uint8_t *buf1, int nx, int ny,
+                                                  int nz, int pass, int max_passes, Ctl *ctl) {
+  if (*(volatile uint32_t *)&ctl->maj_done) return;
+  __shared__ uint8_t tile[HZ][HY][HX];
+  __shared__ uint8_t sx[HZ][HY][SX];
+  __shared__ int last;
+  const uint8_t *__restrict__ src = (pass & 1) ? buf0 : buf1;
+  uint8_t *__restrict__ dst = (pass & 1) ? buf1 : buf0;
+  const int x0 = blockIdx.x * SX, y0 = blockIdx.y * SY, z0 = blockIdx.z * SZ;
+  load_tile(tile, src, x0, y0, z0, nx, ny, nz);
+  __syncthreads();
+  sum_x(sx, tile);
+  __syncthreads();
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int gx = x0 + lx, gy = y0 + ly;
+  unsigned long long c1 = 0, c2 = 0;
+  if (gx < nx && gy < ny) {
+#pragma unroll
+    for (int lz = 0; lz < SZ; ++lz) {
+      const int gz = z0 + lz;
+      if (gz >= nz) break;
+      const int sum = (int)sum_yz(sx, lx, ly, lz);
+      const uint8_t nvv = sum >= 14 ? 1 : 0;
+      const int64_t v = ((int64_t)gz * ny + gy) * nx + gx;
+      const uint8_t old = dst[v];
+      dst[v] = nvv;
+      c1 += (nvv != tile[lz + 1][ly + 1][lx + 1]);
+      c2 += (nvv != old);
+    }
+  }
+  c1 = wave_sum_u64(c1);
+  c2 = wave_sum_u64(c2);
+  if ((threadIdx.x & 63) == 0) {
+    if (c1) atomicAdd(&ctl->maj_chg1, c1);
+    if (c2) atomicAdd(&ctl->maj_chg2, c2);
+  }
+  __threadfence();
+  __syncthreads();
+  const unsigned nblocks = gridDim.x * gridDim.y * gridDim.z;
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    unsigned ticket = atomicAdd(&ctl->maj_blocks, 1u);
+    last = (ticket == nblocks - 1);
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0 && threadIdx.y == 0) {
+    __threadfence();
+    unsigned long long t1 = atomicAdd(&ctl->maj_chg1, 0ull);
+    unsigned long long t2 = atomicAdd(&ctl->maj_chg2, 0ull);
+    bool done = (t1 == 0) || (pass >= 2 && t2 == 0) || pass >= max_passes;
+    ctl->maj_passes = (uint32_t)pass;
+    ctl->maj_result = (uint32_t)(pass & 1);
+    ctl->maj_chg1 = 0;
+    ctl->maj_chg2 = 0;
+    ctl->maj_blocks = 0;
+    __threadfence();
+    ctl->maj_done = done ? 1u : 0u;
+  }
+}
+
+void launch_majority_pass(hipStream_t s, uint8_t *buf0, uint8_t *buf1, const int32_t nv[3],
+                          int pass, int max_passes, Ctl *ctl) {
+  hipLaunchKernelGGL(k_majority, stencil_grid(nv), dim3(SX, SY), 0, s, buf0, buf1, nv[0], nv[1],
+                     nv[2], pass, max_passes, ctl);
+}
+
+// ------------------------------------------- interface marking (Fig. 4c)
+// iface[v] = 1 for a high-density voxel with a low-density face neighbour.
+__global__ __launch_bounds__(256) void k_interface(const uint8_t *buf0, const uint8_t *buf1,
+                                                   int nx, int ny, int nz, const Ctl *ctl,
+                                                   uint8_t *__restrict__ seg,
+                                                   uint8_t *__restrict__ iface) {
+  const uint8_t *__restrict__ s = ctl->maj_result ? buf1 : buf0;
+  const int i = blockIdx.x * SX + threadIdx.x;
+  const int j = blockIdx.y * SY + threadIdx.y;
+  if (i >= nx || j >= ny) return;
+  const int im = i == 0 ? nx - 1 : i - 1, ip = i + 1 == nx ? 0 : i + 1;
+  const int jm = j == 0 ? ny - 1 : j - 1, jp = j + 1 == ny ? 0 : j + 1;
+#pragma unroll
+  for (int q = 0; q < SZ; ++q) {
+    const int k = blockIdx.z * SZ + q;
+    if (k >= nz) break;
+    const int km = k == 0 ? nz - 1 : k - 1, kp = k + 1 == nz ? 0 : k + 1;
+    const int64_t rowk = (int64_t)k * ny;
+    const int64_t v = (rowk + j) * nx + i;
+    const uint8_t sv = s[v];
+    uint8_t f = 0;
+    if (sv)
+      f = (!s[(rowk + j) * nx + im]) | (!s[(rowk + j) * nx + ip]) |
+          (!s[(rowk + jm) * nx + i]) | (!s[(rowk + jp) * nx + i]) |
+          (!s[((int64_t)km * ny + j) * nx + i]) | (!s[((int64_t)kp * ny + j) * nx + i]);
+    seg[v] = sv;
+    iface[v] = f;
+  }
+}
+
+void launch_interface(hipStream_t s, const uint8_t *buf0, const uint8_t *buf1,
+                      const int32_t nv[3], const Ctl *ctl, uint8_t *seg, uint8_t *iface) {
+  hipLaunchKernelGGL(k_interface, stencil_grid(nv), dim3(SX, SY), 0, s, buf0, buf1, nv[0], nv[1],
+                     nv[2], ctl, seg, iface);
+}
+
+}  // namespace dcm

@@ -1,0 +1,359 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Integer work (voxel counts, phase map, interface, threshold, cells, neighbour
+counts) must match bit for bit.  FP64 results must agree within 1e-12
+relative (forces normalised by the oracle's RMS force); FP32-mixed within
+1e-5.  Each stage is fed the oracle's own input for that stage, so that an
+upstream rounding difference cannot perturb a downstream decision; the
+end-to-end tests then chain the whole path."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1701_05242_amd as dcm
+import workloads
+from gpu_util import DEV, F64, Ctx, dev, force_errors, gpu_forces, host, rel
+
+pytestmark = pytest.mark.gpu
+
+SMALL = ["slab_small", "slab_medium"]
+GRIDS = ["slab_small", "slab_medium", "droplet", "cylinder", "slab_large"]
+
+
+@functools.lru_cache(maxsize=None)
+def ref_detect(name):
+    s = workloads.make(name)
+    det = oracle.detect_interface(s.x, s.y, s.z, s.box, s.h)
+    rcg = oracle.rc_grid_for(s.rule, det["hv"])
+    D, passes = oracle.fsm(det["nv"], det["hv"], det["seg"], det["iface"], rcg)
+    delta = oracle.particle_distance(s.x, s.y, s.z, s.box, det["nv"], D)
+    rc = oracle.cutoffs(delta, s.rule)
+    return dict(det, D=D, fsm_passes=passes, rc_grid=rcg, delta=delta, rc=rc)
+
+
+@functools.lru_cache(maxsize=None)
+def ref_forces(name, rule, idx_step=1):
+    s = workloads.make(name)
+    r = ref_detect(name)
+    idx = None if idx_step == 1 else np.arange(0, s.n, idx_step)
+    return oracle.forces(s.x, s.y, s.z, r["rc"], s.box, rule=rule, idx=idx)
+
+
+def _ref_F(f):
+    return np.stack([f["fx"], f["fy"], f["fz"]], 1)
+
+
+# ------------------------------------------------------------------ grid
+
+@pytest.mark.parametrize("name", GRIDS)
+def test_detect_interface_bit_exact(name):
+    print(f"[gpu] detect {name}", flush=True)
+    s = workloads.make(name)
+    ref = ref_detect(name)
+    grid = dcm.make_grid(s.box, s.h)
+    nv = dcm.grid_voxels(grid)
+    assert list(grid.n) == list(ref["nv"])
+    counts = torch.zeros(nv, dtype=torch.uint32, device=DEV)
+    seg = torch.zeros(nv, dtype=torch.uint8, device=DEV)
+    iface = torch.zeros(nv, dtype=torch.uint8, device=DEV)
+    thr = torch.zeros(1, dtype=torch.int32, device=DEV)
+    with Ctx() as ctx:
+        dcm.dcm_detect_interface(ctx, dev(s.x), dev(s.y), dev(s.z), s.box, grid, seg, iface,
+                                 counts=counts, threshold_out=thr)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+    np.testing.assert_array_equal(host(counts), ref["counts"])
+    assert int(host(thr)[0]) == ref["threshold"]
+    np.testing.assert_array_equal(host(seg), ref["seg"])
+    np.testing.assert_array_equal(host(iface), ref["iface"])
+
+
+def test_detect_fixed_split_and_degenerate_flag():
+    s = workloads.make("slab_small")
+    grid = dcm.make_grid(s.box, s.h)
+    nv = dcm.grid_voxels(grid)
+    seg = torch.zeros(nv, dtype=torch.uint8, device=DEV)
+    iface = torch.zeros(nv, dtype=torch.uint8, device=DEV)
+    ref = oracle.detect_interface(s.x, s.y, s.z, s.box, s.h, split=9.5)
+    with Ctx() as ctx:
+        dcm.dcm_detect_interface(ctx, dev(s.x), dev(s.y), dev(s.z), s.box, grid, seg, iface,
+                                 split=9.5)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+    np.testing.assert_array_equal(host(seg), ref["seg"])
+    np.testing.assert_array_equal(host(iface), ref["iface"])
+    # only the liquid slab: one phase, flagged, everything high density
+    liq = s.z < 40.0
+    liq &= s.z >= 20.0
+    x, y, z = s.x[liq], s.y[liq], s.z[liq] - 20.0
+    box = (13.4, 13.4, 20.0)
+    g2 = dcm.make_grid(box, 1.0)
+    nv2 = dcm.grid_voxels(g2)
+    seg = torch.zeros(nv2, dtype=torch.uint8, device=DEV)
+    iface = torch.zeros(nv2, dtype=torch.uint8, device=DEV)
+    ref = oracle.detect_interface(x, y, z, box, 1.0)
+    assert ref["degenerate"]
+    with Ctx() as ctx:
+        dcm.dcm_detect_interface(ctx, dev(x), dev(y), dev(z), box, g2, seg, iface)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_ERR_DEGENERATE
+    np.testing.assert_array_equal(host(seg), ref["seg"])
+    assert host(iface).sum() == 0
+
+
+@pytest.mark.parametrize("name", GRIDS)
+def test_sweep_distance_matches_fsm(name):
+    print(f"[gpu] sweep {name}", flush=True)
+    s = workloads.make(name)
+    ref = ref_detect(name)
+    grid = dcm.make_grid(s.box, s.h)
+    nv = dcm.grid_voxels(grid)
+    dist = torch.zeros(nv, **F64)
+    waves = torch.zeros(1, dtype=torch.int32, device=DEV)
+    with Ctx() as ctx:
+        dcm.dcm_sweep_distance(ctx, dev(ref["seg"], torch.uint8), dev(ref["iface"], torch.uint8),
+                               grid, ref["rc_grid"], 200, dist, waves_out=waves)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+    D = host(dist)
+    assert np.max(np.abs(D - ref["D"])) <= 1e-12 * ref["rc_grid"]
+    assert int(host(waves)[0]) >= 2
+
+
+def test_sweep_wave_limit_is_reported():
+    s = workloads.make("slab_small")
+    ref = ref_detect("slab_small")
+    grid = dcm.make_grid(s.box, s.h)
+    dist = torch.zeros(dcm.grid_voxels(grid), **F64)
+    with Ctx() as ctx:
+        dcm.dcm_sweep_distance(ctx, dev(ref["seg"], torch.uint8), dev(ref["iface"], torch.uint8),
+                               grid, ref["rc_grid"], 2, dist)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_ERR_NOT_CONVERGED
+
+
+@pytest.mark.parametrize("name", GRIDS)
+def test_assign_cutoffs_bit_exact(name):
+    s = workloads.make(name)
+    ref = ref_detect(name)
+    grid = dcm.make_grid(s.box, s.h)
+    delta = torch.zeros(s.n, **F64)
+    rc = torch.zeros(s.n, **F64)
+    with Ctx() as ctx:
+        dcm.dcm_assign_cutoffs(ctx, dev(s.x), dev(s.y), dev(s.z), s.box, grid, dev(ref["D"]),
+                               dcm.make_rule(*s.rule), rc, delta=delta)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+    np.testing.assert_array_equal(host(delta), ref["delta"])
+    np.testing.assert_array_equal(host(rc), ref["rc"])
+
+
+# ------------------------------------------------------------------ cells
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("edge", [0.9, 1.3, 2.5, 6.1])
+def test_build_cells_bit_exact(name, edge):
+    s = workloads.make(name)
+    ref = ref_detect(name)
+    nc = oracle.cell_dims(s.box, edge)
+    ref_of, ref_start = oracle.cells(s.x, s.y, s.z, s.box, nc)
+    cell_of = torch.zeros(s.n, dtype=torch.int32, device=DEV)
+    start = torch.zeros(int(np.prod(nc)) + 1, dtype=torch.int32, device=DEV)
+    with Ctx() as ctx:
+        dcm.dcm_build_cells(ctx, dev(s.x), dev(s.y), dev(s.z), dev(ref["rc"]), s.box, edge,
+                            dcm.DCM_FP64, cell_of=cell_of, cell_start=start)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+        dims, _ = dcm.dcm_cell_dims(ctx)
+    assert dims == list(nc)
+    np.testing.assert_array_equal(host(cell_of), ref_of)
+    np.testing.assert_array_equal(host(start), ref_start)
+
+
+# ------------------------------------------------------------------ forces
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("rule", [dcm.DCM_PAIR_OWN, dcm.DCM_PAIR_MAX])
+@pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
+def test_forces_match_oracle(name, rule, prec):
+    print(f"[gpu] forces {name} rule={rule} prec={prec}", flush=True)
+    s = workloads.make(name)
+    ref = ref_forces(name, rule)
+    got = gpu_forces(s, ref_detect(name)["rc"], prec=prec, rule=rule)
+    assert got["status"] == dcm.DCM_OK
+    np.testing.assert_array_equal(got["nnbr"], ref["nnbr"])
+    assert got["npairs"] == int(ref["nnbr"].sum())
+    tol = 1e-12 if prec == dcm.DCM_FP64 else 1e-5
+    emax, erms, eabs = force_errors(got["F"], _ref_F(ref), detail=True)
+    print(f"[gpu]   err_max={emax:.3e} err_rms={erms:.3e} max/F_rms={eabs:.3e}", flush=True)
+    assert emax <= tol and erms <= tol
+    assert abs(got["E"] - ref["E"]) <= tol * abs(ref["E"])
+    assert rel(got["W"], ref["W"]) <= tol
+
+
+@pytest.mark.parametrize("edge", [0.0, 0.7, 1.9, 3.3])
+def test_forces_independent_of_cell_edge_and_deterministic(edge):
+    s = workloads.make("slab_small")
+    rc = ref_detect("slab_small")["rc"]
+    base = gpu_forces(s, rc, edge=1.3)
+    got = gpu_forces(s, rc, edge=edge)
+    np.testing.assert_array_equal(got["nnbr"], base["nnbr"])
+    emax, _ = force_errors(got["F"], base["F"])
+    assert emax <= 1e-13
+    again = gpu_forces(s, rc, edge=edge)
+    np.testing.assert_array_equal(again["F"], got["F"])
+    assert again["E"] == got["E"]
+
+
+def test_tiny_box_every_axis_wraps():
+    """A box smaller than the cutoff stencil: every cell is visited once and the
+    minimum image is taken per pair."""
+    rng = np.random.default_rng(5)
+    box = (7.0, 7.5, 8.0)
+    pts = []
+    while len(pts) < 150:
+        p = rng.uniform(0, 1, 3) * np.asarray(box)
+        if all(np.sum(((p - q) - np.asarray(box) * np.rint((p - q) / np.asarray(box))) ** 2) > 0.81
+               for q in pts):
+            pts.append(p)
+    pts = np.asarray(pts)
+    s = workloads.System("tiny", pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2].copy(),
+                         *(np.zeros(150) for _ in range(3)), box)
+    rc = rng.uniform(1.0, 3.45, 150)
+    for rule in (dcm.DCM_PAIR_OWN, dcm.DCM_PAIR_MAX):
+        ref = oracle.forces(s.x, s.y, s.z, rc, box, rule=rule)
+        for edge in (0.5, 1.0, 3.4):
+            got = gpu_forces(s, rc, rule=rule, edge=edge)
+            np.testing.assert_array_equal(got["nnbr"], ref["nnbr"])
+            emax, _ = force_errors(got["F"], _ref_F(ref))
+            assert emax <= 1e-12
+
+
+def test_static_cutoff_reduces_to_eq3_and_balances():
+    s = workloads.make("slab_small")
+    rc = np.full(s.n, 3.0)
+    a = gpu_forces(s, rc, rule=dcm.DCM_PAIR_OWN)
+    b = gpu_forces(s, rc, rule=dcm.DCM_PAIR_MAX)
+    np.testing.assert_array_equal(a["nnbr"], b["nnbr"])
+    emax, _ = force_errors(a["F"], b["F"])
+    assert emax <= 1e-14
+    tot = np.abs(a["F"]).sum()
+    assert np.all(np.abs(a["F"].sum(0)) <= 1e-12 * tot)
+
+
+def test_empty_system():
+    s = workloads.System("empty", *(np.zeros(0) for _ in range(6)), (10.0, 10.0, 10.0))
+    got = gpu_forces(s, np.zeros(0))
+    assert got["status"] == dcm.DCM_OK
+    assert got["E"] == 0.0 and got["npairs"] == 0
+
+
+def test_nonfinite_positions_are_flagged():
+    s = workloads.make("slab_small")
+    x = s.x.copy()
+    x[17] = np.nan
+    bad = workloads.System("bad", x, s.y, s.z, s.vx, s.vy, s.vz, s.box)
+    got = gpu_forces(bad, np.full(s.n, 2.5))
+    assert got["status"] == dcm.DCM_ERR_NONFINITE
+
+
+# ------------------------------------------------------------ end to end
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
+def test_pipeline_end_to_end(name, prec):
+    print(f"[gpu] pipeline {name} prec={prec}", flush=True)
+    s = workloads.make(name)
+    ref_d = ref_detect(name)
+    ref = ref_forces(name, dcm.DCM_PAIR_OWN)
+    grid = dcm.make_grid(s.box, s.h)
+    rule = dcm.make_rule(*s.rule)
+    f = [torch.zeros(s.n, **F64) for _ in range(3)]
+    v = [dev(a) for a in (s.vx, s.vy, s.vz)]
+    rc = torch.zeros(s.n, **F64)
+    delta = torch.zeros(s.n, **F64)
+    with Ctx() as ctx:
+        dcm.dcm_step(ctx, dev(s.x), dev(s.y), dev(s.z), *v, *f, s.box, dcm.make_lj(), rule, grid,
+                     dcm.rc_grid_for(rule, grid), dt=0.005, nsteps=0, prec=prec, rc=rc,
+                     delta=delta)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+    assert dcm.rc_grid_for(rule, grid) == ref_d["rc_grid"]
+    # distances come from a floating-point fixed point whose last bit may
+    # depend on the update order: FP64 tolerance, not bit equality
+    np.testing.assert_allclose(host(delta), ref_d["delta"], rtol=0, atol=1e-12 * ref_d["rc_grid"])
+    np.testing.assert_allclose(host(rc), ref_d["rc"], rtol=1e-12, atol=0)
+    F = np.stack([host(t) for t in f], 1)
+    emax, erms = force_errors(F, _ref_F(ref))
+    tol = 1e-12 if prec == dcm.DCM_FP64 else 1e-5
+    assert emax <= tol and erms <= tol
+
+
+def test_verlet_trajectory_tracks_oracle():
+    """20 FP64 steps with re-detection every 5 steps, against the same
+    schedule run entirely on the oracle."""
+    s = workloads.make("slab_small")
+    dt, nsteps, every = 0.005, 20, 5
+    grid = dcm.make_grid(s.box, s.h)
+    rule = dcm.make_rule(*s.rule)
+    rcg = dcm.rc_grid_for(rule, grid)
+    pos = [dev(a) for a in (s.x, s.y, s.z)]
+    vel = [dev(a) for a in (s.vx, s.vy, s.vz)]
+    f = [torch.zeros(s.n, **F64) for _ in range(3)]
+    es = torch.zeros(2 * nsteps, **F64)
+    with Ctx() as ctx:
+        dcm.dcm_step(ctx, *pos, *vel, *f, s.box, dcm.make_lj(), rule, grid, rcg, dt, 0)
+        dcm.dcm_step(ctx, *pos, *vel, *f, s.box, dcm.make_lj(), rule, grid, rcg, dt, nsteps,
+                     redetect_every=every, energy_series=es)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+    # oracle schedule
+    x, v = (s.x, s.y, s.z), (s.vx, s.vy, s.vz)
+    p = oracle.pipeline(*x, s.box, s.h, s.rule)
+    D = p["D"]
+    F = (p["forces"]["fx"], p["forces"]["fy"], p["forces"]["fz"])
+    epot = []
+    for st in range(nsteps):
+        v = oracle.kick(v, F, dt)
+        x = oracle.drift(x, v, dt, s.box)
+        if (st + 1) % every == 0:
+            det = oracle.detect_interface(*x, s.box, s.h)
+            D, _ = oracle.fsm(det["nv"], det["hv"], det["seg"], det["iface"], rcg)
+        rc = oracle.cutoffs(oracle.particle_distance(*x, s.box, p["nv"], D), s.rule)
+        fo = oracle.forces(*x, rc, s.box)
+        F = (fo["fx"], fo["fy"], fo["fz"])
+        v = oracle.kick(v, F, dt)
+        epot.append(fo["E"])
+    L = np.asarray(s.box)
+    for a in range(3):
+        d = host(pos[a]) - x[a]
+        d -= L[a] * np.rint(d / L[a])
+        assert np.max(np.abs(d)) < 1e-9
+    np.testing.assert_allclose(host(es)[0::2], epot, rtol=1e-9)
+    ke = 0.5 * sum(np.sum(c * c) for c in v)
+    assert host(es)[-1] == pytest.approx(ke, rel=1e-9)
+
+
+def test_large_slab_sampled_parity():
+    """The large slab in the benchmark's configuration (FP32-mixed, automatic
+    cells): every cutoff bit-exact, forces on a seeded sample of particles
+    against the oracle's per-particle O(N) sums."""
+    name = "slab_large"
+    print("[gpu] large slab sampled parity", flush=True)
+    s = workloads.make(name)
+    ref_d = ref_detect(name)
+    grid = dcm.make_grid(s.box, s.h)
+    rule = dcm.make_rule(*s.rule)
+    f = [torch.zeros(s.n, **F64) for _ in range(3)]
+    v = [dev(a) for a in (s.vx, s.vy, s.vz)]
+    rc = torch.zeros(s.n, **F64)
+    with Ctx() as ctx:
+        dcm.dcm_step(ctx, dev(s.x), dev(s.y), dev(s.z), *v, *f, s.box, dcm.make_lj(), rule, grid,
+                     dcm.rc_grid_for(rule, grid), dt=0.005, nsteps=0, prec=dcm.DCM_FP32_MIXED,
+                     rc=rc)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+    np.testing.assert_allclose(host(rc), ref_d["rc"], rtol=1e-12, atol=0)
+    idx = workloads.sample_indices(s.n, 1536, seed=4242)
+    # include the particles nearest the interfaces, where cutoffs are largest
+    near = np.argsort(np.minimum(np.abs(s.z - 140.0), np.abs(s.z - 260.0)))[:512]
+    idx = np.unique(np.concatenate([idx, near]))
+    ref = oracle.forces(s.x, s.y, s.z, ref_d["rc"], s.box, idx=idx)
+    F = np.stack([host(t) for t in f], 1)[idx]
+    emax, erms, eabs = force_errors(F, _ref_F(ref), detail=True)
+    print(f"[gpu]   large slab err_max={emax:.3e} err_rms={erms:.3e} max/F_rms={eabs:.3e}",
+          flush=True)
+    assert emax <= 1e-5 and erms <= 1e-5
