@@ -71,7 +71,7 @@ def run_leg(s, prec, steps, warmup, dev):
         def count_pairs():
             npairs = torch.zeros(1, dtype=torch.uint64, device=dev)
             e = torch.zeros(1, **f64)
-            dcm.dcm_build_cells(ctx, *pos, rc, s.box, 0.0, prec)
+            dcm.dcm_build_cells(ctx, *pos, rc, s.box, 0.0, prec, rc_bound=s.rule[1])
             dcm.dcm_forces(ctx, lj, *frc, prec=prec, ev_flags=dcm.DCM_EV_COUNTS | dcm.DCM_EV_ENERGY,
                            energy=e, npairs=npairs)
             torch.cuda.synchronize()

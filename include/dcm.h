@@ -156,17 +156,21 @@ dcm_status dcm_assign_cutoffs(dcm_ctx *ctx, const double *x, const double *y,
                               double *rc);
 
 /* Linked cells (Section 2.3).  Cells of edge L_a/n_a with
- * n_a = floor(L_a/cell_edge) (cell_edge <= 0 picks rc_min-sized cells from the
- * cutoffs), cell c = (c_z*n_y + c_y)*n_x + c_x.  Particles are sorted by cell
- * (stable: ascending caller index within a cell) into context-owned copies of
- * (x, y, z, rc) that dcm_forces reads.  cell_of (int32 [n]) and cell_start
- * (int32 [n_cells + 1], exclusive prefix of per-cell counts) are optional
- * copies for the caller; dcm_cell_dims gives n_cells.  prec selects the
- * layout of the sorted copy for the later dcm_forces call.  The positions
- * and cutoffs are read during this call only. */
+ * n_a = floor(L_a/cell_edge) (cell_edge <= 0: a default of about two
+ * particles per cell at the mean density), cell c = (c_z*n_y + c_y)*n_x + c_x.
+ * Particles are sorted by cell (stable: ascending caller index within a cell)
+ * into context-owned copies of (x, y, z, rc) that dcm_forces reads, together
+ * with periodic ghost images of the cells within rc_bound of the box faces.
+ * rc_bound is an upper bound on every cutoff (<= 0: half the shortest box
+ * edge); larger cutoffs are clamped to it and flag DCM_ERR_RANGE, and so do
+ * cutoffs >= half a box edge (minimum image).  cell_of (int32 [n]) and
+ * cell_start (int32 [n_cells + 1], exclusive prefix of per-cell counts) are
+ * optional copies for the caller; dcm_cell_dims gives n_cells.  prec selects
+ * the layout of the sorted copy for the later dcm_forces call.  The positions
+ * and cutoffs are read during this call only.  n must be below 2^24. */
 dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const double *z,
                            const double *rc, int64_t n, dcm_box box, double cell_edge,
-                           int prec, int32_t *cell_of, int32_t *cell_start);
+                           double rc_bound, int prec, int32_t *cell_of, int32_t *cell_start);
 
 /* Host query: cell counts per axis and cell edge lengths of the last
  * dcm_build_cells call on this context. */

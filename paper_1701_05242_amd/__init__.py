@@ -84,7 +84,7 @@ SIGNATURES = {
     "dcm_detect_interface": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid, _F64, _P, _P, _P, _P],
     "dcm_sweep_distance": [_P, _P, _P, dcm_grid, _F64, _I32, _P, _P],
     "dcm_assign_cutoffs": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid, _P, dcm_rule, _P, _P],
-    "dcm_build_cells": [_P, _P, _P, _P, _P, _I64, dcm_box, _F64, _INT, _P, _P],
+    "dcm_build_cells": [_P, _P, _P, _P, _P, _I64, dcm_box, _F64, _F64, _INT, _P, _P],
     "dcm_cell_dims": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_F64)],
     "dcm_forces": [_P, dcm_lj, _INT, _INT, _INT, _P, _P, _P, _P, _P, _P, _P],
     "dcm_step": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _F64, dcm_box, dcm_lj, dcm_rule,
@@ -229,12 +229,12 @@ def dcm_assign_cutoffs(ctx, x, y, z, box, grid: dcm_grid, dist, rule: dcm_rule, 
 
 
 def dcm_build_cells(ctx, x, y, z, rc, box, cell_edge: float = 0.0, prec: int = DCM_FP64,
-                    cell_of=None, cell_start=None) -> None:
+                    cell_of=None, cell_start=None, rc_bound: float = 0.0) -> None:
     n = x.numel()
     f64 = torch.float64
     code = load_library().dcm_build_cells(
         ctx, _ptr(x, f64, "x", n), _ptr(y, f64, "y", n), _ptr(z, f64, "z", n),
-        _ptr(rc, f64, "rc", n), n, _box(box), float(cell_edge), int(prec),
+        _ptr(rc, f64, "rc", n), n, _box(box), float(cell_edge), float(rc_bound), int(prec),
         _ptr(cell_of, torch.int32, "cell_of", n), _ptr(cell_start, torch.int32, "cell_start"))
     _check(ctx, code)
 

@@ -142,6 +142,8 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
     return DCM_ERR_NOMEM;
   }
   ctx->h_status = static_cast<uint32_t *>(p);
+  ctx->h_ext_total = reinterpret_cast<int32_t *>(static_cast<char *>(p) + 8);
+  *ctx->h_ext_total = 0;
   launch_clear_status(ctx->stream, ctx->d_status);
   launch_reset_ctl(ctx->stream, ctx->ctl);
   dcm_status st = check_launch(ctx, "dcm_create");
@@ -160,7 +162,7 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
 dcm_status dcm_destroy(dcm_ctx *ctx) {
   if (!ctx) return DCM_ERR_INVALID;
   hipStreamSynchronize(ctx->stream);
-  DevBuf *bufs[] = {&ctx->fsm_chg,  &ctx->counts,   &ctx->gray,      &ctx->hist,      &ctx->seg_a,
+  DevBuf *bufs[] = {&ctx->fsm_flags, &ctx->fsm_chg,  &ctx->counts,   &ctx->gray,      &ctx->hist,      &ctx->seg_a,
                     &ctx->seg_b,    &ctx->seg,       &ctx->iface,     &ctx->dA,
                     &ctx->dB,       &ctx->dist,      &ctx->delta,     &ctx->rc,
                     &ctx->partials, &ctx->ke,        &ctx->cell_of,   &ctx->cell_count,
@@ -201,8 +203,10 @@ dcm_status dcm_sync_status(dcm_ctx *ctx) {
     return fail(ctx, DCM_ERR_NONFINITE, "non-finite position or force");
   if (st & ST_NOT_CONVERGED)
     return fail(ctx, DCM_ERR_NOT_CONVERGED, "distance sweep reached its wave limit");
+  if (st & ST_GHOST_OVERFLOW)
+    return fail(ctx, DCM_ERR_RANGE, "ghost images exceeded their buffer; build the cells again");
   if (st & (ST_HIST_RANGE | ST_RC_RANGE))
-    return fail(ctx, DCM_ERR_RANGE, "gray value >= 4096 or cutoff outside [0, L/2)");
+    return fail(ctx, DCM_ERR_RANGE, "gray value >= 4096 or cutoff outside [0, rc_bound]");
   if (st & ST_DEGENERATE)
     return fail(ctx, DCM_ERR_DEGENERATE, "density field holds a single phase");
   return DCM_OK;
@@ -283,15 +287,18 @@ dcm_status dcm_sweep_distance(dcm_ctx *ctx, const uint8_t *seg, const uint8_t *i
   const int64_t ntiles = fsm_tile_count(grid.n);
   DCM_TRY(ensure(ctx, ctx->fsm_chg, 2 * ntiles));
   uint8_t *chg0 = ptr<uint8_t>(ctx->fsm_chg), *chg1 = chg0 + ntiles;
+  DCM_TRY(ensure(ctx, ctx->fsm_flags, (size_t)(max_waves + 2) * sizeof(uint32_t)));
+  uint32_t *flags = ptr<uint32_t>(ctx->fsm_flags);
   hipStream_t s = ctx->stream;
   hipEvent_t ev;
   timer_begin(ctx, "sweep", &ev);
-  launch_fsm_init(s, seg, iface, nvox, ptr<double>(ctx->dA), ptr<double>(ctx->dB), ctx->ctl);
+  launch_fsm_init(s, seg, iface, nvox, ptr<double>(ctx->dA), ptr<double>(ctx->dB), flags,
+                  max_waves);
   for (int w = 1; w <= max_waves; ++w)
     launch_fsm_step(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), chg0, chg1, grid.n, grid.h,
-                    rc_grid, w, max_waves, ctx->ctl, ctx->d_status);
-  launch_fsm_final(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), nvox, rc_grid, ctx->ctl, dist,
-                   waves_out);
+                    rc_grid, w, flags);
+  launch_fsm_final(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), nvox, rc_grid, flags,
+                   max_waves, dist, waves_out, ctx->d_status);
   timer_end(ctx, "sweep", ev);
   return check_launch(ctx, "dcm_sweep_distance");
 }
@@ -319,8 +326,8 @@ dcm_status dcm_assign_cutoffs(dcm_ctx *ctx, const double *x, const double *y, co
 }
 
 dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const double *z,
-                           const double *rc, int64_t n, dcm_box box, double cell_edge, int prec,
-                           int32_t *cell_of, int32_t *cell_start) {
+                           const double *rc, int64_t n, dcm_box box, double cell_edge,
+                           double rc_bound, int prec, int32_t *cell_of, int32_t *cell_start) {
   if (!ctx) return DCM_ERR_INVALID;
   DCM_TRY(check_n(ctx, n));
   DCM_TRY(check_box(ctx, box));
@@ -329,6 +336,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   if (prec != DCM_FP64 && prec != DCM_FP32_MIXED)
     return fail(ctx, DCM_ERR_INVALID, "unknown precision");
   if (!std::isfinite(cell_edge)) return fail(ctx, DCM_ERR_INVALID, "cell_edge must be finite");
+  if (!std::isfinite(rc_bound)) return fail(ctx, DCM_ERR_INVALID, "rc_bound must be finite");
   double edge = cell_edge;
   if (edge <= 0.0) {
     // about two particles per cell at the mean density
@@ -360,7 +368,36 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   }
   const double sc[3] = {(double)nc[0] / box.L[0], (double)nc[1] / box.L[1],
                         (double)nc[2] / box.L[2]};
-  const double rc_cap = 0.5 * std::min(box.L[0], std::min(box.L[1], box.L[2]));
+  // every cutoff is clamped to rc_cap, strictly below half the shortest edge
+  // so that at most one periodic image of a pair can interact
+  const double half = 0.5 * std::min(box.L[0], std::min(box.L[1], box.L[2]));
+  const double below_half = std::nextafter(half, 0.0);
+  const double rc_cap = rc_bound > 0.0 ? std::min(rc_bound, below_half) : below_half;
+  // ghost halo: enough cells on each side for any search radius <= rc_cap
+  int32_t halo[3];
+  int64_t next = 1;
+  double uniform = 1.0, hard = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    const double len = box.L[a] / (double)nc[a];
+    halo[a] = (int32_t)std::ceil(rc_cap / len) + 1;
+    const int64_t ne = nc[a] + 2 * (int64_t)halo[a];
+    next *= ne;
+    if (next >= (int64_t(1) << 30)) return fail(ctx, DCM_ERR_RANGE, "too many ghost cells");
+    uniform *= (double)ne / (double)nc[a];
+    hard *= 1.0 + 2.0 * std::ceil((double)halo[a] / (double)nc[a]);
+  }
+  // ghost-extended particle capacity: the uniform-density count with
+  // headroom, capped by the most any arrangement can need, and grown from
+  // the exact count of an earlier build
+  double want = std::min(1.5 * uniform * (double)n + 4096.0, hard * (double)n + 64.0);
+  want = std::max(want, 1.25 * (double)*ctx->h_ext_total);
+  if (want >= 2147483647.0) return fail(ctx, DCM_ERR_RANGE, "ghost-extended system too large");
+  const int64_t ext_cap = std::max<int64_t>((int64_t)want, ctx->ext_cap);
+  DCM_TRY(ensure(ctx, ctx->ext_count, next * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->ext_start, (next + 1) * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_elems(std::max(ncell, next)) * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->ext_pos, ext_cap * sizeof(double4)));
+  ctx->ext_cap = ext_cap;
   hipStream_t s = ctx->stream;
   hipEvent_t ev;
   timer_begin(ctx, "cells", &ev);
@@ -375,11 +412,18 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, ptr<int32_t>(ctx->perm));
   launch_gather(s, x, y, z, rc, ptr<int32_t>(ctx->perm), n, box.L, rc_cap,
                 ptr<double4>(ctx->sorted));
+  launch_ext_build(s, ptr<int32_t>(ctx->cell_start), ptr<double4>(ctx->sorted), nc, halo, box.L,
+                   ext_cap, ptr<int32_t>(ctx->ext_count), ptr<int32_t>(ctx->ext_start),
+                   ptr<int32_t>(ctx->scan_tmp), ptr<double4>(ctx->ext_pos), ctx->d_status);
+  // exact ghost-extended count, read by a later build to size the buffer
+  hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
+                 hipMemcpyDeviceToHost, s);
   if (cell_start)
     hipMemcpyAsync(cell_start, ctx->cell_start.p, (ncell + 1) * sizeof(int32_t),
                    hipMemcpyDeviceToDevice, s);
   timer_end(ctx, "cells", ev);
   for (int a = 0; a < 3; ++a) {
+    ctx->halo[a] = halo[a];
     ctx->nc[a] = nc[a];
     ctx->cell_len[a] = box.L[a] / (double)nc[a];
     ctx->cell_scale[a] = sc[a];
@@ -387,6 +431,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   }
   ctx->cell_n = n;
   ctx->cell_prec = prec;
+  ctx->rc_bound = rc_cap;
   return check_launch(ctx, "dcm_build_cells");
 }
 
@@ -423,14 +468,19 @@ dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_f
   a.pos = ptr<double4>(ctx->sorted);
   a.cell_start = ptr<int32_t>(ctx->cell_start);
   a.perm = ptr<int32_t>(ctx->perm);
+  a.ext_pos = ptr<double4>(ctx->ext_pos);
+  a.ext_start = ptr<int32_t>(ctx->ext_start);
   a.n = n;
+  a.ext_cap = ctx->ext_cap;
   for (int k = 0; k < 3; ++k) {
     a.nc[k] = ctx->nc[k];
+    a.h[k] = ctx->halo[k];
+    a.ne[k] = ctx->nc[k] + 2 * ctx->halo[k];
     a.len[k] = ctx->cell_len[k];
     a.sc[k] = ctx->cell_scale[k];
     a.L[k] = ctx->cell_box.L[k];
-    a.invL[k] = 1.0 / ctx->cell_box.L[k];
   }
+  a.rc_bound = ctx->rc_bound;
   a.eps = lj.epsilon;
   a.sigma = lj.sigma;
   a.ev_flags = ev_flags;
@@ -506,7 +556,9 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
   auto forces = [&](double *e_out) -> dcm_status {
     DCM_TRY(dcm_assign_cutoffs(ctx, x, y, z, n, box, grid, ptr<double>(ctx->dist), rule, delta,
                                rc));
-    DCM_TRY(dcm_build_cells(ctx, x, y, z, rc, n, box, 0.0, prec, nullptr, nullptr));
+    // small cells (Section 2.3): half the smallest cutoff
+    DCM_TRY(dcm_build_cells(ctx, x, y, z, rc, n, box, 0.5 * rule.rc_min, rule.rc_max, prec,
+                            nullptr, nullptr));
     return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, fx, fy, fz, e_out ? e_out : scal,
                       nullptr, nullptr, nullptr);
   };

@@ -39,6 +39,22 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
+// MI355X has 8 XCDs, each with its own L2; consecutive workgroups are
+// dispatched round-robin across them.  xcd_block(b, n, G) remaps workgroup b
+// so that each XCD receives runs of G consecutive logical blocks (spatially
+// neighbouring work, which shares cell data, then shares an L2) while the
+// runs still interleave across XCDs (work that clusters in space stays
+// spread over all of them).  G = 0 keeps the hardware order; blocks past the
+// last whole group of 8 G keep it too.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks, int group) {
+  if (group <= 0) return b;
+  const int64_t span = (int64_t)kXcds * group;
+  if (b >= (nblocks / span) * span) return b;
+  const int64_t x = b % kXcds, k = b / kXcds;
+  return ((k / group) * kXcds + x) * group + k % group;
+}
+
 // Sum of a value over the 64 lanes of a wavefront (fixed butterfly order).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

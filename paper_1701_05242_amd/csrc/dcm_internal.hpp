@@ -22,6 +22,7 @@ enum : uint32_t {
   ST_NOT_CONVERGED = 1u << 3,
   ST_NONFINITE_FORCE = 1u << 4,
   ST_RC_RANGE = 1u << 5,
+  ST_GHOST_OVERFLOW = 1u << 6,
 };
 
 constexpr int kHistBins = 4096;       // gray values (27-window counts) must stay below this
@@ -30,21 +31,21 @@ constexpr int kPartialSlots = 8;      // per-block partial sums: E, W[6], pair c
 
 // Device-resident control block: scalars produced and consumed on the device
 // so that no stage needs a host round trip.
+// Iterated stages (majority passes, sweep passes) keep one "changed" flag per
+// pass instead of counters: every workgroup that saw a change stores 1 into
+// its pass's slot (no atomics), and pass p+1 runs only if pass p changed
+// something.  The stage's final kernel finds the last pass from the flags.
 struct Ctl {
   // interface detection
   int32_t threshold;
   int32_t degenerate;
   double c0, c1;
-  uint32_t maj_passes, maj_done, maj_result, maj_blocks;
-  unsigned long long maj_chg1, maj_chg2;
-  // distance sweep
-  uint32_t fsm_waves, fsm_done, fsm_result, fsm_blocks;
-  unsigned long long fsm_changed;
+  // majority pass p stores into maj_chg1[p] (differs from state p-1) and
+  // maj_chg2[p] (differs from state p-2)
+  uint32_t maj_chg1[kMajorityMaxPasses + 2];
+  uint32_t maj_chg2[kMajorityMaxPasses + 2];
   // cells: largest cutoff seen (bit pattern of a non-negative double)
   unsigned long long rc_max_bits;
-  // reductions
-  uint32_t red_blocks;
-  uint32_t pad;
 };
 
 struct DevBuf {
@@ -68,12 +69,17 @@ struct dcm_ctx {
   uint32_t *h_status = nullptr;  // pinned
   dcm::Ctl *ctl = nullptr;       // device control block
   // grid scratch
-  dcm::DevBuf counts, gray, hist, seg_a, seg_b, seg, iface, dA, dB, dist, fsm_chg;
+  dcm::DevBuf counts, gray, hist, seg_a, seg_b, seg, iface, dA, dB, dist, fsm_chg, fsm_flags;
   // particle scratch
   dcm::DevBuf delta, rc, partials, ke, scalars;
   // cells
   dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp;
+  dcm::DevBuf ext_count, ext_start, ext_pos;
+  int64_t ext_cap = 0;             // particles ext_pos can hold
+  int32_t *h_ext_total = nullptr;  // pinned: ghost-extended count of the last build
   int32_t nc[3] = {0, 0, 0};
+  int32_t halo[3] = {0, 0, 0};
+  double rc_bound = 0.0;
   double cell_len[3] = {0, 0, 0};
   double cell_scale[3] = {0, 0, 0};
   dcm_box cell_box = {{0, 0, 0}};
@@ -123,16 +129,17 @@ void launch_interface(hipStream_t s, const uint8_t *buf0, const uint8_t *buf1,
 
 // k_fsm.hip
 void launch_fsm_init(hipStream_t s, const uint8_t *seg, const uint8_t *iface, int64_t nvox,
-                     double *dA, double *dB, Ctl *ctl);
+                     double *dA, double *dB, uint32_t *flags, int max_steps);
 // one launch of the sweep: a temporally blocked tile pass when fsm_tiled(nv),
 // else one synchronous wave; chg0/chg1 hold one flag per tile
 bool fsm_tiled(const int32_t nv[3]);
 int64_t fsm_tile_count(const int32_t nv[3]);
 void launch_fsm_step(hipStream_t s, double *dA, double *dB, uint8_t *chg0, uint8_t *chg1,
                      const int32_t nv[3], const double h[3], double rc_grid, int step,
-                     int max_steps, Ctl *ctl, uint32_t *status);
+                     uint32_t *flags);
 void launch_fsm_final(hipStream_t s, const double *dA, const double *dB, int64_t nvox,
-                      double rc_grid, const Ctl *ctl, double *dist, int32_t *waves_out);
+                      double rc_grid, const uint32_t *flags, int max_steps, double *dist,
+                      int32_t *waves_out, uint32_t *status);
 
 // k_cells.hip
 void launch_assign_cutoffs(hipStream_t s, const double *x, const double *y, const double *z,
@@ -152,18 +159,27 @@ void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell, i
 void launch_gather(hipStream_t s, const double *x, const double *y, const double *z,
                    const double *rc, const int32_t *perm, int64_t n, const double L[3],
                    double rc_cap, double4 *sorted);
+void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
+                      const int32_t nc[3], const int32_t h[3], const double L[3],
+                      int64_t ext_cap, int32_t *ext_count, int32_t *ext_start,
+                      int32_t *scan_tmp, double4 *ext_pos, uint32_t *status);
 
 // k_pair.hip
 struct PairArgs {
-  const double4 *pos;        // sorted (x, y, z, rc), wrapped into the box
-  const int32_t *cell_start; // [ncell + 1]
+  const double4 *pos;        // sorted real particles (x, y, z, rc), wrapped into the box
+  const int32_t *cell_start; // real cells [ncell + 1]
   const int32_t *perm;       // sorted -> caller index
+  const double4 *ext_pos;    // real cells plus periodic ghost images, by extended cell
+  const int32_t *ext_start;  // extended cells [next + 1]
   int64_t n;
+  int64_t ext_cap;           // capacity of ext_pos
   int32_t nc[3];
+  int32_t h[3];              // ghost cells on each side
+  int32_t ne[3];             // extended cells per axis = nc + 2h
   double len[3];             // cell edge per axis = L/n
   double sc[3];              // n/L
   double L[3];
-  double invL[3];
+  double rc_bound;
   double eps, sigma;
   int ev_flags;
   const Ctl *ctl;

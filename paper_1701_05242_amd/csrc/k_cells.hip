@@ -87,9 +87,10 @@ __global__ __launch_bounds__(256) void k_cell_count(
       } else {
         atomicOr(status, ST_NONFINITE_POS);
       }
-      if (!(r >= 0.0) || !(r < rc_cap)) {
+      // rc_cap: the build's bound on every cutoff (inclusive, below L/2)
+      if (!(r >= 0.0) || r > rc_cap) {
         atomicOr(status, ST_RC_RANGE);
-        r = (r >= rc_cap) ? rc_cap : 0.0;
+        r = (r > rc_cap) ? rc_cap : 0.0;
       }
       unsigned long long bits = (unsigned long long)__double_as_longlong(r);
       rmax = bits > rmax ? bits : rmax;
@@ -295,6 +296,98 @@ void launch_gather(hipStream_t s, const double *x, const double *y, const double
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_gather, dim3((unsigned)b), dim3(256), 0, s, x, y, z, rc, perm, n, L[0],
                      L[1], L[2], rc_cap, sorted);
+}
+
+// ------------------------------------------------ periodic ghost images
+// The search grid extends the cell grid by h[a] cells on both sides of every
+// axis.  Extended cell (ex, ey, ez) holds a copy of real cell
+// (ex - h[0], ey - h[1], ez - h[2]) wrapped into the box, with positions
+// shifted by the matching multiple of the box length, so that a lane can walk
+// any row of cells around its particle as one contiguous range of the
+// extended array, without wrap-around or image shifts.
+struct ExtGeom {
+  int nc[3];
+  int h[3];
+  int ne[3];
+  double L[3];
+};
+
+__device__ __forceinline__ void ext_to_real(const ExtGeom &g, int64_t e, int &rc, int p[3]) {
+  const int ex = (int)(e % g.ne[0]);
+  const int64_t t = e / g.ne[0];
+  const int ey = (int)(t % g.ne[1]);
+  const int ez = (int)(t / g.ne[1]);
+  const int u[3] = {ex - g.h[0], ey - g.h[1], ez - g.h[2]};
+  int r[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = wrap_index(u[a], g.nc[a]);
+    p[a] = (u[a] - r[a]) / g.nc[a];  // periods crossed: exact division
+  }
+  rc = (r[2] * g.nc[1] + r[1]) * g.nc[0] + r[0];
+}
+
+__global__ __launch_bounds__(256) void k_ext_count(const int32_t *__restrict__ cell_start,
+                                                   ExtGeom g, int64_t next,
+                                                   int32_t *__restrict__ ext_count) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < next;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int rc, p[3];
+    ext_to_real(g, e, rc, p);
+    ext_count[e] = cell_start[rc + 1] - cell_start[rc];
+  }
+}
+
+// Writes stop at the buffer's capacity; running past it flags an overflow
+// (the pair kernel then refuses to read ghost ranges beyond the capacity).
+__global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ cell_start,
+                                                  const int32_t *__restrict__ ext_start,
+                                                  const double4 *__restrict__ sorted, ExtGeom g,
+                                                  int64_t next, int64_t cap,
+                                                  double4 *__restrict__ ext_pos,
+                                                  uint32_t *status) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < next;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int rc, p[3];
+    ext_to_real(g, e, rc, p);
+    const double sx = (double)p[0] * g.L[0], sy = (double)p[1] * g.L[1],
+                 sz = (double)p[2] * g.L[2];
+    const int a = cell_start[rc], b = cell_start[rc + 1];
+    int64_t o = ext_start[e];
+    if (o + (b - a) > cap) {
+      atomicOr(status, ST_GHOST_OVERFLOW);
+      continue;
+    }
+    for (int k = a; k < b; ++k, ++o) {
+      double4 q = sorted[k];
+      q.x = q.x + sx;
+      q.y = q.y + sy;
+      q.z = q.z + sz;
+      ext_pos[o] = q;
+    }
+  }
+}
+
+void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
+                      const int32_t nc[3], const int32_t h[3], const double L[3],
+                      int64_t ext_cap, int32_t *ext_count, int32_t *ext_start,
+                      int32_t *scan_tmp, double4 *ext_pos, uint32_t *status) {
+  ExtGeom g;
+  int64_t next = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.nc[a] = nc[a];
+    g.h[a] = h[a];
+    g.ne[a] = nc[a] + 2 * h[a];
+    g.L[a] = L[a];
+    next *= g.ne[a];
+  }
+  int64_t b = ceil_div(next, 256);
+  if (b > 16384) b = 16384;
+  hipLaunchKernelGGL(k_ext_count, dim3((unsigned)b), dim3(256), 0, s, cell_start, g, next,
+                     ext_count);
+  launch_exclusive_scan(s, ext_count, ext_start, next, scan_tmp);
+  hipLaunchKernelGGL(k_ext_fill, dim3((unsigned)b), dim3(256), 0, s, cell_start, ext_start,
+                     sorted, g, next, ext_cap, ext_pos, status);
 }
 
 }  // namespace dcm

@@ -36,20 +36,15 @@ int64_t fsm_tile_count(const int32_t nv[3]) {
 __global__ __launch_bounds__(256) void k_fsm_init(const uint8_t *__restrict__ seg,
                                                   const uint8_t *__restrict__ iface,
                                                   int64_t nvox, double *dA, double *dB,
-                                                  Ctl *ctl) {
+                                                  uint32_t *flags, int nflags) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
        v += (int64_t)gridDim.x * blockDim.x) {
     double d = (seg[v] == 0 || iface[v]) ? 0.0 : __builtin_huge_val();
     dA[v] = d;
     dB[v] = d;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->fsm_waves = 0;
-    ctl->fsm_done = 0;
-    ctl->fsm_result = 0;
-    ctl->fsm_blocks = 0;
-    ctl->fsm_changed = 0;
-  }
+  if (blockIdx.x == 0)
+    for (int f = threadIdx.x; f < nflags; f += blockDim.x) flags[f] = 0u;
 }
 
 // Godunov solve: with the smaller face neighbour a_k and spacing h_k per axis
@@ -101,35 +96,6 @@ struct SweepGeom {
   double rc_grid;
 };
 
-// Shared end-of-launch bookkeeping: the last workgroup to finish records the
-// launch count and whether another launch is needed.
-__device__ __forceinline__ void finish_launch(Ctl *ctl, int launch, int max_launches,
-                                              uint32_t *status, int *last_flag) {
-  __threadfence();
-  __syncthreads();
-  const unsigned nblocks = gridDim.x * gridDim.y * gridDim.z;
-  if (threadIdx.x == 0) {
-    unsigned ticket = atomicAdd(&ctl->fsm_blocks, 1u);
-    *last_flag = (ticket == nblocks - 1);
-  }
-  __syncthreads();
-  if (*last_flag && threadIdx.x == 0) {
-    __threadfence();
-    unsigned long long c = atomicAdd(&ctl->fsm_changed, 0ull);
-    bool done = (c == 0);
-    if (!done && launch >= max_launches) {
-      done = true;
-      atomicOr(status, ST_NOT_CONVERGED);
-    }
-    ctl->fsm_waves = (uint32_t)launch;
-    ctl->fsm_result = (uint32_t)(launch & 1);
-    ctl->fsm_changed = 0;
-    ctl->fsm_blocks = 0;
-    __threadfence();
-    ctl->fsm_done = done ? 1u : 0u;
-  }
-}
-
 // ------------------------------------------------------------- tiled sweep
 // Launch L reads buf[(L-1)&1] and tile flags chg[(L-1)&1]; writes buf[L&1]
 // for its active tiles and chg[L&1] for every tile.
@@ -137,12 +103,12 @@ __global__ __launch_bounds__(kTileThreads) void k_fsm_tiles(double *dA, double *
                                                             uint8_t *chg0, uint8_t *chg1,
                                                             SweepGeom g, int ntx, int nty,
                                                             int ntz, int launch,
-                                                            int max_launches, Ctl *ctl,
-                                                            uint32_t *status) {
-  if (*(volatile uint32_t *)&ctl->fsm_done) return;
+                                                            uint32_t *flags) {
+  // a pass runs only while the previous one changed something
+  if (launch > 1 && flags[launch - 1] == 0u) return;
   __shared__ double A[QZ][QY][QX];
   __shared__ double B[QZ][QY][QX];
-  __shared__ int act, any, last;
+  __shared__ int act;
   const double *__restrict__ src = (launch & 1) ? dA : dB;
   double *__restrict__ dst = (launch & 1) ? dB : dA;
   const uint8_t *chg_prev = (launch & 1) ? chg0 : chg1;
@@ -235,21 +201,19 @@ __global__ __launch_bounds__(kTileThreads) void k_fsm_tiles(double *dA, double *
     tiles_changed += tile_changed ? 1 : 0;
     __syncthreads();
   }
-  if (tid == 0 && tiles_changed) atomicAdd(&ctl->fsm_changed, tiles_changed);
-  finish_launch(ctl, launch, max_launches, status, &last);
+  if (tid == 0 && tiles_changed) flags[launch] = 1u;
 }
 
 // ------------------------------------------------------------- plain waves
 // Wave w reads state w-1 from buf[(w-1)&1] and writes state w to buf[w&1].
 __global__ __launch_bounds__(256) void k_fsm_wave(double *dA, double *dB, SweepGeom g, int wave,
-                                                  int max_waves, Ctl *ctl, uint32_t *status) {
-  if (*(volatile uint32_t *)&ctl->fsm_done) return;
-  __shared__ int last;
+                                                  uint32_t *flags) {
+  if (wave > 1 && flags[wave - 1] == 0u) return;
   const double *__restrict__ src = (wave & 1) ? dA : dB;
   double *__restrict__ dst = (wave & 1) ? dB : dA;
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-  unsigned long long chg = 0;
+  bool chg = false;
   if (i < g.nx && j < g.ny) {
     const int im = i == 0 ? g.nx - 1 : i - 1, ip = i + 1 == g.nx ? 0 : i + 1;
     const int jm = j == 0 ? g.ny - 1 : j - 1, jp = j + 1 == g.ny ? 0 : j + 1;
@@ -266,25 +230,35 @@ __global__ __launch_bounds__(256) void k_fsm_wave(double *dA, double *dB, SweepG
       const double gv = godunov(ax, ay, az, g.hx, g.hy, g.hz, g.wx, g.wy, g.wz);
       const double nd = (gv < d && gv <= g.rc_grid) ? gv : d;
       dst[v] = nd;
-      chg += (nd != d);
+      chg |= (nd != d);
     }
   }
-  chg = wave_sum_u64(chg);
-  if ((threadIdx.x & 63) == 0 && chg) atomicAdd(&ctl->fsm_changed, chg);
-  finish_launch(ctl, wave, max_waves, status, &last);
+  if (__syncthreads_or(chg ? 1 : 0) && threadIdx.x == 0) flags[wave] = 1u;
 }
 
+// The last pass is the first one that changed nothing (its output equals its
+// input); if every pass changed something the sweep did not converge.
 __global__ __launch_bounds__(256) void k_fsm_final(const double *dA, const double *dB,
-                                                   int64_t nvox, double rc_grid, const Ctl *ctl,
-                                                   double *__restrict__ dist,
-                                                   int32_t *waves_out) {
-  const double *__restrict__ D = ctl->fsm_result ? dB : dA;
+                                                   int64_t nvox, double rc_grid,
+                                                   const uint32_t *flags, int max_steps,
+                                                   double *__restrict__ dist, int32_t *waves_out,
+                                                   uint32_t *status) {
+  int last = max_steps;
+  for (int p = 1; p <= max_steps; ++p)
+    if (flags[p] == 0u) {
+      last = p;
+      break;
+    }
+  const double *__restrict__ D = (last & 1) ? dB : dA;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
        v += (int64_t)gridDim.x * blockDim.x) {
     double d = D[v];
     dist[v] = d > rc_grid ? rc_grid : d;
   }
-  if (waves_out && blockIdx.x == 0 && threadIdx.x == 0) *waves_out = (int32_t)ctl->fsm_waves;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (waves_out) *waves_out = (int32_t)last;
+    if (flags[max_steps] != 0u) atomicOr(status, ST_NOT_CONVERGED);
+  }
 }
 
 static unsigned flat_grid(int64_t nvox) {
@@ -310,35 +284,36 @@ static SweepGeom geom(const int32_t nv[3], const double h[3], double rc_grid) {
 }
 
 void launch_fsm_init(hipStream_t s, const uint8_t *seg, const uint8_t *iface, int64_t nvox,
-                     double *dA, double *dB, Ctl *ctl) {
+                     double *dA, double *dB, uint32_t *flags, int max_steps) {
   hipLaunchKernelGGL(k_fsm_init, dim3(flat_grid(nvox)), dim3(256), 0, s, seg, iface, nvox, dA,
-                     dB, ctl);
+                     dB, flags, max_steps + 2);
 }
 
 void launch_fsm_step(hipStream_t s, double *dA, double *dB, uint8_t *chg0, uint8_t *chg1,
                      const int32_t nv[3], const double h[3], double rc_grid, int step,
-                     int max_steps, Ctl *ctl, uint32_t *status) {
+                     uint32_t *flags) {
   const SweepGeom g = geom(nv, h, rc_grid);
   if (fsm_tiled(nv)) {
     const int ntx = (int)ceil_div(nv[0], TX), nty = (int)ceil_div(nv[1], TY),
               ntz = (int)ceil_div(nv[2], TZ);
     int64_t blocks = (int64_t)ntx * nty * ntz;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 1024) blocks = 1024;  // passes after convergence stay cheap
     hipLaunchKernelGGL(k_fsm_tiles, dim3((unsigned)blocks), dim3(kTileThreads), 0, s, dA, dB,
-                       chg0, chg1, g, ntx, nty, ntz, step, max_steps, ctl, status);
+                       chg0, chg1, g, ntx, nty, ntz, step, flags);
   } else {
     int zb = nv[2] < 64 ? nv[2] : 64;
     hipLaunchKernelGGL(k_fsm_wave,
                        dim3((unsigned)ceil_div(nv[0], 64), (unsigned)ceil_div(nv[1], 4),
                             (unsigned)zb),
-                       dim3(256), 0, s, dA, dB, g, step, max_steps, ctl, status);
+                       dim3(256), 0, s, dA, dB, g, step, flags);
   }
 }
 
 void launch_fsm_final(hipStream_t s, const double *dA, const double *dB, int64_t nvox,
-                      double rc_grid, const Ctl *ctl, double *dist, int32_t *waves_out) {
+                      double rc_grid, const uint32_t *flags, int max_steps, double *dist,
+                      int32_t *waves_out, uint32_t *status) {
   hipLaunchKernelGGL(k_fsm_final, dim3(flat_grid(nvox)), dim3(256), 0, s, dA, dB, nvox,
-                     rc_grid, ctl, dist, waves_out);
+                     rc_grid, flags, max_steps, dist, waves_out, status);
 }
 
 }  // namespace dcm

@@ -294,13 +294,11 @@ __global__ __launch_bounds__(256) void k_threshold(const uint32_t *__restrict__ 
       s = deg ? 1 : ((int64_t)g >= (int64_t)T ? 1 : 0);
     seg0[v] = s;
   }
+  if (blockIdx.x == 0 && threadIdx.x < kMajorityMaxPasses + 2) {
+    ctl->maj_chg1[threadIdx.x] = 0u;
+    ctl->maj_chg2[threadIdx.x] = 0u;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->maj_passes = 0;
-    ctl->maj_done = 0;
-    ctl->maj_result = 0;
-    ctl->maj_blocks = 0;
-    ctl->maj_chg1 = 0;
-    ctl->maj_chg2 = 0;
     if (fixed) {
       ctl->threshold = (int32_t)ceil(split);
       ctl->degenerate = 0;
@@ -327,69 +325,67 @@ void launch_threshold(hipStream_t s, const uint32_t *gray, int64_t nvox, double 
 // counting voxels that differ from state p-1 (no change: fixed point) and
 // from the overwritten state p-2 (no change: 2-cycle).  The last workgroup to
 // finish decides whether later passes run.
+// Pass q ended the iteration if it changed nothing (fixed point) or, from the
+// second pass on, reproduced state q-2 (2-cycle).  A pass that did not run
+// left both flags at 0, so the test also holds for every pass after the end.
+__device__ __forceinline__ bool majority_stopped(const Ctl *ctl, int q) {
+  return ctl->maj_chg1[q] == 0u || (q >= 2 && ctl->maj_chg2[q] == 0u);
+}
+
 __global__ __launch_bounds__(256) void k_majority(uint8_t *buf0, uint8_t *buf1, int nx, int ny,
-                                                  int nz, int pass, int max_passes, Ctl *ctl) {
-  if (*(volatile uint32_t *)&ctl->maj_done) return;
+                                                  int nz, int pass, Ctl *ctl) {
+  if (pass > 1 && majority_stopped(ctl, pass - 1)) return;
   __shared__ uint8_t tile[HZ][HY][HX];
   __shared__ uint8_t sx[HZ][HY][SX];
-  __shared__ int last;
   const uint8_t *__restrict__ src = (pass & 1) ? buf0 : buf1;
   uint8_t *__restrict__ dst = (pass & 1) ? buf1 : buf0;
-  const int x0 = blockIdx.x * SX, y0 = blockIdx.y * SY, z0 = blockIdx.z * SZ;
-  load_tile(tile, src, x0, y0, z0, nx, ny, nz);
-  __syncthreads();
-  sum_x(sx, tile);
-  __syncthreads();
+  // a bounded grid walks the tiles, so a pass after convergence costs only
+  // a small launch
+  const int tnx = (nx + SX - 1) / SX, tny = (ny + SY - 1) / SY, tnz = (nz + SZ - 1) / SZ;
+  const int ntiles = tnx * tny * tnz;
   const int lx = threadIdx.x, ly = threadIdx.y;
-  const int gx = x0 + lx, gy = y0 + ly;
-  unsigned long long c1 = 0, c2 = 0;
-  if (gx < nx && gy < ny) {
+  bool c1 = false, c2 = false;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int x0 = (t % tnx) * SX, y0 = ((t / tnx) % tny) * SY, z0 = (t / (tnx * tny)) * SZ;
+    load_tile(tile, src, x0, y0, z0, nx, ny, nz);
+    __syncthreads();
+    sum_x(sx, tile);
+    __syncthreads();
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx < nx && gy < ny) {
 #pragma unroll
-    for (int lz = 0; lz < SZ; ++lz) {
-      const int gz = z0 + lz;
-      if (gz >= nz) break;
-      const int sum = (int)sum_yz(sx, lx, ly, lz);
-      const uint8_t nvv = sum >= 14 ? 1 : 0;
-      const int64_t v = ((int64_t)gz * ny + gy) * nx + gx;
-      const uint8_t old = dst[v];
-      dst[v] = nvv;
-      c1 += (nvv != tile[lz + 1][ly + 1][lx + 1]);
-      c2 += (nvv != old);
+      for (int lz = 0; lz < SZ; ++lz) {
+        const int gz = z0 + lz;
+        if (gz >= nz) break;
+        const int sum = (int)sum_yz(sx, lx, ly, lz);
+        const uint8_t nvv = sum >= 14 ? 1 : 0;
+        const int64_t v = ((int64_t)gz * ny + gy) * nx + gx;
+        const uint8_t old = dst[v];
+        dst[v] = nvv;
+        c1 |= (nvv != tile[lz + 1][ly + 1][lx + 1]);
+        c2 |= (nvv != old);
+      }
     }
+    __syncthreads();  // the next tile overwrites the LDS tile
   }
-  c1 = wave_sum_u64(c1);
-  c2 = wave_sum_u64(c2);
-  if ((threadIdx.x & 63) == 0) {
-    if (c1) atomicAdd(&ctl->maj_chg1, c1);
-    if (c2) atomicAdd(&ctl->maj_chg2, c2);
-  }
-  __threadfence();
-  __syncthreads();
-  const unsigned nblocks = gridDim.x * gridDim.y * gridDim.z;
+  // any change in this workgroup: store the pass's flag (same value from
+  // every writer, so no atomic is needed)
+  const int any1 = __syncthreads_or(c1 ? 1 : 0);
+  const int any2 = __syncthreads_or(c2 ? 1 : 0);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
-    unsigned ticket = atomicAdd(&ctl->maj_blocks, 1u);
-    last = (ticket == nblocks - 1);
-  }
-  __syncthreads();
-  if (last && threadIdx.x == 0 && threadIdx.y == 0) {
-    __threadfence();
-    unsigned long long t1 = atomicAdd(&ctl->maj_chg1, 0ull);
-    unsigned long long t2 = atomicAdd(&ctl->maj_chg2, 0ull);
-    bool done = (t1 == 0) || (pass >= 2 && t2 == 0) || pass >= max_passes;
-    ctl->maj_passes = (uint32_t)pass;
-    ctl->maj_result = (uint32_t)(pass & 1);
-    ctl->maj_chg1 = 0;
-    ctl->maj_chg2 = 0;
-    ctl->maj_blocks = 0;
-    __threadfence();
-    ctl->maj_done = done ? 1u : 0u;
+    if (any1) ctl->maj_chg1[pass] = 1u;
+    if (any2) ctl->maj_chg2[pass] = 1u;
   }
 }
 
 void launch_majority_pass(hipStream_t s, uint8_t *buf0, uint8_t *buf1, const int32_t nv[3],
                           int pass, int max_passes, Ctl *ctl) {
-  hipLaunchKernelGGL(k_majority, stencil_grid(nv), dim3(SX, SY), 0, s, buf0, buf1, nv[0], nv[1],
-                     nv[2], pass, max_passes, ctl);
+  (void)max_passes;
+  const dim3 g = stencil_grid(nv);
+  int64_t tiles = (int64_t)g.x * g.y * g.z;
+  if (tiles > 1024) tiles = 1024;
+  hipLaunchKernelGGL(k_majority, dim3((unsigned)tiles), dim3(SX, SY), 0, s, buf0, buf1, nv[0],
+                     nv[1], nv[2], pass, ctl);
 }
 
 // ------------------------------------------- interface marking (Fig. 4c)
@@ -398,7 +394,14 @@ __global__ __launch_bounds__(256) void k_interface(const uint8_t *buf0, const ui
                                                    int nx, int ny, int nz, const Ctl *ctl,
                                                    uint8_t *__restrict__ seg,
                                                    uint8_t *__restrict__ iface) {
-  const uint8_t *__restrict__ s = ctl->maj_result ? buf1 : buf0;
+  // state p lives in buf[p & 1]; the last pass is the first that stopped
+  int last = kMajorityMaxPasses;
+  for (int p = 1; p <= kMajorityMaxPasses; ++p)
+    if (majority_stopped(ctl, p)) {
+      last = p;
+      break;
+    }
+  const uint8_t *__restrict__ s = (last & 1) ? buf1 : buf0;
   const int i = blockIdx.x * SX + threadIdx.x;
   const int j = blockIdx.y * SY + threadIdx.y;
   if (i >= nx || j >= ny) return;

@@ -4,21 +4,30 @@
 // One lane owns one particle i (particles in cell order, so a wavefront
 // covers neighbouring particles with similar cutoffs).  Instead of storing
 // the neighbour list of Algorithm 2.2, each lane enumerates the cell rows
-// (fixed y and z cell; consecutive x cells are consecutive in the sorted
-// arrays) that can hold a j within its search radius, trims each row to the
-// chord of the search sphere -- the small-cell traversal of Section 2.3 -- and
-// writes the resulting index segments into a private LDS list.  It then runs
-// one flat loop over all candidates of those segments, so lanes with
-// different row lengths never wait for each other row by row.  The periodic
-// image shift is constant per segment.  No Newton-3 update is made
-// (Section 2.4): a lane writes only its own particle.
+// (fixed y and z cell; consecutive x cells are consecutive in memory) that can
+// hold a j within its search radius and trims each row to the chord of the
+// search sphere -- the small-cell traversal of Section 2.3.  The rows are
+// walked in the ghost-extended cell grid, where periodic images sit in halo
+// cells with their coordinates already shifted, so every row is one
+// contiguous index range and a separation is a plain difference.  A lane
+// writes its rows' ranges into a private LDS list, then runs one flat loop
+// over all their candidates, so lanes with different row lengths never wait
+// for each other row by row.  No Newton-3 update is made (Section 2.4): a
+// lane writes only its own particle.
 #include "dcm_device.hpp"
 #include "dcm_internal.hpp"
 
 namespace dcm {
 
 constexpr int kPairBlock = 256;
-constexpr int kSegCap = 16;  // segments per lane per chunk (LDS: 8 B each)
+#ifndef DCM_PAIR_SEGCAP
+#define DCM_PAIR_SEGCAP 24
+#endif
+constexpr int kSegCap = DCM_PAIR_SEGCAP;  // row ranges per lane per chunk (LDS: 8 B each)
+#ifndef DCM_PAIR_XCD_GROUP
+#define DCM_PAIR_XCD_GROUP 16
+#endif
+constexpr int kXcdGroup = DCM_PAIR_XCD_GROUP;
 int pair_block_size() { return kPairBlock; }
 
 // Per-lane accumulators.
@@ -99,31 +108,91 @@ __device__ __forceinline__ void interact(Acc<PREC> &acc, double dx, double dy, d
   }
 }
 
-// Segment encoding in LDS: .x = first sorted index, .y = count (low 24 bits)
-// | shift code << 24.  Shift code bits: x (2 bits), y (2 bits), z (2 bits),
-// each 0 = none, 1 = +L, 2 = -L; bit 6 = take the image per pair instead.
-constexpr uint32_t kPerPairImage = 1u << 6;
+// Test candidate j (position pj) against lane particle i and accumulate it.
+template <int RULE, int PREC, int EVM>
+__device__ __forceinline__ void candidate(const double4 &pj, int j, int self, double xi,
+                                          double yi, double zi, double rci, double rci2,
+                                          double sig2, Acc<PREC> &acc, int &cnt) {
+  const double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+  const double r2 = (dx * dx + dy * dy) + dz * dz;
+  bool inc;
+  if constexpr (RULE == DCM_PAIR_OWN) {
+    inc = r2 < rci2;
+  } else {
+    double m = rci > pj.w ? rci : pj.w;
+    inc = r2 <= m * m;
+  }
+  if (inc && j != self) {
+    interact<PREC, EVM>(acc, dx, dy, dz, r2, sig2);
+    ++cnt;
+  }
+}
 
-__device__ __forceinline__ double code_shift(uint32_t c, double L) {
-  return c == 1u ? L : (c == 2u ? -L : 0.0);
+// One flat loop over every candidate j of this lane's first nseg listed
+// ranges [seg.x, seg.y) of the extended array, two candidates per trip with
+// two register sets: each candidate's position is loaded a full candidate
+// ahead of its use, without copying registers between trips.
+template <int RULE, int PREC, int EVM>
+__device__ __forceinline__ void scan_ranges(const uint2 (*segs)[kPairBlock], int nseg,
+                                            const double4 *__restrict__ pos, int self, double xi,
+                                            double yi, double zi, double rci, double rci2,
+                                            double sig2, Acc<PREC> &acc, int &cnt) {
+  const int lane_id = threadIdx.x;
+  int sidx = 1;
+  uint2 sg = segs[0][lane_id];
+  int jend = (int)sg.y;
+  // next candidate after j, or -1 when the list is exhausted
+  auto advance = [&](int j) -> int {
+    int jn = j + 1;
+    if (jn >= jend) {
+      if (sidx < nseg) {
+        sg = segs[sidx][lane_id];
+        ++sidx;
+        jn = (int)sg.x;
+        jend = (int)sg.y;
+      } else {
+        jn = -1;
+      }
+    }
+    return jn;
+  };
+  int ja = (int)sg.x;
+  double4 A = pos[ja];
+  int jb = advance(ja);
+  while (true) {
+    double4 B;
+    if (jb >= 0) B = pos[jb];
+    const int jc = jb >= 0 ? advance(jb) : -1;
+    candidate<RULE, PREC, EVM>(A, ja, self, xi, yi, zi, rci, rci2, sig2, acc, cnt);
+    if (jb < 0) break;
+    if (jc >= 0) A = pos[jc];
+    const int jd = jc >= 0 ? advance(jc) : -1;
+    candidate<RULE, PREC, EVM>(B, jb, self, xi, yi, zi, rci, rci2, sig2, acc, cnt);
+    if (jc < 0) break;
+    ja = jc;
+    jb = jd;
+  }
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
 }
 
 template <int RULE, int PREC, int EVM>
 __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   __shared__ uint2 segs[kSegCap][kPairBlock];
   const int lane_id = threadIdx.x;
-  const int64_t s = blockIdx.x * (int64_t)kPairBlock + threadIdx.x;
+  const int64_t lblock = xcd_block(blockIdx.x, gridDim.x, kXcdGroup);
+  const int64_t s = lblock * kPairBlock + threadIdx.x;
   const bool active = s < a.n;
   Acc<PREC> acc;
   int cnt = 0;
-  const double Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
   const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
+  const int hx = a.h[0], hy = a.h[1], hz = a.h[2];
+  const int nex = a.ne[0], ney = a.ne[1];
   const double sig2 = a.sigma * a.sigma;
-  double xi = 0, yi = 0, zi = 0, rci = 0, rci2 = 0;
-  // row enumeration state
-  int zlo = 0, zhi = -1, ylo = 0, yhi = -1, zc = 0, yc = 0, cy = 0, cz = 0;
-  bool fully = false, fullz = false;
-  double R2 = 0, guard = 0;
+  double xi = 0, yi = 0, zi = 0, rci = 0, rci2 = 0, R2 = 0, guard = 0;
+  int zlo = 0, zhi = -1, ylo = 0, yhi = -1, zc = 0, yc = 0, cy = 0, cz = 0, self = -1;
   if (active) {
     const double4 pi = a.pos[s];
     xi = pi.x;
@@ -135,123 +204,62 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
       double rall = __longlong_as_double((long long)a.ctl->rc_max_bits);
       R = rall > R ? rall : R;
     }
+    R = R < a.rc_bound ? R : a.rc_bound;
     rci2 = rci * rci;
     // search radius widened by a hair: rounding in the cell geometry can
     // only add candidates, never drop one
     guard = 1e-9 * (a.len[0] + a.len[1] + a.len[2]);
     const double Rg = R + guard;
     R2 = Rg * Rg;
+    const int cx = slab_index(xi, a.sc[0], nx);
     cy = slab_index(yi, a.sc[1], ny);
     cz = slab_index(zi, a.sc[2], nz);
-    zlo = (int)floor((zi - Rg) * a.sc[2]);
-    zhi = (int)floor((zi + Rg) * a.sc[2]);
-    ylo = (int)floor((yi - Rg) * a.sc[1]);
-    yhi = (int)floor((yi + Rg) * a.sc[1]);
-    fullz = (zhi - zlo + 1) >= nz;
-    fully = (yhi - ylo + 1) >= ny;
-    if (fullz) { zlo = 0; zhi = nz - 1; }
-    if (fully) { ylo = 0; yhi = ny - 1; }
+    // the halo holds ceil(rc_bound/len) + 1 cells, so these stay inside it
+    zlo = clampi((int)floor((zi - Rg) * a.sc[2]), -hz, nz + hz - 1);
+    zhi = clampi((int)floor((zi + Rg) * a.sc[2]), -hz, nz + hz - 1);
+    ylo = clampi((int)floor((yi - Rg) * a.sc[1]), -hy, ny + hy - 1);
+    yhi = clampi((int)floor((yi + Rg) * a.sc[1]), -hy, ny + hy - 1);
     zc = zlo;
     yc = ylo;
+    // this particle's own copy in the extended array
+    const int real_cell = (cz * ny + cy) * nx + cx;
+    const int ext_cell = ((cz + hz) * ney + (cy + hy)) * nex + (cx + hx);
+    self = a.ext_start[ext_cell] + (int)(s - a.cell_start[real_cell]);
   }
   bool rows_left = active;
   while (rows_left) {
-    // ---- fill: append the segments of the next rows to this lane's list
+    // ---- fill: append the ranges of the next rows to this lane's list
     int nseg = 0;
-    while (rows_left && nseg <= kSegCap - 2) {
+    while (rows_left && nseg < kSegCap) {
       const int zcur = zc, ycur = yc;
       if (++yc > yhi) {
         yc = ylo;
         if (++zc > zhi) rows_left = false;
       }
-      int zw = zcur, yw = ycur;
-      uint32_t cz_code = 0, cy_code = 0;
       double ez = 0.0, ey = 0.0;
-      if (!fullz) {
-        if (zcur < 0) { zw = zcur + nz; cz_code = 1; }
-        else if (zcur >= nz) { zw = zcur - nz; cz_code = 2; }
-        if (zcur < cz) ez = zi - (double)(zcur + 1) * a.len[2];
-        else if (zcur > cz) ez = (double)zcur * a.len[2] - zi;
-        ez = ez > guard ? ez - guard : 0.0;
-      }
-      if (!fully) {
-        if (ycur < 0) { yw = ycur + ny; cy_code = 1; }
-        else if (ycur >= ny) { yw = ycur - ny; cy_code = 2; }
-        if (ycur < cy) ey = yi - (double)(ycur + 1) * a.len[1];
-        else if (ycur > cy) ey = (double)ycur * a.len[1] - yi;
-        ey = ey > guard ? ey - guard : 0.0;
-      }
+      if (zcur < cz) ez = zi - (double)(zcur + 1) * a.len[2];
+      else if (zcur > cz) ez = (double)zcur * a.len[2] - zi;
+      ez = ez > guard ? ez - guard : 0.0;
+      if (ycur < cy) ey = yi - (double)(ycur + 1) * a.len[1];
+      else if (ycur > cy) ey = (double)ycur * a.len[1] - yi;
+      ey = ey > guard ? ey - guard : 0.0;
       const double rem = R2 - ez * ez - ey * ey;
       if (rem < 0.0) continue;
       // chord half-width, rounded up generously (it only selects cells)
       const double w = (double)(sqrtf((float)rem) * 1.00001f) + guard;
-      const int xlo = (int)floor((xi - w) * a.sc[0]);
-      const int xhi = (int)floor((xi + w) * a.sc[0]);
-      const int32_t *cs = a.cell_start + (zw * ny + yw) * nx;
-      const uint32_t yz = (cy_code << 2) | (cz_code << 4);
-      auto push = [&](int c0, int c1, uint32_t code) {  // cells [c0, c1)
-        int j0 = cs[c0], j1 = cs[c1];
-        if (j1 > j0) {
-          segs[nseg][lane_id] = make_uint2((uint32_t)j0, (uint32_t)(j1 - j0) | (code << 24));
-          ++nseg;
-        }
-      };
-      if (xhi - xlo + 1 >= nx) {
-        push(0, nx, kPerPairImage);
-      } else if (fully || fullz) {
-        int lo = xlo, hi = xhi;
-        if (lo < 0) { push(lo + nx, nx, kPerPairImage); lo = 0; }
-        if (hi >= nx) { push(0, hi - nx + 1, kPerPairImage); hi = nx - 1; }
-        push(lo, hi + 1, kPerPairImage);
-      } else {
-        int lo = xlo, hi = xhi;
-        if (lo < 0) { push(lo + nx, nx, yz | 1u); lo = 0; }
-        if (hi >= nx) { push(0, hi - nx + 1, yz | 2u); hi = nx - 1; }
-        push(lo, hi + 1, yz);
+      const int xlo = clampi((int)floor((xi - w) * a.sc[0]), -hx, nx + hx - 1);
+      const int xhi = clampi((int)floor((xi + w) * a.sc[0]), -hx, nx + hx - 1);
+      const int32_t *es = a.ext_start + ((int64_t)(zcur + hz) * ney + (ycur + hy)) * nex + hx;
+      int j0 = es[xlo], j1 = es[xhi + 1];
+      if (j1 > a.ext_cap) j1 = (int)a.ext_cap;  // overflowed ghosts (flagged at build)
+      if (j1 > j0) {
+        segs[nseg][lane_id] = make_uint2((uint32_t)j0, (uint32_t)j1);
+        ++nseg;
       }
     }
-    // ---- scan: one flat loop over every candidate of the listed segments
-    int sidx = 0, j = 0, jend = 0;
-    double shx = 0.0, shy = 0.0, shz = 0.0;
-    bool per_pair = false;
-    while (true) {
-      if (j >= jend) {
-        if (sidx >= nseg) break;
-        const uint2 sg = segs[sidx][lane_id];
-        ++sidx;
-        j = (int)sg.x;
-        jend = j + (int)(sg.y & 0xffffffu);
-        const uint32_t code = sg.y >> 24;
-        per_pair = (code & kPerPairImage) != 0;
-        shx = code_shift(code & 3u, Lx);
-        shy = code_shift((code >> 2) & 3u, Ly);
-        shz = code_shift((code >> 4) & 3u, Lz);
-      }
-      const double4 pj = a.pos[j];
-      double dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
-      if (per_pair) {
-        dx = dx - Lx * rint(dx / Lx);
-        dy = dy - Ly * rint(dy / Ly);
-        dz = dz - Lz * rint(dz / Lz);
-      } else {
-        dx = dx + shx;
-        dy = dy + shy;
-        dz = dz + shz;
-      }
-      const double r2 = (dx * dx + dy * dy) + dz * dz;
-      bool inc;
-      if constexpr (RULE == DCM_PAIR_OWN) {
-        inc = r2 < rci2;
-      } else {
-        double m = rci > pj.w ? rci : pj.w;
-        inc = r2 <= m * m;
-      }
-      if (inc && j != (int)s) {
-        interact<PREC, EVM>(acc, dx, dy, dz, r2, sig2);
-        ++cnt;
-      }
-      ++j;
-    }
+    if (nseg > 0)
+      scan_ranges<RULE, PREC, EVM>(segs, nseg, a.ext_pos, self, xi, yi, zi, rci, rci2, sig2, acc,
+                                   cnt);
   }
   if (active) {
     const double c24 = 24.0 * a.eps;
@@ -281,7 +289,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < kPairBlock / 64; ++q) t += red[q][threadIdx.x];
-    a.partials[blockIdx.x * (int64_t)kPartialSlots + threadIdx.x] = t;
+    a.partials[lblock * kPartialSlots + threadIdx.x] = t;
   }
 }
 

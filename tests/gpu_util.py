@@ -58,8 +58,11 @@ class Ctx:
 
 
 def gpu_forces(s, rc, prec=dcm.DCM_FP64, rule=dcm.DCM_PAIR_OWN, edge=0.0, eps=1.0, sigma=1.0,
-               idx=None):
-    """Cells + forces on the GPU from the given cutoffs; returns host arrays."""
+               idx=None, rc_bound=None):
+    """Cells + forces on the GPU from the given cutoffs; returns host arrays.
+    rc_bound defaults to the largest given cutoff."""
+    if rc_bound is None:
+        rc_bound = float(np.max(rc)) if len(rc) else 0.0
     x, y, z, r = dev(s.x), dev(s.y), dev(s.z), dev(rc)
     n = s.n
     fx, fy, fz = (torch.zeros(n, **F64) for _ in range(3))
@@ -68,7 +71,7 @@ def gpu_forces(s, rc, prec=dcm.DCM_FP64, rule=dcm.DCM_PAIR_OWN, edge=0.0, eps=1.
     nn = torch.zeros(n, dtype=torch.int32, device=DEV)
     npairs = torch.zeros(1, dtype=torch.uint64, device=DEV)
     with Ctx() as ctx:
-        dcm.dcm_build_cells(ctx, x, y, z, r, s.box, edge, prec)
+        dcm.dcm_build_cells(ctx, x, y, z, r, s.box, edge, prec, rc_bound=rc_bound)
         dcm.dcm_forces(ctx, dcm.make_lj(eps, sigma), fx, fy, fz, pair_rule=rule, prec=prec,
                        ev_flags=dcm.DCM_EV_ENERGY | dcm.DCM_EV_VIRIAL | dcm.DCM_EV_COUNTS,
                        energy=e, virial=w, nnbr=nn, npairs=npairs)

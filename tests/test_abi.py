@@ -59,7 +59,7 @@ def test_null_context_is_rejected_before_any_device_call(lib):
     assert lib.dcm_sync_status(None) == dcm.DCM_ERR_INVALID
     assert lib.dcm_forces(None, dcm.make_lj(), 0, 0, 0, None, None, None, None, None, None,
                           None) == dcm.DCM_ERR_INVALID
-    assert lib.dcm_build_cells(None, None, None, None, None, 0, box, 1.0, 0, None,
+    assert lib.dcm_build_cells(None, None, None, None, None, 0, box, 1.0, 0.0, 0, None,
                                None) == dcm.DCM_ERR_INVALID
     assert lib.dcm_destroy(None) == dcm.DCM_ERR_INVALID
     assert lib.dcm_last_error(None) == b"null context"

@@ -237,6 +237,20 @@ def test_static_cutoff_reduces_to_eq3_and_balances():
     assert np.all(np.abs(a["F"].sum(0)) <= 1e-12 * tot)
 
 
+def test_cutoff_above_bound_is_flagged():
+    s = workloads.make("slab_small")
+    rc = ref_detect("slab_small")["rc"]
+    got = gpu_forces(s, rc, rc_bound=5.0)
+    assert got["status"] == dcm.DCM_ERR_RANGE
+    ok = gpu_forces(s, np.minimum(rc, 5.0), rc_bound=5.0)
+    assert ok["status"] == dcm.DCM_OK
+    # without a bound the ghost halo covers half the box: same forces
+    free = gpu_forces(s, rc, rc_bound=0.0)
+    ref = gpu_forces(s, rc)
+    np.testing.assert_array_equal(free["nnbr"], ref["nnbr"])
+    assert force_errors(free["F"], ref["F"])[0] <= 1e-13
+
+
 def test_empty_system():
     s = workloads.System("empty", *(np.zeros(0) for _ in range(6)), (10.0, 10.0, 10.0))
     got = gpu_forces(s, np.zeros(0))
