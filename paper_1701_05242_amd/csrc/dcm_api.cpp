@@ -167,7 +167,9 @@ dcm_status dcm_destroy(dcm_ctx *ctx) {
                     &ctx->dB,       &ctx->dist,      &ctx->delta,     &ctx->rc,
                     &ctx->partials, &ctx->ke,        &ctx->cell_of,   &ctx->cell_count,
                     &ctx->cell_start, &ctx->cell_fill, &ctx->perm,    &ctx->sorted,
-                    &ctx->scan_tmp, &ctx->scalars};
+                    &ctx->scan_tmp, &ctx->scalars, &ctx->ext_count, &ctx->ext_start,
+                    &ctx->ext_pos, &ctx->ws[0], &ctx->ws[1], &ctx->ws_owner[0],
+                    &ctx->ws_owner[1]};
   for (DevBuf *b : bufs)
     if (b->p) hipFree(b->p);
   for (auto &kv : ctx->timers)
@@ -529,13 +531,64 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
   DCM_TRY(ensure(ctx, ctx->dist, nvox * sizeof(double)));
   DCM_TRY(ensure(ctx, ctx->scalars, 16 * sizeof(double)));
   DCM_TRY(ensure(ctx, ctx->ke, kinetic_blocks(n) * sizeof(double)));
-  if (!rc) {
-    DCM_TRY(ensure(ctx, ctx->rc, n * sizeof(double)));
-    rc = ptr<double>(ctx->rc);
+  // working copies: fields x y z, vx vy vz, fx fy fz, delta, rc of every
+  // particle, kept in cell order between cell builds
+  enum { WX = 0, WY, WZ, WVX, WVY, WVZ, WFX, WFY, WFZ, WDELTA, WRC, WFIELDS };
+  static_assert(WFIELDS == kPermFields, "one permute pass moves every field");
+  const int64_t nn = std::max<int64_t>(n, 1);
+  for (int b = 0; b < 2; ++b) {
+    DCM_TRY(ensure(ctx, ctx->ws[b], (size_t)WFIELDS * nn * sizeof(double)));
+    DCM_TRY(ensure(ctx, ctx->ws_owner[b], nn * sizeof(int32_t)));
   }
   if (ctx->field_n[0] != grid.n[0] || ctx->field_n[1] != grid.n[1] ||
       ctx->field_n[2] != grid.n[2])
     ctx->have_field = false;
+  hipStream_t s = ctx->stream;
+  int cur = 0;
+  auto field = [&](int set, int k) { return ptr<double>(ctx->ws[set]) + (int64_t)k * nn; };
+  auto owner = [&](int set) { return ptr<int32_t>(ctx->ws_owner[set]); };
+  {
+    double *src[] = {x, y, z, vx, vy, vz, fx, fy, fz};
+    const int nload = nsteps > 0 ? 9 : 3;
+    for (int k = 0; k < nload; ++k)
+      if (n > 0 && src[k])
+        hipMemcpyAsync(field(0, k), src[k], n * sizeof(double), hipMemcpyDeviceToDevice, s);
+    launch_iota(s, owner(0), n);
+  }
+  double *W[WFIELDS];
+  auto bind = [&]() {
+    for (int k = 0; k < WFIELDS; ++k) W[k] = field(cur, k);
+  };
+  bind();
+  // reorder the working copies into the order of the last cell build
+  auto reorder = [&]() {
+    PermFields f;
+    f.nf = WFIELDS;
+    for (int k = 0; k < WFIELDS; ++k) {
+      f.src[k] = field(cur, k);
+      f.dst[k] = field(1 - cur, k);
+    }
+    launch_permute_gather(s, f, ptr<int32_t>(ctx->perm), owner(cur), owner(1 - cur), n);
+    cur = 1 - cur;
+    bind();
+  };
+  // results back to the caller's order
+  auto unload = [&]() -> dcm_status {
+    PermFields f;
+    f.nf = 0;
+    double *dst[] = {x, y, z, vx, vy, vz, fx, fy, fz, delta, rc};
+    const bool want[] = {nsteps > 0, nsteps > 0, nsteps > 0, nsteps > 0, nsteps > 0,
+                         nsteps > 0, true,       true,       true,       delta != nullptr,
+                         rc != nullptr};
+    for (int k = 0; k < WFIELDS; ++k)
+      if (want[k] && dst[k]) {
+        f.src[f.nf] = W[k];
+        f.dst[f.nf] = dst[k];
+        ++f.nf;
+      }
+    launch_permute_scatter(s, f, owner(cur), n);
+    return check_launch(ctx, "dcm_step");
+  };
   // sweep passes stop early once one changes nothing; the cap only bounds
   // the launches.  A tiled pass settles whole 16x8x8 tiles, so a front
   // crosses at least a tile per pass; a plain pass advances one voxel.
@@ -545,44 +598,55 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
                           : std::max<int32_t>(64, (int32_t)std::ceil(4.0 * rc_grid / hmin) + 8);
   double *scal = ptr<double>(ctx->scalars);
   auto detect = [&]() -> dcm_status {
-    DCM_TRY(dcm_detect_interface(ctx, x, y, z, n, box, grid, 0.0, nullptr, ptr<uint8_t>(ctx->seg),
-                                 ptr<uint8_t>(ctx->iface), nullptr));
+    DCM_TRY(dcm_detect_interface(ctx, W[WX], W[WY], W[WZ], n, box, grid, 0.0, nullptr,
+                                 ptr<uint8_t>(ctx->seg), ptr<uint8_t>(ctx->iface), nullptr));
     DCM_TRY(dcm_sweep_distance(ctx, ptr<uint8_t>(ctx->seg), ptr<uint8_t>(ctx->iface), grid,
                                rc_grid, max_waves, ptr<double>(ctx->dist), nullptr));
     ctx->have_field = true;
     for (int a = 0; a < 3; ++a) ctx->field_n[a] = grid.n[a];
     return DCM_OK;
   };
+  // cutoffs, cells and forces of the working copies; the forces land in the
+  // working order (the cells map sorted slots back to it)
   auto forces = [&](double *e_out) -> dcm_status {
-    DCM_TRY(dcm_assign_cutoffs(ctx, x, y, z, n, box, grid, ptr<double>(ctx->dist), rule, delta,
-                               rc));
+    DCM_TRY(dcm_assign_cutoffs(ctx, W[WX], W[WY], W[WZ], n, box, grid, ptr<double>(ctx->dist),
+                               rule, W[WDELTA], W[WRC]));
     // small cells (Section 2.3): half the smallest cutoff
-    DCM_TRY(dcm_build_cells(ctx, x, y, z, rc, n, box, 0.5 * rule.rc_min, rule.rc_max, prec,
-                            nullptr, nullptr));
-    return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, fx, fy, fz, e_out ? e_out : scal,
-                      nullptr, nullptr, nullptr);
+    DCM_TRY(dcm_build_cells(ctx, W[WX], W[WY], W[WZ], W[WRC], n, box, 0.5 * rule.rc_min,
+                            rule.rc_max, prec, nullptr, nullptr));
+    return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, W[WFX], W[WFY], W[WFZ],
+                      e_out ? e_out : scal, nullptr, nullptr, nullptr);
   };
   if (nsteps == 0) {
     DCM_TRY(detect());
-    return forces(nullptr);
+    DCM_TRY(forces(nullptr));
+    return unload();
   }
   const double c = (0.5 * dt) / mass;
   for (int32_t st = 0; st < nsteps; ++st) {
     hipEvent_t ev;
     timer_begin(ctx, "verlet", &ev);
-    launch_kick_drift(ctx->stream, x, y, z, vx, vy, vz, fx, fy, fz, n, c, dt, box.L);
+    launch_kick_drift(s, W[WX], W[WY], W[WZ], W[WVX], W[WVY], W[WVZ], W[WFX], W[WFY], W[WFZ],
+                      n, c, dt, box.L);
     timer_end(ctx, "verlet", ev);
     if (!ctx->have_field || (step0 + st + 1) % redetect_every == 0) DCM_TRY(detect());
     DCM_TRY(forces(energy_series ? energy_series + 2 * (int64_t)st : nullptr));
     timer_begin(ctx, "verlet", &ev);
-    launch_kick(ctx->stream, vx, vy, vz, fx, fy, fz, n, c);
+    launch_kick(s, W[WVX], W[WVY], W[WVZ], W[WFX], W[WFY], W[WFZ], n, c);
     timer_end(ctx, "verlet", ev);
     if (energy_series)
-      launch_kinetic(ctx->stream, vx, vy, vz, n, mass, ptr<double>(ctx->ke), kinetic_blocks(n),
+      launch_kinetic(s, W[WVX], W[WVY], W[WVZ], n, mass, ptr<double>(ctx->ke), kinetic_blocks(n),
                      energy_series + 2 * (int64_t)st + 1);
+    // keep the working copies in cell order: after the first build, then
+    // every few steps (particles move little between steps)
+    if (st + 1 < nsteps && (st == 0 || (st + 1) % kReorderEvery == 0)) {
+      timer_begin(ctx, "verlet", &ev);
+      reorder();
+      timer_end(ctx, "verlet", ev);
+    }
     DCM_TRY(check_launch(ctx, "dcm_step"));
   }
-  return DCM_OK;
+  return unload();
 }
 
 dcm_status dcm_set_profiling(dcm_ctx *ctx, int enable) {

@@ -28,6 +28,7 @@ enum : uint32_t {
 constexpr int kHistBins = 4096;       // gray values (27-window counts) must stay below this
 constexpr int kMajorityMaxPasses = 16;
 constexpr int kPartialSlots = 8;      // per-block partial sums: E, W[6], pair count
+constexpr int kReorderEvery = 8;      // dcm_step re-sorts its working copies this often
 
 // Device-resident control block: scalars produced and consumed on the device
 // so that no stage needs a host round trip.
@@ -85,6 +86,9 @@ struct dcm_ctx {
   dcm_box cell_box = {{0, 0, 0}};
   int64_t cell_n = -1;
   int cell_prec = 0;
+  // dcm_step's working copies in cell order: two sets of 11 fields (x y z,
+  // vx vy vz, fx fy fz, delta, rc) and the caller index of each slot
+  dcm::DevBuf ws[2], ws_owner[2];
   // last distance field kept for dcm_step
   bool have_field = false;
   int32_t field_n[3] = {0, 0, 0};
@@ -192,6 +196,19 @@ int pair_block_size();
 void launch_pair(hipStream_t s, const PairArgs &a, int rule, int prec);
 void launch_reduce_partials(hipStream_t s, const double *partials, int64_t blocks, double eps,
                             int ev_flags, double *energy, double *virial, uint64_t *npairs);
+
+// k_order.hip
+constexpr int kPermFields = 11;
+struct PermFields {
+  const double *src[kPermFields];
+  double *dst[kPermFields];
+  int nf;
+};
+void launch_iota(hipStream_t s, int32_t *p, int64_t n);
+void launch_permute_gather(hipStream_t s, const PermFields &f, const int32_t *perm,
+                           const int32_t *owner_src, int32_t *owner_dst, int64_t n);
+void launch_permute_scatter(hipStream_t s, const PermFields &f, const int32_t *owner,
+                            int64_t n);
 
 // k_verlet.hip
 void launch_kick(hipStream_t s, double *vx, double *vy, double *vz, const double *fx,
