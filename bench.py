@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a plain device copy of MIB MiB five times (the reference "
+                        "kernel for scaling the HBM traffic counters) and exit")
     return p.parse_args()
 
 
@@ -136,8 +139,63 @@ def cpu_baseline(s, seconds):
                        f"(all {s.n} j each), {pairs} interacting pairs in {dt:.1f} s")
 
 
+def copy_calibration(mib):
+    """Five launches of torch's plain device copy of a known number of bytes."""
+    import torch
+
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}), flush=True)
+
+
+PAIR_SOURCES = ("k_pair.hip", "dcm_device.hpp", "dcm_internal.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_slab_large_traffic.txt")
+
+
+def pair_source_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in PAIR_SOURCES:
+        with open(os.path.join(ROOT, "paper_1701_05242_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, prec_name):
+    """HBM bytes per pair launch from the committed counter summary, or None.
+
+    The summary holds FETCH_SIZE and WRITE_SIZE per dispatch of the pair
+    kernel, each scaled by the same counter's reading for a plain copy of
+    known size.  It applies only while the pair kernel's sources hash to the
+    digest recorded with the counters, and only to the workload and precision
+    they were taken on.
+    """
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if (kv.get("source_sha256") != pair_source_digest() or kv.get("workload") != workload
+            or kv.get("precision") != prec_name):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the path is single-GPU by design", file=sys.stderr)
@@ -184,7 +242,8 @@ def main():
         "force_evals_per_s": main_leg["force_evals"],
         "stage_ms": main_leg["stage_ms"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS,
+                     "traffic": measured_traffic(s.name, args.prec)},
         "roofline_note": (f"pair kernel, {FLOP_PER_PAIR_FE} flop per interacting pair "
                           f"(force+energy), avg {main_leg['avg_pair_ms']:.3f} ms per launch; "
                           f"vs packed-FP32 peak {VALU_PEAK_FP32_PACKED}: "
