@@ -41,6 +41,7 @@ def parse():
     p.add_argument("--prec", default="fp32_mixed", choices=["fp32_mixed", "fp64"])
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of MIB MiB five times (the reference "
@@ -109,6 +110,82 @@ def run_leg(s, prec, steps, warmup, dev):
                 pair_kernel_tflops=pairs * FLOP_PER_PAIR_FE / avg_pair_s / 1e12,
                 stage_ms={k: v[0] / max(v[1], 1) for k, v in fam_ms.items()},
                 stage_launches={k: v[1] for k, v in fam_ms.items()})
+
+
+def batched_leg(steps, dev):
+    """64 independent slabs (2,000-200,000 particles, rc_max 4-8): cells +
+    forces for all of them as one replayed graph around one persistent pair
+    launch (FP32-mixed, tuned cell edge), against the same work as 64
+    sequential single-system FP64 calls.  Cutoffs come from the library's own
+    detection / sweep / assignment steps, run once before timing."""
+    import torch
+
+    import paper_1701_05242_amd as dcm
+    import workloads
+
+    f64 = dict(dtype=torch.float64, device=dev)
+    systems = workloads.batched_systems()
+    lj = dcm.make_lj()
+    ctx = dcm.dcm_create()
+    try:
+        batch = []
+        for s in systems:
+            x, y, z = (torch.tensor(a, **f64) for a in (s.x, s.y, s.z))
+            rc = torch.zeros(s.n, **f64)
+            grid = dcm.make_grid(s.box, s.h)
+            nv = dcm.grid_voxels(grid)
+            seg = torch.zeros(nv, dtype=torch.uint8, device=dev)
+            iface = torch.zeros(nv, dtype=torch.uint8, device=dev)
+            dist = torch.zeros(nv, **f64)
+            rule = dcm.make_rule(*s.rule)
+            dcm.dcm_detect_interface(ctx, x, y, z, s.box, grid, seg, iface)
+            dcm.dcm_sweep_distance(ctx, seg, iface, grid, dcm.rc_grid_for(rule, grid), 128, dist)
+            dcm.dcm_assign_cutoffs(ctx, x, y, z, s.box, grid, dist, rule, rc)
+            batch.append(dict(x=x, y=y, z=z, rc=rc, fx=torch.zeros(s.n, **f64),
+                              fy=torch.zeros(s.n, **f64), fz=torch.zeros(s.n, **f64),
+                              energy=torch.zeros(1, **f64),
+                              npairs=torch.zeros(1, dtype=torch.uint64, device=dev),
+                              box=s.box, cell_edge=0.0, rc_bound=s.rule[1]))
+        if dcm.dcm_sync_status(ctx) != dcm.DCM_OK:
+            raise RuntimeError(dcm.dcm_last_error(ctx))
+        ev = dcm.DCM_EV_ENERGY | dcm.DCM_EV_COUNTS
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        arr = dcm.make_systems(batch)
+        graph_s = timed(lambda: dcm.dcm_forces_batched(ctx, arr, lj, prec=dcm.DCM_FP32_MIXED,
+                                                       ev_flags=ev, use_graph=True), steps)
+        if dcm.dcm_sync_status(ctx) != dcm.DCM_OK:
+            raise RuntimeError(dcm.dcm_last_error(ctx))
+        pairs = sum(int(d["npairs"].cpu().numpy()[0]) for d in batch)
+        edge = dcm.dcm_batched_edge(ctx)
+
+        def sequential():
+            for s, d in zip(systems, batch):
+                dcm.dcm_build_cells(ctx, d["x"], d["y"], d["z"], d["rc"], s.box, edge,
+                                    dcm.DCM_FP64, rc_bound=s.rule[1])
+                dcm.dcm_forces(ctx, lj, d["fx"], d["fy"], d["fz"], prec=dcm.DCM_FP64,
+                               ev_flags=ev, energy=d["energy"], npairs=d["npairs"])
+
+        seq_s = timed(sequential, max(2, steps // 4))
+        if dcm.dcm_sync_status(ctx) != dcm.DCM_OK:
+            raise RuntimeError(dcm.dcm_last_error(ctx))
+        seq_pairs = sum(int(d["npairs"].cpu().numpy()[0]) for d in batch)
+    finally:
+        dcm.dcm_destroy(ctx)
+    n_total = sum(s.n for s in systems)
+    return {"workload": f"{len(systems)} slabs, N 2e3-2e5 log-uniform (total {n_total}), "
+                        "rc_max U[4,8], cells + forces per evaluation",
+            "n_particles": n_total, "pairs": pairs, "tuned_cell_edge": edge,
+            "graph_fp32_mixed": {"ms": graph_s * 1e3, "pair_rate": pairs / graph_s},
+            "sequential_fp64": {"ms": seq_s * 1e3, "pair_rate": seq_pairs / seq_s}}
 
 
 def cpu_baseline(s, seconds):
@@ -216,6 +293,10 @@ def main():
     if not args.no_fp64 and prec != dcm.DCM_FP64:
         fp64_leg = run_leg(s, dcm.DCM_FP64, max(3, args.steps // 4), 1, dev)
         print(f"[bench] fp64 leg {json.dumps(fp64_leg)}", file=sys.stderr, flush=True)
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(args.steps, dev)
+        print(f"[bench] batched {json.dumps(batched)}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(s, args.cpu_seconds)
@@ -253,6 +334,7 @@ def main():
             "force_evals_per_s": fp64_leg["force_evals"],
             "pair_kernel_ms": fp64_leg["avg_pair_ms"],
             "pair_kernel_tflops": fp64_leg["pair_kernel_tflops"]},
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -210,10 +210,54 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
                     int32_t redetect_every, int64_t step0, double *energy_series,
                     double *delta, double *rc);
 
+/* ---------------------------------------------------------- batched form */
+
+/* One system of a batch: the caller's device arrays and periodic box. */
+typedef struct {
+  const double *x, *y, *z, *rc; /* double [n], caller order; required when n > 0 */
+  double *fx, *fy, *fz;         /* double [n], caller order; required when n > 0 */
+  int32_t *nnbr;                /* int32 [n]; written with DCM_EV_COUNTS if not NULL */
+  double *energy;               /* device scalar; required with DCM_EV_ENERGY */
+  double *virial;               /* device double [6]; required with DCM_EV_VIRIAL */
+  uint64_t *npairs;             /* device scalar; written with DCM_EV_COUNTS if not NULL */
+  int64_t n;                    /* particles, >= 0 */
+  dcm_box box;
+  double cell_edge;             /* as in dcm_build_cells; <= 0: picked by the tuner */
+  double rc_bound;              /* as in dcm_build_cells (<= 0: half the shortest edge) */
+} dcm_system;
+
+/* Linked cells and dynamic-cutoff forces (Sections 2.3-2.4, Algorithm 2.3)
+ * of nsys independent systems in one pass.  For every system the outputs are
+ * those of dcm_build_cells(x, y, z, rc, n, box, cell_edge, rc_bound) followed
+ * by dcm_forces(lj, pair_rule, prec, ev_flags) -- bit for bit when the cell
+ * edge is the same -- but all systems share one launch of each build kernel
+ * and one persistent pair kernel that takes blocks of 256 particles from a
+ * work queue ordered by estimated cost (largest first), so systems of very
+ * different size and cutoff balance across the GPU (the dynamic scheduling
+ * of Section 2.4).
+ * sys: host array of nsys descriptors (nsys = 0 is a no-op).  Systems whose
+ * cell_edge is <= 0 share one edge chosen by timing a few candidates the
+ * first time a batch is seen (this call synchronises the stream); the choice
+ * is kept for later calls with the same descriptors.
+ * use_graph != 0: the first call for a given set of descriptors and
+ * parameters records the launches in a HIP graph; later identical calls
+ * replay it (the arrays' contents may change between calls, their addresses
+ * and sizes may not).  Work is ordered after earlier work on the context's
+ * stream and before later work on it.
+ * Limits: sum of n below 2^24.  Device-detected conditions (non-finite
+ * input or force, cutoffs above rc_bound) as for the single-system calls. */
+dcm_status dcm_forces_batched(dcm_ctx *ctx, int32_t nsys, const dcm_system *sys, dcm_lj lj,
+                              int pair_rule, int prec, int ev_flags, int use_graph);
+
+/* Cell edge the tuner chose for the last batch (0 if none was needed). */
+dcm_status dcm_batched_edge(const dcm_ctx *ctx, double *edge);
+
 /* ------------------------------------------------------------ profiling */
 
 /* Record HIP events around every launch of the named kernel family
- * ("pair", "cells", "detect", "sweep", "cutoffs", "verlet") when enabled. */
+ * ("pair", "cells", "detect", "sweep", "cutoffs", "verlet"; "batch_cells",
+ * "batch_pair" for the batched form, "batch_graph" for a replayed graph)
+ * when enabled. */
 dcm_status dcm_set_profiling(dcm_ctx *ctx, int enable);
 
 /* Synchronise, then return the summed event time (ms) and launch count of a

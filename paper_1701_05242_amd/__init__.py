@@ -61,6 +61,15 @@ class dcm_grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3)]
 
 
+class dcm_system(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("rc", ctypes.c_void_p), ("fx", ctypes.c_void_p), ("fy", ctypes.c_void_p),
+                ("fz", ctypes.c_void_p), ("nnbr", ctypes.c_void_p),
+                ("energy", ctypes.c_void_p), ("virial", ctypes.c_void_p),
+                ("npairs", ctypes.c_void_p), ("n", ctypes.c_int64), ("box", dcm_box),
+                ("cell_edge", ctypes.c_double), ("rc_bound", ctypes.c_double)]
+
+
 class DcmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
@@ -89,6 +98,8 @@ SIGNATURES = {
     "dcm_forces": [_P, dcm_lj, _INT, _INT, _INT, _P, _P, _P, _P, _P, _P, _P],
     "dcm_step": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _F64, dcm_box, dcm_lj, dcm_rule,
                  dcm_grid, _F64, _INT, _INT, _F64, _I32, _I32, _I64, _P, _P, _P],
+    "dcm_forces_batched": [_P, _I32, _P, dcm_lj, _INT, _INT, _INT, _INT],
+    "dcm_batched_edge": [_P, ctypes.POINTER(_F64)],
     "dcm_set_profiling": [_P, _INT],
     "dcm_kernel_time": [_P, ctypes.c_char_p, ctypes.POINTER(_F64), ctypes.POINTER(_I64)],
 }
@@ -274,6 +285,52 @@ def dcm_step(ctx, x, y, z, vx, vy, vz, fx, fy, fz, box, lj: dcm_lj, rule: dcm_ru
         _ptr(energy_series, f64, "energy_series", 2 * max(int(nsteps), 0)),
         _ptr(delta, f64, "delta", n), _ptr(rc, f64, "rc", n))
     _check(ctx, code)
+
+
+def make_systems(systems) -> "ctypes.Array":
+    """Descriptor array for dcm_forces_batched from a sequence of dicts with
+    keys x, y, z, rc, fx, fy, fz (float64 [n] device tensors), box, and
+    optionally nnbr (int32 [n]), energy (float64 [1]), virial (float64 [6]),
+    npairs (uint64 [1]), cell_edge and rc_bound (floats, default 0).  Keep the
+    tensors alive while the array is in use."""
+    arr = (dcm_system * max(len(systems), 1))()
+    f64 = torch.float64
+    for b, d in enumerate(systems):
+        n = d["x"].numel()
+        s = arr[b]
+        for k in ("x", "y", "z", "rc", "fx", "fy", "fz"):
+            p = _ptr(d[k], f64, f"systems[{b}].{k}", n)
+            setattr(s, k, p.value if p is not None else None)
+        for k, dt, m in (("nnbr", torch.int32, n), ("energy", f64, 1), ("virial", f64, 6),
+                         ("npairs", torch.uint64, 1)):
+            p = _ptr(d.get(k), dt, f"systems[{b}].{k}", m)
+            setattr(s, k, p.value if p is not None else None)
+        s.n = n
+        s.box = _box(d["box"])
+        s.cell_edge = float(d.get("cell_edge", 0.0))
+        s.rc_bound = float(d.get("rc_bound", 0.0))
+    return arr
+
+
+def dcm_forces_batched(ctx, systems, lj: dcm_lj, pair_rule: int = DCM_PAIR_OWN,
+                       prec: int = DCM_FP64, ev_flags: int = 0, use_graph: bool = False):
+    """systems: a sequence of dicts (see make_systems) or a descriptor array
+    made by make_systems (reuse it to replay a recorded graph)."""
+    if isinstance(systems, ctypes.Array):
+        arr, nsys = systems, len(systems)
+    else:
+        arr, nsys = make_systems(systems), len(systems)
+    code = load_library().dcm_forces_batched(
+        ctx, int(nsys), ctypes.cast(arr, ctypes.c_void_p), lj, int(pair_rule), int(prec),
+        int(ev_flags), 1 if use_graph else 0)
+    _check(ctx, code)
+    return arr
+
+
+def dcm_batched_edge(ctx) -> float:
+    e = ctypes.c_double()
+    _check(ctx, load_library().dcm_batched_edge(ctx, ctypes.byref(e)))
+    return float(e.value)
 
 
 def dcm_set_profiling(ctx, enable: bool) -> None:

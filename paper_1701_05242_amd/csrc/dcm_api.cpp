@@ -172,6 +172,7 @@ dcm_status dcm_destroy(dcm_ctx *ctx) {
                     &ctx->ws_owner[1]};
   for (DevBuf *b : bufs)
     if (b->p) hipFree(b->p);
+  batch_free(ctx);
   for (auto &kv : ctx->timers)
     for (auto &pr : kv.second.pending) {
       hipEventDestroy(pr.first);

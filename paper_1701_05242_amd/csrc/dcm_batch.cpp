@@ -1,0 +1,442 @@
+// Host side of dcm_forces_batched: the plan (per-system cell geometry, the
+// concatenated layout, block tables and the cost-ordered work queue), the
+// cell-edge tuner, and the HIP graph that replays a recorded batch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "dcm_internal.hpp"
+
+namespace dcm {
+
+namespace {
+
+constexpr int kItem = 256;  // particles per work item = pair kernel block
+// cell edges the tuner tries for systems that leave the edge to the library
+constexpr double kTuneEdges[] = {1.0, 1.15, 1.3, 1.5};
+
+template <typename T>
+T *dptr(const DevBuf &b, size_t byte_off = 0) {
+  return reinterpret_cast<T *>(static_cast<char *>(b.p) + byte_off);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct BatchState {
+  // descriptors of the batch the plan was made for
+  std::vector<dcm_system> desc;
+  bool have_plan = false;
+  double plan_edge = 0.0;  // edge used for systems with cell_edge <= 0
+  bool tuned = false;
+  double tuned_edge = 0.0;
+  bool needs_tuning = false;
+  // plan
+  std::vector<SysGeom> geo;
+  std::vector<int2> items;  // natural order: system-major, also the particle block table
+  std::vector<int2> eblk;
+  std::vector<int32_t> queue;
+  int64_t n_total = 0, cells_total = 0, ext_cells_total = 0, ext_cap = 0;
+  size_t off_geo = 0, off_items = 0, off_eblk = 0, off_queue = 0, table_bytes = 0;
+  std::vector<unsigned char> table_host;
+  // device memory
+  DevBuf tables, cell_of, cell_count, cell_fill, cell_start, perm, sorted, scan_tmp, ext_count,
+      ext_start, ext_pos, partials, rcmax, head;
+  // recorded graph
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<unsigned char> graph_key;
+
+  void drop_graph() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    graph_key.clear();
+  }
+};
+
+namespace {
+
+bool same_desc(const std::vector<dcm_system> &a, int32_t nsys, const dcm_system *b) {
+  return (int64_t)a.size() == nsys &&
+         (nsys == 0 || std::memcmp(a.data(), b, sizeof(dcm_system) * nsys) == 0);
+}
+
+dcm_status check_system(dcm_ctx *ctx, const dcm_system &s, int32_t b, int ev_flags) {
+  auto bad = [&](const char *what) {
+    return fail(ctx, DCM_ERR_INVALID,
+                std::string("dcm_forces_batched: system ") + std::to_string(b) + ": " + what);
+  };
+  if (s.n < 0) return bad("particle count must be >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(s.box.L[a]) || !(s.box.L[a] > 0.0)) return bad("box lengths must be > 0");
+  if (!std::isfinite(s.cell_edge)) return bad("cell_edge must be finite");
+  if (!std::isfinite(s.rc_bound)) return bad("rc_bound must be finite");
+  if (s.n > 0 && (!s.x || !s.y || !s.z || !s.rc || !s.fx || !s.fy || !s.fz))
+    return bad("null array");
+  if ((ev_flags & DCM_EV_ENERGY) && !s.energy) return bad("energy requested without a pointer");
+  if ((ev_flags & DCM_EV_VIRIAL) && !s.virial) return bad("virial requested without a pointer");
+  return DCM_OK;
+}
+
+// Cell geometry, concatenated layout, block tables and work queue for the
+// batch, with `edge` for the systems that leave the cell edge to the tuner.
+dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
+  const int32_t nsys = (int32_t)B.desc.size();
+  B.geo.assign(nsys, SysGeom{});
+  B.items.clear();
+  B.eblk.clear();
+  std::vector<double> cost_pp(nsys, 0.0);
+  int64_t p0 = 0, cell0 = 0, ext_cell0 = 0;
+  double ext_bound = 0.0;
+  for (int32_t b = 0; b < nsys; ++b) {
+    const dcm_system &d = B.desc[b];
+    SysGeom &g = B.geo[b];
+    g.x = d.x;
+    g.y = d.y;
+    g.z = d.z;
+    g.rc = d.rc;
+    g.fx = d.fx;
+    g.fy = d.fy;
+    g.fz = d.fz;
+    g.nnbr = d.nnbr;
+    g.energy = d.energy;
+    g.virial = d.virial;
+    g.npairs = d.npairs;
+    g.n = d.n;
+    const double e = d.cell_edge > 0.0 ? d.cell_edge : edge;
+    const double half = 0.5 * std::min(d.box.L[0], std::min(d.box.L[1], d.box.L[2]));
+    const double below_half = std::nextafter(half, 0.0);
+    g.rc_cap = d.rc_bound > 0.0 ? std::min(d.rc_bound, below_half) : below_half;
+    int64_t cells = 1, next = 1;
+    double mult = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      double k = std::floor(d.box.L[a] / e);
+      if (k < 1.0) k = 1.0;
+      if (k > 65536.0)
+        return fail(ctx, DCM_ERR_RANGE, "dcm_forces_batched: more than 65536 cells along an axis");
+      g.nc[a] = (int32_t)k;
+      g.L[a] = d.box.L[a];
+      g.len[a] = d.box.L[a] / (double)g.nc[a];
+      g.sc[a] = (double)g.nc[a] / d.box.L[a];
+      g.h[a] = (int32_t)std::ceil(g.rc_cap / g.len[a]) + 1;
+      g.ne[a] = g.nc[a] + 2 * g.h[a];
+      cells *= g.nc[a];
+      next *= g.ne[a];
+      // copies of one real cell in the extended grid along this axis
+      mult *= std::ceil((double)g.ne[a] / (double)g.nc[a]);
+      if (cells >= (int64_t(1) << 30) || next >= (int64_t(1) << 30))
+        return fail(ctx, DCM_ERR_RANGE, "dcm_forces_batched: too many cells");
+    }
+    g.p0 = p0;
+    g.cell0 = cell0;
+    g.ext_cell0 = ext_cell0;
+    g.item0 = (int64_t)B.items.size();
+    g.nitems = (d.n + kItem - 1) / kItem;
+    for (int64_t k = 0; k < g.nitems; ++k) B.items.push_back(make_int2(b, (int)(k * kItem)));
+    for (int64_t k = 0; k < next; k += 256) B.eblk.push_back(make_int2(b, (int)k));
+    p0 += d.n;
+    cell0 += cells;
+    ext_cell0 += next;
+    ext_bound += mult * (double)d.n;
+    // candidates per particle grow with the density and the search volume
+    const double vol = d.box.L[0] * d.box.L[1] * d.box.L[2];
+    cost_pp[b] = ((double)d.n / vol) * g.rc_cap * g.rc_cap * g.rc_cap;
+    if (p0 >= (int64_t(1) << 24))
+      return fail(ctx, DCM_ERR_RANGE, "dcm_forces_batched: 2^24 or more particles in total");
+    if (cell0 >= (int64_t(1) << 30) || ext_cell0 >= (int64_t(1) << 30))
+      return fail(ctx, DCM_ERR_RANGE, "dcm_forces_batched: too many cells");
+  }
+  if (ext_bound >= 2147483000.0)
+    return fail(ctx, DCM_ERR_RANGE, "dcm_forces_batched: ghost-extended batch too large");
+  B.n_total = p0;
+  B.cells_total = cell0;
+  B.ext_cells_total = ext_cell0;
+  // the most ghost copies any arrangement of the particles can need
+  B.ext_cap = std::max<int64_t>((int64_t)ext_bound, 1);
+  // work queue: largest estimated cost first, ties in natural order
+  const int64_t nitems = (int64_t)B.items.size();
+  std::vector<double> cost(nitems);
+  for (int64_t k = 0; k < nitems; ++k) {
+    const int b = B.items[k].x;
+    const int64_t cnt = std::min<int64_t>(kItem, B.desc[b].n - B.items[k].y);
+    cost[k] = cost_pp[b] * (double)cnt;
+  }
+  B.queue.resize(nitems);
+  std::iota(B.queue.begin(), B.queue.end(), 0);
+  std::stable_sort(B.queue.begin(), B.queue.end(),
+                   [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  // device tables, uploaded once per plan
+  B.off_geo = 0;
+  B.off_items = align256(sizeof(SysGeom) * nsys);
+  B.off_eblk = B.off_items + align256(sizeof(int2) * std::max<int64_t>(nitems, 1));
+  B.off_queue = B.off_eblk + align256(sizeof(int2) * std::max<size_t>(B.eblk.size(), 1));
+  B.table_bytes = B.off_queue + align256(sizeof(int32_t) * std::max<int64_t>(nitems, 1));
+  B.table_host.assign(B.table_bytes, 0);
+  std::memcpy(B.table_host.data() + B.off_geo, B.geo.data(), sizeof(SysGeom) * nsys);
+  if (nitems) {
+    std::memcpy(B.table_host.data() + B.off_items, B.items.data(), sizeof(int2) * nitems);
+    std::memcpy(B.table_host.data() + B.off_queue, B.queue.data(), sizeof(int32_t) * nitems);
+  }
+  if (!B.eblk.empty())
+    std::memcpy(B.table_host.data() + B.off_eblk, B.eblk.data(), sizeof(int2) * B.eblk.size());
+  // growing a buffer moves it: a recorded graph would hold stale addresses
+  B.drop_graph();
+  dcm_status st;
+  if ((st = ensure(ctx, B.tables, B.table_bytes)) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.cell_of, sizeof(int32_t) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
+    return st;
+  if ((st = ensure(ctx, B.cell_count, sizeof(int32_t) * B.cells_total)) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.cell_fill, sizeof(int32_t) * B.cells_total)) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.cell_start, sizeof(int32_t) * (B.cells_total + 1))) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.perm, sizeof(int32_t) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
+    return st;
+  if ((st = ensure(ctx, B.sorted, sizeof(double4) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
+    return st;
+  if ((st = ensure(ctx, B.scan_tmp,
+                   sizeof(int32_t) * scan_tmp_elems(std::max(B.cells_total, B.ext_cells_total)))) !=
+      DCM_OK)
+    return st;
+  if ((st = ensure(ctx, B.ext_count, sizeof(int32_t) * B.ext_cells_total)) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.ext_start, sizeof(int32_t) * (B.ext_cells_total + 1))) != DCM_OK)
+    return st;
+  if ((st = ensure(ctx, B.ext_pos, sizeof(double4) * B.ext_cap)) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.partials,
+                   sizeof(double) * kPartialSlots * std::max<int64_t>(nitems, 1))) != DCM_OK)
+    return st;
+  if ((st = ensure(ctx, B.rcmax, sizeof(unsigned long long) * nsys)) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.head, sizeof(uint32_t))) != DCM_OK) return st;
+  // plans change rarely: a synchronous upload keeps the host copy free to
+  // change as soon as this returns
+  if (hipMemcpyAsync(B.tables.p, B.table_host.data(), B.table_bytes, hipMemcpyHostToDevice,
+                     ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: table upload failed");
+  B.have_plan = true;
+  B.plan_edge = edge;
+  return DCM_OK;
+}
+
+// Enqueue the whole batch on stream s (no allocation, no host sync).
+void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, int prec,
+             int ev_flags, bool timed) {
+  const int32_t nsys = (int32_t)B.desc.size();
+  const SysGeom *geo = dptr<SysGeom>(B.tables, B.off_geo);
+  const int2 *items = dptr<int2>(B.tables, B.off_items);
+  const int2 *eblk = dptr<int2>(B.tables, B.off_eblk);
+  const int32_t *queue = dptr<int32_t>(B.tables, B.off_queue);
+  const int64_t nitems = (int64_t)B.items.size();
+  hipEvent_t ev = nullptr;
+  if (timed) timer_begin(ctx, "batch_cells", &ev);
+  launch_fill_i32(s, dptr<int32_t>(B.cell_count), 0, B.cells_total);
+  launch_fill_i32(s, dptr<int32_t>(B.cell_fill), 0, B.cells_total);
+  launch_fill_u64(s, dptr<unsigned long long>(B.rcmax), 0ull, nsys);
+  launch_fill_u32(s, dptr<uint32_t>(B.head), 0u, 1);
+  launch_batch_cell_count(s, geo, items, nitems, dptr<int32_t>(B.cell_of),
+                          dptr<int32_t>(B.cell_count), dptr<unsigned long long>(B.rcmax),
+                          ctx->d_status);
+  launch_exclusive_scan(s, dptr<int32_t>(B.cell_count), dptr<int32_t>(B.cell_start),
+                        B.cells_total, dptr<int32_t>(B.scan_tmp));
+  launch_batch_cell_scatter(s, geo, items, nitems, dptr<int32_t>(B.cell_of),
+                            dptr<int32_t>(B.cell_start), dptr<int32_t>(B.cell_fill),
+                            dptr<int32_t>(B.perm));
+  launch_cell_sort(s, dptr<int32_t>(B.cell_start), B.cells_total, dptr<int32_t>(B.perm));
+  launch_batch_gather(s, geo, items, nitems, dptr<int32_t>(B.perm), dptr<double4>(B.sorted));
+  launch_batch_ext(s, geo, eblk, (int64_t)B.eblk.size(), dptr<int32_t>(B.cell_start),
+                   dptr<double4>(B.sorted), B.ext_cells_total, B.ext_cap,
+                   dptr<int32_t>(B.ext_count), dptr<int32_t>(B.ext_start),
+                   dptr<int32_t>(B.scan_tmp), dptr<double4>(B.ext_pos), ctx->d_status);
+  if (timed) timer_end(ctx, "batch_cells", ev);
+  BatchPairArgs a;
+  a.sys = geo;
+  a.items = items;
+  a.queue = queue;
+  a.nitems = (int32_t)nitems;
+  a.head = dptr<uint32_t>(B.head);
+  a.pos = dptr<double4>(B.sorted);
+  a.cell_start = dptr<int32_t>(B.cell_start);
+  a.perm = dptr<int32_t>(B.perm);
+  a.ext_pos = dptr<double4>(B.ext_pos);
+  a.ext_start = dptr<int32_t>(B.ext_start);
+  a.ext_cap = B.ext_cap;
+  a.rc_max_bits = dptr<unsigned long long>(B.rcmax);
+  a.eps = lj.epsilon;
+  a.sigma = lj.sigma;
+  a.ev_flags = ev_flags;
+  a.partials = dptr<double>(B.partials);
+  a.status = ctx->d_status;
+  if (timed) timer_begin(ctx, "batch_pair", &ev);
+  launch_pair_batched(s, a, rule, prec);
+  launch_batch_reduce(s, geo, nsys, dptr<double>(B.partials), ev_flags);
+  if (timed) timer_end(ctx, "batch_pair", ev);
+}
+
+// Time the batch at each candidate edge (second of two runs) and keep the
+// fastest.  Synchronises the stream.
+dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int ev_flags) {
+  double best_ms = 0.0, best_edge = kTuneEdges[0];
+  bool first = true;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(ctx, DCM_ERR_HIP, "event create failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(ctx, DCM_ERR_HIP, "event create failed");
+  }
+  dcm_status st = DCM_OK;
+  for (double edge : kTuneEdges) {
+    if ((st = make_plan(ctx, B, edge)) != DCM_OK) break;
+    enqueue(ctx, B, ctx->stream, lj, rule, prec, ev_flags, false);
+    hipEventRecord(e0, ctx->stream);
+    enqueue(ctx, B, ctx->stream, lj, rule, prec, ev_flags, false);
+    hipEventRecord(e1, ctx->stream);
+    if ((st = check_launch(ctx, "dcm_forces_batched (tuning)")) != DCM_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      st = fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: tuning run failed");
+      break;
+    }
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (first || ms < best_ms) {
+      best_ms = ms;
+      best_edge = edge;
+      first = false;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != DCM_OK) return st;
+  B.tuned = true;
+  B.tuned_edge = best_edge;
+  return DCM_OK;
+}
+
+std::vector<unsigned char> graph_key(const BatchState &B, dcm_lj lj, int rule, int prec,
+                                     int ev_flags) {
+  std::vector<unsigned char> k(sizeof(dcm_system) * B.desc.size() + 64);
+  std::memcpy(k.data(), B.desc.data(), sizeof(dcm_system) * B.desc.size());
+  unsigned char *t = k.data() + sizeof(dcm_system) * B.desc.size();
+  std::memcpy(t, &lj, sizeof(lj));
+  std::memcpy(t + 16, &rule, sizeof(int));
+  std::memcpy(t + 20, &prec, sizeof(int));
+  std::memcpy(t + 24, &ev_flags, sizeof(int));
+  std::memcpy(t + 28, &B.plan_edge, sizeof(double));
+  return k;
+}
+
+}  // namespace
+
+void batch_free(dcm_ctx *ctx) {
+  BatchState *B = ctx->batch;
+  if (!B) return;
+  B->drop_graph();
+  DevBuf *bufs[] = {&B->tables,    &B->cell_of,   &B->cell_count, &B->cell_fill, &B->cell_start,
+                    &B->perm,      &B->sorted,    &B->scan_tmp,   &B->ext_count, &B->ext_start,
+                    &B->ext_pos,   &B->partials,  &B->rcmax,      &B->head};
+  for (DevBuf *b : bufs)
+    if (b->p) hipFree(b->p);
+  if (B->cap) hipStreamDestroy(B->cap);
+  delete B;
+  ctx->batch = nullptr;
+}
+
+}  // namespace dcm
+
+using namespace dcm;
+
+extern "C" {
+
+dcm_status dcm_forces_batched(dcm_ctx *ctx, int32_t nsys, const dcm_system *sys, dcm_lj lj,
+                              int pair_rule, int prec, int ev_flags, int use_graph) {
+  if (!ctx) return DCM_ERR_INVALID;
+  if (nsys < 0) return fail(ctx, DCM_ERR_INVALID, "dcm_forces_batched: nsys must be >= 0");
+  if (nsys > 0 && !sys) return fail(ctx, DCM_ERR_INVALID, "dcm_forces_batched: null systems");
+  if (pair_rule != DCM_PAIR_OWN && pair_rule != DCM_PAIR_MAX)
+    return fail(ctx, DCM_ERR_INVALID, "unknown pair rule");
+  if (prec != DCM_FP64 && prec != DCM_FP32_MIXED)
+    return fail(ctx, DCM_ERR_INVALID, "unknown precision");
+  if (!std::isfinite(lj.epsilon) || !(lj.epsilon > 0.0) || !std::isfinite(lj.sigma) ||
+      !(lj.sigma > 0.0))
+    return fail(ctx, DCM_ERR_INVALID, "LJ epsilon and sigma must be > 0");
+  if (nsys == 0) return DCM_OK;
+  for (int32_t b = 0; b < nsys; ++b) {
+    dcm_status st = check_system(ctx, sys[b], b, ev_flags);
+    if (st != DCM_OK) return st;
+  }
+  if (!ctx->batch) {
+    ctx->batch = new (std::nothrow) BatchState();
+    if (!ctx->batch) return DCM_ERR_NOMEM;
+  }
+  BatchState &B = *ctx->batch;
+  dcm_status st;
+  if (!same_desc(B.desc, nsys, sys)) {
+    B.desc.assign(sys, sys + nsys);
+    B.have_plan = false;
+    B.tuned = false;
+    B.drop_graph();
+    B.needs_tuning = false;
+    for (int32_t b = 0; b < nsys; ++b)
+      if (!(sys[b].cell_edge > 0.0)) B.needs_tuning = true;
+  }
+  if (B.needs_tuning && !B.tuned) {
+    if ((st = tune(ctx, B, lj, pair_rule, prec, ev_flags)) != DCM_OK) {
+      B.have_plan = false;
+      return st;
+    }
+  }
+  const double edge = B.needs_tuning ? B.tuned_edge : 0.0;
+  if (!B.have_plan || B.plan_edge != edge) {
+    if ((st = make_plan(ctx, B, edge)) != DCM_OK) {
+      B.have_plan = false;
+      return st;
+    }
+  }
+  if (!use_graph) {
+    enqueue(ctx, B, ctx->stream, lj, pair_rule, prec, ev_flags, ctx->profile);
+    return check_launch(ctx, "dcm_forces_batched");
+  }
+  std::vector<unsigned char> key = graph_key(B, lj, pair_rule, prec, ev_flags);
+  if (!B.exec || key != B.graph_key) {
+    B.drop_graph();
+    if (!B.cap && hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking) != hipSuccess) {
+      B.cap = nullptr;
+      return fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: stream create failed");
+    }
+    // recorded on a stream of our own (the context's stream may be the
+    // default stream, which cannot be captured), replayed on the context's
+    if (hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: begin capture failed");
+    enqueue(ctx, B, B.cap, lj, pair_rule, prec, ev_flags, false);
+    hipError_t ce = hipStreamEndCapture(B.cap, &B.graph);
+    if (ce != hipSuccess || !B.graph) {
+      hipGetLastError();
+      B.graph = nullptr;
+      return fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: capture failed");
+    }
+    if (hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGetLastError();
+      B.drop_graph();
+      return fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: graph instantiation failed");
+    }
+    B.graph_key = key;
+  }
+  hipEvent_t ev = nullptr;
+  timer_begin(ctx, "batch_graph", &ev);
+  if (hipGraphLaunch(B.exec, ctx->stream) != hipSuccess) {
+    hipGetLastError();
+    return fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: graph launch failed");
+  }
+  timer_end(ctx, "batch_graph", ev);
+  return check_launch(ctx, "dcm_forces_batched");
+}
+
+dcm_status dcm_batched_edge(const dcm_ctx *ctx, double *edge) {
+  if (!ctx || !edge) return DCM_ERR_INVALID;
+  *edge = (ctx->batch && ctx->batch->needs_tuning) ? ctx->batch->tuned_edge : 0.0;
+  return DCM_OK;
+}
+
+}  // extern "C"

@@ -39,6 +39,33 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
+// Ghost-extended cell grid: the cell grid grown by h[a] cells on both sides
+// of every axis.  Extended cell (ex, ey, ez) holds a copy of real cell
+// (ex - h[0], ey - h[1], ez - h[2]) wrapped into the box, with positions
+// shifted by the matching multiple of the box length.
+struct ExtGeom {
+  int nc[3];
+  int h[3];
+  int ne[3];
+  double L[3];
+};
+
+// Real cell rc behind extended cell e, and the periods p[a] crossed.
+__device__ __forceinline__ void ext_to_real(const ExtGeom &g, int64_t e, int &rc, int p[3]) {
+  const int ex = (int)(e % g.ne[0]);
+  const int64_t t = e / g.ne[0];
+  const int ey = (int)(t % g.ne[1]);
+  const int ez = (int)(t / g.ne[1]);
+  const int u[3] = {ex - g.h[0], ey - g.h[1], ez - g.h[2]};
+  int r[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = wrap_index(u[a], g.nc[a]);
+    p[a] = (u[a] - r[a]) / g.nc[a];  // periods crossed: exact division
+  }
+  rc = (r[2] * g.nc[1] + r[1]) * g.nc[0] + r[0];
+}
+
 // MI355X has 8 XCDs, each with its own L2; consecutive workgroups are
 // dispatched round-robin across them.  xcd_block(b, n, G) remaps workgroup b
 // so that each XCD receives runs of G consecutive logical blocks (spatially

@@ -60,6 +60,28 @@ struct Timer {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
 };
 
+// One system of a batch as the device sees it: the caller's arrays, its
+// slices of the concatenated particle, cell and extended-cell orders, and
+// its cell geometry.
+struct SysGeom {
+  const double *x, *y, *z, *rc;
+  double *fx, *fy, *fz;
+  int32_t *nnbr;
+  double *energy, *virial;
+  uint64_t *npairs;
+  int64_t n;
+  int64_t p0;         // first slot of the system in the concatenated particle order
+  int64_t cell0;      // first real cell
+  int64_t ext_cell0;  // first extended cell
+  int64_t item0;      // first pair work item (blocks of 256 particles)
+  int64_t nitems;
+  int32_t nc[3], h[3], ne[3];
+  double len[3], sc[3], L[3];
+  double rc_cap;
+};
+
+struct BatchState;  // dcm_batch.cpp
+
 }  // namespace dcm
 
 struct dcm_ctx {
@@ -92,6 +114,8 @@ struct dcm_ctx {
   // last distance field kept for dcm_step
   bool have_field = false;
   int32_t field_n[3] = {0, 0, 0};
+  // batched form: plan, buffers and recorded graph
+  dcm::BatchState *batch = nullptr;
   // profiling
   bool profile = false;
   std::map<std::string, dcm::Timer> timers;
@@ -105,6 +129,7 @@ dcm_status ensure(dcm_ctx *ctx, DevBuf &b, size_t bytes);
 dcm_status check_launch(dcm_ctx *ctx, const char *what);
 void timer_begin(dcm_ctx *ctx, const char *family, hipEvent_t *ev);
 void timer_end(dcm_ctx *ctx, const char *family, hipEvent_t ev);
+void batch_free(dcm_ctx *ctx);  // dcm_batch.cpp
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -194,6 +219,45 @@ struct PairArgs {
 };
 int pair_block_size();
 void launch_pair(hipStream_t s, const PairArgs &a, int rule, int prec);
+
+struct BatchPairArgs {
+  const SysGeom *sys;
+  const int2 *items;          // work item -> (system, first local particle)
+  const int32_t *queue;       // items in the order they are handed out
+  int32_t nitems;
+  uint32_t *head;             // queue position, zero before the launch
+  const double4 *pos;         // sorted particles, concatenated
+  const int32_t *cell_start;  // concatenated real cells
+  const int32_t *perm;        // sorted slot -> concatenated particle id
+  const double4 *ext_pos;
+  const int32_t *ext_start;   // concatenated extended cells
+  int64_t ext_cap;
+  const unsigned long long *rc_max_bits;  // per system
+  double eps, sigma;
+  int ev_flags;
+  double *partials;           // [nitems * kPartialSlots], by item
+  uint32_t *status;
+};
+void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int prec);
+
+// k_batch.hip: build kernels of the batched form.  pblk holds one (system,
+// first local particle) entry per block of 256 particles, eblk one (system,
+// first local extended cell) entry per block of 256 extended cells.
+void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
+                             int32_t *cell_of, int32_t *cell_count,
+                             unsigned long long *rc_max_bits, uint32_t *status);
+void launch_batch_cell_scatter(hipStream_t s, const SysGeom *sys, const int2 *pblk,
+                               int64_t npblk, const int32_t *cell_of, const int32_t *cell_start,
+                               int32_t *cell_fill, int32_t *perm);
+void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
+                         const int32_t *perm, double4 *sorted);
+void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64_t neblk,
+                      const int32_t *cell_start, const double4 *sorted, int64_t next_total,
+                      int64_t ext_cap, int32_t *ext_count, int32_t *ext_start, int32_t *scan_tmp,
+                      double4 *ext_pos, uint32_t *status);
+void launch_batch_reduce(hipStream_t s, const SysGeom *sys, int32_t nsys,
+                         const double *partials, int ev_flags);
+void launch_fill_u64(hipStream_t s, unsigned long long *p, unsigned long long v, int64_t n);
 void launch_reduce_partials(hipStream_t s, const double *partials, int64_t blocks, double eps,
                             int ev_flags, double *energy, double *virial, uint64_t *npairs);
 

@@ -1,0 +1,238 @@
+// Build kernels of the batched form: linked cells (Section 2.3) and ghost
+// images for many independent systems, one launch per stage.  The systems'
+// particles, cells and extended cells are concatenated in system order, so a
+// single exclusive scan over all cells yields every system's cell starts and
+// keeps each system's sorted particles in its own contiguous slice.  A block
+// of 256 threads always works inside one system: the host lists one
+// (system, first index) entry per block.
+#include "dcm_device.hpp"
+#include "dcm_internal.hpp"
+
+namespace dcm {
+
+constexpr int kBatchBlock = 256;
+
+__device__ __forceinline__ int block_system(const int2 *tab, int64_t &first) {
+  const int2 w = tab[blockIdx.x];
+  first = __builtin_amdgcn_readfirstlane(w.y);
+  return __builtin_amdgcn_readfirstlane(w.x);
+}
+
+__device__ __forceinline__ ExtGeom ext_geom(const SysGeom &g) {
+  ExtGeom e;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    e.nc[a] = g.nc[a];
+    e.h[a] = g.h[a];
+    e.ne[a] = g.ne[a];
+    e.L[a] = g.L[a];
+  }
+  return e;
+}
+
+// Cell of every particle (concatenated cell index), per-cell counts, and the
+// largest cutoff of each system.
+__global__ __launch_bounds__(kBatchBlock) void kb_cell_count(
+    const SysGeom *__restrict__ sys, const int2 *__restrict__ pblk, int32_t *__restrict__ cell_of,
+    int32_t *count, unsigned long long *rc_max_bits, uint32_t *status) {
+  int64_t first;
+  const int b = block_system(pblk, first);
+  const SysGeom &g = sys[b];
+  const int64_t i = first + threadIdx.x;
+  const bool valid = i < g.n;
+  int c = 0;
+  unsigned long long bits = 0;
+  if (valid) {
+    const double px = g.x[i], py = g.y[i], pz = g.z[i];
+    double r = g.rc[i];
+    int lc = 0;
+    if (finite3(px, py, pz)) {
+      const int cx = slab_index(wrap_coord(px, g.L[0]), g.sc[0], g.nc[0]);
+      const int cy = slab_index(wrap_coord(py, g.L[1]), g.sc[1], g.nc[1]);
+      const int cz = slab_index(wrap_coord(pz, g.L[2]), g.sc[2], g.nc[2]);
+      lc = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+    } else {
+      atomicOr(status, ST_NONFINITE_POS);
+    }
+    if (!(r >= 0.0) || r > g.rc_cap) {
+      atomicOr(status, ST_RC_RANGE);
+      r = (r > g.rc_cap) ? g.rc_cap : 0.0;
+    }
+    bits = (unsigned long long)__double_as_longlong(r);
+    c = (int)g.cell0 + lc;
+    cell_of[g.p0 + i] = c;
+  }
+  wave_aggregated_add(count, (uint32_t)c, valid);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(bits, off, 64);
+    bits = o > bits ? o : bits;
+  }
+  if ((threadIdx.x & 63) == 0 && bits > *(volatile unsigned long long *)&rc_max_bits[b])
+    atomicMax(&rc_max_bits[b], bits);
+}
+
+// Slot of every particle inside its cell; perm[slot] = concatenated id.
+__global__ __launch_bounds__(kBatchBlock) void kb_cell_scatter(
+    const SysGeom *__restrict__ sys, const int2 *__restrict__ pblk,
+    const int32_t *__restrict__ cell_of, const int32_t *__restrict__ cell_start, int32_t *fill,
+    int32_t *__restrict__ perm) {
+  int64_t first;
+  const int b = block_system(pblk, first);
+  const SysGeom &g = sys[b];
+  const int64_t i = first + threadIdx.x;
+  const bool valid = i < g.n;
+  const int c = valid ? cell_of[g.p0 + i] : 0;
+  const int slot = wave_aggregated_slot(fill, (uint32_t)c, valid);
+  if (valid) perm[cell_start[c] + slot] = (int32_t)(g.p0 + i);
+}
+
+// Sorted copy (x, y, z, rc) with positions wrapped into each system's box.
+__global__ __launch_bounds__(kBatchBlock) void kb_gather(const SysGeom *__restrict__ sys,
+                                                         const int2 *__restrict__ pblk,
+                                                         const int32_t *__restrict__ perm,
+                                                         double4 *__restrict__ sorted) {
+  int64_t first;
+  const int b = block_system(pblk, first);
+  const SysGeom &g = sys[b];
+  const int64_t k = first + threadIdx.x;
+  if (k >= g.n) return;
+  const int64_t s = g.p0 + k;
+  const int64_t i = perm[s] - g.p0;
+  const double px = g.x[i], py = g.y[i], pz = g.z[i];
+  double4 o;
+  if (finite3(px, py, pz)) {
+    o.x = wrap_coord(px, g.L[0]);
+    o.y = wrap_coord(py, g.L[1]);
+    o.z = wrap_coord(pz, g.L[2]);
+  } else {
+    o.x = o.y = o.z = 0.0;
+  }
+  const double r = g.rc[i];
+  o.w = (r >= 0.0) ? (r < g.rc_cap ? r : g.rc_cap) : 0.0;  // NaN -> 0
+  sorted[s] = o;
+}
+
+__device__ __forceinline__ int64_t ext_cells_of(const SysGeom &g) {
+  return (int64_t)g.ne[0] * g.ne[1] * g.ne[2];
+}
+
+__global__ __launch_bounds__(kBatchBlock) void kb_ext_count(const SysGeom *__restrict__ sys,
+                                                            const int2 *__restrict__ eblk,
+                                                            const int32_t *__restrict__ cell_start,
+                                                            int32_t *__restrict__ ext_count) {
+  int64_t first;
+  const int b = block_system(eblk, first);
+  const SysGeom &g = sys[b];
+  const int64_t e = first + threadIdx.x;
+  if (e >= ext_cells_of(g)) return;
+  int rc, p[3];
+  ext_to_real(ext_geom(g), e, rc, p);
+  const int64_t c = g.cell0 + rc;
+  ext_count[g.ext_cell0 + e] = cell_start[c + 1] - cell_start[c];
+}
+
+// Writes stop at the buffer's capacity; running past it flags an overflow.
+__global__ __launch_bounds__(kBatchBlock) void kb_ext_fill(
+    const SysGeom *__restrict__ sys, const int2 *__restrict__ eblk,
+    const int32_t *__restrict__ cell_start, const int32_t *__restrict__ ext_start,
+    const double4 *__restrict__ sorted, int64_t cap, double4 *__restrict__ ext_pos,
+    uint32_t *status) {
+  int64_t first;
+  const int b = block_system(eblk, first);
+  const SysGeom &g = sys[b];
+  const int64_t e = first + threadIdx.x;
+  if (e >= ext_cells_of(g)) return;
+  int rc, p[3];
+  ext_to_real(ext_geom(g), e, rc, p);
+  const double sx = (double)p[0] * g.L[0], sy = (double)p[1] * g.L[1], sz = (double)p[2] * g.L[2];
+  const int64_t c = g.cell0 + rc;
+  const int a0 = cell_start[c], a1 = cell_start[c + 1];
+  int64_t o = ext_start[g.ext_cell0 + e];
+  if (o + (a1 - a0) > cap) {
+    atomicOr(status, ST_GHOST_OVERFLOW);
+    return;
+  }
+  for (int k = a0; k < a1; ++k, ++o) {
+    double4 q = sorted[k];
+    q.x = q.x + sx;
+    q.y = q.y + sy;
+    q.z = q.z + sz;
+    ext_pos[o] = q;
+  }
+}
+
+// One workgroup per system sums the system's work-item partials in a fixed
+// order (the same order as the single-system reduction over its blocks).
+__global__ __launch_bounds__(256) void kb_reduce(const SysGeom *__restrict__ sys,
+                                                 const double *__restrict__ partials,
+                                                 int ev_flags) {
+  const SysGeom &g = sys[blockIdx.x];
+  __shared__ double red[4][kPartialSlots];
+  double v[kPartialSlots];
+#pragma unroll
+  for (int k = 0; k < kPartialSlots; ++k) v[k] = 0.0;
+  const double *p = partials + g.item0 * kPartialSlots;
+  for (int64_t t = threadIdx.x; t < g.nitems; t += 256)
+#pragma unroll
+    for (int k = 0; k < kPartialSlots; ++k) v[k] += p[t * kPartialSlots + k];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kPartialSlots; ++k) {
+    double t = wave_sum(v[k]);
+    if (lane == 0) red[wid][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[kPartialSlots];
+    for (int k = 0; k < kPartialSlots; ++k)
+      t[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    if (g.energy && (ev_flags & DCM_EV_ENERGY)) *g.energy = t[0];
+    if (g.virial && (ev_flags & DCM_EV_VIRIAL))
+      for (int k = 0; k < 6; ++k) g.virial[k] = t[1 + k];
+    if (g.npairs && (ev_flags & DCM_EV_COUNTS)) *g.npairs = (uint64_t)t[7];
+  }
+}
+
+void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
+                             int32_t *cell_of, int32_t *cell_count,
+                             unsigned long long *rc_max_bits, uint32_t *status) {
+  if (npblk <= 0) return;
+  hipLaunchKernelGGL(kb_cell_count, dim3((unsigned)npblk), dim3(kBatchBlock), 0, s, sys, pblk,
+                     cell_of, cell_count, rc_max_bits, status);
+}
+
+void launch_batch_cell_scatter(hipStream_t s, const SysGeom *sys, const int2 *pblk,
+                               int64_t npblk, const int32_t *cell_of, const int32_t *cell_start,
+                               int32_t *cell_fill, int32_t *perm) {
+  if (npblk <= 0) return;
+  hipLaunchKernelGGL(kb_cell_scatter, dim3((unsigned)npblk), dim3(kBatchBlock), 0, s, sys, pblk,
+                     cell_of, cell_start, cell_fill, perm);
+}
+
+void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
+                         const int32_t *perm, double4 *sorted) {
+  if (npblk <= 0) return;
+  hipLaunchKernelGGL(kb_gather, dim3((unsigned)npblk), dim3(kBatchBlock), 0, s, sys, pblk, perm,
+                     sorted);
+}
+
+void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64_t neblk,
+                      const int32_t *cell_start, const double4 *sorted, int64_t next_total,
+                      int64_t ext_cap, int32_t *ext_count, int32_t *ext_start, int32_t *scan_tmp,
+                      double4 *ext_pos, uint32_t *status) {
+  if (neblk <= 0) return;
+  hipLaunchKernelGGL(kb_ext_count, dim3((unsigned)neblk), dim3(kBatchBlock), 0, s, sys, eblk,
+                     cell_start, ext_count);
+  launch_exclusive_scan(s, ext_count, ext_start, next_total, scan_tmp);
+  hipLaunchKernelGGL(kb_ext_fill, dim3((unsigned)neblk), dim3(kBatchBlock), 0, s, sys, eblk,
+                     cell_start, ext_start, sorted, ext_cap, ext_pos, status);
+}
+
+void launch_batch_reduce(hipStream_t s, const SysGeom *sys, int32_t nsys,
+                         const double *partials, int ev_flags) {
+  if (nsys <= 0) return;
+  hipLaunchKernelGGL(kb_reduce, dim3((unsigned)nsys), dim3(256), 0, s, sys, partials, ev_flags);
+}
+
+}  // namespace dcm

@@ -299,34 +299,9 @@ void launch_gather(hipStream_t s, const double *x, const double *y, const double
 }
 
 // ------------------------------------------------ periodic ghost images
-// The search grid extends the cell grid by h[a] cells on both sides of every
-// axis.  Extended cell (ex, ey, ez) holds a copy of real cell
-// (ex - h[0], ey - h[1], ez - h[2]) wrapped into the box, with positions
-// shifted by the matching multiple of the box length, so that a lane can walk
-// any row of cells around its particle as one contiguous range of the
-// extended array, without wrap-around or image shifts.
-struct ExtGeom {
-  int nc[3];
-  int h[3];
-  int ne[3];
-  double L[3];
-};
-
-__device__ __forceinline__ void ext_to_real(const ExtGeom &g, int64_t e, int &rc, int p[3]) {
-  const int ex = (int)(e % g.ne[0]);
-  const int64_t t = e / g.ne[0];
-  const int ey = (int)(t % g.ne[1]);
-  const int ez = (int)(t / g.ne[1]);
-  const int u[3] = {ex - g.h[0], ey - g.h[1], ez - g.h[2]};
-  int r[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    r[a] = wrap_index(u[a], g.nc[a]);
-    p[a] = (u[a] - r[a]) / g.nc[a];  // periods crossed: exact division
-  }
-  rc = (r[2] * g.nc[1] + r[1]) * g.nc[0] + r[0];
-}
-
+// The extended grid (ExtGeom) lets a lane walk any row of cells around its
+// particle as one contiguous range of the extended array, without
+// wrap-around or image shifts.
 __global__ __launch_bounds__(256) void k_ext_count(const int32_t *__restrict__ cell_start,
                                                    ExtGeom g, int64_t next,
                                                    int32_t *__restrict__ ext_count) {

@@ -17,6 +17,12 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     p[i] = v;
 }
 
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void k_reset_ctl(Ctl *ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     Ctl c = {};
@@ -43,6 +49,11 @@ void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n) {
 void launch_fill_i32(hipStream_t s, int32_t *p, int32_t v, int64_t n) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_fill_u64(hipStream_t s, unsigned long long *p, unsigned long long v, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
 }
 
 void launch_reset_ctl(hipStream_t s, Ctl *ctl) {

@@ -178,53 +178,73 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
+// Everything one lane needs to find and sum its particle's neighbours; the
+// single-system kernel fills it from its arguments, the batched kernel from
+// the table entry of the system a work item belongs to.
+struct PairView {
+  const double4 *pos;            // sorted particles (x, y, z, rc)
+  const int32_t *cell_start;     // this system's real cells -> sorted slots
+  const int32_t *perm;           // sorted slot -> particle id
+  int64_t id0;                   // particle id of the system's first caller index
+  const double4 *ext_pos;        // extended (ghost) array
+  const int32_t *ext_start;      // this system's extended cells -> extended slots
+  int64_t ext_cap;
+  int nc[3], h[3], ne[3];
+  double len[3], sc[3];
+  double rc_bound;
+  const unsigned long long *rc_all_bits;  // largest cutoff of the system (rule MAX)
+  double *fx, *fy, *fz;
+  int32_t *nnbr;
+};
+
+// One block of kPairBlock particles: sorted slot s for this lane (active if
+// it holds a particle).  Writes the forces and, from lanes 0..7, the block's
+// partial sums E, W[6], pair count to partial_out.
 template <int RULE, int PREC, int EVM>
-__global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
-  __shared__ uint2 segs[kSegCap][kPairBlock];
+__device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool active, double eps,
+                                           double sig2, uint2 (*segs)[kPairBlock],
+                                           double (*red)[kPartialSlots], uint32_t *status,
+                                           double *partial_out) {
   const int lane_id = threadIdx.x;
-  const int64_t lblock = xcd_block(blockIdx.x, gridDim.x, kXcdGroup);
-  const int64_t s = lblock * kPairBlock + threadIdx.x;
-  const bool active = s < a.n;
   Acc<PREC> acc;
   int cnt = 0;
-  const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
-  const int hx = a.h[0], hy = a.h[1], hz = a.h[2];
-  const int nex = a.ne[0], ney = a.ne[1];
-  const double sig2 = a.sigma * a.sigma;
+  const int nx = v.nc[0], ny = v.nc[1], nz = v.nc[2];
+  const int hx = v.h[0], hy = v.h[1], hz = v.h[2];
+  const int nex = v.ne[0], ney = v.ne[1];
   double xi = 0, yi = 0, zi = 0, rci = 0, rci2 = 0, R2 = 0, guard = 0;
   int zlo = 0, zhi = -1, ylo = 0, yhi = -1, zc = 0, yc = 0, cy = 0, cz = 0, self = -1;
   if (active) {
-    const double4 pi = a.pos[s];
+    const double4 pi = v.pos[s];
     xi = pi.x;
     yi = pi.y;
     zi = pi.z;
     rci = pi.w;
     double R = rci;
     if constexpr (RULE == DCM_PAIR_MAX) {
-      double rall = __longlong_as_double((long long)a.ctl->rc_max_bits);
+      double rall = __longlong_as_double((long long)*v.rc_all_bits);
       R = rall > R ? rall : R;
     }
-    R = R < a.rc_bound ? R : a.rc_bound;
+    R = R < v.rc_bound ? R : v.rc_bound;
     rci2 = rci * rci;
     // search radius widened by a hair: rounding in the cell geometry can
     // only add candidates, never drop one
-    guard = 1e-9 * (a.len[0] + a.len[1] + a.len[2]);
+    guard = 1e-9 * (v.len[0] + v.len[1] + v.len[2]);
     const double Rg = R + guard;
     R2 = Rg * Rg;
-    const int cx = slab_index(xi, a.sc[0], nx);
-    cy = slab_index(yi, a.sc[1], ny);
-    cz = slab_index(zi, a.sc[2], nz);
+    const int cx = slab_index(xi, v.sc[0], nx);
+    cy = slab_index(yi, v.sc[1], ny);
+    cz = slab_index(zi, v.sc[2], nz);
     // the halo holds ceil(rc_bound/len) + 1 cells, so these stay inside it
-    zlo = clampi((int)floor((zi - Rg) * a.sc[2]), -hz, nz + hz - 1);
-    zhi = clampi((int)floor((zi + Rg) * a.sc[2]), -hz, nz + hz - 1);
-    ylo = clampi((int)floor((yi - Rg) * a.sc[1]), -hy, ny + hy - 1);
-    yhi = clampi((int)floor((yi + Rg) * a.sc[1]), -hy, ny + hy - 1);
+    zlo = clampi((int)floor((zi - Rg) * v.sc[2]), -hz, nz + hz - 1);
+    zhi = clampi((int)floor((zi + Rg) * v.sc[2]), -hz, nz + hz - 1);
+    ylo = clampi((int)floor((yi - Rg) * v.sc[1]), -hy, ny + hy - 1);
+    yhi = clampi((int)floor((yi + Rg) * v.sc[1]), -hy, ny + hy - 1);
     zc = zlo;
     yc = ylo;
     // this particle's own copy in the extended array
     const int real_cell = (cz * ny + cy) * nx + cx;
     const int ext_cell = ((cz + hz) * ney + (cy + hy)) * nex + (cx + hx);
-    self = a.ext_start[ext_cell] + (int)(s - a.cell_start[real_cell]);
+    self = v.ext_start[ext_cell] + (int)(s - v.cell_start[real_cell]);
   }
   bool rows_left = active;
   while (rows_left) {
@@ -237,51 +257,50 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
         if (++zc > zhi) rows_left = false;
       }
       double ez = 0.0, ey = 0.0;
-      if (zcur < cz) ez = zi - (double)(zcur + 1) * a.len[2];
-      else if (zcur > cz) ez = (double)zcur * a.len[2] - zi;
+      if (zcur < cz) ez = zi - (double)(zcur + 1) * v.len[2];
+      else if (zcur > cz) ez = (double)zcur * v.len[2] - zi;
       ez = ez > guard ? ez - guard : 0.0;
-      if (ycur < cy) ey = yi - (double)(ycur + 1) * a.len[1];
-      else if (ycur > cy) ey = (double)ycur * a.len[1] - yi;
+      if (ycur < cy) ey = yi - (double)(ycur + 1) * v.len[1];
+      else if (ycur > cy) ey = (double)ycur * v.len[1] - yi;
       ey = ey > guard ? ey - guard : 0.0;
       const double rem = R2 - ez * ez - ey * ey;
       if (rem < 0.0) continue;
       // chord half-width, rounded up generously (it only selects cells)
       const double w = (double)(sqrtf((float)rem) * 1.00001f) + guard;
-      const int xlo = clampi((int)floor((xi - w) * a.sc[0]), -hx, nx + hx - 1);
-      const int xhi = clampi((int)floor((xi + w) * a.sc[0]), -hx, nx + hx - 1);
-      const int32_t *es = a.ext_start + ((int64_t)(zcur + hz) * ney + (ycur + hy)) * nex + hx;
+      const int xlo = clampi((int)floor((xi - w) * v.sc[0]), -hx, nx + hx - 1);
+      const int xhi = clampi((int)floor((xi + w) * v.sc[0]), -hx, nx + hx - 1);
+      const int32_t *es = v.ext_start + ((int64_t)(zcur + hz) * ney + (ycur + hy)) * nex + hx;
       int j0 = es[xlo], j1 = es[xhi + 1];
-      if (j1 > a.ext_cap) j1 = (int)a.ext_cap;  // overflowed ghosts (flagged at build)
+      if (j1 > v.ext_cap) j1 = (int)v.ext_cap;  // overflowed ghosts (flagged at build)
       if (j1 > j0) {
         segs[nseg][lane_id] = make_uint2((uint32_t)j0, (uint32_t)j1);
         ++nseg;
       }
     }
     if (nseg > 0)
-      scan_ranges<RULE, PREC, EVM>(segs, nseg, a.ext_pos, self, xi, yi, zi, rci, rci2, sig2, acc,
+      scan_ranges<RULE, PREC, EVM>(segs, nseg, v.ext_pos, self, xi, yi, zi, rci, rci2, sig2, acc,
                                    cnt);
   }
   if (active) {
-    const double c24 = 24.0 * a.eps;
+    const double c24 = 24.0 * eps;
     const double Fx = c24 * acc.fx, Fy = c24 * acc.fy, Fz = c24 * acc.fz;
-    const int32_t i = a.perm[s];
-    a.fx[i] = Fx;
-    a.fy[i] = Fy;
-    a.fz[i] = Fz;
-    if (a.nnbr) a.nnbr[i] = cnt;
-    if (!finite3(Fx, Fy, Fz)) atomicOr(a.status, ST_NONFINITE_FORCE);
+    const int64_t i = v.perm[s] - v.id0;
+    v.fx[i] = Fx;
+    v.fy[i] = Fy;
+    v.fz[i] = Fz;
+    if (v.nnbr) v.nnbr[i] = cnt;
+    if (!finite3(Fx, Fy, Fz)) atomicOr(status, ST_NONFINITE_FORCE);
   }
   // deterministic block partials: E, W[6], pair count
-  double v[kPartialSlots];
-  v[0] = (double)acc.e * (2.0 * a.eps);
+  double pv[kPartialSlots];
+  pv[0] = (double)acc.e * (2.0 * eps);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) v[1 + k] = (double)acc.w[k] * (12.0 * a.eps);
-  v[7] = (double)cnt;
-  __shared__ double red[kPairBlock / 64][kPartialSlots];
+  for (int k = 0; k < 6; ++k) pv[1 + k] = (double)acc.w[k] * (12.0 * eps);
+  pv[7] = (double)cnt;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < kPartialSlots; ++k) {
-    double t = wave_sum(v[k]);
+    double t = wave_sum(pv[k]);
     if (lane == 0) red[wid][k] = t;
   }
   __syncthreads();
@@ -289,7 +308,87 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
     double t = 0.0;
 #pragma unroll
     for (int q = 0; q < kPairBlock / 64; ++q) t += red[q][threadIdx.x];
-    a.partials[lblock * kPartialSlots + threadIdx.x] = t;
+    partial_out[threadIdx.x] = t;
+  }
+}
+
+template <int RULE, int PREC, int EVM>
+__global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
+  __shared__ uint2 segs[kSegCap][kPairBlock];
+  __shared__ double red[kPairBlock / 64][kPartialSlots];
+  const int64_t lblock = xcd_block(blockIdx.x, gridDim.x, kXcdGroup);
+  const int64_t s = lblock * kPairBlock + threadIdx.x;
+  PairView v;
+  v.pos = a.pos;
+  v.cell_start = a.cell_start;
+  v.perm = a.perm;
+  v.id0 = 0;
+  v.ext_pos = a.ext_pos;
+  v.ext_start = a.ext_start;
+  v.ext_cap = a.ext_cap;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v.nc[k] = a.nc[k];
+    v.h[k] = a.h[k];
+    v.ne[k] = a.ne[k];
+    v.len[k] = a.len[k];
+    v.sc[k] = a.sc[k];
+  }
+  v.rc_bound = a.rc_bound;
+  v.rc_all_bits = &a.ctl->rc_max_bits;
+  v.fx = a.fx;
+  v.fy = a.fy;
+  v.fz = a.fz;
+  v.nnbr = a.nnbr;
+  pair_block<RULE, PREC, EVM>(v, s, s < a.n, a.eps, a.sigma * a.sigma, segs, red, a.status,
+                              a.partials + lblock * kPartialSlots);
+}
+
+// Batched form: a persistent grid takes work items (blocks of kPairBlock
+// particles of one system) from a queue ordered by estimated cost.  Every
+// workgroup leaves the loop once the queue head passes the item count.
+template <int RULE, int PREC, int EVM>
+__global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
+  __shared__ uint2 segs[kSegCap][kPairBlock];
+  __shared__ double red[kPairBlock / 64][kPartialSlots];
+  __shared__ int32_t next_item;
+  const double sig2 = a.sigma * a.sigma;
+  while (true) {
+    if (threadIdx.x == 0) next_item = (int32_t)atomicAdd(a.head, 1u);
+    __syncthreads();
+    const int32_t qi = next_item;
+    __syncthreads();
+    if (qi >= a.nitems) break;
+    const int32_t item = __builtin_amdgcn_readfirstlane(a.queue[qi]);
+    const int2 w = a.items[item];
+    const int b = __builtin_amdgcn_readfirstlane(w.x);
+    const int64_t first = __builtin_amdgcn_readfirstlane(w.y);
+    const SysGeom &g = a.sys[b];
+    PairView v;
+    v.pos = a.pos;
+    v.cell_start = a.cell_start + g.cell0;
+    v.perm = a.perm;
+    v.id0 = g.p0;
+    v.ext_pos = a.ext_pos;
+    v.ext_start = a.ext_start + g.ext_cell0;
+    v.ext_cap = a.ext_cap;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v.nc[k] = g.nc[k];
+      v.h[k] = g.h[k];
+      v.ne[k] = g.ne[k];
+      v.len[k] = g.len[k];
+      v.sc[k] = g.sc[k];
+    }
+    v.rc_bound = g.rc_cap;
+    v.rc_all_bits = a.rc_max_bits + b;
+    v.fx = g.fx;
+    v.fy = g.fy;
+    v.fz = g.fz;
+    v.nnbr = g.nnbr;
+    const int64_t local = first + threadIdx.x;
+    pair_block<RULE, PREC, EVM>(v, g.p0 + local, local < g.n, a.eps, sig2, segs, red, a.status,
+                                a.partials + (int64_t)item * kPartialSlots);
   }
 }
 
@@ -313,6 +412,57 @@ void launch_pair(hipStream_t s, const PairArgs &a, int rule, int prec) {
   } else {
     if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_MAX, DCM_FP64>(s, a, g, b);
     else launch_pair_ev<DCM_PAIR_MAX, DCM_FP32_MIXED>(s, a, g, b);
+  }
+}
+
+template <int RULE, int PREC>
+static void launch_pair_batched_ev(hipStream_t s, const BatchPairArgs &a, dim3 g, dim3 b) {
+  const int evm = ((a.ev_flags & DCM_EV_ENERGY) ? 1 : 0) | ((a.ev_flags & DCM_EV_VIRIAL) ? 2 : 0);
+  switch (evm) {
+    case 0: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 0>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 1>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 2>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 3>), g, b, 0, s, a); break;
+  }
+}
+
+// Resident workgroups of the persistent kernel: what the occupancy allows on
+// every compute unit, never more than the number of items.
+static int64_t persistent_grid(int rule, int prec, int64_t nitems) {
+  static int cached[2][2] = {{0, 0}, {0, 0}};
+  int &per_cu = cached[rule][prec];
+  if (per_cu == 0) {
+    const void *fn;
+    if (rule == DCM_PAIR_OWN)
+      fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP64, 3>
+                            : (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP32_MIXED, 3>;
+    else
+      fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP64, 3>
+                            : (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP32_MIXED, 3>;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kPairBlock, 0) != hipSuccess ||
+        blocks < 1)
+      blocks = 1;
+    per_cu = blocks;
+  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 1;
+  int64_t g = (int64_t)per_cu * cus;
+  return g < nitems ? g : (nitems > 0 ? nitems : 1);
+}
+
+void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int prec) {
+  if (a.nitems <= 0) return;
+  dim3 g((unsigned)persistent_grid(rule, prec, a.nitems)), b(kPairBlock);
+  if (rule == DCM_PAIR_OWN) {
+    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP64>(s, a, g, b);
+    else launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED>(s, a, g, b);
+  } else {
+    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP64>(s, a, g, b);
+    else launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP32_MIXED>(s, a, g, b);
   }
 }
 

@@ -63,6 +63,21 @@ def test_null_context_is_rejected_before_any_device_call(lib):
                                None) == dcm.DCM_ERR_INVALID
     assert lib.dcm_destroy(None) == dcm.DCM_ERR_INVALID
     assert lib.dcm_last_error(None) == b"null context"
+    assert lib.dcm_forces_batched(None, 0, None, dcm.make_lj(), 0, 0, 0,
+                                  0) == dcm.DCM_ERR_INVALID
+    assert lib.dcm_batched_edge(None, None) == dcm.DCM_ERR_INVALID
+
+
+def test_system_descriptor_layout_matches_header():
+    """The binding's dcm_system mirrors the C struct: eleven pointers, then
+    n, the box, cell_edge and rc_bound, with no padding."""
+    import paper_1701_05242_amd as dcm
+    S = dcm.dcm_system
+    assert ctypes.sizeof(S) == 11 * 8 + 8 + 24 + 8 + 8
+    assert [f[0] for f in S._fields_] == ["x", "y", "z", "rc", "fx", "fy", "fz", "nnbr",
+                                         "energy", "virial", "npairs", "n", "box", "cell_edge",
+                                         "rc_bound"]
+    assert S.n.offset == 88 and S.box.offset == 96 and S.rc_bound.offset == 128
 
 
 def test_binding_refuses_host_tensors():

@@ -315,3 +315,10 @@ def sample_indices(n: int, k: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(np.random.PCG64(seed))
     k = min(k, n)
     return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)
+
+
+def uniform_cutoffs(n: int, rc_min: float, rc_max: float, seed: int) -> np.ndarray:
+    """Seeded per-particle cutoffs drawn uniformly from [rc_min, rc_max): an
+    input that exercises very different cutoffs between neighbours."""
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    return rng.uniform(rc_min, rc_max, size=n)
