@@ -246,8 +246,8 @@ dcm_status dcm_detect_interface(dcm_ctx *ctx, const double *x, const double *y, 
   if (!std::isfinite(split)) return fail(ctx, DCM_ERR_INVALID, "split must be finite");
   DCM_TRY(ensure(ctx, ctx->gray, nvox * sizeof(uint32_t)));
   DCM_TRY(ensure(ctx, ctx->hist, kHistBins * sizeof(uint32_t)));
-  DCM_TRY(ensure(ctx, ctx->seg_a, nvox));
-  DCM_TRY(ensure(ctx, ctx->seg_b, nvox));
+  DCM_TRY(ensure(ctx, ctx->seg_a, phase_bits_words(grid.n) * sizeof(uint32_t)));
+  DCM_TRY(ensure(ctx, ctx->seg_b, phase_bits_words(grid.n) * sizeof(uint32_t)));
   if (!counts) {
     DCM_TRY(ensure(ctx, ctx->counts, nvox * sizeof(uint32_t)));
     counts = ptr<uint32_t>(ctx->counts);
@@ -264,12 +264,12 @@ dcm_status dcm_detect_interface(dcm_ctx *ctx, const double *x, const double *y, 
   launch_hist(s, ptr<uint32_t>(ctx->gray), nvox, ptr<uint32_t>(ctx->hist), ctx->d_status);
   if (split <= 0.0)
     launch_otsu(s, ptr<uint32_t>(ctx->hist), nvox, ctx->ctl, threshold_out, ctx->d_status);
-  launch_threshold(s, ptr<uint32_t>(ctx->gray), nvox, split, ctx->ctl, ptr<uint8_t>(ctx->seg_a),
-                   threshold_out);
+  launch_threshold(s, ptr<uint32_t>(ctx->gray), grid.n, split, ctx->ctl,
+                   ptr<uint32_t>(ctx->seg_a), threshold_out);
   for (int p = 1; p <= kMajorityMaxPasses; ++p)
-    launch_majority_pass(s, ptr<uint8_t>(ctx->seg_a), ptr<uint8_t>(ctx->seg_b), grid.n, p,
+    launch_majority_pass(s, ptr<uint32_t>(ctx->seg_a), ptr<uint32_t>(ctx->seg_b), grid.n, p,
                          kMajorityMaxPasses, ctx->ctl);
-  launch_interface(s, ptr<uint8_t>(ctx->seg_a), ptr<uint8_t>(ctx->seg_b), grid.n, ctx->ctl, seg,
+  launch_interface(s, ptr<uint32_t>(ctx->seg_a), ptr<uint32_t>(ctx->seg_b), grid.n, ctx->ctl, seg,
                    iface);
   timer_end(ctx, "detect", ev);
   return check_launch(ctx, "dcm_detect_interface");
@@ -394,7 +394,8 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   // the exact count of an earlier build
   double want = std::min(1.5 * uniform * (double)n + 4096.0, hard * (double)n + 64.0);
   want = std::max(want, 1.25 * (double)*ctx->h_ext_total);
-  if (want >= 2147483647.0) return fail(ctx, DCM_ERR_RANGE, "ghost-extended system too large");
+  if (want > (double)kMaxExtSlots)
+    return fail(ctx, DCM_ERR_RANGE, "ghost-extended system too large");
   const int64_t ext_cap = std::max<int64_t>((int64_t)want, ctx->ext_cap);
   DCM_TRY(ensure(ctx, ctx->ext_count, next * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->ext_start, (next + 1) * sizeof(int32_t)));

@@ -151,12 +151,13 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
     if (cell0 >= (int64_t(1) << 30) || ext_cell0 >= (int64_t(1) << 30))
       return fail(ctx, DCM_ERR_RANGE, "dcm_forces_batched: too many cells");
   }
-  if (ext_bound >= 2147483000.0)
-    return fail(ctx, DCM_ERR_RANGE, "dcm_forces_batched: ghost-extended batch too large");
+  // beyond the addressable size the build flags an overflow instead
+  if (ext_bound > (double)kMaxExtSlots) ext_bound = (double)kMaxExtSlots;
   B.n_total = p0;
   B.cells_total = cell0;
   B.ext_cells_total = ext_cell0;
   // the most ghost copies any arrangement of the particles can need
+  // (capped at what the pair kernel can address)
   B.ext_cap = std::max<int64_t>((int64_t)ext_bound, 1);
   // work queue: largest estimated cost first, ties in natural order
   const int64_t nitems = (int64_t)B.items.size();

@@ -109,6 +109,52 @@ __device__ __forceinline__ void wave_aggregated_add(Counter *hist, uint32_t key,
   }
 }
 
+// Run-aggregated counters for key-ordered input (cell-sorted particles): the
+// lanes of a wavefront are cut into runs of consecutive valid lanes with equal
+// keys, and the first lane of every run issues one atomic for its run -- all
+// runs in the same instruction, however many distinct keys the wavefront
+// holds.  Equal keys in separate runs take separate atomics, so any input
+// order gives the same totals.
+__device__ __forceinline__ unsigned long long wave_run_heads(uint32_t key, bool valid,
+                                                             unsigned long long &vmask) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint32_t prev = __shfl_up(key, 1, 64);
+  const int prev_valid = __shfl_up(valid ? 1 : 0, 1, 64);
+  const bool head = valid && (lane == 0 || !prev_valid || prev != key);
+  vmask = __ballot(valid);
+  return __ballot(head);
+}
+
+// length of the run starting at head lane `lane`
+__device__ __forceinline__ int wave_run_len(int lane, unsigned long long heads,
+                                            unsigned long long vmask) {
+  const unsigned long long stops =
+      lane == 63 ? 0ull : (heads | ~vmask) & (~0ull << (lane + 1));
+  return (stops ? __ffsll((long long)stops) - 1 : 64) - lane;
+}
+
+template <typename Counter>
+__device__ __forceinline__ void wave_run_add(Counter *hist, uint32_t key, bool valid) {
+  const int lane = (int)(threadIdx.x & 63);
+  unsigned long long vmask;
+  const unsigned long long heads = wave_run_heads(key, valid, vmask);
+  if ((heads >> lane) & 1ull) atomicAdd(&hist[key], (Counter)wave_run_len(lane, heads, vmask));
+}
+
+// One slot per valid lane in fill[key]: the run's first lane reserves the
+// run's slots, the run's lanes take them in lane order.
+__device__ __forceinline__ int wave_run_slot(int32_t *fill, uint32_t key, bool valid) {
+  const int lane = (int)(threadIdx.x & 63);
+  unsigned long long vmask;
+  const unsigned long long heads = wave_run_heads(key, valid, vmask);
+  int base = 0;
+  if ((heads >> lane) & 1ull)
+    base = atomicAdd(&fill[key], (int32_t)wave_run_len(lane, heads, vmask));
+  const unsigned long long upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+  const int hl = upto ? 63 - __clzll((long long)upto) : lane;
+  return __shfl(base, hl, 64) + (lane - hl);
+}
+
 // Reserve one slot per valid lane in fill[key] (lanes with equal keys share
 // one atomic and take consecutive slots in lane order); returns the slot.
 __device__ __forceinline__ int wave_aggregated_slot(int32_t *fill, uint32_t key, bool valid) {

@@ -29,6 +29,8 @@ constexpr int kHistBins = 4096;       // gray values (27-window counts) must sta
 constexpr int kMajorityMaxPasses = 16;
 constexpr int kPartialSlots = 8;      // per-block partial sums: E, W[6], pair count
 constexpr int kReorderEvery = 8;      // dcm_step re-sorts its working copies this often
+// the pair kernel addresses the ghost-extended array with 32-bit byte offsets
+constexpr int64_t kMaxExtSlots = (int64_t(1) << 27) - 1;
 
 // Device-resident control block: scalars produced and consumed on the device
 // so that no stage needs a host round trip.
@@ -149,11 +151,14 @@ void launch_hist(hipStream_t s, const uint32_t *gray, int64_t nvox, uint32_t *hi
                  uint32_t *status);
 void launch_otsu(hipStream_t s, const uint32_t *hist, int64_t nvox, Ctl *ctl, int32_t *t_out,
                  uint32_t *status);
-void launch_threshold(hipStream_t s, const uint32_t *gray, int64_t nvox, double split,
-                      const Ctl *ctl, uint8_t *seg0, int32_t *t_out);
-void launch_majority_pass(hipStream_t s, uint8_t *buf0, uint8_t *buf1, const int32_t nv[3],
+// phase maps of the majority passes are bit-packed: ceil(nx/32) words per
+// x-row; phase_bits_words gives the words of one map
+int64_t phase_bits_words(const int32_t nv[3]);
+void launch_threshold(hipStream_t s, const uint32_t *gray, const int32_t nv[3], double split,
+                      const Ctl *ctl, uint32_t *bits0, int32_t *t_out);
+void launch_majority_pass(hipStream_t s, uint32_t *buf0, uint32_t *buf1, const int32_t nv[3],
                           int pass, int max_passes, Ctl *ctl);
-void launch_interface(hipStream_t s, const uint8_t *buf0, const uint8_t *buf1,
+void launch_interface(hipStream_t s, const uint32_t *buf0, const uint32_t *buf1,
                       const int32_t nv[3], const Ctl *ctl, uint8_t *seg, uint8_t *iface);
 
 // k_fsm.hip

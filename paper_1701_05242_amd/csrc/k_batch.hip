@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBatchBlock) void kb_cell_count(
     c = (int)g.cell0 + lc;
     cell_of[g.p0 + i] = c;
   }
-  wave_aggregated_add(count, (uint32_t)c, valid);
+  wave_run_add(count, (uint32_t)c, valid);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     unsigned long long o = __shfl_xor(bits, off, 64);
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBatchBlock) void kb_cell_scatter(
   const int64_t i = first + threadIdx.x;
   const bool valid = i < g.n;
   const int c = valid ? cell_of[g.p0 + i] : 0;
-  const int slot = wave_aggregated_slot(fill, (uint32_t)c, valid);
+  const int slot = wave_run_slot(fill, (uint32_t)c, valid);
   if (valid) perm[cell_start[c] + slot] = (int32_t)(g.p0 + i);
 }
 

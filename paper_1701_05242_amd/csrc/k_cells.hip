@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_cell_count(
     int nz, double sx, double sy, double sz, double rc_cap, int32_t *__restrict__ cell_of,
     int32_t *count, Ctl *ctl, uint32_t *status) {
   unsigned long long rmax = 0;
-  // uniform trip count: every lane reaches the wave-aggregated atomic
+  // uniform trip count: every lane reaches the run-aggregated atomic
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
     const int64_t i = base + threadIdx.x;
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_cell_count(
       rmax = bits > rmax ? bits : rmax;
       cell_of[i] = c;
     }
-    wave_aggregated_add(count, (uint32_t)c, valid);
+    wave_run_add(count, (uint32_t)c, valid);
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void k_cell_scatter(const int32_t *__restrict_
     const int64_t i = base + threadIdx.x;
     const bool valid = i < n;
     const int c = valid ? cell_of[i] : 0;
-    const int slot = wave_aggregated_slot(fill, (uint32_t)c, valid);
+    const int slot = wave_run_slot(fill, (uint32_t)c, valid);
     if (valid) perm[cell_start[c] + slot] = (int32_t)i;
   }
 }

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_bin_density(const double *__restrict__ 
                                                      double sz, uint32_t *counts,
                                                      uint32_t *status) {
   // grid-stride loop with a uniform trip count so every lane reaches the
-  // wave-aggregated atomic together
+  // run-aggregated atomic together
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
     const int64_t i = base + threadIdx.x;
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_bin_density(const double *__restrict__ 
         v = (uint32_t)(((int64_t)vz * ny + vy) * nx + vx);
       }
     }
-    wave_aggregated_add(counts, v, valid);
+    wave_run_add(counts, v, valid);
   }
 }
 
@@ -275,24 +275,44 @@ void launch_otsu(hipStream_t s, const uint32_t *hist, int64_t nvox, Ctl *ctl, in
   hipLaunchKernelGGL(k_otsu, dim3(1), dim3(1024), 0, s, hist, ctl, t_out, status);
 }
 
+// ------------------------------- bit-packed phase maps (majority filter)
+// The phase map of every majority pass is stored one bit per voxel: each
+// x-row is W = ceil(nx/32) 32-bit words, bit b of word k holding voxel
+// x = 32k + b; bits at x >= nx are always 0.  A pass then evaluates 32
+// voxels per lane with bitwise arithmetic instead of byte stencils.
+__host__ __device__ __forceinline__ int row_words(int nx) { return (nx + 31) >> 5; }
+
 // Initial phase map s0 = [g >= T] (or [g >= split] for a fixed split); a
-// single-phase volume is all high density.  Also resets the majority-pass
-// state for the passes that follow.
-__global__ __launch_bounds__(256) void k_threshold(const uint32_t *__restrict__ gray,
-                                                   int64_t nvox, double split, Ctl *ctl,
-                                                   uint8_t *seg0, int32_t *t_out) {
+// single-phase volume is all high density.  One lane per (row, bit) slot of
+// the padded rows; a ballot packs 32 lanes into a word.  Also resets the
+// majority-pass state for the passes that follow.
+__global__ __launch_bounds__(256) void k_threshold(const uint32_t *__restrict__ gray, int nx,
+                                                   int64_t rows, double split, Ctl *ctl,
+                                                   uint32_t *__restrict__ bits0,
+                                                   int32_t *t_out) {
   const bool fixed = split > 0.0;
   const int T = ctl->threshold;
   const bool deg = !fixed && ctl->degenerate;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t g = gray[v];
-    uint8_t s;
-    if (fixed)
-      s = ((double)g >= split) ? 1 : 0;
-    else
-      s = deg ? 1 : ((int64_t)g >= (int64_t)T ? 1 : 0);
-    seg0[v] = s;
+  const int W = row_words(nx);
+  const int64_t slots = rows * W * 32;
+  const int lane = threadIdx.x & 63;
+  // uniform trip count: whole wavefronts reach every ballot
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < slots; base += stride) {
+    const int64_t t = base + threadIdx.x;
+    const int64_t word = t >> 5;
+    const int64_t row = word / W;
+    const int x = (int)(word - row * W) * 32 + (int)(t & 31);
+    bool s = false;
+    if (t < slots && x < nx) {
+      const uint32_t g = gray[row * nx + x];
+      if (fixed)
+        s = (double)g >= split;
+      else
+        s = deg || (int64_t)g >= (int64_t)T;
+    }
+    const unsigned long long m = __ballot(s);
+    if ((lane & 31) == 0 && t < slots) bits0[word] = (uint32_t)(m >> (lane & 32));
   }
   if (blockIdx.x == 0 && threadIdx.x < kMajorityMaxPasses + 2) {
     ctl->maj_chg1[threadIdx.x] = 0u;
@@ -307,24 +327,24 @@ __global__ __launch_bounds__(256) void k_threshold(const uint32_t *__restrict__ 
   }
 }
 
-static unsigned flat_grid(int64_t nvox) {
-  int64_t b = ceil_div(nvox, 256 * 4);
+static unsigned flat_grid(int64_t n) {
+  int64_t b = ceil_div(n, 256 * 4);
   if (b < 1) b = 1;
   if (b > 4096) b = 4096;
   return (unsigned)b;
 }
 
-void launch_threshold(hipStream_t s, const uint32_t *gray, int64_t nvox, double split,
-                      const Ctl *ctl, uint8_t *seg0, int32_t *t_out) {
-  hipLaunchKernelGGL(k_threshold, dim3(flat_grid(nvox)), dim3(256), 0, s, gray, nvox, split,
-                     const_cast<Ctl *>(ctl), seg0, t_out);
+void launch_threshold(hipStream_t s, const uint32_t *gray, const int32_t nv[3], double split,
+                      const Ctl *ctl, uint32_t *bits0, int32_t *t_out) {
+  const int64_t rows = (int64_t)nv[1] * nv[2];
+  hipLaunchKernelGGL(k_threshold, dim3(flat_grid(rows * row_words(nv[0]) * 32)), dim3(256), 0, s,
+                     gray, nv[0], rows, split, const_cast<Ctl *>(ctl), bits0, t_out);
 }
 
 // ---------------------------------------- majority regularisation (4b)
 // Pass p reads state p-1 from buf[(p-1)&1] and writes state p to buf[p&1],
-// counting voxels that differ from state p-1 (no change: fixed point) and
-// from the overwritten state p-2 (no change: 2-cycle).  The last workgroup to
-// finish decides whether later passes run.
+// noting whether any voxel differs from state p-1 (none: fixed point) and
+// from the overwritten state p-2 (none: 2-cycle).
 // Pass q ended the iteration if it changed nothing (fixed point) or, from the
 // second pass on, reproduced state q-2 (2-cycle).  A pass that did not run
 // left both flags at 0, so the test also holds for every pass after the end.
@@ -332,65 +352,106 @@ __device__ __forceinline__ bool majority_stopped(const Ctl *ctl, int q) {
   return ctl->maj_chg1[q] == 0u || (q >= 2 && ctl->maj_chg2[q] == 0u);
 }
 
-__global__ __launch_bounds__(256) void k_majority(uint8_t *buf0, uint8_t *buf1, int nx, int ny,
+// Word k of a row with its periodic x-neighbours: a holds bit x-1 and c bit
+// x+1 at the position of x.  lw / rw are the row's words k-1 and k+1
+// (cyclically); `top` is the bit position of x = nx - 1 in the last word.
+__device__ __forceinline__ void x_neighbours(uint32_t lw, uint32_t w, uint32_t rw, bool first,
+                                             bool lastw, int top, uint32_t &a, uint32_t &c) {
+  a = (w << 1) | (first ? ((lw >> top) & 1u) : (lw >> 31));
+  c = (w >> 1) | (lastw ? ((rw & 1u) << top) : (rw << 31));
+}
+
+// One lane per word: the 27-window count of each of its 32 voxels as a
+// bit-sliced 5-bit number (c0..c4), then [count >= 14].
+__global__ __launch_bounds__(256) void k_majority(uint32_t *buf0, uint32_t *buf1, int nx, int ny,
                                                   int nz, int pass, Ctl *ctl) {
   if (pass > 1 && majority_stopped(ctl, pass - 1)) return;
-  __shared__ uint8_t tile[HZ][HY][HX];
-  __shared__ uint8_t sx[HZ][HY][SX];
-  const uint8_t *__restrict__ src = (pass & 1) ? buf0 : buf1;
-  uint8_t *__restrict__ dst = (pass & 1) ? buf1 : buf0;
-  // a bounded grid walks the tiles, so a pass after convergence costs only
-  // a small launch
-  const int tnx = (nx + SX - 1) / SX, tny = (ny + SY - 1) / SY, tnz = (nz + SZ - 1) / SZ;
-  const int ntiles = tnx * tny * tnz;
-  const int lx = threadIdx.x, ly = threadIdx.y;
-  bool c1 = false, c2 = false;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int x0 = (t % tnx) * SX, y0 = ((t / tnx) % tny) * SY, z0 = (t / (tnx * tny)) * SZ;
-    load_tile(tile, src, x0, y0, z0, nx, ny, nz);
-    __syncthreads();
-    sum_x(sx, tile);
-    __syncthreads();
-    const int gx = x0 + lx, gy = y0 + ly;
-    if (gx < nx && gy < ny) {
+  const uint32_t *__restrict__ src = (pass & 1) ? buf0 : buf1;
+  uint32_t *__restrict__ dst = (pass & 1) ? buf1 : buf0;
+  const int W = row_words(nx);
+  const int top = (nx - 1) & 31;
+  const uint32_t last_mask = (nx & 31) ? ((1u << (nx & 31)) - 1u) : 0xffffffffu;
+  const int64_t words = (int64_t)ny * nz * W;
+  bool ch1 = false, ch2 = false;
+  for (int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; wi < words;
+       wi += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = wi / W;
+    const int k = (int)(wi - row * W);
+    const int y = (int)(row % ny), z = (int)(row / ny);
+    const int kl = k == 0 ? W - 1 : k - 1, kr = k == W - 1 ? 0 : k + 1;
+    const bool first = k == 0, lastw = k == W - 1;
+    uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, prev = 0;
 #pragma unroll
-      for (int lz = 0; lz < SZ; ++lz) {
-        const int gz = z0 + lz;
-        if (gz >= nz) break;
-        const int sum = (int)sum_yz(sx, lx, ly, lz);
-        const uint8_t nvv = sum >= 14 ? 1 : 0;
-        const int64_t v = ((int64_t)gz * ny + gy) * nx + gx;
-        const uint8_t old = dst[v];
-        dst[v] = nvv;
-        c1 |= (nvv != tile[lz + 1][ly + 1][lx + 1]);
-        c2 |= (nvv != old);
+    for (int dz = -1; dz <= 1; ++dz) {
+      int zz = z + dz;
+      zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        int yy = y + dy;
+        yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+        const uint32_t *r = src + ((int64_t)zz * ny + yy) * W;
+        const uint32_t w = r[k];
+        if (dz == 0 && dy == 0) prev = w;
+        uint32_t a, c;
+        x_neighbours(r[kl], w, r[kr], first, lastw, top, a, c);
+        // x-window sum a + w + c as two bit slices
+        const uint32_t h0 = a ^ w ^ c;
+        const uint32_t h1 = (a & w) | (c & (a ^ w));
+        // add the 2-bit number (h1 h0) into the 5-bit counter
+        const uint32_t k0 = c0 & h0;
+        c0 ^= h0;
+        const uint32_t t1 = c1 ^ h1;
+        const uint32_t k1 = (c1 & h1) | (k0 & t1);
+        c1 = t1 ^ k0;
+        const uint32_t k2 = c2 & k1;
+        c2 ^= k1;
+        const uint32_t k3 = c3 & k2;
+        c3 ^= k2;
+        c4 ^= k3;
       }
     }
-    __syncthreads();  // the next tile overwrites the LDS tile
+    // count >= 14: 16..27 have c4 set, 14 and 15 are 0111x
+    uint32_t nw = c4 | (c3 & c2 & c1);
+    if (lastw) nw &= last_mask;
+    const uint32_t old = dst[wi];
+    dst[wi] = nw;
+    ch1 |= nw != prev;
+    ch2 |= nw != old;
   }
   // any change in this workgroup: store the pass's flag (same value from
   // every writer, so no atomic is needed)
-  const int any1 = __syncthreads_or(c1 ? 1 : 0);
-  const int any2 = __syncthreads_or(c2 ? 1 : 0);
-  if (threadIdx.x == 0 && threadIdx.y == 0) {
+  const int any1 = __syncthreads_or(ch1 ? 1 : 0);
+  const int any2 = __syncthreads_or(ch2 ? 1 : 0);
+  if (threadIdx.x == 0) {
     if (any1) ctl->maj_chg1[pass] = 1u;
     if (any2) ctl->maj_chg2[pass] = 1u;
   }
 }
 
-void launch_majority_pass(hipStream_t s, uint8_t *buf0, uint8_t *buf1, const int32_t nv[3],
+int64_t phase_bits_words(const int32_t nv[3]) {
+  return (int64_t)nv[1] * nv[2] * row_words(nv[0]);
+}
+
+void launch_majority_pass(hipStream_t s, uint32_t *buf0, uint32_t *buf1, const int32_t nv[3],
                           int pass, int max_passes, Ctl *ctl) {
   (void)max_passes;
-  const dim3 g = stencil_grid(nv);
-  int64_t tiles = (int64_t)g.x * g.y * g.z;
-  if (tiles > 1024) tiles = 1024;
-  hipLaunchKernelGGL(k_majority, dim3((unsigned)tiles), dim3(SX, SY), 0, s, buf0, buf1, nv[0],
-                     nv[1], nv[2], pass, ctl);
+  int64_t b = ceil_div(phase_bits_words(nv), 256);
+  if (b < 1) b = 1;
+  if (b > 2048) b = 2048;
+  hipLaunchKernelGGL(k_majority, dim3((unsigned)b), dim3(256), 0, s, buf0, buf1, nv[0], nv[1],
+                     nv[2], pass, ctl);
 }
 
 // ------------------------------------------- interface marking (Fig. 4c)
-// iface[v] = 1 for a high-density voxel with a low-density face neighbour.
-__global__ __launch_bounds__(256) void k_interface(const uint8_t *buf0, const uint8_t *buf1,
+// seg[v] = final phase; iface[v] = 1 for a high-density voxel with a
+// low-density face neighbour.
+__device__ __forceinline__ uint32_t phase_bit(const uint32_t *s, int W, int nx, int ny, int x,
+                                              int y, int z) {
+  (void)nx;
+  return (s[((int64_t)z * ny + y) * W + (x >> 5)] >> (x & 31)) & 1u;
+}
+
+__global__ __launch_bounds__(256) void k_interface(const uint32_t *buf0, const uint32_t *buf1,
                                                    int nx, int ny, int nz, const Ctl *ctl,
                                                    uint8_t *__restrict__ seg,
                                                    uint8_t *__restrict__ iface) {
@@ -401,7 +462,8 @@ __global__ __launch_bounds__(256) void k_interface(const uint8_t *buf0, const ui
       last = p;
       break;
     }
-  const uint8_t *__restrict__ s = (last & 1) ? buf1 : buf0;
+  const uint32_t *__restrict__ s = (last & 1) ? buf1 : buf0;
+  const int W = row_words(nx);
   const int i = blockIdx.x * SX + threadIdx.x;
   const int j = blockIdx.y * SY + threadIdx.y;
   if (i >= nx || j >= ny) return;
@@ -412,20 +474,19 @@ __global__ __launch_bounds__(256) void k_interface(const uint8_t *buf0, const ui
     const int k = blockIdx.z * SZ + q;
     if (k >= nz) break;
     const int km = k == 0 ? nz - 1 : k - 1, kp = k + 1 == nz ? 0 : k + 1;
-    const int64_t rowk = (int64_t)k * ny;
-    const int64_t v = (rowk + j) * nx + i;
-    const uint8_t sv = s[v];
-    uint8_t f = 0;
+    const int64_t v = ((int64_t)k * ny + j) * nx + i;
+    const uint32_t sv = phase_bit(s, W, nx, ny, i, j, k);
+    uint32_t f = 0;
     if (sv)
-      f = (!s[(rowk + j) * nx + im]) | (!s[(rowk + j) * nx + ip]) |
-          (!s[(rowk + jm) * nx + i]) | (!s[(rowk + jp) * nx + i]) |
-          (!s[((int64_t)km * ny + j) * nx + i]) | (!s[((int64_t)kp * ny + j) * nx + i]);
-    seg[v] = sv;
-    iface[v] = f;
+      f = (phase_bit(s, W, nx, ny, im, j, k) & phase_bit(s, W, nx, ny, ip, j, k) &
+           phase_bit(s, W, nx, ny, i, jm, k) & phase_bit(s, W, nx, ny, i, jp, k) &
+           phase_bit(s, W, nx, ny, i, j, km) & phase_bit(s, W, nx, ny, i, j, kp)) ^ 1u;
+    seg[v] = (uint8_t)sv;
+    iface[v] = (uint8_t)f;
   }
 }
 
-void launch_interface(hipStream_t s, const uint8_t *buf0, const uint8_t *buf1,
+void launch_interface(hipStream_t s, const uint32_t *buf0, const uint32_t *buf1,
                       const int32_t nv[3], const Ctl *ctl, uint8_t *seg, uint8_t *iface) {
   hipLaunchKernelGGL(k_interface, stencil_grid(nv), dim3(SX, SY), 0, s, buf0, buf1, nv[0], nv[1],
                      nv[2], ctl, seg, iface);
