@@ -371,3 +371,34 @@ def test_large_slab_sampled_parity():
     print(f"[gpu]   large slab err_max={emax:.3e} err_rms={erms:.3e} max/F_rms={eabs:.3e}",
           flush=True)
     assert emax <= 1e-5 and erms <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
+@pytest.mark.parametrize("name", ["droplet", "cylinder"])
+def test_curved_interface_forces_sampled(name, prec):
+    """Curved interfaces (sphere, cylinder): the whole path from positions
+    through dcm_step's force evaluation, against the oracle's cutoffs and
+    per-particle sums on a seeded sample that includes the particles nearest
+    the interface (largest cutoffs)."""
+    print(f"[gpu] curved {name} prec={prec}", flush=True)
+    s = workloads.make(name)
+    ref_d = ref_detect(name)
+    grid = dcm.make_grid(s.box, s.h)
+    rule = dcm.make_rule(*s.rule)
+    f = [torch.zeros(s.n, **F64) for _ in range(3)]
+    v = [dev(a) for a in (s.vx, s.vy, s.vz)]
+    rc = torch.zeros(s.n, **F64)
+    with Ctx() as ctx:
+        dcm.dcm_step(ctx, dev(s.x), dev(s.y), dev(s.z), *v, *f, s.box, dcm.make_lj(), rule, grid,
+                     dcm.rc_grid_for(rule, grid), dt=0.005, nsteps=0, prec=prec, rc=rc)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+    np.testing.assert_allclose(host(rc), ref_d["rc"], rtol=1e-12, atol=0)
+    idx = workloads.sample_indices(s.n, 1024, seed=5151)
+    near = np.argsort(np.abs(ref_d["delta"] - 0.5))[:256]
+    idx = np.unique(np.concatenate([idx, near]))
+    ref = oracle.forces(s.x, s.y, s.z, ref_d["rc"], s.box, idx=idx)
+    F = np.stack([host(t) for t in f], 1)[idx]
+    emax, erms = force_errors(F, _ref_F(ref))
+    tol = 1e-12 if prec == dcm.DCM_FP64 else 1e-5
+    print(f"[gpu]   {name} prec={prec} err_max={emax:.3e} err_rms={erms:.3e}", flush=True)
+    assert emax <= tol and erms <= tol
