@@ -169,7 +169,7 @@ dcm_status dcm_destroy(dcm_ctx *ctx) {
                     &ctx->cell_start, &ctx->cell_fill, &ctx->perm,    &ctx->sorted,
                     &ctx->scan_tmp, &ctx->scalars, &ctx->ext_count, &ctx->ext_start,
                     &ctx->ext_pos, &ctx->ws[0], &ctx->ws[1], &ctx->ws_owner[0],
-                    &ctx->ws_owner[1]};
+                    &ctx->ws_owner[1], &ctx->ext_rel};
   for (DevBuf *b : bufs)
     if (b->p) hipFree(b->p);
   batch_free(ctx);
@@ -401,6 +401,9 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   DCM_TRY(ensure(ctx, ctx->ext_start, (next + 1) * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_elems(std::max(ncell, next)) * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->ext_pos, ext_cap * sizeof(double4)));
+  // FP32-mixed builds also write the compact records the pair kernel reads
+  const bool rel = prec == DCM_FP32_MIXED && halo[1] <= kRelMaxHalo && halo[2] <= kRelMaxHalo;
+  if (rel) DCM_TRY(ensure(ctx, ctx->ext_rel, ext_cap * sizeof(float4)));
   ctx->ext_cap = ext_cap;
   hipStream_t s = ctx->stream;
   hipEvent_t ev;
@@ -418,7 +421,8 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
                 ptr<double4>(ctx->sorted));
   launch_ext_build(s, ptr<int32_t>(ctx->cell_start), ptr<double4>(ctx->sorted), nc, halo, box.L,
                    ext_cap, ptr<int32_t>(ctx->ext_count), ptr<int32_t>(ctx->ext_start),
-                   ptr<int32_t>(ctx->scan_tmp), ptr<double4>(ctx->ext_pos), ctx->d_status);
+                   ptr<int32_t>(ctx->scan_tmp), ptr<double4>(ctx->ext_pos),
+                   rel ? ptr<float4>(ctx->ext_rel) : nullptr, ctx->d_status);
   // exact ghost-extended count, read by a later build to size the buffer
   hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
                  hipMemcpyDeviceToHost, s);
@@ -435,6 +439,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   }
   ctx->cell_n = n;
   ctx->cell_prec = prec;
+  ctx->cell_rel = rel;
   ctx->rc_bound = rc_cap;
   return check_launch(ctx, "dcm_build_cells");
 }
@@ -473,6 +478,13 @@ dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_f
   a.cell_start = ptr<int32_t>(ctx->cell_start);
   a.perm = ptr<int32_t>(ctx->perm);
   a.ext_pos = ptr<double4>(ctx->ext_pos);
+  // FP32-mixed own-cutoff forces on an FP32-mixed build read the compact records
+  const bool rel = ctx->cell_rel && prec == DCM_FP32_MIXED && pair_rule == DCM_PAIR_OWN;
+  a.ext_rel = rel ? ptr<float4>(ctx->ext_rel) : nullptr;
+  double span = 0.0;  // largest coordinate magnitude in the extended grid
+  for (int k = 0; k < 3; ++k)
+    span = std::max(span, ctx->cell_box.L[k] + 2.0 * ctx->halo[k] * ctx->cell_len[k]);
+  a.rel_delta = rel_record_delta(ctx->cell_len, span);
   a.ext_start = ptr<int32_t>(ctx->ext_start);
   a.n = n;
   a.ext_cap = ctx->ext_cap;

@@ -39,11 +39,12 @@ struct BatchState {
   std::vector<int2> eblk;
   std::vector<int32_t> queue;
   int64_t n_total = 0, cells_total = 0, ext_cells_total = 0, ext_cap = 0;
+  bool rel_ok = true;  // every system's halos fit the compact records
   size_t off_geo = 0, off_items = 0, off_eblk = 0, off_queue = 0, table_bytes = 0;
   std::vector<unsigned char> table_host;
   // device memory
   DevBuf tables, cell_of, cell_count, cell_fill, cell_start, perm, sorted, scan_tmp, ext_count,
-      ext_start, ext_pos, partials, rcmax, head;
+      ext_start, ext_pos, ext_rel, partials, rcmax, head;
   // recorded graph
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -93,6 +94,7 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   std::vector<double> cost_pp(nsys, 0.0);
   int64_t p0 = 0, cell0 = 0, ext_cell0 = 0;
   double ext_bound = 0.0;
+  B.rel_ok = true;
   for (int32_t b = 0; b < nsys; ++b) {
     const dcm_system &d = B.desc[b];
     SysGeom &g = B.geo[b];
@@ -132,6 +134,10 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
       if (cells >= (int64_t(1) << 30) || next >= (int64_t(1) << 30))
         return fail(ctx, DCM_ERR_RANGE, "dcm_forces_batched: too many cells");
     }
+    double span = 0.0;  // largest coordinate magnitude in the extended grid
+    for (int a = 0; a < 3; ++a) span = std::max(span, g.L[a] + 2.0 * g.h[a] * g.len[a]);
+    g.rel_delta = rel_record_delta(g.len, span);
+    if (g.h[1] > kRelMaxHalo || g.h[2] > kRelMaxHalo) B.rel_ok = false;
     g.p0 = p0;
     g.cell0 = cell0;
     g.ext_cell0 = ext_cell0;
@@ -206,6 +212,7 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   if ((st = ensure(ctx, B.ext_start, sizeof(int32_t) * (B.ext_cells_total + 1))) != DCM_OK)
     return st;
   if ((st = ensure(ctx, B.ext_pos, sizeof(double4) * B.ext_cap)) != DCM_OK) return st;
+  if (B.rel_ok && (st = ensure(ctx, B.ext_rel, sizeof(float4) * B.ext_cap)) != DCM_OK) return st;
   if ((st = ensure(ctx, B.partials,
                    sizeof(double) * kPartialSlots * std::max<int64_t>(nitems, 1))) != DCM_OK)
     return st;
@@ -231,6 +238,10 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   const int2 *eblk = dptr<int2>(B.tables, B.off_eblk);
   const int32_t *queue = dptr<int32_t>(B.tables, B.off_queue);
   const int64_t nitems = (int64_t)B.items.size();
+  // FP32-mixed own-cutoff forces read the compact records
+  float4 *rel = (B.rel_ok && prec == DCM_FP32_MIXED && rule == DCM_PAIR_OWN)
+                    ? dptr<float4>(B.ext_rel)
+                    : nullptr;
   hipEvent_t ev = nullptr;
   if (timed) timer_begin(ctx, "batch_cells", &ev);
   launch_fill_i32(s, dptr<int32_t>(B.cell_count), 0, B.cells_total);
@@ -250,7 +261,7 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   launch_batch_ext(s, geo, eblk, (int64_t)B.eblk.size(), dptr<int32_t>(B.cell_start),
                    dptr<double4>(B.sorted), B.ext_cells_total, B.ext_cap,
                    dptr<int32_t>(B.ext_count), dptr<int32_t>(B.ext_start),
-                   dptr<int32_t>(B.scan_tmp), dptr<double4>(B.ext_pos), ctx->d_status);
+                   dptr<int32_t>(B.scan_tmp), dptr<double4>(B.ext_pos), rel, ctx->d_status);
   if (timed) timer_end(ctx, "batch_cells", ev);
   BatchPairArgs a;
   a.sys = geo;
@@ -262,6 +273,7 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   a.cell_start = dptr<int32_t>(B.cell_start);
   a.perm = dptr<int32_t>(B.perm);
   a.ext_pos = dptr<double4>(B.ext_pos);
+  a.ext_rel = rel;
   a.ext_start = dptr<int32_t>(B.ext_start);
   a.ext_cap = B.ext_cap;
   a.rc_max_bits = dptr<unsigned long long>(B.rcmax);
@@ -336,7 +348,7 @@ void batch_free(dcm_ctx *ctx) {
   B->drop_graph();
   DevBuf *bufs[] = {&B->tables,    &B->cell_of,   &B->cell_count, &B->cell_fill, &B->cell_start,
                     &B->perm,      &B->sorted,    &B->scan_tmp,   &B->ext_count, &B->ext_start,
-                    &B->ext_pos,   &B->partials,  &B->rcmax,      &B->head};
+                    &B->ext_pos,   &B->ext_rel,   &B->partials,  &B->rcmax,      &B->head};
   for (DevBuf *b : bufs)
     if (b->p) hipFree(b->p);
   if (B->cap) hipStreamDestroy(B->cap);

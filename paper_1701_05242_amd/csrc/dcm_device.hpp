@@ -39,6 +39,22 @@ __device__ __forceinline__ bool finite3(double a, double b, double c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
+// Compact candidate record of the FP32-mixed pair kernel (16 bytes instead of
+// 32): the position relative to the centre of its extended cell (ex, ey, ez)
+// in FP32 -- each component lies within half a cell edge of 0, so it keeps
+// a few 1e-8 of absolute precision -- and ex + 1/2 (exact in FP32) in the
+// last word.  A lane rebuilds the separation in FP64 from its own position
+// and the cell centre.
+__device__ __forceinline__ float4 rel_record(const double4 &q, int ex, int ey, int ez,
+                                             const double len[3]) {
+  float4 r;
+  r.x = (float)(q.x - ((double)ex + 0.5) * len[0]);
+  r.y = (float)(q.y - ((double)ey + 0.5) * len[1]);
+  r.z = (float)(q.z - ((double)ez + 0.5) * len[2]);
+  r.w = (float)ex + 0.5f;
+  return r;
+}
+
 // Ghost-extended cell grid: the cell grid grown by h[a] cells on both sides
 // of every axis.  Extended cell (ex, ey, ez) holds a copy of real cell
 // (ex - h[0], ey - h[1], ez - h[2]) wrapped into the box, with positions

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <map>
@@ -31,6 +33,22 @@ constexpr int kPartialSlots = 8;      // per-block partial sums: E, W[6], pair c
 constexpr int kReorderEvery = 8;      // dcm_step re-sorts its working copies this often
 // the pair kernel addresses the ghost-extended array with 32-bit byte offsets
 constexpr int64_t kMaxExtSlots = (int64_t(1) << 27) - 1;
+
+// Bound on the per-coordinate error of a separation rebuilt from the compact
+// (cell-centre-relative FP32) candidate records: half an FP32 ulp of the
+// largest offset from a cell centre (half the largest cell edge, widened a
+// hair for particles binned across a rounded cell boundary), plus the FP64
+// rounding of forming the offset and of rebuilding, each at most a few units
+// of 2^-53 of the largest extended-grid coordinate `span`.
+inline double rel_record_delta(const double len[3], double span) {
+  const double m = std::max(len[0], std::max(len[1], len[2]));
+  int e = 0;
+  std::frexp(0.5 * m * (1.0 + 1e-9), &e);  // in [2^(e-1), 2^e): ulp 2^(e-24)
+  return std::ldexp(1.0, e - 25) + 1e-15 * (span + 1.0);
+}
+// the compact-record path packs a row's cell offset from the lane's cell in
+// 8 bits, so it needs halos of at most this many cells
+constexpr int kRelMaxHalo = 127;
 
 // Device-resident control block: scalars produced and consumed on the device
 // so that no stage needs a host round trip.
@@ -77,6 +95,7 @@ struct SysGeom {
   int64_t ext_cell0;  // first extended cell
   int64_t item0;      // first pair work item (blocks of 256 particles)
   int64_t nitems;
+  double rel_delta;   // error bound of the compact records (rel_record_delta)
   int32_t nc[3], h[3], ne[3];
   double len[3], sc[3], L[3];
   double rc_cap;
@@ -100,6 +119,7 @@ struct dcm_ctx {
   // cells
   dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp;
   dcm::DevBuf ext_count, ext_start, ext_pos;
+  dcm::DevBuf ext_rel;  // FP32-mixed builds: compact cell-relative copy of ext_pos
   int64_t ext_cap = 0;             // particles ext_pos can hold
   int32_t *h_ext_total = nullptr;  // pinned: ghost-extended count of the last build
   int32_t nc[3] = {0, 0, 0};
@@ -110,6 +130,7 @@ struct dcm_ctx {
   dcm_box cell_box = {{0, 0, 0}};
   int64_t cell_n = -1;
   int cell_prec = 0;
+  bool cell_rel = false;  // the last build wrote ext_rel
   // dcm_step's working copies in cell order: two sets of 11 fields (x y z,
   // vx vy vz, fx fy fz, delta, rc) and the caller index of each slot
   dcm::DevBuf ws[2], ws_owner[2];
@@ -196,7 +217,7 @@ void launch_gather(hipStream_t s, const double *x, const double *y, const double
 void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
                       const int32_t nc[3], const int32_t h[3], const double L[3],
                       int64_t ext_cap, int32_t *ext_count, int32_t *ext_start,
-                      int32_t *scan_tmp, double4 *ext_pos, uint32_t *status);
+                      int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel, uint32_t *status);
 
 // k_pair.hip
 struct PairArgs {
@@ -204,6 +225,8 @@ struct PairArgs {
   const int32_t *cell_start; // real cells [ncell + 1]
   const int32_t *perm;       // sorted -> caller index
   const double4 *ext_pos;    // real cells plus periodic ghost images, by extended cell
+  const float4 *ext_rel;     // compact cell-relative copy of ext_pos, or null
+  double rel_delta;          // its per-coordinate error bound
   const int32_t *ext_start;  // extended cells [next + 1]
   int64_t n;
   int64_t ext_cap;           // capacity of ext_pos
@@ -234,6 +257,7 @@ struct BatchPairArgs {
   const double4 *pos;         // sorted particles, concatenated
   const int32_t *cell_start;  // concatenated real cells
   const int32_t *perm;        // sorted slot -> concatenated particle id
+  const float4 *ext_rel;      // compact cell-relative copy of ext_pos, or null
   const double4 *ext_pos;
   const int32_t *ext_start;   // concatenated extended cells
   int64_t ext_cap;
@@ -259,7 +283,7 @@ void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, in
 void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64_t neblk,
                       const int32_t *cell_start, const double4 *sorted, int64_t next_total,
                       int64_t ext_cap, int32_t *ext_count, int32_t *ext_start, int32_t *scan_tmp,
-                      double4 *ext_pos, uint32_t *status);
+                      double4 *ext_pos, float4 *ext_rel, uint32_t *status);
 void launch_batch_reduce(hipStream_t s, const SysGeom *sys, int32_t nsys,
                          const double *partials, int ev_flags);
 void launch_fill_u64(hipStream_t s, unsigned long long *p, unsigned long long v, int64_t n);

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBatchBlock) void kb_ext_fill(
     const SysGeom *__restrict__ sys, const int2 *__restrict__ eblk,
     const int32_t *__restrict__ cell_start, const int32_t *__restrict__ ext_start,
     const double4 *__restrict__ sorted, int64_t cap, double4 *__restrict__ ext_pos,
-    uint32_t *status) {
+    float4 *__restrict__ ext_rel, uint32_t *status) {
   int64_t first;
   const int b = block_system(eblk, first);
   const SysGeom &g = sys[b];
@@ -153,12 +153,16 @@ __global__ __launch_bounds__(kBatchBlock) void kb_ext_fill(
     atomicOr(status, ST_GHOST_OVERFLOW);
     return;
   }
+  const int ex = (int)(e % g.ne[0]) - g.h[0];
+  const int ey = (int)((e / g.ne[0]) % g.ne[1]) - g.h[1];
+  const int ez = (int)(e / ((int64_t)g.ne[0] * g.ne[1])) - g.h[2];
   for (int k = a0; k < a1; ++k, ++o) {
     double4 q = sorted[k];
     q.x = q.x + sx;
     q.y = q.y + sy;
     q.z = q.z + sz;
     ext_pos[o] = q;
+    if (ext_rel) ext_rel[o] = rel_record(q, ex, ey, ez, g.len);
   }
 }
 
@@ -220,13 +224,13 @@ void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, in
 void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64_t neblk,
                       const int32_t *cell_start, const double4 *sorted, int64_t next_total,
                       int64_t ext_cap, int32_t *ext_count, int32_t *ext_start, int32_t *scan_tmp,
-                      double4 *ext_pos, uint32_t *status) {
+                      double4 *ext_pos, float4 *ext_rel, uint32_t *status) {
   if (neblk <= 0) return;
   hipLaunchKernelGGL(kb_ext_count, dim3((unsigned)neblk), dim3(kBatchBlock), 0, s, sys, eblk,
                      cell_start, ext_count);
   launch_exclusive_scan(s, ext_count, ext_start, next_total, scan_tmp);
   hipLaunchKernelGGL(kb_ext_fill, dim3((unsigned)neblk), dim3(kBatchBlock), 0, s, sys, eblk,
-                     cell_start, ext_start, sorted, ext_cap, ext_pos, status);
+                     cell_start, ext_start, sorted, ext_cap, ext_pos, ext_rel, status);
 }
 
 void launch_batch_reduce(hipStream_t s, const SysGeom *sys, int32_t nsys,

@@ -320,7 +320,10 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
                                                   const double4 *__restrict__ sorted, ExtGeom g,
                                                   int64_t next, int64_t cap,
                                                   double4 *__restrict__ ext_pos,
+                                                  float4 *__restrict__ ext_rel,
                                                   uint32_t *status) {
+  const double len[3] = {g.L[0] / (double)g.nc[0], g.L[1] / (double)g.nc[1],
+                         g.L[2] / (double)g.nc[2]};
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < next;
        e += (int64_t)gridDim.x * blockDim.x) {
     int rc, p[3];
@@ -333,12 +336,17 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
       atomicOr(status, ST_GHOST_OVERFLOW);
       continue;
     }
+    // extended cell coordinates, relative to the real grid
+    const int ex = (int)(e % g.ne[0]) - g.h[0];
+    const int ey = (int)((e / g.ne[0]) % g.ne[1]) - g.h[1];
+    const int ez = (int)(e / ((int64_t)g.ne[0] * g.ne[1])) - g.h[2];
     for (int k = a; k < b; ++k, ++o) {
       double4 q = sorted[k];
       q.x = q.x + sx;
       q.y = q.y + sy;
       q.z = q.z + sz;
       ext_pos[o] = q;
+      if (ext_rel) ext_rel[o] = rel_record(q, ex, ey, ez, len);
     }
   }
 }
@@ -346,7 +354,7 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
 void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
                       const int32_t nc[3], const int32_t h[3], const double L[3],
                       int64_t ext_cap, int32_t *ext_count, int32_t *ext_start,
-                      int32_t *scan_tmp, double4 *ext_pos, uint32_t *status) {
+                      int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel, uint32_t *status) {
   ExtGeom g;
   int64_t next = 1;
   for (int a = 0; a < 3; ++a) {
@@ -362,7 +370,7 @@ void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *s
                      ext_count);
   launch_exclusive_scan(s, ext_count, ext_start, next, scan_tmp);
   hipLaunchKernelGGL(k_ext_fill, dim3((unsigned)b), dim3(256), 0, s, cell_start, ext_start,
-                     sorted, g, next, ext_cap, ext_pos, status);
+                     sorted, g, next, ext_cap, ext_pos, ext_rel, status);
 }
 
 }  // namespace dcm

@@ -28,6 +28,10 @@ constexpr int kSegCap = DCM_PAIR_SEGCAP;  // row ranges per lane per chunk (LDS:
 #define DCM_PAIR_XCD_GROUP 16
 #endif
 constexpr int kXcdGroup = DCM_PAIR_XCD_GROUP;
+#ifndef DCM_PAIR_FILL
+#define DCM_PAIR_FILL 2
+#endif
+constexpr int kFillRows = DCM_PAIR_FILL;  // cell rows whose starts are read together
 int pair_block_size() { return kPairBlock; }
 
 // Per-lane accumulators.
@@ -187,6 +191,8 @@ struct PairView {
   const int32_t *perm;           // sorted slot -> particle id
   int64_t id0;                   // particle id of the system's first caller index
   const double4 *ext_pos;        // extended (ghost) array
+  const float4 *ext_rel;         // its compact cell-relative copy (FP32-mixed builds)
+  double rel_delta;              // bound on the per-coordinate error of ext_rel
   const int32_t *ext_start;      // this system's extended cells -> extended slots
   int64_t ext_cap;
   int nc[3], h[3], ne[3];
@@ -197,89 +203,308 @@ struct PairView {
   int32_t *nnbr;
 };
 
+// One lane's particle and search window.
+struct LaneGeo {
+  double xi, yi, zi, rci, rci2, R2, guard;
+  // compact records: a rebuilt r^2 below tin is surely inside the cutoff, one
+  // within margin of rci2 cannot be decided; a0y, a0z are yi, zi relative to
+  // the centre of the lane's cell
+  double tin, margin, a0y, a0z;
+  int zlo, zhi, ylo, yhi, cy, cz, self;
+};
+
+// One pair of the own-cutoff FP32-mixed kernel evaluated for every lane, the
+// result kept only where inc is set: the force of a lane without an
+// interaction in this step is computed and discarded instead of branched
+// around (the wavefront executes it anyway whenever any lane interacts).
+template <int EVM>
+__device__ __forceinline__ void interact_masked(Acc<DCM_FP32_MIXED> &acc, double dx, double dy,
+                                                double dz, double r2, double sig2, bool inc) {
+  const float r2i = recip_to_f32(r2);
+  const float s2 = (float)sig2 * r2i;
+  const float s6 = s2 * s2 * s2;
+  const float fpv = s6 * fmaf(2.0f, s6, -1.0f) * r2i;
+  const float fp = inc ? fpv : 0.0f;
+  const double fpd = (double)fp;
+  acc.fx = fma(fpd, dx, acc.fx);
+  acc.fy = fma(fpd, dy, acc.fy);
+  acc.fz = fma(fpd, dz, acc.fz);
+  if constexpr ((EVM & 1) != 0) {
+    const float et = s6 * (s6 - 1.0f);
+    acc.e += inc ? et : 0.0f;
+  }
+  if constexpr ((EVM & 2) != 0) {
+    const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
+    const float fdx = fp * dxf, fdy = fp * dyf, fdz = fp * dzf;
+    acc.w[0] = fmaf(fdx, dxf, acc.w[0]);
+    acc.w[1] = fmaf(fdy, dyf, acc.w[1]);
+    acc.w[2] = fmaf(fdz, dzf, acc.w[2]);
+    acc.w[3] = fmaf(fdy, dxf, acc.w[3]);
+    acc.w[4] = fmaf(fdz, dxf, acc.w[4]);
+    acc.w[5] = fmaf(fdz, dyf, acc.w[5]);
+  }
+}
+
+// Compact records are read through a buffer resource: 32-bit offsets, and a
+// read past the resource's size returns zeros instead of touching memory.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit dword access (gfx9 family)
+
+__device__ __forceinline__ float4 load_rel(__amdgpu_buffer_rsrc_t rs, int j) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, j << 4, 0, 0);
+  return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                     __uint_as_float(v.w));
+}
+
+// Flat loop over the compact-record candidates of this lane's first nseg
+// listed rows (FP32-mixed, own-cutoff rule).  A list entry is (first slot,
+// length | (row y - cy) << 16 | (row z - cz) << 24), the offsets as signed
+// bytes; the lane's own slot is never listed.  Separations are rebuilt in
+// FP64 from the cell-centre-relative FP32 record; a pair whose rebuilt r^2
+// lies within the proven error margin of the cutoff cannot be decided here
+// and marks the lane for the exact pass.  The stream is advanced with
+// selects, two register sets take turns so that every record is loaded a
+// full candidate before its use.
+template <int EVM>
+__device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int nseg,
+                                         __amdgpu_buffer_rsrc_t rs, const LaneGeo &g,
+                                         const double len[3], double sig2,
+                                         Acc<DCM_FP32_MIXED> &acc, int &cnt, bool &redo) {
+  const int lane_id = threadIdx.x;
+  const int last = nseg - 1;
+  const uint2 s0 = segs[0][lane_id];
+  int j = (int)s0.x, jend = (int)s0.x + (int)(s0.y & 0xffffu), sidx = 1;
+  uint32_t tag = s0.y;
+  uint2 nx = segs[last < 1 ? last : 1][lane_id];
+  // next candidate of the stream and its row tag; -1 once exhausted
+  auto advance = [&](uint32_t &t) -> int {
+    const int jn = j + 1;
+    const bool sw = jn >= jend;
+    const bool ok = !sw || sidx < nseg;
+    j = sw ? (int)nx.x : jn;
+    jend = sw ? (int)nx.x + (int)(nx.y & 0xffffu) : jend;
+    tag = sw ? nx.y : tag;
+    sidx = sw ? sidx + 1 : sidx;
+    nx = segs[sidx < last ? sidx : last][lane_id];
+    t = tag;
+    return ok ? j : -1;
+  };
+  bool amb = false;
+  auto eval = [&](const float4 &r, uint32_t t) {
+    const int dyc = (int)(t << 8) >> 24, dzc = (int)t >> 24;
+    const double ay = fma(-(double)dyc, len[1], g.a0y);
+    const double az = fma(-(double)dzc, len[2], g.a0z);
+    const double dx = fma(-(double)r.w, len[0], g.xi) - (double)r.x;
+    const double dy = ay - (double)r.y, dz = az - (double)r.z;
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const bool inc = r2 < g.tin;
+    amb |= fabs(r2 - g.rci2) <= g.margin;
+    interact_masked<EVM>(acc, dx, dy, dz, r2, sig2, inc);
+    cnt += inc ? 1 : 0;
+  };
+  int ja = j;
+  uint32_t ta = tag, tb = 0;
+  float4 A = load_rel(rs, ja);
+  int jb = advance(tb);
+  while (true) {
+    float4 B = load_rel(rs, jb >= 0 ? jb : ja);
+    uint32_t tc = 0;
+    const int jc = jb >= 0 ? advance(tc) : -1;
+    eval(A, ta);
+    if (jb < 0) break;
+    A = load_rel(rs, jc >= 0 ? jc : jb);
+    uint32_t td = 0;
+    const int jd = jc >= 0 ? advance(td) : -1;
+    eval(B, tb);
+    if (jc < 0) break;
+    ja = jc;
+    ta = tc;
+    jb = jd;
+    tb = td;
+  }
+  redo |= amb;
+}
+
+// Walk this lane's rows (fill a list, scan it, repeat) for a lane with run
+// set.  REL: compact records (FP32-mixed, own-cutoff rule); else the FP64
+// records.
+template <int RULE, int PREC, int EVM, bool REL>
+__device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const LaneGeo &g,
+                                           double sig2, uint2 (*segs)[kPairBlock],
+                                           Acc<PREC> &acc, int &cnt, bool &redo) {
+  const int lane_id = threadIdx.x;
+  const int nx = v.nc[0], hx = v.h[0], hy = v.h[1], hz = v.h[2];
+  const int nex = v.ne[0], ney = v.ne[1];
+  int zc = g.zlo, yc = g.ylo;
+  bool rows_left = run;
+  __amdgpu_buffer_rsrc_t rs;
+  if constexpr (REL)
+    rs = __builtin_amdgcn_make_buffer_rsrc((void *)v.ext_rel, (short)0,
+                                           (int)(v.ext_cap * (int64_t)sizeof(float4)),
+                                           kBufferWord3);
+  while (rows_left) {
+    // ---- fill: append the ranges of the next rows to this lane's list,
+    // kFillRows rows at a time: the two ext_start reads of all of them are
+    // issued before the first is used, so their latencies overlap
+    int nseg = 0;
+    // a row adds at most two entries (compact records: the own row is split)
+    while (rows_left && nseg <= kSegCap - kFillRows - 1) {
+      int j0[kFillRows], j1[kFillRows], rz[kFillRows], ry[kFillRows];
+      bool ok[kFillRows];
+#pragma unroll
+      for (int k = 0; k < kFillRows; ++k) {
+        const int zcur = zc, ycur = yc;
+        bool in = rows_left;
+        if (rows_left && ++yc > g.yhi) {
+          yc = g.ylo;
+          if (++zc > g.zhi) rows_left = false;
+        }
+        double ez = 0.0, ey = 0.0;
+        if (zcur < g.cz) ez = g.zi - (double)(zcur + 1) * v.len[2];
+        else if (zcur > g.cz) ez = (double)zcur * v.len[2] - g.zi;
+        ez = ez > g.guard ? ez - g.guard : 0.0;
+        if (ycur < g.cy) ey = g.yi - (double)(ycur + 1) * v.len[1];
+        else if (ycur > g.cy) ey = (double)ycur * v.len[1] - g.yi;
+        ey = ey > g.guard ? ey - g.guard : 0.0;
+        const double rem = g.R2 - ez * ez - ey * ey;
+        in = in && rem >= 0.0;
+        // chord half-width, rounded up generously (it only selects cells)
+        const double w = in ? (double)(sqrtf((float)rem) * 1.00001f) + g.guard : 0.0;
+        const int xlo = clampi((int)floor((g.xi - w) * v.sc[0]), -hx, nx + hx - 1);
+        const int xhi = clampi((int)floor((g.xi + w) * v.sc[0]), -hx, nx + hx - 1);
+        // a row that is not taken still reads (its own cell row's) starts
+        const int zs = in ? zcur : g.cz, ys = in ? ycur : g.cy;
+        const int32_t *es = v.ext_start + ((int64_t)(zs + hz) * ney + (ys + hy)) * nex + hx;
+        j0[k] = es[xlo];
+        j1[k] = es[xhi + 1];
+        rz[k] = zcur;
+        ry[k] = ycur;
+        ok[k] = in;
+      }
+#pragma unroll
+      for (int k = 0; k < kFillRows; ++k) {
+        if (!ok[k]) continue;
+        const int a0 = j0[k];
+        const int a1 = j1[k] > v.ext_cap ? (int)v.ext_cap : j1[k];  // overflow (flagged at build)
+        if constexpr (REL) {
+          const uint32_t rowtag = ((uint32_t)(uint8_t)(ry[k] - g.cy) << 16) |
+                                  ((uint32_t)(uint8_t)(rz[k] - g.cz) << 24);
+          const bool own = g.self >= a0 && g.self < a1;
+          const int e1 = own ? g.self : a1;
+          // entries hold at most 65535 slots; a longer row goes to the exact pass
+          if (e1 - a0 > 65535 || (own && a1 - g.self - 1 > 65535)) {
+            redo = true;
+            continue;
+          }
+          if (e1 > a0) {
+            segs[nseg][lane_id] = make_uint2((uint32_t)a0, (uint32_t)(e1 - a0) | rowtag);
+            ++nseg;
+          }
+          if (own && a1 > g.self + 1) {
+            segs[nseg][lane_id] =
+                make_uint2((uint32_t)(g.self + 1), (uint32_t)(a1 - g.self - 1) | rowtag);
+            ++nseg;
+          }
+        } else {
+          if (a1 > a0) {
+            segs[nseg][lane_id] = make_uint2((uint32_t)a0, (uint32_t)a1);
+            ++nseg;
+          }
+        }
+      }
+    }
+    if (nseg > 0) {
+      if constexpr (REL)
+        scan_rel<EVM>(segs, nseg, rs, g, v.len, sig2, acc, cnt, redo);
+      else
+        scan_ranges<RULE, PREC, EVM>(segs, nseg, v.ext_pos, g.self, g.xi, g.yi, g.zi, g.rci,
+                                     g.rci2, sig2, acc, cnt);
+    }
+  }
+}
+
 // One block of kPairBlock particles: sorted slot s for this lane (active if
 // it holds a particle).  Writes the forces and, from lanes 0..7, the block's
-// partial sums E, W[6], pair count to partial_out.
-template <int RULE, int PREC, int EVM>
+// partial sums E, W[6], pair count to partial_out.  REL: FP32-mixed
+// own-cutoff evaluation on compact records, then the lanes that met an
+// undecidable pair are recomputed from the FP64 records.
+template <int RULE, int PREC, int EVM, bool REL>
 __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool active, double eps,
                                            double sig2, uint2 (*segs)[kPairBlock],
                                            double (*red)[kPartialSlots], uint32_t *status,
                                            double *partial_out) {
-  const int lane_id = threadIdx.x;
   Acc<PREC> acc;
   int cnt = 0;
   const int nx = v.nc[0], ny = v.nc[1], nz = v.nc[2];
   const int hx = v.h[0], hy = v.h[1], hz = v.h[2];
   const int nex = v.ne[0], ney = v.ne[1];
-  double xi = 0, yi = 0, zi = 0, rci = 0, rci2 = 0, R2 = 0, guard = 0;
-  int zlo = 0, zhi = -1, ylo = 0, yhi = -1, zc = 0, yc = 0, cy = 0, cz = 0, self = -1;
+  LaneGeo g;
+  g.xi = g.yi = g.zi = g.rci = g.rci2 = g.R2 = g.guard = 0.0;
+  g.tin = g.margin = g.a0y = g.a0z = 0.0;
+  g.zlo = g.ylo = 0;
+  g.zhi = g.yhi = -1;
+  g.cy = g.cz = 0;
+  g.self = -1;
   if (active) {
     const double4 pi = v.pos[s];
-    xi = pi.x;
-    yi = pi.y;
-    zi = pi.z;
-    rci = pi.w;
-    double R = rci;
+    g.xi = pi.x;
+    g.yi = pi.y;
+    g.zi = pi.z;
+    g.rci = pi.w;
+    double R = g.rci;
     if constexpr (RULE == DCM_PAIR_MAX) {
       double rall = __longlong_as_double((long long)*v.rc_all_bits);
       R = rall > R ? rall : R;
     }
     R = R < v.rc_bound ? R : v.rc_bound;
-    rci2 = rci * rci;
+    g.rci2 = g.rci * g.rci;
     // search radius widened by a hair: rounding in the cell geometry can
     // only add candidates, never drop one
-    guard = 1e-9 * (v.len[0] + v.len[1] + v.len[2]);
-    const double Rg = R + guard;
-    R2 = Rg * Rg;
-    const int cx = slab_index(xi, v.sc[0], nx);
-    cy = slab_index(yi, v.sc[1], ny);
-    cz = slab_index(zi, v.sc[2], nz);
-    // the halo holds ceil(rc_bound/len) + 1 cells, so these stay inside it
-    zlo = clampi((int)floor((zi - Rg) * v.sc[2]), -hz, nz + hz - 1);
-    zhi = clampi((int)floor((zi + Rg) * v.sc[2]), -hz, nz + hz - 1);
-    ylo = clampi((int)floor((yi - Rg) * v.sc[1]), -hy, ny + hy - 1);
-    yhi = clampi((int)floor((yi + Rg) * v.sc[1]), -hy, ny + hy - 1);
-    zc = zlo;
-    yc = ylo;
-    // this particle's own copy in the extended array
-    const int real_cell = (cz * ny + cy) * nx + cx;
-    const int ext_cell = ((cz + hz) * ney + (cy + hy)) * nex + (cx + hx);
-    self = v.ext_start[ext_cell] + (int)(s - v.cell_start[real_cell]);
-  }
-  bool rows_left = active;
-  while (rows_left) {
-    // ---- fill: append the ranges of the next rows to this lane's list
-    int nseg = 0;
-    while (rows_left && nseg < kSegCap) {
-      const int zcur = zc, ycur = yc;
-      if (++yc > yhi) {
-        yc = ylo;
-        if (++zc > zhi) rows_left = false;
-      }
-      double ez = 0.0, ey = 0.0;
-      if (zcur < cz) ez = zi - (double)(zcur + 1) * v.len[2];
-      else if (zcur > cz) ez = (double)zcur * v.len[2] - zi;
-      ez = ez > guard ? ez - guard : 0.0;
-      if (ycur < cy) ey = yi - (double)(ycur + 1) * v.len[1];
-      else if (ycur > cy) ey = (double)ycur * v.len[1] - yi;
-      ey = ey > guard ? ey - guard : 0.0;
-      const double rem = R2 - ez * ez - ey * ey;
-      if (rem < 0.0) continue;
-      // chord half-width, rounded up generously (it only selects cells)
-      const double w = (double)(sqrtf((float)rem) * 1.00001f) + guard;
-      const int xlo = clampi((int)floor((xi - w) * v.sc[0]), -hx, nx + hx - 1);
-      const int xhi = clampi((int)floor((xi + w) * v.sc[0]), -hx, nx + hx - 1);
-      const int32_t *es = v.ext_start + ((int64_t)(zcur + hz) * ney + (ycur + hy)) * nex + hx;
-      int j0 = es[xlo], j1 = es[xhi + 1];
-      if (j1 > v.ext_cap) j1 = (int)v.ext_cap;  // overflowed ghosts (flagged at build)
-      if (j1 > j0) {
-        segs[nseg][lane_id] = make_uint2((uint32_t)j0, (uint32_t)j1);
-        ++nseg;
-      }
+    g.guard = 1e-9 * (v.len[0] + v.len[1] + v.len[2]);
+    const double Rg = R + g.guard;
+    g.R2 = Rg * Rg;
+    if constexpr (REL) {
+      // With per-coordinate errors d <= rel_delta, |rebuilt r^2 - r^2| <=
+      // E(r) = 2 sqrt(3) r d + 3 d^2 (+ FP64 rounding of r^2).  A pair with
+      // r^2 < rc^2 has r <= rc, so its rebuilt r^2 stays below rc^2 + E(rc);
+      // a pair with r^2 >= rc^2 has a rebuilt r^2 of at least rc^2 - E(rc),
+      // as r^2 - E(r) grows with r.  A margin of twice E(rc) therefore decides
+      // every pair with |rebuilt r^2 - rc^2| > margin exactly as the FP64
+      // records would.
+      const double d = v.rel_delta, r = Rg;
+      g.margin = 2.0 * (3.4641016151377548 * r * d + 3.0 * d * d + 1e-15 * r * r);
+      g.tin = g.rci2 - g.margin;
     }
-    if (nseg > 0)
-      scan_ranges<RULE, PREC, EVM>(segs, nseg, v.ext_pos, self, xi, yi, zi, rci, rci2, sig2, acc,
-                                   cnt);
+    const int cx = slab_index(g.xi, v.sc[0], nx);
+    g.cy = slab_index(g.yi, v.sc[1], ny);
+    g.cz = slab_index(g.zi, v.sc[2], nz);
+    if constexpr (REL) {
+      g.a0y = g.yi - ((double)g.cy + 0.5) * v.len[1];
+      g.a0z = g.zi - ((double)g.cz + 0.5) * v.len[2];
+    }
+    // the halo holds ceil(rc_bound/len) + 1 cells, so these stay inside it
+    g.zlo = clampi((int)floor((g.zi - Rg) * v.sc[2]), -hz, nz + hz - 1);
+    g.zhi = clampi((int)floor((g.zi + Rg) * v.sc[2]), -hz, nz + hz - 1);
+    g.ylo = clampi((int)floor((g.yi - Rg) * v.sc[1]), -hy, ny + hy - 1);
+    g.yhi = clampi((int)floor((g.yi + Rg) * v.sc[1]), -hy, ny + hy - 1);
+    // this particle's own copy in the extended array
+    const int real_cell = (g.cz * ny + g.cy) * nx + cx;
+    const int ext_cell = ((g.cz + hz) * ney + (g.cy + hy)) * nex + (cx + hx);
+    g.self = v.ext_start[ext_cell] + (int)(s - v.cell_start[real_cell]);
+  }
+  bool redo = false;
+  sweep_rows<RULE, PREC, EVM, REL>(v, active, g, sig2, segs, acc, cnt, redo);
+  if constexpr (REL) {
+    // rare: lanes with a pair too close to their cutoff to decide from the
+    // compact records start over on the FP64 records
+    if (__syncthreads_or(redo ? 1 : 0)) {
+      if (redo) {
+        acc = Acc<PREC>();
+        cnt = 0;
+      }
+      bool unused = false;
+      sweep_rows<RULE, PREC, EVM, false>(v, active && redo, g, sig2, segs, acc, cnt, unused);
+    }
   }
   if (active) {
     const double c24 = 24.0 * eps;
@@ -312,7 +537,7 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   }
 }
 
-template <int RULE, int PREC, int EVM>
+template <int RULE, int PREC, int EVM, bool REL>
 __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   __shared__ uint2 segs[kSegCap][kPairBlock];
   __shared__ double red[kPairBlock / 64][kPartialSlots];
@@ -324,6 +549,8 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   v.perm = a.perm;
   v.id0 = 0;
   v.ext_pos = a.ext_pos;
+  v.ext_rel = a.ext_rel;
+  v.rel_delta = a.rel_delta;
   v.ext_start = a.ext_start;
   v.ext_cap = a.ext_cap;
 #pragma unroll
@@ -340,14 +567,14 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   v.fy = a.fy;
   v.fz = a.fz;
   v.nnbr = a.nnbr;
-  pair_block<RULE, PREC, EVM>(v, s, s < a.n, a.eps, a.sigma * a.sigma, segs, red, a.status,
+  pair_block<RULE, PREC, EVM, REL>(v, s, s < a.n, a.eps, a.sigma * a.sigma, segs, red, a.status,
                               a.partials + lblock * kPartialSlots);
 }
 
 // Batched form: a persistent grid takes work items (blocks of kPairBlock
 // particles of one system) from a queue ordered by estimated cost.  Every
 // workgroup leaves the loop once the queue head passes the item count.
-template <int RULE, int PREC, int EVM>
+template <int RULE, int PREC, int EVM, bool REL>
 __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
   __shared__ uint2 segs[kSegCap][kPairBlock];
   __shared__ double red[kPairBlock / 64][kPartialSlots];
@@ -370,6 +597,8 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
     v.perm = a.perm;
     v.id0 = g.p0;
     v.ext_pos = a.ext_pos;
+    v.ext_rel = a.ext_rel;
+    v.rel_delta = g.rel_delta;
     v.ext_start = a.ext_start + g.ext_cell0;
     v.ext_cap = a.ext_cap;
 #pragma unroll
@@ -387,19 +616,20 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
     v.fz = g.fz;
     v.nnbr = g.nnbr;
     const int64_t local = first + threadIdx.x;
-    pair_block<RULE, PREC, EVM>(v, g.p0 + local, local < g.n, a.eps, sig2, segs, red, a.status,
+    pair_block<RULE, PREC, EVM, REL>(v, g.p0 + local, local < g.n, a.eps, sig2, segs, red,
+                                     a.status,
                                 a.partials + (int64_t)item * kPartialSlots);
   }
 }
 
-template <int RULE, int PREC>
+template <int RULE, int PREC, bool REL>
 static void launch_pair_ev(hipStream_t s, const PairArgs &a, dim3 g, dim3 b) {
   const int evm = ((a.ev_flags & DCM_EV_ENERGY) ? 1 : 0) | ((a.ev_flags & DCM_EV_VIRIAL) ? 2 : 0);
   switch (evm) {
-    case 0: hipLaunchKernelGGL((k_pair<RULE, PREC, 0>), g, b, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_pair<RULE, PREC, 1>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pair<RULE, PREC, 2>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pair<RULE, PREC, 3>), g, b, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_pair<RULE, PREC, 0, REL>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pair<RULE, PREC, 1, REL>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pair<RULE, PREC, 2, REL>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pair<RULE, PREC, 3, REL>), g, b, 0, s, a); break;
   }
 }
 
@@ -407,22 +637,23 @@ void launch_pair(hipStream_t s, const PairArgs &a, int rule, int prec) {
   const int64_t blocks = ceil_div(a.n, kPairBlock) > 0 ? ceil_div(a.n, kPairBlock) : 1;
   dim3 g((unsigned)blocks), b(kPairBlock);
   if (rule == DCM_PAIR_OWN) {
-    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_OWN, DCM_FP64>(s, a, g, b);
-    else launch_pair_ev<DCM_PAIR_OWN, DCM_FP32_MIXED>(s, a, g, b);
+    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_OWN, DCM_FP64, false>(s, a, g, b);
+    else if (a.ext_rel) launch_pair_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true>(s, a, g, b);
+    else launch_pair_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, false>(s, a, g, b);
   } else {
-    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_MAX, DCM_FP64>(s, a, g, b);
-    else launch_pair_ev<DCM_PAIR_MAX, DCM_FP32_MIXED>(s, a, g, b);
+    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_MAX, DCM_FP64, false>(s, a, g, b);
+    else launch_pair_ev<DCM_PAIR_MAX, DCM_FP32_MIXED, false>(s, a, g, b);
   }
 }
 
-template <int RULE, int PREC>
+template <int RULE, int PREC, bool REL>
 static void launch_pair_batched_ev(hipStream_t s, const BatchPairArgs &a, dim3 g, dim3 b) {
   const int evm = ((a.ev_flags & DCM_EV_ENERGY) ? 1 : 0) | ((a.ev_flags & DCM_EV_VIRIAL) ? 2 : 0);
   switch (evm) {
-    case 0: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 0>), g, b, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 1>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 2>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 3>), g, b, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 0, REL>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 1, REL>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 2, REL>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 3, REL>), g, b, 0, s, a); break;
   }
 }
 
@@ -434,11 +665,11 @@ static int64_t persistent_grid(int rule, int prec, int64_t nitems) {
   if (per_cu == 0) {
     const void *fn;
     if (rule == DCM_PAIR_OWN)
-      fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP64, 3>
-                            : (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP32_MIXED, 3>;
+      fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP64, 3, false>
+                            : (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP32_MIXED, 3, true>;
     else
-      fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP64, 3>
-                            : (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP32_MIXED, 3>;
+      fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP64, 3, false>
+                            : (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP32_MIXED, 3, false>;
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, kPairBlock, 0) != hipSuccess ||
         blocks < 1)
@@ -458,11 +689,12 @@ void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int pr
   if (a.nitems <= 0) return;
   dim3 g((unsigned)persistent_grid(rule, prec, a.nitems)), b(kPairBlock);
   if (rule == DCM_PAIR_OWN) {
-    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP64>(s, a, g, b);
-    else launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED>(s, a, g, b);
+    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP64, false>(s, a, g, b);
+    else if (a.ext_rel) launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true>(s, a, g, b);
+    else launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, false>(s, a, g, b);
   } else {
-    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP64>(s, a, g, b);
-    else launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP32_MIXED>(s, a, g, b);
+    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP64, false>(s, a, g, b);
+    else launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP32_MIXED, false>(s, a, g, b);
   }
 }
 

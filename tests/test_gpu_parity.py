@@ -225,6 +225,67 @@ def test_tiny_box_every_axis_wraps():
             assert emax <= 1e-12
 
 
+def cutoff_boundary_system(seed):
+    """Centres on a grid (spacing 10) with cutoffs in [2.5, 3.5], each with two
+    partners at distance rc_i (1 -/+ eps) for eps from 1e-13 to 1e-5 (partner
+    cutoff 0.5, so only the centre's decision counts).  The smallest eps lie
+    inside the undecidable band of the FP32-mixed compact records and must be
+    settled by the exact pass; the largest are decided from the records."""
+    rng = np.random.default_rng(seed)
+    box = (60.0, 60.0, 60.0)
+    g = np.arange(6) * 10.0 + 5.0
+    C = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    C = C + rng.uniform(-0.5, 0.5, C.shape)
+    m = len(C)
+    rcc = rng.uniform(2.5, 3.5, m)
+    eps = np.array([1e-13, 1e-11, 1e-9, 1e-7, 1e-5])[rng.integers(0, 5, m)]
+    u = rng.normal(size=(m, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    # the two partners on opposite sides of their centre
+    P = [C] + [C + (sign * rcc * (1.0 + sign * eps))[:, None] * u for sign in (-1.0, 1.0)]
+    X = np.concatenate(P)
+    rc = np.concatenate([rcc, np.full(2 * m, 0.5)])
+    sysm = workloads.System("boundary", X[:, 0].copy(), X[:, 1].copy(), X[:, 2].copy(),
+                            *(np.zeros(len(X)) for _ in range(3)), box)
+    return sysm, rc
+
+
+def test_fp32_mixed_pairs_at_the_cutoff():
+    print("[gpu] FP32-mixed pairs within 1e-13..1e-5 of the cutoff", flush=True)
+    s, rc = cutoff_boundary_system(11)
+    ref = oracle.forces(s.x, s.y, s.z, rc, s.box)
+    m = s.n // 3
+    # each centre sees exactly its inner partner
+    assert np.all(ref["nnbr"][:m] == 1) and np.all(ref["nnbr"][m:] == 0)
+    for edge in (0.9, 1.25, 3.6):
+        got = gpu_forces(s, rc, prec=dcm.DCM_FP32_MIXED, edge=edge, rc_bound=3.5)
+        assert got["status"] == dcm.DCM_OK
+        np.testing.assert_array_equal(got["nnbr"], ref["nnbr"])
+        emax, erms = force_errors(got["F"], _ref_F(ref))
+        assert emax <= 1e-5 and erms <= 1e-5, (edge, emax, erms)
+    # the batched form: two such systems in one pass
+    s2, rc2 = cutoff_boundary_system(12)
+    ref2 = oracle.forces(s2.x, s2.y, s2.z, rc2, s2.box)
+    batch = []
+    for t, r in ((s, rc), (s2, rc2)):
+        batch.append(dict(
+            x=dev(t.x), y=dev(t.y), z=dev(t.z), rc=dev(r),
+            fx=torch.zeros(t.n, **F64), fy=torch.zeros(t.n, **F64), fz=torch.zeros(t.n, **F64),
+            nnbr=torch.zeros(t.n, dtype=torch.int32, device=DEV),
+            energy=torch.zeros(1, **F64), virial=torch.zeros(6, **F64),
+            npairs=torch.zeros(1, dtype=torch.uint64, device=DEV),
+            box=t.box, cell_edge=1.25, rc_bound=3.5))
+    with Ctx() as ctx:
+        dcm.dcm_forces_batched(ctx, batch, dcm.make_lj(), prec=dcm.DCM_FP32_MIXED,
+                               ev_flags=dcm.DCM_EV_COUNTS)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
+    for d, r in zip(batch, (ref, ref2)):
+        np.testing.assert_array_equal(host(d["nnbr"]), r["nnbr"])
+        F = np.stack([host(d["fx"]), host(d["fy"]), host(d["fz"])], 1)
+        emax, erms = force_errors(F, _ref_F(r))
+        assert emax <= 1e-5 and erms <= 1e-5
+
+
 def test_static_cutoff_reduces_to_eq3_and_balances():
     s = workloads.make("slab_small")
     rc = np.full(s.n, 3.0)
