@@ -167,7 +167,8 @@ dcm_status dcm_destroy(dcm_ctx *ctx) {
                     &ctx->dB,       &ctx->dist,      &ctx->delta,     &ctx->rc,
                     &ctx->partials, &ctx->ke,        &ctx->cell_of,   &ctx->cell_count,
                     &ctx->cell_start, &ctx->cell_fill, &ctx->perm,    &ctx->sorted,
-                    &ctx->scan_tmp, &ctx->scalars, &ctx->ext_count, &ctx->ext_start,
+                    &ctx->scan_tmp, &ctx->scalars, &ctx->ext_row_count, &ctx->ext_row_start,
+                    &ctx->ext_row_lo, &ctx->ext_start, &ctx->rcmax_part,
                     &ctx->ext_pos, &ctx->ws[0], &ctx->ws[1], &ctx->ws_owner[0],
                     &ctx->ws_owner[1], &ctx->ext_rel};
   for (DevBuf *b : bufs)
@@ -295,7 +296,7 @@ dcm_status dcm_sweep_distance(dcm_ctx *ctx, const uint8_t *seg, const uint8_t *i
   hipStream_t s = ctx->stream;
   hipEvent_t ev;
   timer_begin(ctx, "sweep", &ev);
-  launch_fsm_init(s, seg, iface, nvox, ptr<double>(ctx->dA), ptr<double>(ctx->dB), flags,
+  launch_fsm_init(s, seg, iface, grid.n, ptr<double>(ctx->dA), ptr<double>(ctx->dB), chg0, flags,
                   max_waves);
   for (int w = 1; w <= max_waves; ++w)
     launch_fsm_step(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), chg0, chg1, grid.n, grid.h,
@@ -397,9 +398,13 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   if (want > (double)kMaxExtSlots)
     return fail(ctx, DCM_ERR_RANGE, "ghost-extended system too large");
   const int64_t ext_cap = std::max<int64_t>((int64_t)want, ctx->ext_cap);
-  DCM_TRY(ensure(ctx, ctx->ext_count, next * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->rcmax_part, cell_count_blocks(n) * sizeof(unsigned long long)));
+  const int64_t nrow1 = ext_row_scratch_elems(nc, halo);
+  DCM_TRY(ensure(ctx, ctx->ext_row_count, nrow1 * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->ext_row_start, nrow1 * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->ext_row_lo, nrow1 * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->ext_start, (next + 1) * sizeof(int32_t)));
-  DCM_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_elems(std::max(ncell, next)) * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_elems(std::max(ncell, nrow1)) * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->ext_pos, ext_cap * sizeof(double4)));
   // FP32-mixed builds also write the compact records the pair kernel reads
   const bool rel = prec == DCM_FP32_MIXED && halo[1] <= kRelMaxHalo && halo[2] <= kRelMaxHalo;
@@ -410,7 +415,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   timer_begin(ctx, "cells", &ev);
   launch_fill_i32(s, ptr<int32_t>(ctx->cell_count), 0, ncell);
   launch_cell_count(s, x, y, z, rc, n, box.L, nc, sc, rc_cap, cof, ptr<int32_t>(ctx->cell_count),
-                    ctx->ctl, ctx->d_status);
+                    ptr<unsigned long long>(ctx->rcmax_part), ctx->ctl, ctx->d_status);
   launch_exclusive_scan(s, ptr<int32_t>(ctx->cell_count), ptr<int32_t>(ctx->cell_start), ncell,
                         ptr<int32_t>(ctx->scan_tmp));
   launch_fill_i32(s, ptr<int32_t>(ctx->cell_fill), 0, ncell);
@@ -420,7 +425,8 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   launch_gather(s, x, y, z, rc, ptr<int32_t>(ctx->perm), n, box.L, rc_cap,
                 ptr<double4>(ctx->sorted));
   launch_ext_build(s, ptr<int32_t>(ctx->cell_start), ptr<double4>(ctx->sorted), nc, halo, box.L,
-                   ext_cap, ptr<int32_t>(ctx->ext_count), ptr<int32_t>(ctx->ext_start),
+                   ext_cap, ptr<int32_t>(ctx->ext_row_count), ptr<int32_t>(ctx->ext_row_start),
+                   ptr<int32_t>(ctx->ext_row_lo), ptr<int32_t>(ctx->ext_start),
                    ptr<int32_t>(ctx->scan_tmp), ptr<double4>(ctx->ext_pos),
                    rel ? ptr<float4>(ctx->ext_rel) : nullptr, ctx->d_status);
   // exact ghost-extended count, read by a later build to size the buffer

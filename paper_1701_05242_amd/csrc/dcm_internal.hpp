@@ -117,8 +117,8 @@ struct dcm_ctx {
   // particle scratch
   dcm::DevBuf delta, rc, partials, ke, scalars;
   // cells
-  dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp;
-  dcm::DevBuf ext_count, ext_start, ext_pos;
+  dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp, rcmax_part;
+  dcm::DevBuf ext_row_count, ext_row_start, ext_row_lo, ext_start, ext_pos;
   dcm::DevBuf ext_rel;  // FP32-mixed builds: compact cell-relative copy of ext_pos
   int64_t ext_cap = 0;             // particles ext_pos can hold
   int32_t *h_ext_total = nullptr;  // pinned: ghost-extended count of the last build
@@ -183,8 +183,9 @@ void launch_interface(hipStream_t s, const uint32_t *buf0, const uint32_t *buf1,
                       const int32_t nv[3], const Ctl *ctl, uint8_t *seg, uint8_t *iface);
 
 // k_fsm.hip
-void launch_fsm_init(hipStream_t s, const uint8_t *seg, const uint8_t *iface, int64_t nvox,
-                     double *dA, double *dB, uint32_t *flags, int max_steps);
+// initial distances; with tiles also the first pass's tile flags in chg0
+void launch_fsm_init(hipStream_t s, const uint8_t *seg, const uint8_t *iface, const int32_t nv[3],
+                     double *dA, double *dB, uint8_t *chg0, uint32_t *flags, int max_steps);
 // one launch of the sweep: a temporally blocked tile pass when fsm_tiled(nv),
 // else one synchronous wave; chg0/chg1 hold one flag per tile
 bool fsm_tiled(const int32_t nv[3]);
@@ -201,10 +202,12 @@ void launch_assign_cutoffs(hipStream_t s, const double *x, const double *y, cons
                            int64_t n, const double L[3], const int32_t nv[3],
                            const double sc[3], const double *dist, dcm_rule rule,
                            double *delta, double *rc);
+// workgroups of the cell-count kernel: the size of its block_max scratch
+int64_t cell_count_blocks(int64_t n);
 void launch_cell_count(hipStream_t s, const double *x, const double *y, const double *z,
                        const double *rc, int64_t n, const double L[3], const int32_t nc[3],
                        const double sc[3], double rc_cap, int32_t *cell_of, int32_t *cell_count,
-                       Ctl *ctl, uint32_t *status);
+                       unsigned long long *block_max, Ctl *ctl, uint32_t *status);
 void launch_exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64_t n,
                            int32_t *tmp);
 int64_t scan_tmp_elems(int64_t n);
@@ -214,10 +217,13 @@ void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell, i
 void launch_gather(hipStream_t s, const double *x, const double *y, const double *z,
                    const double *rc, const int32_t *perm, int64_t n, const double L[3],
                    double rc_cap, double4 *sorted);
+// rows of the extended grid + 1: the size of each per-row scratch array
+int64_t ext_row_scratch_elems(const int32_t nc[3], const int32_t h[3]);
 void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
                       const int32_t nc[3], const int32_t h[3], const double L[3],
-                      int64_t ext_cap, int32_t *ext_count, int32_t *ext_start,
-                      int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel, uint32_t *status);
+                      int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
+                      int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
+                      uint32_t *status);
 
 // k_pair.hip
 struct PairArgs {

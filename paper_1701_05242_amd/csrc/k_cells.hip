@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_cell_count(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     const double *__restrict__ rc, int64_t n, double Lx, double Ly, double Lz, int nx, int ny,
     int nz, double sx, double sy, double sz, double rc_cap, int32_t *__restrict__ cell_of,
-    int32_t *count, Ctl *ctl, uint32_t *status) {
+    int32_t *count, unsigned long long *__restrict__ block_max, uint32_t *status) {
   unsigned long long rmax = 0;
   // uniform trip count: every lane reaches the run-aggregated atomic
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -98,116 +98,193 @@ __global__ __launch_bounds__(256) void k_cell_count(
     }
     wave_run_add(count, (uint32_t)c, valid);
   }
+  // the workgroup's largest cutoff, stored without atomics (one address
+  // shared by every workgroup would serialise them)
+  __shared__ unsigned long long wmax[4];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     unsigned long long o = __shfl_xor(rmax, off, 64);
     rmax = o > rmax ? o : rmax;
   }
-  // most waves hold no new maximum: look before taking the atomic
-  if ((threadIdx.x & 63) == 0 && rmax > *(volatile unsigned long long *)&ctl->rc_max_bits)
-    atomicMax(&ctl->rc_max_bits, rmax);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = rmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = wmax[0];
+    for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+    block_max[blockIdx.x] = m;
+  }
 }
 
-__global__ void k_reset_rcmax(Ctl *ctl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->rc_max_bits = 0ull;
+// Largest of the workgroup maxima into the control block.
+__global__ __launch_bounds__(1024) void k_reduce_rcmax(const unsigned long long *__restrict__ bm,
+                                                       int64_t nb, Ctl *ctl) {
+  __shared__ unsigned long long wmax[16];
+  unsigned long long m = 0;
+  for (int64_t b = threadIdx.x; b < nb; b += 1024) m = bm[b] > m ? bm[b] : m;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) m = wmax[w] > m ? wmax[w] : m;
+    m = wmax[0] > m ? wmax[0] : m;
+    ctl->rc_max_bits = m;
+  }
+}
+
+int64_t cell_count_blocks(int64_t n) {
+  int64_t b = ceil_div(n, 256);
+  if (b > 16384) b = 16384;
+  return b < 1 ? 1 : b;
 }
 
 void launch_cell_count(hipStream_t s, const double *x, const double *y, const double *z,
                        const double *rc, int64_t n, const double L[3], const int32_t nc[3],
                        const double sc[3], double rc_cap, int32_t *cell_of, int32_t *cell_count,
-                       Ctl *ctl, uint32_t *status) {
-  hipLaunchKernelGGL(k_reset_rcmax, dim3(1), dim3(64), 0, s, ctl);
-  if (n <= 0) return;
-  int64_t b = ceil_div(n, 256);
-  if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_cell_count, dim3((unsigned)b), dim3(256), 0, s, x, y, z, rc, n, L[0],
-                     L[1], L[2], nc[0], nc[1], nc[2], sc[0], sc[1], sc[2], rc_cap, cell_of,
-                     cell_count, ctl, status);
+                       unsigned long long *block_max, Ctl *ctl, uint32_t *status) {
+  const int64_t b = cell_count_blocks(n);
+  if (n > 0)
+    hipLaunchKernelGGL(k_cell_count, dim3((unsigned)b), dim3(256), 0, s, x, y, z, rc, n, L[0],
+                       L[1], L[2], nc[0], nc[1], nc[2], sc[0], sc[1], sc[2], rc_cap, cell_of,
+                       cell_count, block_max, status);
+  hipLaunchKernelGGL(k_reduce_rcmax, dim3(1), dim3(1024), 0, s, block_max, n > 0 ? b : 0, ctl);
 }
 
 // ------------------------------------------------------- exclusive scan
-// Three phases over tiles of kScanTile elements: tile totals, a single-block
-// scan of the totals, then each tile's local scan plus its offset.
+// Three phases over tiles of kScanTile elements: tile totals, one workgroup
+// scanning the totals, then each tile's local scan plus its offset.  A thread
+// owns kScanPer consecutive elements, read and written as int4.
 constexpr int kScanThreads = 256;
-constexpr int kScanPer = 8;
+constexpr int kScanPer = 16;
 constexpr int kScanTile = kScanThreads * kScanPer;
+constexpr int kTotalsThreads = 1024;
 
 int64_t scan_tmp_elems(int64_t n) { return ceil_div(n, kScanTile) + 1; }
 
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *lds, int32_t *total) {
-  // lds: kScanThreads entries; Hillis-Steele inclusive scan, then shift
-  const int tid = threadIdx.x;
-  lds[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    int32_t o = tid >= off ? lds[tid - off] : 0;
-    __syncthreads();
-    lds[tid] += o;
-    __syncthreads();
+// Inclusive scan over the 64 lanes of a wavefront.
+__device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t o = __shfl_up(v, off, 64);
+    if (lane >= off) v += o;
   }
-  int32_t incl = lds[tid];
-  *total = lds[kScanThreads - 1];
+  return v;
+}
+
+// Exclusive scan over the workgroup (NW wavefronts); lds holds NW entries.
+template <int NW>
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *lds, int32_t *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int32_t incl = wave_inclusive_scan(v);
+  if (lane == 63) lds[w] = incl;
   __syncthreads();
-  return incl - v;
+  int32_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int32_t t = lds[k];
+    before += k < w ? t : 0;
+    all += t;
+  }
+  __syncthreads();  // lds may be reused after this
+  *total = all;
+  return before + incl - v;
+}
+
+// this thread's kScanPer elements starting at base (zeros past n)
+__device__ __forceinline__ void load_run(const int32_t *__restrict__ in, int64_t base, int64_t n,
+                                         int32_t (&v)[kScanPer]) {
+  if (base + kScanPer <= n) {
+    const int4 *p = reinterpret_cast<const int4 *>(in + base);
+#pragma unroll
+    for (int q = 0; q < kScanPer / 4; ++q) {
+      const int4 t = p[q];
+      v[4 * q] = t.x;
+      v[4 * q + 1] = t.y;
+      v[4 * q + 2] = t.z;
+      v[4 * q + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) v[q] = base + q < n ? in[base + q] : 0;
+  }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const int32_t *__restrict__ in,
                                                              int64_t n, int32_t *tile_sum) {
-  __shared__ int32_t lds[kScanThreads];
+  __shared__ int32_t lds[kScanThreads / 64];
   const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanPer;
+  int32_t v[kScanPer];
+  load_run(in, base, n, v);
   int32_t s = 0;
 #pragma unroll
-  for (int q = 0; q < kScanPer; ++q)
-    if (base + q < n) s += in[base + q];
+  for (int q = 0; q < kScanPer; ++q) s += v[q];
   int32_t total;
-  block_exclusive_scan(s, lds, &total);
+  block_exclusive_scan<kScanThreads / 64>(s, lds, &total);
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_totals(int32_t *tile_sum, int64_t ntiles,
-                                                              int32_t *out_last) {
-  __shared__ int32_t lds[kScanThreads];
-  int32_t carry = 0;
-  for (int64_t b0 = 0; b0 < ntiles; b0 += kScanThreads) {
-    int64_t t = b0 + threadIdx.x;
-    int32_t v = t < ntiles ? tile_sum[t] : 0;
-    int32_t total;
-    int32_t ex = block_exclusive_scan(v, lds, &total);
-    if (t < ntiles) tile_sum[t] = ex + carry;
-    carry += total;
+// Exclusive scan of the tile totals in place; each thread owns a run of
+// consecutive tiles.
+__global__ __launch_bounds__(kTotalsThreads) void k_scan_totals(int32_t *tile_sum, int64_t ntiles,
+                                                                int32_t *out_last) {
+  __shared__ int32_t lds[kTotalsThreads / 64];
+  const int64_t per = (ntiles + kTotalsThreads - 1) / kTotalsThreads;
+  const int64_t t0 = threadIdx.x * per;
+  const int64_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
+  int32_t s = 0;
+  for (int64_t t = t0; t < t1; ++t) s += tile_sum[t];
+  int32_t total;
+  int32_t run = block_exclusive_scan<kTotalsThreads / 64>(s, lds, &total);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int32_t v = tile_sum[t];
+    tile_sum[t] = run;
+    run += v;
   }
-  if (threadIdx.x == 0) *out_last = carry;
+  if (threadIdx.x == 0) *out_last = total;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *__restrict__ in,
                                                              int64_t n,
                                                              const int32_t *__restrict__ tile_off,
                                                              int32_t *__restrict__ out) {
-  __shared__ int32_t lds[kScanThreads];
+  __shared__ int32_t lds[kScanThreads / 64];
   const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanPer;
   int32_t v[kScanPer];
+  load_run(in, base, n, v);
   int32_t s = 0;
 #pragma unroll
-  for (int q = 0; q < kScanPer; ++q) {
-    v[q] = (base + q < n) ? in[base + q] : 0;
-    s += v[q];
-  }
+  for (int q = 0; q < kScanPer; ++q) s += v[q];
   int32_t total;
-  int32_t run = block_exclusive_scan(s, lds, &total) + tile_off[blockIdx.x];
+  int32_t run = block_exclusive_scan<kScanThreads / 64>(s, lds, &total) + tile_off[blockIdx.x];
+  int32_t o[kScanPer];
 #pragma unroll
   for (int q = 0; q < kScanPer; ++q) {
-    if (base + q < n) out[base + q] = run;
+    o[q] = run;
     run += v[q];
+  }
+  if (base + kScanPer <= n) {
+    int4 *p = reinterpret_cast<int4 *>(out + base);
+#pragma unroll
+    for (int q = 0; q < kScanPer / 4; ++q)
+      p[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q)
+      if (base + q < n) out[base + q] = o[q];
   }
 }
 
 void launch_exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64_t n,
                            int32_t *tmp) {
-  // out has n + 1 entries; out[n] = total
+  // out has n + 1 entries; out[n] = total.  in and out are 16-byte aligned.
   int64_t ntiles = ceil_div(n, kScanTile);
   if (ntiles < 1) ntiles = 1;
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n, tmp);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, s, tmp, ntiles, out + n);
+  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTotalsThreads), 0, s, tmp, ntiles, out + n);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n, tmp,
                      out);
 }
@@ -302,59 +379,143 @@ void launch_gather(hipStream_t s, const double *x, const double *y, const double
 // The extended grid (ExtGeom) lets a lane walk any row of cells around its
 // particle as one contiguous range of the extended array, without
 // wrap-around or image shifts.
-__global__ __launch_bounds__(256) void k_ext_count(const int32_t *__restrict__ cell_start,
-                                                   ExtGeom g, int64_t next,
-                                                   int32_t *__restrict__ ext_count) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < next;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int rc, p[3];
-    ext_to_real(g, e, rc, p);
-    ext_count[e] = cell_start[rc + 1] - cell_start[rc];
+//
+// It is built row by row.  An extended row (ey, ez) repeats real row
+// (ry, rz) periodically along x.  With S(r) the particles of the real row in
+// its cells [0, r) and T its total, the particles in unwrapped cells [0, u)
+// number F(u) = p T + S(r) for u = p n_x + r, 0 <= r < n_x, and the extended
+// row holds unwrapped cells [-h_x, n_x + h_x): its k-th particle is the
+// unwrapped particle P = F(-h_x) + k, i.e. particle P mod T of the real row
+// shifted by floor(P / T) periods.
+
+// floor(a / b) for b > 0
+__device__ __forceinline__ int floor_div(int a, int b) {
+  const int q = a / b;
+  return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+// Real row behind extended row (ey, ez): its first cell, and the y and z
+// periods crossed.
+struct ExtRow {
+  int r0;     // first real cell of the row
+  int py, pz;
+  int ey, ez;  // extended cell coordinates relative to the real grid
+};
+
+__device__ __forceinline__ ExtRow ext_row(const ExtGeom &g, int row) {
+  ExtRow r;
+  const int ez0 = row / g.ne[1];
+  const int ey = row - ez0 * g.ne[1] - g.h[1];
+  const int ez = ez0 - g.h[2];
+  const int ry = wrap_index(ey, g.nc[1]), rz = wrap_index(ez, g.nc[2]);
+  r.py = (ey - ry) / g.nc[1];
+  r.pz = (ez - rz) / g.nc[2];
+  r.r0 = (rz * g.nc[1] + ry) * g.nc[0];
+  r.ey = ey;
+  r.ez = ez;
+  return r;
+}
+
+// F(u) of the row starting at real cell r0 (T: the row's total)
+__device__ __forceinline__ int64_t row_prefix(const int32_t *__restrict__ cell_start, int r0,
+                                              int nx, int64_t T, int u) {
+  const int p = floor_div(u, nx);
+  const int r = u - p * nx;
+  return (int64_t)p * T + (cell_start[r0 + r] - cell_start[r0]);
+}
+
+// Per extended row: its particle count and F(-h_x).
+__global__ __launch_bounds__(256) void k_ext_rows(const int32_t *__restrict__ cell_start,
+                                                  ExtGeom g, int64_t nrows,
+                                                  int32_t *__restrict__ row_count,
+                                                  int32_t *__restrict__ row_lo) {
+  for (int row = blockIdx.x * blockDim.x + threadIdx.x; row < (int)nrows;
+       row += gridDim.x * blockDim.x) {
+    const ExtRow r = ext_row(g, row);
+    const int64_t T = cell_start[r.r0 + g.nc[0]] - cell_start[r.r0];
+    const int64_t lo = row_prefix(cell_start, r.r0, g.nc[0], T, -g.h[0]);
+    const int64_t hi = row_prefix(cell_start, r.r0, g.nc[0], T, g.nc[0] + g.h[0]);
+    row_count[row] = (int32_t)(hi - lo);
+    row_lo[row] = (int32_t)lo;
   }
 }
 
-// Writes stop at the buffer's capacity; running past it flags an overflow
-// (the pair kernel then refuses to read ghost ranges beyond the capacity).
+// ext_start of every extended cell (and of one past the last) from the row
+// starts.
+__global__ __launch_bounds__(256) void k_ext_starts(const int32_t *__restrict__ cell_start,
+                                                    const int32_t *__restrict__ row_start,
+                                                    const int32_t *__restrict__ row_lo,
+                                                    ExtGeom g, int64_t next, int64_t nrows,
+                                                    int32_t *__restrict__ ext_start) {
+  // next < 2^30 (checked at build), so 32-bit index arithmetic suffices
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e <= (int)next; e += gridDim.x * blockDim.x) {
+    if (e == (int)next) {
+      ext_start[e] = row_start[nrows];
+      continue;
+    }
+    const int row = e / g.ne[0];
+    const int ex = e - row * g.ne[0];
+    const ExtRow r = ext_row(g, row);
+    const int64_t T = cell_start[r.r0 + g.nc[0]] - cell_start[r.r0];
+    const int64_t f = row_prefix(cell_start, r.r0, g.nc[0], T, ex - g.h[0]);
+    ext_start[e] = (int32_t)(row_start[row] + (f - row_lo[row]));
+  }
+}
+
+// Copy of every extended row, one wavefront per row.  Writes stop at the
+// buffer's capacity; running past it flags an overflow (the pair kernel then
+// refuses to read ghost ranges beyond the capacity).
 __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ cell_start,
-                                                  const int32_t *__restrict__ ext_start,
+                                                  const int32_t *__restrict__ row_start,
+                                                  const int32_t *__restrict__ row_lo,
                                                   const double4 *__restrict__ sorted, ExtGeom g,
-                                                  int64_t next, int64_t cap,
+                                                  int64_t nrows, int64_t cap,
                                                   double4 *__restrict__ ext_pos,
                                                   float4 *__restrict__ ext_rel,
                                                   uint32_t *status) {
   const double len[3] = {g.L[0] / (double)g.nc[0], g.L[1] / (double)g.nc[1],
                          g.L[2] / (double)g.nc[2]};
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < next;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int rc, p[3];
-    ext_to_real(g, e, rc, p);
-    const double sx = (double)p[0] * g.L[0], sy = (double)p[1] * g.L[1],
-                 sz = (double)p[2] * g.L[2];
-    const int a = cell_start[rc], b = cell_start[rc + 1];
-    int64_t o = ext_start[e];
-    if (o + (b - a) > cap) {
-      atomicOr(status, ST_GHOST_OVERFLOW);
-      continue;
-    }
-    // extended cell coordinates, relative to the real grid
-    const int ex = (int)(e % g.ne[0]) - g.h[0];
-    const int ey = (int)((e / g.ne[0]) % g.ne[1]) - g.h[1];
-    const int ez = (int)(e / ((int64_t)g.ne[0] * g.ne[1])) - g.h[2];
-    for (int k = a; k < b; ++k, ++o) {
-      double4 q = sorted[k];
-      q.x = q.x + sx;
+  const double sc0 = (double)g.nc[0] / g.L[0];
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t row = wave; row < nrows; row += nwaves) {
+    const ExtRow r = ext_row(g, (int)row);
+    const int first = cell_start[r.r0];
+    const int T = cell_start[r.r0 + g.nc[0]] - first;
+    const int64_t o0 = row_start[row], cnt = row_start[row + 1] - o0;
+    const int lo = row_lo[row];
+    const double sy = (double)r.py * g.L[1], sz = (double)r.pz * g.L[2];
+    bool over = false;
+    for (int k = lane; k < cnt; k += 64) {
+      const int P = lo + k;
+      const int p = floor_div(P, T);  // cnt > 0 implies T > 0
+      const int64_t o = o0 + k;
+      if (o >= cap) {
+        over = true;
+        continue;
+      }
+      double4 q = sorted[first + (P - p * T)];
+      const int ex = slab_index(q.x, sc0, g.nc[0]) + p * g.nc[0];
+      q.x = q.x + (double)p * g.L[0];
       q.y = q.y + sy;
       q.z = q.z + sz;
       ext_pos[o] = q;
-      if (ext_rel) ext_rel[o] = rel_record(q, ex, ey, ez, len);
+      if (ext_rel) ext_rel[o] = rel_record(q, ex, r.ey, r.ez, len);
     }
+    if (over) atomicOr(status, ST_GHOST_OVERFLOW);
   }
+}
+
+int64_t ext_row_scratch_elems(const int32_t nc[3], const int32_t h[3]) {
+  return (int64_t)(nc[1] + 2 * h[1]) * (nc[2] + 2 * h[2]) + 1;
 }
 
 void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
                       const int32_t nc[3], const int32_t h[3], const double L[3],
-                      int64_t ext_cap, int32_t *ext_count, int32_t *ext_start,
-                      int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel, uint32_t *status) {
+                      int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
+                      int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
+                      uint32_t *status) {
   ExtGeom g;
   int64_t next = 1;
   for (int a = 0; a < 3; ++a) {
@@ -364,13 +525,20 @@ void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *s
     g.L[a] = L[a];
     next *= g.ne[a];
   }
-  int64_t b = ceil_div(next, 256);
+  const int64_t nrows = (int64_t)g.ne[1] * g.ne[2];
+  int64_t b = ceil_div(nrows, 256);
   if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_ext_count, dim3((unsigned)b), dim3(256), 0, s, cell_start, g, next,
-                     ext_count);
-  launch_exclusive_scan(s, ext_count, ext_start, next, scan_tmp);
-  hipLaunchKernelGGL(k_ext_fill, dim3((unsigned)b), dim3(256), 0, s, cell_start, ext_start,
-                     sorted, g, next, ext_cap, ext_pos, ext_rel, status);
+  hipLaunchKernelGGL(k_ext_rows, dim3((unsigned)b), dim3(256), 0, s, cell_start, g, nrows,
+                     row_count, row_lo);
+  launch_exclusive_scan(s, row_count, row_start, nrows, scan_tmp);
+  b = ceil_div(next + 1, 256);
+  if (b > 16384) b = 16384;
+  hipLaunchKernelGGL(k_ext_starts, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
+                     row_lo, g, next, nrows, ext_start);
+  b = ceil_div(nrows, 4);  // four rows per workgroup of 256
+  if (b > 16384) b = 16384;
+  hipLaunchKernelGGL(k_ext_fill, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
+                     row_lo, sorted, g, nrows, ext_cap, ext_pos, ext_rel, status);
 }
 
 }  // namespace dcm

@@ -33,18 +33,32 @@ int64_t fsm_tile_count(const int32_t nv[3]) {
   return ceil_div(nv[0], TX) * ceil_div(nv[1], TY) * ceil_div(nv[2], TZ);
 }
 
+__global__ void k_fsm_clear(uint8_t *chg0, int ntiles, uint32_t *flags, int nflags) {
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) chg0[t] = 0;
+  for (int f = threadIdx.x; f < nflags; f += blockDim.x) flags[f] = 0u;
+}
+
+// Sources (low-density phase and interface) start at 0, the rest at +inf.
+// With tiles, every tile holding an interface voxel is flagged as changed
+// before the first pass: only next to an interface can a pass change
+// anything at first (a liquid voxel with a source face neighbour is itself
+// an interface voxel).
 __global__ __launch_bounds__(256) void k_fsm_init(const uint8_t *__restrict__ seg,
                                                   const uint8_t *__restrict__ iface,
-                                                  int64_t nvox, double *dA, double *dB,
-                                                  uint32_t *flags, int nflags) {
+                                                  int64_t nvox, int nx, int ny, double *dA,
+                                                  double *dB, uint8_t *chg0, int ntx, int nty) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
        v += (int64_t)gridDim.x * blockDim.x) {
-    double d = (seg[v] == 0 || iface[v]) ? 0.0 : __builtin_huge_val();
+    const bool fc = iface[v] != 0;
+    double d = (seg[v] == 0 || fc) ? 0.0 : __builtin_huge_val();
     dA[v] = d;
     dB[v] = d;
+    if (fc && chg0) {
+      const int64_t row = v / nx;
+      const int x = (int)(v - row * nx), y = (int)(row % ny), z = (int)(row / ny);
+      chg0[((z / TZ) * nty + y / TY) * ntx + x / TX] = 1;
+    }
   }
-  if (blockIdx.x == 0)
-    for (int f = threadIdx.x; f < nflags; f += blockDim.x) flags[f] = 0u;
 }
 
 // Godunov solve: with the smaller face neighbour a_k and spacing h_k per axis
@@ -121,10 +135,11 @@ __global__ __launch_bounds__(kTileThreads) void k_fsm_tiles(double *dA, double *
     const int tr = t / ntx;
     const int ty = tr % nty;
     const int tz = tr / nty;
-    // active: first launch, or this tile or a neighbour changed last launch
-    if (tid == 0) act = (launch == 1);
+    // active: this tile or a neighbour changed in the last launch (before
+    // the first, the tiles holding interface voxels count as changed)
+    if (tid == 0) act = 0;
     __syncthreads();
-    if (launch > 1 && tid < 27) {
+    if (tid < 27) {
       const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
       const int nxp = wrap_index(tx + dx, ntx), nyp = wrap_index(ty + dy, nty),
                 nzp = wrap_index(tz + dz, ntz);
@@ -283,10 +298,15 @@ static SweepGeom geom(const int32_t nv[3], const double h[3], double rc_grid) {
   return g;
 }
 
-void launch_fsm_init(hipStream_t s, const uint8_t *seg, const uint8_t *iface, int64_t nvox,
-                     double *dA, double *dB, uint32_t *flags, int max_steps) {
-  hipLaunchKernelGGL(k_fsm_init, dim3(flat_grid(nvox)), dim3(256), 0, s, seg, iface, nvox, dA,
-                     dB, flags, max_steps + 2);
+void launch_fsm_init(hipStream_t s, const uint8_t *seg, const uint8_t *iface, const int32_t nv[3],
+                     double *dA, double *dB, uint8_t *chg0, uint32_t *flags, int max_steps) {
+  const int64_t nvox = (int64_t)nv[0] * nv[1] * nv[2];
+  const bool tiled = fsm_tiled(nv);
+  const int ntx = (int)ceil_div(nv[0], TX), nty = (int)ceil_div(nv[1], TY);
+  const int ntiles = tiled ? (int)fsm_tile_count(nv) : 0;
+  hipLaunchKernelGGL(k_fsm_clear, dim3(1), dim3(1024), 0, s, chg0, ntiles, flags, max_steps + 2);
+  hipLaunchKernelGGL(k_fsm_init, dim3(flat_grid(nvox)), dim3(256), 0, s, seg, iface, nvox, nv[0],
+                     nv[1], dA, dB, tiled ? chg0 : nullptr, ntx, nty);
 }
 
 void launch_fsm_step(hipStream_t s, double *dA, double *dB, uint8_t *chg0, uint8_t *chg1,

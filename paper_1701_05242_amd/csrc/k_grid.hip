@@ -135,23 +135,44 @@ void launch_gray(hipStream_t s, const uint32_t *counts, uint32_t *gray, const in
                      nv[2]);
 }
 
-// Histogram of the gray values: a private LDS histogram per workgroup,
-// filled with wave-aggregated atomics, merged once into the global one.
+// Histogram of the gray values: a private LDS histogram per workgroup, merged
+// once into the global one.  Each lane reads four voxels at a time.  The
+// low-density phase puts most voxels into the first few bins: a lane counts
+// those in registers and adds them to the LDS histogram once at the end;
+// every other voxel takes one LDS atomic (lanes that hit the same bin are
+// serialised by the LDS itself).
+constexpr int kHistLow = 3;
+
 __global__ __launch_bounds__(256) void k_hist(const uint32_t *__restrict__ gray, int64_t nvox,
                                               uint32_t *hist, uint32_t *status) {
   __shared__ uint32_t lh[kHistBins];
   for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) lh[b] = 0u;
   __syncthreads();
+  uint32_t low[kHistLow] = {0u, 0u, 0u};
   bool over = false;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < nvox; base += stride) {
-    const int64_t v = base + threadIdx.x;
-    uint32_t g = v < nvox ? gray[v] : 0u;
-    bool valid = v < nvox && g < (uint32_t)kHistBins;
-    over |= (v < nvox) && !valid;
-    wave_aggregated_add(lh, g, valid);
+  auto add = [&](uint32_t g) {
+#pragma unroll
+    for (int k = 0; k < kHistLow; ++k) low[k] += g == (uint32_t)k ? 1u : 0u;
+    if (g >= (uint32_t)kHistLow) {
+      if (g < (uint32_t)kHistBins) atomicAdd(&lh[g], 1u);
+      else over = true;
+    }
+  };
+  const int64_t nq = nvox >> 2;  // whole uint4 groups (gray is 16-byte aligned)
+  const uint4 *g4 = reinterpret_cast<const uint4 *>(gray);
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 v = g4[q];
+    add(v.x);
+    add(v.y);
+    add(v.z);
+    add(v.w);
   }
+  if (blockIdx.x == 0 && threadIdx.x < (nvox & 3)) add(gray[(nq << 2) + threadIdx.x]);
   if (over) atomicOr(status, ST_HIST_RANGE);
+#pragma unroll
+  for (int k = 0; k < kHistLow; ++k)
+    if (low[k]) atomicAdd(&lh[k], low[k]);
   __syncthreads();
   for (int b = threadIdx.x; b < kHistBins; b += blockDim.x)
     if (lh[b]) atomicAdd(&hist[b], lh[b]);
@@ -161,7 +182,7 @@ void launch_hist(hipStream_t s, const uint32_t *gray, int64_t nvox, uint32_t *hi
                  uint32_t *status) {
   int64_t b = ceil_div(nvox, 256 * 16);
   if (b < 1) b = 1;
-  if (b > 512) b = 512;
+  if (b > 2048) b = 2048;
   hipLaunchKernelGGL(k_hist, dim3((unsigned)b), dim3(256), 0, s, gray, nvox, hist, status);
 }
 
