@@ -43,6 +43,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--table1", action="store_true",
+                   help="only run the DCM-versus-static-cutoff timing of the paper's Table 1 "
+                        "settings on the 1.2M-particle planar slab and print that as the line")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of MIB MiB five times (the reference "
                         "kernel for scaling the HBM traffic counters) and exit")
@@ -110,6 +113,70 @@ def run_leg(s, prec, steps, warmup, dev):
                 pair_kernel_tflops=pairs * FLOP_PER_PAIR_FE / avg_pair_s / 1e12,
                 stage_ms={k: v[0] / max(v[1], 1) for k, v in fam_ms.items()},
                 stage_launches={k: v[1] for k, v in fam_ms.items()})
+
+
+# (rc_min, rc_max) settings of the paper's Table 1 and the speedups it prints
+# (DCM over a static cutoff rc = rc_max, planar system, Section 4.2)
+TABLE1 = ((3.0, 7.0, 2.31), (3.0, 8.0, 2.66), (3.5, 8.0, 2.38), (3.0, 9.0, 2.42), (3.5, 9.0, 2.23))
+
+
+def table1_leg(steps, warmup, dev, prec):
+    """Seconds per velocity-Verlet step of the planar slab under DCM (cutoff
+    ramp rc_max -> rc_min over 5 sigma from the interface, re-detection every
+    10 steps) and under a static cutoff rc_max for every particle (no
+    detection inside the timed steps), for each Table 1 setting."""
+    import torch
+
+    import paper_1701_05242_amd as dcm
+    import workloads
+
+    s = workloads.make("slab_table1")
+    f64 = dict(dtype=torch.float64, device=dev)
+    grid = dcm.make_grid(s.box, s.h)
+    lj = dcm.make_lj()
+
+    def run(rule_t, every):
+        pos = [torch.tensor(a, **f64) for a in (s.x, s.y, s.z)]
+        vel = [torch.tensor(a, **f64) for a in (s.vx, s.vy, s.vz)]
+        frc = [torch.zeros(s.n, **f64) for _ in range(3)]
+        rc = torch.zeros(s.n, **f64)
+        rule = dcm.make_rule(*rule_t)
+        rcg = dcm.rc_grid_for(rule, grid)
+        ctx = dcm.dcm_create()
+        try:
+            dcm.dcm_step(ctx, *pos, *vel, *frc, s.box, lj, rule, grid, rcg, 0.005, 0, prec=prec,
+                         rc=rc)
+            dcm.dcm_step(ctx, *pos, *vel, *frc, s.box, lj, rule, grid, rcg, 0.005, warmup,
+                         prec=prec, redetect_every=every, rc=rc)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dcm.dcm_step(ctx, *pos, *vel, *frc, s.box, lj, rule, grid, rcg, 0.005, steps,
+                         prec=prec, redetect_every=every, step0=warmup, rc=rc)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            npairs = torch.zeros(1, dtype=torch.uint64, device=dev)
+            dcm.dcm_build_cells(ctx, *pos, rc, s.box, 0.5 * rule_t[0], prec, rc_bound=rule_t[1])
+            dcm.dcm_forces(ctx, lj, *frc, prec=prec, ev_flags=dcm.DCM_EV_COUNTS, npairs=npairs)
+            if dcm.dcm_sync_status(ctx) != dcm.DCM_OK:
+                raise RuntimeError(dcm.dcm_last_error(ctx))
+            pairs = int(npairs.cpu().numpy()[0])
+        finally:
+            dcm.dcm_destroy(ctx)
+        return (t1 - t0) / steps * 1e3, pairs
+
+    rows = []
+    for rmin, rmax, paper in TABLE1:
+        dcm_ms, dcm_pairs = run((rmin, rmax, 5.0), 10)
+        static_ms, static_pairs = run((rmax, rmax, 5.0), 1 << 30)
+        rows.append(dict(setting=f"{rmin}/{rmax}", dcm_ms_per_step=dcm_ms,
+                         static_ms_per_step=static_ms, speedup=static_ms / dcm_ms,
+                         paper_speedup=paper, dcm_pairs=dcm_pairs, static_pairs=static_pairs,
+                         pair_ratio=static_pairs / dcm_pairs))
+        print(f"[bench] table1 {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
+    return dict(experiment="Table 1 analogue: DCM vs static rc = rc_max, planar slab",
+                workload=f"slab_table1: 120x120x250 LJ slab, N={s.n}, liquid 75 <= z < 175",
+                steps=steps, warmup=warmup, precision="fp32_mixed" if prec else "fp64",
+                redetect_every=10, rows=rows)
 
 
 def batched_leg(steps, dev):
@@ -284,9 +351,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    prec = dcm.DCM_FP32_MIXED if args.prec == "fp32_mixed" else dcm.DCM_FP64
+    if args.table1:
+        print(json.dumps(table1_leg(args.steps, args.warmup, dev, prec)), flush=True)
+        return
     s = workloads.make(args.workload)
     print(f"[bench] {s.name} n={s.n} box={s.box} rule={s.rule}", file=sys.stderr, flush=True)
-    prec = dcm.DCM_FP32_MIXED if args.prec == "fp32_mixed" else dcm.DCM_FP64
     main_leg = run_leg(s, prec, args.steps, args.warmup, dev)
     print(f"[bench] main leg {json.dumps(main_leg)}", file=sys.stderr, flush=True)
     fp64_leg = None

@@ -261,6 +261,14 @@ WORKLOADS = {
     # large slab: 160 x 160 x 400, liquid for 140 <= z < 260, ~2.6M particles
     "slab_large": dict(kind="slab", box=(160.0, 160.0, 400.0), z_lo=140.0,
                        thickness=120.0, rule=(2.5, 8.0, 5.0), index=2),
+    # planar slab of the paper's accuracy experiment (about 19,200 particles):
+    # 26.8 x 26.8 x 90, liquid for 28.5 <= z < 61.5, ~19.8k particles
+    "slab_fig6": dict(kind="slab", box=(26.8, 26.8, 90.0), z_lo=28.5, thickness=33.0,
+                      rule=(3.0, 8.0, 5.0), index=5),
+    # planar slab of the paper's DCM-versus-static timing (1024 cores x 1200
+    # particles): 120 x 120 x 250, liquid for 75 <= z < 175, ~1.2M particles
+    "slab_table1": dict(kind="slab", box=(120.0, 120.0, 250.0), z_lo=75.0, thickness=100.0,
+                        rule=(3.0, 8.0, 5.0), index=6),
     # droplet of radius 30 in a 120^3 box, ~123k particles
     "droplet": dict(kind="droplet", box=(120.0, 120.0, 120.0), radius=30.0,
                     rule=(2.5, 8.0, 5.0), index=3),
