@@ -37,14 +37,15 @@ struct BatchState {
   std::vector<SysGeom> geo;
   std::vector<int2> items;  // natural order: system-major, also the particle block table
   std::vector<int2> eblk;
+  std::vector<int2> rblk;  // (system, first extended row) per group of 256 rows
   std::vector<int32_t> queue;
-  int64_t n_total = 0, cells_total = 0, ext_cells_total = 0, ext_cap = 0;
+  int64_t n_total = 0, cells_total = 0, ext_cells_total = 0, ext_rows_total = 0, ext_cap = 0;
   bool rel_ok = true;  // every system's halos fit the compact records
-  size_t off_geo = 0, off_items = 0, off_eblk = 0, off_queue = 0, table_bytes = 0;
+  size_t off_geo = 0, off_items = 0, off_eblk = 0, off_rblk = 0, off_queue = 0, table_bytes = 0;
   std::vector<unsigned char> table_host;
   // device memory
-  DevBuf tables, cell_of, cell_count, cell_fill, cell_start, perm, sorted, scan_tmp, ext_count,
-      ext_start, ext_pos, ext_rel, partials, rcmax, head;
+  DevBuf tables, cell_of, cell_count, cell_fill, cell_start, perm, sorted, scan_tmp, row_count,
+      row_start, row_lo, ext_start, ext_pos, ext_rel, partials, rcmax, rcmax_part, head;
   // recorded graph
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -91,8 +92,9 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   B.geo.assign(nsys, SysGeom{});
   B.items.clear();
   B.eblk.clear();
+  B.rblk.clear();
   std::vector<double> cost_pp(nsys, 0.0);
-  int64_t p0 = 0, cell0 = 0, ext_cell0 = 0;
+  int64_t p0 = 0, cell0 = 0, ext_cell0 = 0, row0 = 0;
   double ext_bound = 0.0;
   B.rel_ok = true;
   for (int32_t b = 0; b < nsys; ++b) {
@@ -141,6 +143,10 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
     g.p0 = p0;
     g.cell0 = cell0;
     g.ext_cell0 = ext_cell0;
+    g.row0 = row0;
+    const int64_t rows = (int64_t)g.ne[1] * g.ne[2];
+    for (int64_t k = 0; k < rows; k += 256) B.rblk.push_back(make_int2(b, (int)k));
+    row0 += rows;
     g.item0 = (int64_t)B.items.size();
     g.nitems = (d.n + kItem - 1) / kItem;
     for (int64_t k = 0; k < g.nitems; ++k) B.items.push_back(make_int2(b, (int)(k * kItem)));
@@ -162,6 +168,7 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   B.n_total = p0;
   B.cells_total = cell0;
   B.ext_cells_total = ext_cell0;
+  B.ext_rows_total = row0;
   // the most ghost copies any arrangement of the particles can need
   // (capped at what the pair kernel can address)
   B.ext_cap = std::max<int64_t>((int64_t)ext_bound, 1);
@@ -181,7 +188,8 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   B.off_geo = 0;
   B.off_items = align256(sizeof(SysGeom) * nsys);
   B.off_eblk = B.off_items + align256(sizeof(int2) * std::max<int64_t>(nitems, 1));
-  B.off_queue = B.off_eblk + align256(sizeof(int2) * std::max<size_t>(B.eblk.size(), 1));
+  B.off_rblk = B.off_eblk + align256(sizeof(int2) * std::max<size_t>(B.eblk.size(), 1));
+  B.off_queue = B.off_rblk + align256(sizeof(int2) * std::max<size_t>(B.rblk.size(), 1));
   B.table_bytes = B.off_queue + align256(sizeof(int32_t) * std::max<int64_t>(nitems, 1));
   B.table_host.assign(B.table_bytes, 0);
   std::memcpy(B.table_host.data() + B.off_geo, B.geo.data(), sizeof(SysGeom) * nsys);
@@ -191,6 +199,8 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   }
   if (!B.eblk.empty())
     std::memcpy(B.table_host.data() + B.off_eblk, B.eblk.data(), sizeof(int2) * B.eblk.size());
+  if (!B.rblk.empty())
+    std::memcpy(B.table_host.data() + B.off_rblk, B.rblk.data(), sizeof(int2) * B.rblk.size());
   // growing a buffer moves it: a recorded graph would hold stale addresses
   B.drop_graph();
   dcm_status st;
@@ -205,10 +215,12 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   if ((st = ensure(ctx, B.sorted, sizeof(double4) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
     return st;
   if ((st = ensure(ctx, B.scan_tmp,
-                   sizeof(int32_t) * scan_tmp_elems(std::max(B.cells_total, B.ext_cells_total)))) !=
+                   sizeof(int32_t) * scan_tmp_elems(std::max(B.cells_total, B.ext_rows_total)))) !=
       DCM_OK)
     return st;
-  if ((st = ensure(ctx, B.ext_count, sizeof(int32_t) * B.ext_cells_total)) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.row_count, sizeof(int32_t) * (B.ext_rows_total + 1))) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.row_start, sizeof(int32_t) * (B.ext_rows_total + 1))) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.row_lo, sizeof(int32_t) * (B.ext_rows_total + 1))) != DCM_OK) return st;
   if ((st = ensure(ctx, B.ext_start, sizeof(int32_t) * (B.ext_cells_total + 1))) != DCM_OK)
     return st;
   if ((st = ensure(ctx, B.ext_pos, sizeof(double4) * B.ext_cap)) != DCM_OK) return st;
@@ -217,6 +229,9 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
                    sizeof(double) * kPartialSlots * std::max<int64_t>(nitems, 1))) != DCM_OK)
     return st;
   if ((st = ensure(ctx, B.rcmax, sizeof(unsigned long long) * nsys)) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.rcmax_part, sizeof(unsigned long long) * std::max<int64_t>(nitems, 1))) !=
+      DCM_OK)
+    return st;
   if ((st = ensure(ctx, B.head, sizeof(uint32_t))) != DCM_OK) return st;
   // plans change rarely: a synchronous upload keeps the host copy free to
   // change as soon as this returns
@@ -246,11 +261,10 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   if (timed) timer_begin(ctx, "batch_cells", &ev);
   launch_fill_i32(s, dptr<int32_t>(B.cell_count), 0, B.cells_total);
   launch_fill_i32(s, dptr<int32_t>(B.cell_fill), 0, B.cells_total);
-  launch_fill_u64(s, dptr<unsigned long long>(B.rcmax), 0ull, nsys);
   launch_fill_u32(s, dptr<uint32_t>(B.head), 0u, 1);
-  launch_batch_cell_count(s, geo, items, nitems, dptr<int32_t>(B.cell_of),
-                          dptr<int32_t>(B.cell_count), dptr<unsigned long long>(B.rcmax),
-                          ctx->d_status);
+  launch_batch_cell_count(s, geo, nsys, items, nitems, dptr<int32_t>(B.cell_of),
+                          dptr<int32_t>(B.cell_count), dptr<unsigned long long>(B.rcmax_part),
+                          dptr<unsigned long long>(B.rcmax), ctx->d_status);
   launch_exclusive_scan(s, dptr<int32_t>(B.cell_count), dptr<int32_t>(B.cell_start),
                         B.cells_total, dptr<int32_t>(B.scan_tmp));
   launch_batch_cell_scatter(s, geo, items, nitems, dptr<int32_t>(B.cell_of),
@@ -258,9 +272,10 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
                             dptr<int32_t>(B.perm));
   launch_cell_sort(s, dptr<int32_t>(B.cell_start), B.cells_total, dptr<int32_t>(B.perm));
   launch_batch_gather(s, geo, items, nitems, dptr<int32_t>(B.perm), dptr<double4>(B.sorted));
-  launch_batch_ext(s, geo, eblk, (int64_t)B.eblk.size(), dptr<int32_t>(B.cell_start),
-                   dptr<double4>(B.sorted), B.ext_cells_total, B.ext_cap,
-                   dptr<int32_t>(B.ext_count), dptr<int32_t>(B.ext_start),
+  launch_batch_ext(s, geo, eblk, (int64_t)B.eblk.size(), dptr<int2>(B.tables, B.off_rblk),
+                   (int64_t)B.rblk.size(), dptr<int32_t>(B.cell_start), dptr<double4>(B.sorted),
+                   B.ext_cells_total, B.ext_rows_total, B.ext_cap, dptr<int32_t>(B.row_count),
+                   dptr<int32_t>(B.row_start), dptr<int32_t>(B.row_lo), dptr<int32_t>(B.ext_start),
                    dptr<int32_t>(B.scan_tmp), dptr<double4>(B.ext_pos), rel, ctx->d_status);
   if (timed) timer_end(ctx, "batch_cells", ev);
   BatchPairArgs a;
@@ -347,8 +362,8 @@ void batch_free(dcm_ctx *ctx) {
   if (!B) return;
   B->drop_graph();
   DevBuf *bufs[] = {&B->tables,    &B->cell_of,   &B->cell_count, &B->cell_fill, &B->cell_start,
-                    &B->perm,      &B->sorted,    &B->scan_tmp,   &B->ext_count, &B->ext_start,
-                    &B->ext_pos,   &B->ext_rel,   &B->partials,  &B->rcmax,      &B->head};
+                    &B->perm,      &B->sorted,    &B->scan_tmp,   &B->row_count, &B->row_start, &B->row_lo, &B->ext_start,
+                    &B->ext_pos,   &B->ext_rel,   &B->partials,  &B->rcmax,    &B->rcmax_part,      &B->head};
   for (DevBuf *b : bufs)
     if (b->p) hipFree(b->p);
   if (B->cap) hipStreamDestroy(B->cap);

@@ -82,6 +82,42 @@ __device__ __forceinline__ void ext_to_real(const ExtGeom &g, int64_t e, int &rc
   rc = (r[2] * g.nc[1] + r[1]) * g.nc[0] + r[0];
 }
 
+// floor(a / b) for b > 0
+__device__ __forceinline__ int floor_div(int a, int b) {
+  const int q = a / b;
+  return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+// Real row behind extended row (ey, ez): its first cell, and the y and z
+// periods crossed.
+struct ExtRow {
+  int r0;     // first real cell of the row
+  int py, pz;
+  int ey, ez;  // extended cell coordinates relative to the real grid
+};
+
+__device__ __forceinline__ ExtRow ext_row(const ExtGeom &g, int row) {
+  ExtRow r;
+  const int ez0 = row / g.ne[1];
+  const int ey = row - ez0 * g.ne[1] - g.h[1];
+  const int ez = ez0 - g.h[2];
+  const int ry = wrap_index(ey, g.nc[1]), rz = wrap_index(ez, g.nc[2]);
+  r.py = (ey - ry) / g.nc[1];
+  r.pz = (ez - rz) / g.nc[2];
+  r.r0 = (rz * g.nc[1] + ry) * g.nc[0];
+  r.ey = ey;
+  r.ez = ez;
+  return r;
+}
+
+// F(u) of the row starting at real cell r0 (T: the row's total)
+__device__ __forceinline__ int64_t row_prefix(const int32_t *__restrict__ cell_start, int r0,
+                                              int nx, int64_t T, int u) {
+  const int p = floor_div(u, nx);
+  const int r = u - p * nx;
+  return (int64_t)p * T + (cell_start[r0 + r] - cell_start[r0]);
+}
+
 // MI355X has 8 XCDs, each with its own L2; consecutive workgroups are
 // dispatched round-robin across them.  xcd_block(b, n, G) remaps workgroup b
 // so that each XCD receives runs of G consecutive logical blocks (spatially

@@ -93,6 +93,7 @@ struct SysGeom {
   int64_t p0;         // first slot of the system in the concatenated particle order
   int64_t cell0;      // first real cell
   int64_t ext_cell0;  // first extended cell
+  int64_t row0;       // first extended row (rows: ne[1] * ne[2] per system)
   int64_t item0;      // first pair work item (blocks of 256 particles)
   int64_t nitems;
   double rel_delta;   // error bound of the compact records (rel_record_delta)
@@ -278,18 +279,21 @@ void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int pr
 // k_batch.hip: build kernels of the batched form.  pblk holds one (system,
 // first local particle) entry per block of 256 particles, eblk one (system,
 // first local extended cell) entry per block of 256 extended cells.
-void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
-                             int32_t *cell_of, int32_t *cell_count,
-                             unsigned long long *rc_max_bits, uint32_t *status);
+void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, int32_t nsys, const int2 *pblk,
+                             int64_t npblk, int32_t *cell_of, int32_t *cell_count,
+                             unsigned long long *block_max, unsigned long long *rc_max_bits,
+                             uint32_t *status);
 void launch_batch_cell_scatter(hipStream_t s, const SysGeom *sys, const int2 *pblk,
                                int64_t npblk, const int32_t *cell_of, const int32_t *cell_start,
                                int32_t *cell_fill, int32_t *perm);
 void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
                          const int32_t *perm, double4 *sorted);
 void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64_t neblk,
-                      const int32_t *cell_start, const double4 *sorted, int64_t next_total,
-                      int64_t ext_cap, int32_t *ext_count, int32_t *ext_start, int32_t *scan_tmp,
-                      double4 *ext_pos, float4 *ext_rel, uint32_t *status);
+                      const int2 *rblk, int64_t nrblk, const int32_t *cell_start,
+                      const double4 *sorted, int64_t next_total, int64_t nrows_total,
+                      int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
+                      int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
+                      uint32_t *status);
 void launch_batch_reduce(hipStream_t s, const SysGeom *sys, int32_t nsys,
                          const double *partials, int ev_flags);
 void launch_fill_u64(hipStream_t s, unsigned long long *p, unsigned long long v, int64_t n);

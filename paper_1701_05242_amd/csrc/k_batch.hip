@@ -31,10 +31,10 @@ __device__ __forceinline__ ExtGeom ext_geom(const SysGeom &g) {
 }
 
 // Cell of every particle (concatenated cell index), per-cell counts, and the
-// largest cutoff of each system.
+// largest cutoff of each workgroup (reduced per system by kb_reduce_rcmax).
 __global__ __launch_bounds__(kBatchBlock) void kb_cell_count(
     const SysGeom *__restrict__ sys, const int2 *__restrict__ pblk, int32_t *__restrict__ cell_of,
-    int32_t *count, unsigned long long *rc_max_bits, uint32_t *status) {
+    int32_t *count, unsigned long long *__restrict__ block_max, uint32_t *status) {
   int64_t first;
   const int b = block_system(pblk, first);
   const SysGeom &g = sys[b];
@@ -63,13 +63,44 @@ __global__ __launch_bounds__(kBatchBlock) void kb_cell_count(
     cell_of[g.p0 + i] = c;
   }
   wave_run_add(count, (uint32_t)c, valid);
+  __shared__ unsigned long long wmax[kBatchBlock / 64];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     unsigned long long o = __shfl_xor(bits, off, 64);
     bits = o > bits ? o : bits;
   }
-  if ((threadIdx.x & 63) == 0 && bits > *(volatile unsigned long long *)&rc_max_bits[b])
-    atomicMax(&rc_max_bits[b], bits);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = bits;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = wmax[0];
+    for (int w = 1; w < kBatchBlock / 64; ++w) m = wmax[w] > m ? wmax[w] : m;
+    block_max[blockIdx.x] = m;
+  }
+}
+
+// Largest cutoff of each system from its workgroups' maxima (a system's
+// workgroups are items [item0, item0 + nitems) of the block table).
+__global__ __launch_bounds__(256) void kb_reduce_rcmax(const SysGeom *__restrict__ sys,
+                                                       const unsigned long long *__restrict__ bm,
+                                                       unsigned long long *rc_max_bits) {
+  const SysGeom &g = sys[blockIdx.x];
+  __shared__ unsigned long long wmax[4];
+  unsigned long long m = 0;
+  for (int64_t t = threadIdx.x; t < g.nitems; t += 256) {
+    const unsigned long long v = bm[g.item0 + t];
+    m = v > m ? v : m;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+    rc_max_bits[blockIdx.x] = m;
+  }
 }
 
 // Slot of every particle inside its cell; perm[slot] = concatenated id.
@@ -117,53 +148,102 @@ __device__ __forceinline__ int64_t ext_cells_of(const SysGeom &g) {
   return (int64_t)g.ne[0] * g.ne[1] * g.ne[2];
 }
 
-__global__ __launch_bounds__(kBatchBlock) void kb_ext_count(const SysGeom *__restrict__ sys,
-                                                            const int2 *__restrict__ eblk,
-                                                            const int32_t *__restrict__ cell_start,
-                                                            int32_t *__restrict__ ext_count) {
-  int64_t first;
-  const int b = block_system(eblk, first);
-  const SysGeom &g = sys[b];
-  const int64_t e = first + threadIdx.x;
-  if (e >= ext_cells_of(g)) return;
-  int rc, p[3];
-  ext_to_real(ext_geom(g), e, rc, p);
-  const int64_t c = g.cell0 + rc;
-  ext_count[g.ext_cell0 + e] = cell_start[c + 1] - cell_start[c];
+// Ghost images row by row (the scheme of k_cells.hip): per extended row of a
+// system its particle count and F(-h_x), one scan over the rows of all
+// systems, the extended-cell starts from the row starts, and one wavefront
+// copying each row.  rblk lists (system, first row) per group of kBatchBlock
+// rows; row indices are local to a system, g.row0 its first row overall.
+__device__ __forceinline__ int64_t ext_rows_of(const SysGeom &g) {
+  return (int64_t)g.ne[1] * g.ne[2];
 }
 
-// Writes stop at the buffer's capacity; running past it flags an overflow.
-__global__ __launch_bounds__(kBatchBlock) void kb_ext_fill(
+__global__ __launch_bounds__(kBatchBlock) void kb_ext_rows(const SysGeom *__restrict__ sys,
+                                                           const int2 *__restrict__ rblk,
+                                                           const int32_t *__restrict__ cell_start,
+                                                           int32_t *__restrict__ row_count,
+                                                           int32_t *__restrict__ row_lo) {
+  int64_t first;
+  const int b = block_system(rblk, first);
+  const SysGeom &g = sys[b];
+  const int64_t row = first + threadIdx.x;
+  if (row >= ext_rows_of(g)) return;
+  const ExtGeom eg = ext_geom(g);
+  const ExtRow r = ext_row(eg, (int)row);
+  const int32_t *cs = cell_start + g.cell0;
+  const int64_t T = cs[r.r0 + g.nc[0]] - cs[r.r0];
+  const int64_t lo = row_prefix(cs, r.r0, g.nc[0], T, -g.h[0]);
+  const int64_t hi = row_prefix(cs, r.r0, g.nc[0], T, g.nc[0] + g.h[0]);
+  row_count[g.row0 + row] = (int32_t)(hi - lo);
+  row_lo[g.row0 + row] = (int32_t)lo;
+}
+
+__global__ __launch_bounds__(kBatchBlock) void kb_ext_starts(
     const SysGeom *__restrict__ sys, const int2 *__restrict__ eblk,
-    const int32_t *__restrict__ cell_start, const int32_t *__restrict__ ext_start,
-    const double4 *__restrict__ sorted, int64_t cap, double4 *__restrict__ ext_pos,
-    float4 *__restrict__ ext_rel, uint32_t *status) {
+    const int32_t *__restrict__ cell_start, const int32_t *__restrict__ row_start,
+    const int32_t *__restrict__ row_lo, int64_t next_total, int64_t nrows_total,
+    int32_t *__restrict__ ext_start) {
   int64_t first;
   const int b = block_system(eblk, first);
   const SysGeom &g = sys[b];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ext_start[next_total] = row_start[nrows_total];
   const int64_t e = first + threadIdx.x;
   if (e >= ext_cells_of(g)) return;
-  int rc, p[3];
-  ext_to_real(ext_geom(g), e, rc, p);
-  const double sx = (double)p[0] * g.L[0], sy = (double)p[1] * g.L[1], sz = (double)p[2] * g.L[2];
-  const int64_t c = g.cell0 + rc;
-  const int a0 = cell_start[c], a1 = cell_start[c + 1];
-  int64_t o = ext_start[g.ext_cell0 + e];
-  if (o + (a1 - a0) > cap) {
-    atomicOr(status, ST_GHOST_OVERFLOW);
-    return;
+  const int row = (int)(e / g.ne[0]);
+  const int ex = (int)(e - (int64_t)row * g.ne[0]);
+  const ExtRow r = ext_row(ext_geom(g), row);
+  const int32_t *cs = cell_start + g.cell0;
+  const int64_t T = cs[r.r0 + g.nc[0]] - cs[r.r0];
+  const int64_t f = row_prefix(cs, r.r0, g.nc[0], T, ex - g.h[0]);
+  ext_start[g.ext_cell0 + e] = (int32_t)(row_start[g.row0 + row] + (f - row_lo[g.row0 + row]));
+}
+
+// One wavefront per row: workgroup w takes rows 4 (w mod 64) .. + 3 of row
+// group w / 64.  Writes stop at the buffer's capacity; running past it flags
+// an overflow.
+constexpr int kFillGroups = kBatchBlock / (kBatchBlock / 64);  // workgroups per row group
+
+__global__ __launch_bounds__(kBatchBlock) void kb_ext_fill(
+    const SysGeom *__restrict__ sys, const int2 *__restrict__ rblk,
+    const int32_t *__restrict__ cell_start, const int32_t *__restrict__ row_start,
+    const int32_t *__restrict__ row_lo, const double4 *__restrict__ sorted, int64_t cap,
+    double4 *__restrict__ ext_pos, float4 *__restrict__ ext_rel, uint32_t *status) {
+  const int2 w = rblk[blockIdx.x / kFillGroups];
+  const int b = __builtin_amdgcn_readfirstlane(w.x);
+  const int64_t first = __builtin_amdgcn_readfirstlane(w.y);
+  const SysGeom &g = sys[b];
+  const ExtGeom eg = ext_geom(g);
+  const int64_t nrows = ext_rows_of(g);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double sc0 = (double)g.nc[0] / g.L[0];
+  bool over = false;
+  const int64_t row = first + (int64_t)(blockIdx.x % kFillGroups) * (kBatchBlock / 64) + wave;
+  if (row < nrows) {
+    const ExtRow r = ext_row(eg, (int)row);
+    const int32_t *cs = cell_start + g.cell0;
+    const int start = cs[r.r0];
+    const int T = cs[r.r0 + g.nc[0]] - start;
+    const int64_t o0 = row_start[g.row0 + row];
+    const int64_t cnt = row_start[g.row0 + row + 1] - o0;
+    const int lo = row_lo[g.row0 + row];
+    const double sy = (double)r.py * g.L[1], sz = (double)r.pz * g.L[2];
+    for (int k = lane; k < cnt; k += 64) {
+      const int P = lo + k;
+      const int p = floor_div(P, T);  // cnt > 0 implies T > 0
+      const int64_t o = o0 + k;
+      if (o >= cap) {
+        over = true;
+        continue;
+      }
+      double4 q = sorted[start + (P - p * T)];
+      const int ex = slab_index(q.x, sc0, g.nc[0]) + p * g.nc[0];
+      q.x = q.x + (double)p * g.L[0];
+      q.y = q.y + sy;
+      q.z = q.z + sz;
+      ext_pos[o] = q;
+      if (ext_rel) ext_rel[o] = rel_record(q, ex, r.ey, r.ez, g.len);
+    }
   }
-  const int ex = (int)(e % g.ne[0]) - g.h[0];
-  const int ey = (int)((e / g.ne[0]) % g.ne[1]) - g.h[1];
-  const int ez = (int)(e / ((int64_t)g.ne[0] * g.ne[1])) - g.h[2];
-  for (int k = a0; k < a1; ++k, ++o) {
-    double4 q = sorted[k];
-    q.x = q.x + sx;
-    q.y = q.y + sy;
-    q.z = q.z + sz;
-    ext_pos[o] = q;
-    if (ext_rel) ext_rel[o] = rel_record(q, ex, ey, ez, g.len);
-  }
+  if (over) atomicOr(status, ST_GHOST_OVERFLOW);
 }
 
 // One workgroup per system sums the system's work-item partials in a fixed
@@ -198,12 +278,16 @@ __global__ __launch_bounds__(256) void kb_reduce(const SysGeom *__restrict__ sys
   }
 }
 
-void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
-                             int32_t *cell_of, int32_t *cell_count,
-                             unsigned long long *rc_max_bits, uint32_t *status) {
-  if (npblk <= 0) return;
-  hipLaunchKernelGGL(kb_cell_count, dim3((unsigned)npblk), dim3(kBatchBlock), 0, s, sys, pblk,
-                     cell_of, cell_count, rc_max_bits, status);
+void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, int32_t nsys, const int2 *pblk,
+                             int64_t npblk, int32_t *cell_of, int32_t *cell_count,
+                             unsigned long long *block_max, unsigned long long *rc_max_bits,
+                             uint32_t *status) {
+  if (npblk > 0)
+    hipLaunchKernelGGL(kb_cell_count, dim3((unsigned)npblk), dim3(kBatchBlock), 0, s, sys, pblk,
+                       cell_of, cell_count, block_max, status);
+  if (nsys > 0)
+    hipLaunchKernelGGL(kb_reduce_rcmax, dim3((unsigned)nsys), dim3(256), 0, s, sys, block_max,
+                       rc_max_bits);
 }
 
 void launch_batch_cell_scatter(hipStream_t s, const SysGeom *sys, const int2 *pblk,
@@ -222,15 +306,20 @@ void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, in
 }
 
 void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64_t neblk,
-                      const int32_t *cell_start, const double4 *sorted, int64_t next_total,
-                      int64_t ext_cap, int32_t *ext_count, int32_t *ext_start, int32_t *scan_tmp,
-                      double4 *ext_pos, float4 *ext_rel, uint32_t *status) {
-  if (neblk <= 0) return;
-  hipLaunchKernelGGL(kb_ext_count, dim3((unsigned)neblk), dim3(kBatchBlock), 0, s, sys, eblk,
-                     cell_start, ext_count);
-  launch_exclusive_scan(s, ext_count, ext_start, next_total, scan_tmp);
-  hipLaunchKernelGGL(kb_ext_fill, dim3((unsigned)neblk), dim3(kBatchBlock), 0, s, sys, eblk,
-                     cell_start, ext_start, sorted, ext_cap, ext_pos, ext_rel, status);
+                      const int2 *rblk, int64_t nrblk, const int32_t *cell_start,
+                      const double4 *sorted, int64_t next_total, int64_t nrows_total,
+                      int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
+                      int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
+                      uint32_t *status) {
+  if (nrblk <= 0 || neblk <= 0) return;
+  hipLaunchKernelGGL(kb_ext_rows, dim3((unsigned)nrblk), dim3(kBatchBlock), 0, s, sys, rblk,
+                     cell_start, row_count, row_lo);
+  launch_exclusive_scan(s, row_count, row_start, nrows_total, scan_tmp);
+  hipLaunchKernelGGL(kb_ext_starts, dim3((unsigned)neblk), dim3(kBatchBlock), 0, s, sys, eblk,
+                     cell_start, row_start, row_lo, next_total, nrows_total, ext_start);
+  hipLaunchKernelGGL(kb_ext_fill, dim3((unsigned)(nrblk * kFillGroups)), dim3(kBatchBlock), 0, s,
+                     sys, rblk, cell_start, row_start, row_lo, sorted, ext_cap, ext_pos, ext_rel,
+                     status);
 }
 
 void launch_batch_reduce(hipStream_t s, const SysGeom *sys, int32_t nsys,

@@ -335,8 +335,33 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
   const int lane_id = threadIdx.x;
   const int nx = v.nc[0], hx = v.h[0], hy = v.h[1], hz = v.h[2];
   const int nex = v.ne[0], ney = v.ne[1];
-  int zc = g.zlo, yc = g.ylo;
-  bool rows_left = run;
+  const int ny = v.nc[1];
+  // rows are walked plane by plane (z), each plane's rows limited to the
+  // y range its circle of radius sqrt(R^2 - ez^2) can reach
+  int zc = g.zlo, yc = 0, ylo_c = 0, yhi_c = -1;
+  double ez2c = 0.0;
+  auto plane = [&](int z) -> bool {
+    double ez = 0.0;
+    if (z < g.cz) ez = g.zi - (double)(z + 1) * v.len[2];
+    else if (z > g.cz) ez = (double)z * v.len[2] - g.zi;
+    ez = ez > g.guard ? ez - g.guard : 0.0;
+    const double remz = g.R2 - ez * ez;
+    if (remz < 0.0) return false;
+    // half-width, rounded up generously (it only selects rows)
+    const double w = (double)(sqrtf((float)remz) * 1.00001f) + g.guard;
+    ylo_c = clampi((int)floor((g.yi - w) * v.sc[1]), -hy, ny + hy - 1);
+    yhi_c = clampi((int)floor((g.yi + w) * v.sc[1]), -hy, ny + hy - 1);
+    ez2c = ez * ez;
+    return true;
+  };
+  bool rows_left = false;
+  if (run)
+    for (; zc <= g.zhi; ++zc)
+      if (plane(zc)) {
+        rows_left = true;
+        break;
+      }
+  yc = ylo_c;
   __amdgpu_buffer_rsrc_t rs;
   if constexpr (REL)
     rs = __builtin_amdgcn_make_buffer_rsrc((void *)v.ext_rel, (short)0,
@@ -354,19 +379,23 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
 #pragma unroll
       for (int k = 0; k < kFillRows; ++k) {
         const int zcur = zc, ycur = yc;
+        const double ez2 = ez2c;
         bool in = rows_left;
-        if (rows_left && ++yc > g.yhi) {
-          yc = g.ylo;
-          if (++zc > g.zhi) rows_left = false;
+        if (rows_left && ++yc > yhi_c) {
+          bool more = false;
+          while (++zc <= g.zhi)
+            if (plane(zc)) {
+              more = true;
+              break;
+            }
+          if (more) yc = ylo_c;
+          else rows_left = false;
         }
-        double ez = 0.0, ey = 0.0;
-        if (zcur < g.cz) ez = g.zi - (double)(zcur + 1) * v.len[2];
-        else if (zcur > g.cz) ez = (double)zcur * v.len[2] - g.zi;
-        ez = ez > g.guard ? ez - g.guard : 0.0;
+        double ey = 0.0;
         if (ycur < g.cy) ey = g.yi - (double)(ycur + 1) * v.len[1];
         else if (ycur > g.cy) ey = (double)ycur * v.len[1] - g.yi;
         ey = ey > g.guard ? ey - g.guard : 0.0;
-        const double rem = g.R2 - ez * ez - ey * ey;
+        const double rem = g.R2 - ez2 - ey * ey;
         in = in && rem >= 0.0;
         // chord half-width, rounded up generously (it only selects cells)
         const double w = in ? (double)(sqrtf((float)rem) * 1.00001f) + g.guard : 0.0;
