@@ -70,6 +70,8 @@ def _load():
         "orc_gray27": (None, [P, P, P]),
         "orc_otsu": (ctypes.c_int, [i64, P, P, P, P]),
         "orc_majority": (ctypes.c_int, [P, P, ctypes.c_int]),
+        "orc_potts": (ctypes.c_int, [P, P, f64, f64, f64, P, ctypes.c_int]),
+        "orc_bubble_filter": (i64, [P, P, i64, P]),
         "orc_interface": (None, [P, P, P]),
         "orc_godunov": (f64, [f64, f64, f64, f64, f64, f64]),
         "orc_fsm": (ctypes.c_int, [P, P, P, P, f64, ctypes.c_int, P]),
@@ -155,6 +157,30 @@ def majority(nv, s, max_passes: int = MAJORITY_MAX_PASSES):
     s = np.ascontiguousarray(s, dtype=np.uint8).copy()
     passes = _load().orc_majority(_p(nv), _p(s), int(max_passes))
     return s, int(passes)
+
+
+def potts(nv, g, c0: float, c1: float, nu: float, s, max_passes: int = MAJORITY_MAX_PASSES):
+    """Length-term regularisation of the two-phase split (Section 2.1): synchronous
+    iterated conditional modes on sum (g - c_s)^2 + nu * (26-neighbour pairs in
+    different phases), means held fixed.  Returns (s, passes)."""
+    nv = np.ascontiguousarray(nv, dtype=np.int32)
+    g = np.ascontiguousarray(g, dtype=np.uint32)
+    s = np.array(s, dtype=np.uint8, copy=True)
+    passes = _load().orc_potts(_p(nv), _p(g), float(c0), float(c1), float(nu), _p(s),
+                               int(max_passes))
+    return s, int(passes)
+
+
+def bubble_filter(nv, s, min_volume: int):
+    """Section 2.1's bubble filter: every periodic 6-connected component of either
+    phase with fewer than min_volume voxels takes the other phase.  Returns
+    (s, label, flipped): label = smallest voxel index of each voxel's component
+    in the input map."""
+    nv = np.ascontiguousarray(nv, dtype=np.int32)
+    s = np.array(s, dtype=np.uint8, copy=True)
+    label = np.zeros(s.size, np.int32)
+    flipped = _load().orc_bubble_filter(_p(nv), _p(s), int(min_volume), _p(label))
+    return s, label, int(flipped)
 
 
 def interface(nv, s) -> np.ndarray:
@@ -269,12 +295,17 @@ def rc_grid_for(rule, hv) -> float:
     return float(rule[2]) + 3.0 * float(np.max(hv))
 
 
-def detect_interface(x, y, z, box, h: float, split: float = 0.0) -> dict:
-    """Section 2.1: bin -> gray value -> two-phase split -> regularise -> interface.
+def detect_interface(x, y, z, box, h: float, split: float = 0.0, nu: float = -1.0,
+                     min_volume: int = 0) -> dict:
+    """Section 2.1: bin -> gray value -> two-phase split -> regularise -> bubble
+    filter -> interface.
 
     split <= 0 picks the threshold by the two-phase (2-means) criterion;
     split > 0 uses s = [g >= split].  A single-phase volume (degenerate) is
-    classified as all high-density (no interface).
+    classified as all high-density (no interface).  nu < 0 regularises with
+    the majority vote, nu >= 0 with the length term of weight nu (needs the
+    two-phase split; skipped for a single phase).  min_volume > 0 removes
+    smaller components of either phase.
     """
     nv, hv = grid_dims(box, h)
     counts = voxel_counts(x, y, z, box, nv)
@@ -290,10 +321,20 @@ def detect_interface(x, y, z, box, h: float, split: float = 0.0) -> dict:
             s0 = np.ones(g.size, np.uint8)
         else:
             s0 = (g >= t).astype(np.uint8)
-    s, passes = majority(nv, s0)
+    if nu < 0:
+        s, passes = majority(nv, s0)
+    elif degenerate:
+        s, passes = s0.copy(), 1
+    else:
+        if split > 0:
+            raise ValueError("a length-term weight needs the two-phase split (split <= 0)")
+        s, passes = potts(nv, g, c0, c1, nu, s0)
+    flipped = 0
+    if min_volume > 0:
+        s, _, flipped = bubble_filter(nv, s, min_volume)
     f = interface(nv, s)
     return dict(nv=nv, hv=hv, counts=counts, g=g, threshold=t, c0=c0, c1=c1,
-                degenerate=degenerate, s0=s0, seg=s, passes=passes, iface=f)
+                degenerate=degenerate, s0=s0, seg=s, passes=passes, iface=f, flipped=flipped)
 
 
 def pipeline(x, y, z, box, h: float, rule, eps=1.0, sigma=1.0, pair_rule=RULE_OWN,

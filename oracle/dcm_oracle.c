@@ -232,6 +232,101 @@ int orc_majority(const int32_t *nv, uint8_t *s, int max_passes) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Step 4b': regularise with the length term of the two-phase piecewise-     */
+/* constant Mumford-Shah energy (Section 2.1).  reading: on the voxel grid   */
+/* the energy is sum_v (g_v - c_{s_v})^2 + nu * (number of periodic 26-      */
+/* neighbour pairs in different phases), minimised over s by synchronous     */
+/* iterated conditional modes with the phase means c0, c1 of the two-phase   */
+/* split held fixed.  A pass sets each voxel to the phase of lower local     */
+/* energy: d = ((g - c1)^2 - (g - c0)^2) + nu * (26 - 2 n1), with n1 its     */
+/* 26 neighbours in phase 1; s = 1 if d < 0, 0 if d > 0, unchanged if d = 0. */
+/* The passes stop as the majority vote's do (fixed point, 2-cycle or        */
+/* max_passes).  Returns the number of passes run.                           */
+/* ------------------------------------------------------------------------ */
+int orc_potts(const int32_t *nv, const uint32_t *g, double c0, double c1, double nu, uint8_t *s,
+              int max_passes) {
+    int64_t nx = nv[0], ny = nv[1], nz = nv[2], nvox = nx * ny * nz;
+    uint8_t *prev = (uint8_t *)malloc((size_t)nvox);
+    uint8_t *prev2 = (uint8_t *)malloc((size_t)nvox);
+    uint8_t *next = (uint8_t *)malloc((size_t)nvox);
+    memcpy(prev, s, (size_t)nvox);
+    int have_prev2 = 0, passes = 0;
+    while (passes < max_passes) {
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < ny; ++j)
+                for (int64_t i = 0; i < nx; ++i) {
+                    int64_t v = (k * ny + j) * nx + i;
+                    int n1 = 0;
+                    for (int dz = -1; dz <= 1; ++dz)
+                        for (int dy = -1; dy <= 1; ++dy)
+                            for (int dx = -1; dx <= 1; ++dx)
+                                if (dx || dy || dz)
+                                    n1 += prev[(imod(k + dz, nz) * ny + imod(j + dy, ny)) * nx +
+                                               imod(i + dx, nx)];
+                    double a = (double)g[v] - c1, b = (double)g[v] - c0;
+                    double d = (a * a - b * b) + nu * (double)(26 - 2 * n1);
+                    next[v] = d < 0.0 ? 1 : (d > 0.0 ? 0 : prev[v]);
+                }
+        ++passes;
+        int same_as_prev = memcmp(next, prev, (size_t)nvox) == 0;
+        int same_as_prev2 = have_prev2 && memcmp(next, prev2, (size_t)nvox) == 0;
+        memcpy(prev2, prev, (size_t)nvox);
+        have_prev2 = 1;
+        memcpy(prev, next, (size_t)nvox);
+        if (same_as_prev || same_as_prev2) break;
+    }
+    memcpy(s, prev, (size_t)nvox);
+    free(prev); free(prev2); free(next);
+    return passes;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 4c: bubble filter (Section 2.1): connected components of either      */
+/* phase smaller than a user-given volume are removed.  reading: components  */
+/* are 6-connected with periodic neighbours, volumes count voxels, and every */
+/* component with fewer than min_volume voxels takes the other phase, all on */
+/* the same input map.  label[v] (may be NULL) gets the smallest voxel index */
+/* of v's component.  Breadth-first search.  Returns the number of voxels    */
+/* flipped.                                                                  */
+/* ------------------------------------------------------------------------ */
+int64_t orc_bubble_filter(const int32_t *nv, uint8_t *s, int64_t min_volume, int32_t *label) {
+    int64_t nx = nv[0], ny = nv[1], nz = nv[2], nvox = nx * ny * nz;
+    int32_t *lab = (int32_t *)malloc((size_t)nvox * sizeof(int32_t));
+    int64_t *queue = (int64_t *)malloc((size_t)nvox * sizeof(int64_t));
+    uint8_t *flip = (uint8_t *)calloc((size_t)nvox, 1);
+    for (int64_t v = 0; v < nvox; ++v) lab[v] = -1;
+    for (int64_t start = 0; start < nvox; ++start) {
+        if (lab[start] >= 0) continue;
+        /* visiting voxels in increasing order: start is the component's smallest index */
+        int64_t head = 0, tail = 0;
+        queue[tail++] = start;
+        lab[start] = (int32_t)start;
+        while (head < tail) {
+            int64_t v = queue[head++];
+            int64_t i = v % nx, j = (v / nx) % ny, k = v / (nx * ny);
+            int64_t nb[6] = {(k * ny + j) * nx + imod(i - 1, nx), (k * ny + j) * nx + imod(i + 1, nx),
+                             (k * ny + imod(j - 1, ny)) * nx + i, (k * ny + imod(j + 1, ny)) * nx + i,
+                             (imod(k - 1, nz) * ny + j) * nx + i, (imod(k + 1, nz) * ny + j) * nx + i};
+            for (int q = 0; q < 6; ++q) {
+                int64_t u = nb[q];
+                if (lab[u] < 0 && s[u] == s[v]) {
+                    lab[u] = (int32_t)start;
+                    queue[tail++] = u;
+                }
+            }
+        }
+        if (tail < min_volume)
+            for (int64_t q = 0; q < tail; ++q) flip[queue[q]] = 1;
+    }
+    int64_t flipped = 0;
+    for (int64_t v = 0; v < nvox; ++v)
+        if (flip[v]) { s[v] = (uint8_t)(1 - s[v]); ++flipped; }
+    if (label) memcpy(label, lab, (size_t)nvox * sizeof(int32_t));
+    free(lab); free(queue); free(flip);
+    return flipped;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Step 5: the interface is where adjacent boxes carry different phases      */
 /* (Section 2.1, Fig. 4c).  reading: a voxel is an interface voxel when it   */
 /* is high-density and one of its 6 periodic face neighbours is low-density. */

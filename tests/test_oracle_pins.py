@@ -331,6 +331,85 @@ def test_slab_segmentation_gives_analytic_planes(orc):
         assert not det["degenerate"]
 
 
+def test_length_term_limits_and_flip_threshold(orc):
+    """The length-term regulariser against what fixes it independently: with no
+    length term the two-phase split is already optimal for fixed means (the
+    global 2-means split assigns every value to its nearer mean); with no data
+    term (c0 = c1) the pass is the 27-window majority vote; an isolated voxel
+    flips exactly when the length penalty exceeds its data-term gain."""
+    for name in ("slab_small", "slab_fig6"):
+        s = workloads.make(name)
+        det = orc.detect_interface(s.x, s.y, s.z, s.box, s.h)
+        seg, passes = orc.potts(det["nv"], det["g"], det["c0"], det["c1"], 0.0, det["s0"])
+        assert passes == 1
+        np.testing.assert_array_equal(seg, det["s0"])
+    rng = np.random.default_rng(3)
+    for shape in [(5, 4, 6), (9, 8, 7), (2, 3, 11)]:
+        nv = np.array(shape, np.int32)
+        n = int(np.prod(shape))
+        g = rng.integers(0, 40, size=n).astype(np.uint32)
+        s0 = (rng.random(n) < 0.5).astype(np.uint8)
+        a, pa = orc.potts(nv, g, 12.5, 12.5, 0.7, s0)
+        b, pb = orc.majority(nv, s0)
+        np.testing.assert_array_equal(a, b)
+        assert pa == pb
+    # one voxel with g = c1 among voxels with g = c0: the data term favours it
+    # by (c1 - c0)^2 = 100, the length term charges 26 nu
+    nv = np.array((5, 5, 5), np.int32)
+    g = np.zeros(125, np.uint32)
+    s0 = np.zeros(125, np.uint8)
+    g[62] = 10
+    s0[62] = 1
+    kept, _ = orc.potts(nv, g, 0.0, 10.0, 3.8, s0, max_passes=1)
+    gone, _ = orc.potts(nv, g, 0.0, 10.0, 3.9, s0, max_passes=1)
+    assert kept[62] == 1 and kept.sum() == 1
+    assert gone.sum() == 0
+
+
+def test_bubble_filter_matches_scipy_components(orc):
+    """Connected components from scipy.ndimage.label (6-connected) on maps
+    framed by a low-density layer, where periodic and open boundaries give the
+    same components; plus one component that exists only through the periodic
+    wrap."""
+    ndimage = pytest.importorskip("scipy.ndimage")
+    six = ndimage.generate_binary_structure(3, 1)
+    rng = np.random.default_rng(11)
+    for shape in [(12, 10, 9), (7, 15, 6)]:
+        nz, ny, nx = shape[2], shape[1], shape[0]
+        inner = (rng.random((nz - 2, ny - 2, nx - 2)) < 0.55).astype(np.uint8)
+        s3 = np.zeros((nz, ny, nx), np.uint8)
+        s3[1:-1, 1:-1, 1:-1] = inner
+        s = s3.ravel()
+        nv = np.array((nx, ny, nz), np.int32)
+        comps = []
+        for phase in (0, 1):
+            lab, k = ndimage.label(s3 == phase, structure=six)
+            for c in range(1, k + 1):
+                comps.append(np.flatnonzero(lab.ravel() == c))
+        for min_volume in (1, 3, 8, 30):
+            expect = s.copy()
+            want_label = np.empty(s.size, np.int64)
+            for idx in comps:
+                want_label[idx] = idx.min()
+                if idx.size < min_volume:
+                    expect[idx] = 1 - expect[idx]
+            got, label, flipped = orc.bubble_filter(nv, s, min_volume)
+            np.testing.assert_array_equal(got, expect)
+            np.testing.assert_array_equal(label, want_label)
+            assert flipped == int(np.sum(got != s))
+    # a high-density pair joined only across the periodic x boundary
+    nv = np.array((8, 5, 5), np.int32)
+    s3 = np.zeros((5, 5, 8), np.uint8)
+    s3[2, 2, 0] = s3[2, 2, 7] = 1
+    s = s3.ravel()
+    got, label, _ = orc.bubble_filter(nv, s, 2)
+    np.testing.assert_array_equal(got, s)
+    v0, v7 = (2 * 5 + 2) * 8 + 0, (2 * 5 + 2) * 8 + 7
+    assert label[v0] == label[v7] == v0
+    got, _, flipped = orc.bubble_filter(nv, s, 3)
+    assert flipped == 2 and got.sum() == 0
+
+
 # ------------------------------------------------------------ distances
 
 def test_godunov_closed_forms(orc):
