@@ -136,6 +136,34 @@ dcm_status dcm_detect_interface(dcm_ctx *ctx, const double *x, const double *y,
                                 double split, uint32_t *counts, uint8_t *seg,
                                 uint8_t *iface, int32_t *threshold_out);
 
+/* Segmentation options of dcm_detect_interface_opts (Section 2.1, Eq. 4). */
+typedef struct {
+  double split;        /* as in dcm_detect_interface */
+  double nu;           /* < 0: majority-vote regularisation, as in dcm_detect_interface;
+                          >= 0: length term of weight nu (needs split <= 0) */
+  int64_t min_volume;  /* > 0: bubble filter with this volume in voxels; 0: none */
+} dcm_detect_opts;
+
+/* Interface detection with the length term of the two-phase piecewise-
+ * constant Mumford-Shah energy and the bubble filter (Section 2.1).
+ * With nu >= 0 the split is regularised by synchronous iterated conditional
+ * modes on sum_v (g_v - c_{s_v})^2 + nu * (pairs of periodic 26-neighbours in
+ * different phases), the phase means c0, c1 of the two-phase split held
+ * fixed: a voxel takes phase 1 if ((g - c1)^2 - (g - c0)^2) + nu (26 - 2 n1)
+ * < 0, phase 0 if > 0, and keeps its phase if = 0 (n1: its neighbours in
+ * phase 1); passes stop as the majority vote's do (fixed point, 2-cycle, 16
+ * passes).  nu = 0 leaves the split as it is; a single-phase volume is not
+ * regularised.  With min_volume > 0, every periodic 6-connected component of
+ * either phase with fewer than min_volume voxels then takes the other phase
+ * (all on the same map), and the interface is marked on the result.
+ * Arguments and outputs as in dcm_detect_interface; opts is a host pointer.
+ * Errors: DCM_ERR_INVALID for a null opts, a non-finite nu, nu >= 0 with
+ * split > 0, or min_volume < 0 or >= 2^31. */
+dcm_status dcm_detect_interface_opts(dcm_ctx *ctx, const double *x, const double *y,
+                                     const double *z, int64_t n, dcm_box box, dcm_grid grid,
+                                     const dcm_detect_opts *opts, uint32_t *counts,
+                                     uint8_t *seg, uint8_t *iface, int32_t *threshold_out);
+
 /* Box-interface distances (Section 2.2, Algorithm 2.1).  Interface and
  * low-density voxels start at 0, the rest at +infinity; the first-order
  * Godunov upwind update of |grad d| = 1 is applied to every voxel in

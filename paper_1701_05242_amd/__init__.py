@@ -61,6 +61,11 @@ class dcm_grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3)]
 
 
+class dcm_detect_opts(ctypes.Structure):
+    _fields_ = [("split", ctypes.c_double), ("nu", ctypes.c_double),
+                ("min_volume", ctypes.c_int64)]
+
+
 class dcm_system(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("rc", ctypes.c_void_p), ("fx", ctypes.c_void_p), ("fy", ctypes.c_void_p),
@@ -91,6 +96,8 @@ SIGNATURES = {
     "dcm_last_error": [_P],
     "dcm_make_grid": [dcm_box, _F64, ctypes.POINTER(dcm_grid)],
     "dcm_detect_interface": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid, _F64, _P, _P, _P, _P],
+    "dcm_detect_interface_opts": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid,
+                                  ctypes.POINTER(dcm_detect_opts), _P, _P, _P, _P],
     "dcm_sweep_distance": [_P, _P, _P, dcm_grid, _F64, _I32, _P, _P],
     "dcm_assign_cutoffs": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid, _P, dcm_rule, _P, _P],
     "dcm_build_cells": [_P, _P, _P, _P, _P, _I64, dcm_box, _F64, _F64, _INT, _P, _P],
@@ -213,6 +220,21 @@ def dcm_detect_interface(ctx, x, y, z, box, grid: dcm_grid, seg, iface, split: f
     code = load_library().dcm_detect_interface(
         ctx, _ptr(x, f64, "x", n), _ptr(y, f64, "y", n), _ptr(z, f64, "z", n), n, _box(box),
         grid, float(split), _ptr(counts, torch.uint32, "counts", nv),
+        _ptr(seg, torch.uint8, "seg", nv), _ptr(iface, torch.uint8, "iface", nv),
+        _ptr(threshold_out, torch.int32, "threshold_out", 1))
+    _check(ctx, code)
+
+
+def dcm_detect_interface_opts(ctx, x, y, z, box, grid: dcm_grid, seg, iface, split: float = 0.0,
+                              nu: float = -1.0, min_volume: int = 0, counts=None,
+                              threshold_out=None) -> None:
+    n = x.numel()
+    nv = grid_voxels(grid)
+    f64 = torch.float64
+    opts = dcm_detect_opts(float(split), float(nu), int(min_volume))
+    code = load_library().dcm_detect_interface_opts(
+        ctx, _ptr(x, f64, "x", n), _ptr(y, f64, "y", n), _ptr(z, f64, "z", n), n, _box(box), grid,
+        ctypes.byref(opts), _ptr(counts, torch.uint32, "counts", nv),
         _ptr(seg, torch.uint8, "seg", nv), _ptr(iface, torch.uint8, "iface", nv),
         _ptr(threshold_out, torch.int32, "threshold_out", 1))
     _check(ctx, code)

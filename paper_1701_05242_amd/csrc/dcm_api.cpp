@@ -162,7 +162,7 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
 dcm_status dcm_destroy(dcm_ctx *ctx) {
   if (!ctx) return DCM_ERR_INVALID;
   hipStreamSynchronize(ctx->stream);
-  DevBuf *bufs[] = {&ctx->fsm_flags, &ctx->fsm_chg,  &ctx->counts,   &ctx->gray,      &ctx->hist,      &ctx->seg_a,
+  DevBuf *bufs[] = {&ctx->ccl_label, &ctx->ccl_size, &ctx->fsm_flags, &ctx->fsm_chg,  &ctx->counts,   &ctx->gray,      &ctx->hist,      &ctx->seg_a,
                     &ctx->seg_b,    &ctx->seg,       &ctx->iface,     &ctx->dA,
                     &ctx->dB,       &ctx->dist,      &ctx->delta,     &ctx->rc,
                     &ctx->partials, &ctx->ke,        &ctx->cell_of,   &ctx->cell_count,
@@ -237,7 +237,23 @@ dcm_status dcm_detect_interface(dcm_ctx *ctx, const double *x, const double *y, 
                                 int64_t n, dcm_box box, dcm_grid grid, double split,
                                 uint32_t *counts, uint8_t *seg, uint8_t *iface,
                                 int32_t *threshold_out) {
+  const dcm_detect_opts opts = {split, -1.0, 0};
+  return dcm_detect_interface_opts(ctx, x, y, z, n, box, grid, &opts, counts, seg, iface,
+                                   threshold_out);
+}
+
+dcm_status dcm_detect_interface_opts(dcm_ctx *ctx, const double *x, const double *y,
+                                     const double *z, int64_t n, dcm_box box, dcm_grid grid,
+                                     const dcm_detect_opts *opts, uint32_t *counts,
+                                     uint8_t *seg, uint8_t *iface, int32_t *threshold_out) {
   if (!ctx) return DCM_ERR_INVALID;
+  if (!opts) return fail(ctx, DCM_ERR_INVALID, "dcm_detect_interface_opts: null opts");
+  const double split = opts->split, nu = opts->nu;
+  if (!std::isfinite(nu)) return fail(ctx, DCM_ERR_INVALID, "nu must be finite");
+  if (nu >= 0.0 && split > 0.0)
+    return fail(ctx, DCM_ERR_INVALID, "a length-term weight needs the two-phase split (split <= 0)");
+  if (opts->min_volume < 0 || opts->min_volume >= (int64_t(1) << 31))
+    return fail(ctx, DCM_ERR_INVALID, "min_volume must be in [0, 2^31)");
   int64_t nvox = 0;
   DCM_TRY(check_n(ctx, n));
   DCM_TRY(check_box(ctx, box));
@@ -249,6 +265,10 @@ dcm_status dcm_detect_interface(dcm_ctx *ctx, const double *x, const double *y, 
   DCM_TRY(ensure(ctx, ctx->hist, kHistBins * sizeof(uint32_t)));
   DCM_TRY(ensure(ctx, ctx->seg_a, phase_bits_words(grid.n) * sizeof(uint32_t)));
   DCM_TRY(ensure(ctx, ctx->seg_b, phase_bits_words(grid.n) * sizeof(uint32_t)));
+  if (opts->min_volume > 0) {
+    DCM_TRY(ensure(ctx, ctx->ccl_label, nvox * sizeof(int32_t)));
+    DCM_TRY(ensure(ctx, ctx->ccl_size, nvox * sizeof(int32_t)));
+  }
   if (!counts) {
     DCM_TRY(ensure(ctx, ctx->counts, nvox * sizeof(uint32_t)));
     counts = ptr<uint32_t>(ctx->counts);
@@ -267,11 +287,19 @@ dcm_status dcm_detect_interface(dcm_ctx *ctx, const double *x, const double *y, 
     launch_otsu(s, ptr<uint32_t>(ctx->hist), nvox, ctx->ctl, threshold_out, ctx->d_status);
   launch_threshold(s, ptr<uint32_t>(ctx->gray), grid.n, split, ctx->ctl,
                    ptr<uint32_t>(ctx->seg_a), threshold_out);
-  for (int p = 1; p <= kMajorityMaxPasses; ++p)
-    launch_majority_pass(s, ptr<uint32_t>(ctx->seg_a), ptr<uint32_t>(ctx->seg_b), grid.n, p,
-                         kMajorityMaxPasses, ctx->ctl);
+  for (int p = 1; p <= kMajorityMaxPasses; ++p) {
+    if (nu < 0.0)
+      launch_majority_pass(s, ptr<uint32_t>(ctx->seg_a), ptr<uint32_t>(ctx->seg_b), grid.n, p,
+                           kMajorityMaxPasses, ctx->ctl);
+    else
+      launch_potts_pass(s, ptr<uint32_t>(ctx->seg_a), ptr<uint32_t>(ctx->seg_b),
+                        ptr<uint32_t>(ctx->gray), grid.n, nu, p, ctx->ctl);
+  }
   launch_interface(s, ptr<uint32_t>(ctx->seg_a), ptr<uint32_t>(ctx->seg_b), grid.n, ctx->ctl, seg,
                    iface);
+  if (opts->min_volume > 0)
+    launch_bubble_filter(s, grid.n, opts->min_volume, seg, iface, ptr<int32_t>(ctx->ccl_label),
+                         ptr<int32_t>(ctx->ccl_size), ctx->d_status);
   timer_end(ctx, "detect", ev);
   return check_launch(ctx, "dcm_detect_interface");
 }

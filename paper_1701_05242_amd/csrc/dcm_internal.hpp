@@ -115,6 +115,7 @@ struct dcm_ctx {
   dcm::Ctl *ctl = nullptr;       // device control block
   // grid scratch
   dcm::DevBuf counts, gray, hist, seg_a, seg_b, seg, iface, dA, dB, dist, fsm_chg, fsm_flags;
+  dcm::DevBuf ccl_label, ccl_size;  // bubble filter
   // particle scratch
   dcm::DevBuf delta, rc, partials, ke, scalars;
   // cells
@@ -176,6 +177,12 @@ void launch_otsu(hipStream_t s, const uint32_t *hist, int64_t nvox, Ctl *ctl, in
 // phase maps of the majority passes are bit-packed: ceil(nx/32) words per
 // x-row; phase_bits_words gives the words of one map
 int64_t phase_bits_words(const int32_t nv[3]);
+// one length-term pass (same buffers and flags as launch_majority_pass)
+void launch_potts_pass(hipStream_t s, uint32_t *buf0, uint32_t *buf1, const uint32_t *gray,
+                       const int32_t nv[3], double nu, int pass, Ctl *ctl);
+// k_ccl.hip: bubble filter on the byte phase map, then its interface
+void launch_bubble_filter(hipStream_t s, const int32_t nv[3], int64_t min_volume, uint8_t *seg,
+                          uint8_t *iface, int32_t *label, int32_t *size, uint32_t *status);
 void launch_threshold(hipStream_t s, const uint32_t *gray, const int32_t nv[3], double split,
                       const Ctl *ctl, uint32_t *bits0, int32_t *t_out);
 void launch_majority_pass(hipStream_t s, uint32_t *buf0, uint32_t *buf1, const int32_t nv[3],

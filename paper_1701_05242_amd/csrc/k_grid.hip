@@ -449,6 +449,98 @@ __global__ __launch_bounds__(256) void k_majority(uint32_t *buf0, uint32_t *buf1
   }
 }
 
+// ------------------------------ length-term regularisation (4b', Eq. 4)
+// The two-phase piecewise-constant energy with a length term of weight nu,
+// sum_v (g_v - c_{s_v})^2 + nu * (differing 26-neighbour pairs), lowered by
+// synchronous iterated conditional modes with the phase means of the split
+// held fixed: d = ((g - c1)^2 - (g - c0)^2) + nu * (26 - 2 n1) for the n1
+// high-density neighbours; phase 1 if d < 0, 0 if d > 0, unchanged if d = 0.
+// Same buffers, pass numbering and stop flags as the majority vote.  A
+// single-phase volume is left as it is.
+__global__ __launch_bounds__(256) void k_potts(uint32_t *buf0, uint32_t *buf1,
+                                               const uint32_t *__restrict__ gray, int nx, int ny,
+                                               int nz, double nu, int pass, Ctl *ctl) {
+  if (pass > 1 && majority_stopped(ctl, pass - 1)) return;
+  const uint32_t *__restrict__ src = (pass & 1) ? buf0 : buf1;
+  uint32_t *__restrict__ dst = (pass & 1) ? buf1 : buf0;
+  const bool keep = ctl->degenerate != 0;
+  const double c0 = ctl->c0, c1 = ctl->c1;
+  const int W = row_words(nx);
+  const int top = (nx - 1) & 31;
+  const int64_t words = (int64_t)ny * nz * W;
+  bool ch1 = false, ch2 = false;
+  for (int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; wi < words;
+       wi += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = wi / W;
+    const int k = (int)(wi - row * W);
+    const int y = (int)(row % ny), z = (int)(row / ny);
+    const int kl = k == 0 ? W - 1 : k - 1, kr = k == W - 1 ? 0 : k + 1;
+    const bool first = k == 0, lastw = k == W - 1;
+    uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, prev = 0;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      int zz = z + dz;
+      zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        int yy = y + dy;
+        yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+        const uint32_t *r = src + ((int64_t)zz * ny + yy) * W;
+        const uint32_t w = r[k];
+        if (dz == 0 && dy == 0) prev = w;
+        uint32_t a, c;
+        x_neighbours(r[kl], w, r[kr], first, lastw, top, a, c);
+        const uint32_t h0 = a ^ w ^ c;
+        const uint32_t h1 = (a & w) | (c & (a ^ w));
+        const uint32_t k0 = q0 & h0;
+        q0 ^= h0;
+        const uint32_t t1 = q1 ^ h1;
+        const uint32_t k1 = (q1 & h1) | (k0 & t1);
+        q1 = t1 ^ k0;
+        const uint32_t k2 = q2 & k1;
+        q2 ^= k1;
+        const uint32_t k3 = q3 & k2;
+        q3 ^= k2;
+        q4 ^= k3;
+      }
+    }
+    uint32_t nw = prev;
+    if (!keep) {
+      nw = 0u;
+      const int nb = lastw ? top + 1 : 32;
+      const uint32_t *grow = gray + row * nx + k * 32;
+      for (int b = 0; b < nb; ++b) {
+        const uint32_t self = (prev >> b) & 1u;
+        const int n1 = (int)(((q0 >> b) & 1u) + 2u * ((q1 >> b) & 1u) + 4u * ((q2 >> b) & 1u) +
+                             8u * ((q3 >> b) & 1u) + 16u * ((q4 >> b) & 1u) - self);
+        const double ga = (double)grow[b] - c1, gb = (double)grow[b] - c0;
+        const double d = (ga * ga - gb * gb) + nu * (double)(26 - 2 * n1);
+        const uint32_t bit = d < 0.0 ? 1u : (d > 0.0 ? 0u : self);
+        nw |= bit << b;
+      }
+    }
+    const uint32_t old = dst[wi];
+    dst[wi] = nw;
+    ch1 |= nw != prev;
+    ch2 |= nw != old;
+  }
+  const int any1 = __syncthreads_or(ch1 ? 1 : 0);
+  const int any2 = __syncthreads_or(ch2 ? 1 : 0);
+  if (threadIdx.x == 0) {
+    if (any1) ctl->maj_chg1[pass] = 1u;
+    if (any2) ctl->maj_chg2[pass] = 1u;
+  }
+}
+
+void launch_potts_pass(hipStream_t s, uint32_t *buf0, uint32_t *buf1, const uint32_t *gray,
+                       const int32_t nv[3], double nu, int pass, Ctl *ctl) {
+  int64_t b = ceil_div(phase_bits_words(nv), 256);
+  if (b < 1) b = 1;
+  if (b > 2048) b = 2048;
+  hipLaunchKernelGGL(k_potts, dim3((unsigned)b), dim3(256), 0, s, buf0, buf1, gray, nv[0], nv[1],
+                     nv[2], nu, pass, ctl);
+}
+
 int64_t phase_bits_words(const int32_t nv[3]) {
   return (int64_t)nv[1] * nv[2] * row_words(nv[0]);
 }

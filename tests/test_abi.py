@@ -80,6 +80,18 @@ def test_system_descriptor_layout_matches_header():
     assert S.n.offset == 88 and S.box.offset == 96 and S.rc_bound.offset == 128
 
 
+def test_detect_options_layout_and_null_options(lib):
+    """dcm_detect_opts is split, nu, min_volume (24 bytes, no padding); a null
+    options pointer is refused before any device work."""
+    import paper_1701_05242_amd as dcm
+    O = dcm.dcm_detect_opts
+    assert ctypes.sizeof(O) == 24
+    assert (O.split.offset, O.nu.offset, O.min_volume.offset) == (0, 8, 16)
+    code = lib.dcm_detect_interface_opts(None, None, None, None, 0, dcm.dcm_box((1.0, 1.0, 1.0)),
+                                         dcm.dcm_grid(), None, None, None, None, None)
+    assert code == dcm.DCM_ERR_INVALID
+
+
 def test_binding_refuses_host_tensors():
     import torch
 
