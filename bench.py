@@ -42,6 +42,7 @@ def parse():
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
+    p.add_argument("--no-list", action="store_true", help="skip the Verlet-list leg")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--table1", action="store_true",
                    help="only run the DCM-versus-static-cutoff timing of the paper's Table 1 "
@@ -255,6 +256,64 @@ def batched_leg(steps, dev):
             "sequential_fp64": {"ms": seq_s * 1e3, "pair_rate": seq_pairs / seq_s}}
 
 
+def list_leg(s, dev, reps=5, skin=0.3):
+    """Verlet lists (Algorithms 2.2-2.3) against the cell walk on the same
+    cells: per precision, the average pair-kernel time of dcm_forces and of
+    dcm_forces_list with skins 0 and `skin`, the list build and a list update
+    (HIP events of the library's "pair" and "list" families).  Cutoffs come
+    from one detection / sweep / assignment pass before timing."""
+    import torch
+
+    import paper_1701_05242_amd as dcm
+
+    f64 = dict(dtype=torch.float64, device=dev)
+    x, y, z = (torch.tensor(a, **f64) for a in (s.x, s.y, s.z))
+    grid = dcm.make_grid(s.box, s.h)
+    rule = dcm.make_rule(*s.rule)
+    nv = dcm.grid_voxels(grid)
+    seg = torch.zeros(nv, dtype=torch.uint8, device=dev)
+    iface = torch.zeros_like(seg)
+    dist = torch.zeros(nv, **f64)
+    rc = torch.zeros(s.n, **f64)
+    F = [torch.zeros(s.n, **f64) for _ in range(3)]
+    e = torch.zeros(1, **f64)
+    lj = dcm.make_lj()
+    ctx = dcm.dcm_create()
+    out = {"workload": s.name, "cell_edge": 1.25}
+    try:
+        dcm.dcm_detect_interface(ctx, x, y, z, s.box, grid, seg, iface)
+        dcm.dcm_sweep_distance(ctx, seg, iface, grid, dcm.rc_grid_for(rule, grid), 64, dist)
+        dcm.dcm_assign_cutoffs(ctx, x, y, z, s.box, grid, dist, rule, rc)
+
+        def avg(fam, fn, n):
+            dcm.dcm_set_profiling(ctx, True)
+            dcm.dcm_kernel_time(ctx, fam)
+            for _ in range(n):
+                fn()
+            ms, k = dcm.dcm_kernel_time(ctx, fam)
+            dcm.dcm_set_profiling(ctx, False)
+            return ms / max(k, 1)
+
+        forces = lambda p: dcm.dcm_forces(ctx, lj, *F, prec=p, ev_flags=dcm.DCM_EV_ENERGY,
+                                          energy=e)
+        forces_list = lambda p: dcm.dcm_forces_list(ctx, lj, *F, prec=p,
+                                                    ev_flags=dcm.DCM_EV_ENERGY, energy=e)
+        for name, p in (("fp64", dcm.DCM_FP64), ("fp32_mixed", dcm.DCM_FP32_MIXED)):
+            dcm.dcm_build_cells(ctx, x, y, z, rc, s.box, 1.25, p, rc_bound=s.rule[1])
+            leg = {"cell_walk_ms": avg("pair", lambda: forces(p), reps)}
+            for sk in (0.0, skin):
+                leg[f"skin_{sk:g}"] = {
+                    "build_ms": avg("list", lambda: dcm.dcm_build_list(ctx, sk), 2),
+                    "forces_ms": avg("pair", lambda: forces_list(p), reps)}
+            leg["update_ms"] = avg("list", lambda: dcm.dcm_update_list(ctx, x, y, z, rc), 2)
+            out[name] = leg
+        if dcm.dcm_sync_status(ctx) != dcm.DCM_OK:
+            raise RuntimeError(dcm.dcm_last_error(ctx))
+    finally:
+        dcm.dcm_destroy(ctx)
+    return out
+
+
 def cpu_baseline(s, seconds):
     """The oracle's O(N) per-particle sums on a seeded sample of particles."""
     import numpy as np
@@ -367,6 +426,10 @@ def main():
     if not args.no_batched:
         batched = batched_leg(args.steps, dev)
         print(f"[bench] batched {json.dumps(batched)}", file=sys.stderr, flush=True)
+    vlist = None
+    if not args.no_list:
+        vlist = list_leg(s, dev)
+        print(f"[bench] verlet list {json.dumps(vlist)}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(s, args.cpu_seconds)
@@ -405,6 +468,7 @@ def main():
             "pair_kernel_ms": fp64_leg["avg_pair_ms"],
             "pair_kernel_tflops": fp64_leg["pair_kernel_tflops"]},
         "batched": batched,
+        "verlet_list": vlist,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -220,6 +220,46 @@ dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_f
                       double *fx, double *fy, double *fz, double *energy, double *virial,
                       int32_t *nnbr, uint64_t *npairs);
 
+/* Verlet neighbour list with a skin (Section 2.3, Algorithm 2.2) on the cells
+ * of the last dcm_build_cells: particle i's list holds every other particle or
+ * periodic image j with r_ij^2 < R_i^2, R_i = min(r_c(i), rc_bound) + skin,
+ * in the order in which dcm_forces visits its candidates.  skin in
+ * [0, smallest cell edge].  The list belongs to that cell build; a new build
+ * discards it.  Synchronises the context's stream (the list's size is read
+ * back to size its buffer).
+ * Errors: DCM_ERR_INVALID before a cell build, after dcm_update_list, or for
+ * a skin out of range. */
+dcm_status dcm_build_list(dcm_ctx *ctx, double skin);
+
+/* Reuse of the list over steps (Section 2.3): new positions x, y, z and
+ * cutoffs rc (double [n], caller order, n as in the cell build) replace those
+ * of the build; dcm_forces_list then evaluates them.  Each particle moves by
+ * the minimum image of its displacement from its position at the list build,
+ * so wrapped and unwrapped coordinates give the same result.
+ * *valid (host int32, required) is set to 1 when the list still holds every
+ * pair that interacts now: with D the largest displacement since the list
+ * build and S the smallest R_i - r_c(i) (new cutoffs), when S - 2 D exceeds a
+ * rounding margin of 1e-12 (rc_bound + skin), or D = 0 and S >= 0.
+ * Otherwise 0: build the cells and the list again.  max_disp and min_slack
+ * (host doubles, optional) receive D and S.  Cutoffs are clamped to
+ * [0, rc_bound] and flag DCM_ERR_RANGE at dcm_sync_status as in the cell
+ * build.  After this call dcm_forces (the cell walk) and dcm_build_list
+ * refuse until the cells are built again.  Synchronises the stream.
+ * Errors: DCM_ERR_INVALID without a list for the current cell build, for
+ * another n, or for a null pointer. */
+dcm_status dcm_update_list(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                           const double *rc, int64_t n, double *max_disp, double *min_slack,
+                           int32_t *valid);
+
+/* Own-cutoff forces (Algorithm 2.3) over the list of the current cell build:
+ * arguments and results as dcm_forces with DCM_PAIR_OWN.  Until an update,
+ * the pairs and their summation order are those of dcm_forces, so both give
+ * identical results.
+ * Errors: DCM_ERR_INVALID without a list for the current cell build. */
+dcm_status dcm_forces_list(dcm_ctx *ctx, dcm_lj lj, int prec, int ev_flags, double *fx,
+                           double *fy, double *fz, double *energy, double *virial, int32_t *nnbr,
+                           uint64_t *npairs);
+
 /* Velocity-Verlet MD with the whole DCM pipeline (Fig. 3).
  * nsteps == 0: compute forces at the current positions (detection, distances,
  * cutoffs, cells, forces) into fx, fy, fz.

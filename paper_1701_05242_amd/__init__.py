@@ -103,6 +103,10 @@ SIGNATURES = {
     "dcm_build_cells": [_P, _P, _P, _P, _P, _I64, dcm_box, _F64, _F64, _INT, _P, _P],
     "dcm_cell_dims": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_F64)],
     "dcm_forces": [_P, dcm_lj, _INT, _INT, _INT, _P, _P, _P, _P, _P, _P, _P],
+    "dcm_build_list": [_P, _F64],
+    "dcm_update_list": [_P, _P, _P, _P, _P, _I64, ctypes.POINTER(_F64), ctypes.POINTER(_F64),
+                        ctypes.POINTER(_I32)],
+    "dcm_forces_list": [_P, dcm_lj, _INT, _INT, _P, _P, _P, _P, _P, _P, _P],
     "dcm_step": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I64, _F64, dcm_box, dcm_lj, dcm_rule,
                  dcm_grid, _F64, _INT, _INT, _F64, _I32, _I32, _I64, _P, _P, _P],
     "dcm_forces_batched": [_P, _I32, _P, dcm_lj, _INT, _INT, _INT, _INT],
@@ -289,6 +293,34 @@ def dcm_forces(ctx, lj: dcm_lj, fx, fy, fz, pair_rule: int = DCM_PAIR_OWN,
         _ptr(fy, f64, "fy", n), _ptr(fz, f64, "fz", n), _ptr(energy, f64, "energy", 1),
         _ptr(virial, f64, "virial", 6), _ptr(nnbr, torch.int32, "nnbr", n),
         _ptr(npairs, torch.uint64, "npairs", 1))
+    _check(ctx, code)
+
+
+def dcm_build_list(ctx, skin: float) -> None:
+    _check(ctx, load_library().dcm_build_list(ctx, float(skin)))
+
+
+def dcm_update_list(ctx, x, y, z, rc):
+    """New positions and cutoffs for the list of the current cell build.
+    Returns (valid, max_disp, min_slack)."""
+    n = x.numel()
+    f64 = torch.float64
+    d, sl, v = _F64(0.0), _F64(0.0), _I32(0)
+    code = load_library().dcm_update_list(
+        ctx, _ptr(x, f64, "x", n), _ptr(y, f64, "y", n), _ptr(z, f64, "z", n),
+        _ptr(rc, f64, "rc", n), n, ctypes.byref(d), ctypes.byref(sl), ctypes.byref(v))
+    _check(ctx, code)
+    return bool(v.value), d.value, sl.value
+
+
+def dcm_forces_list(ctx, lj: dcm_lj, fx, fy, fz, prec: int = DCM_FP64, ev_flags: int = 0,
+                    energy=None, virial=None, nnbr=None, npairs=None) -> None:
+    n = fx.numel()
+    f64 = torch.float64
+    code = load_library().dcm_forces_list(
+        ctx, lj, int(prec), int(ev_flags), _ptr(fx, f64, "fx", n), _ptr(fy, f64, "fy", n),
+        _ptr(fz, f64, "fz", n), _ptr(energy, f64, "energy", 1), _ptr(virial, f64, "virial", 6),
+        _ptr(nnbr, torch.int32, "nnbr", n), _ptr(npairs, torch.uint64, "npairs", 1))
     _check(ctx, code)
 
 

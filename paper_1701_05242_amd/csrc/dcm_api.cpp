@@ -144,6 +144,8 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
   ctx->h_status = static_cast<uint32_t *>(p);
   ctx->h_ext_total = reinterpret_cast<int32_t *>(static_cast<char *>(p) + 8);
   *ctx->h_ext_total = 0;
+  ctx->h_list_total = reinterpret_cast<int32_t *>(static_cast<char *>(p) + 16);
+  ctx->h_list_verdict = reinterpret_cast<double *>(static_cast<char *>(p) + 24);
   launch_clear_status(ctx->stream, ctx->d_status);
   launch_reset_ctl(ctx->stream, ctx->ctl);
   dcm_status st = check_launch(ctx, "dcm_create");
@@ -168,7 +170,8 @@ dcm_status dcm_destroy(dcm_ctx *ctx) {
                     &ctx->partials, &ctx->ke,        &ctx->cell_of,   &ctx->cell_count,
                     &ctx->cell_start, &ctx->cell_fill, &ctx->perm,    &ctx->sorted,
                     &ctx->scan_tmp, &ctx->scalars, &ctx->ext_row_count, &ctx->ext_row_start,
-                    &ctx->ext_row_lo, &ctx->ext_start, &ctx->rcmax_part,
+                    &ctx->ext_row_lo, &ctx->ext_start, &ctx->rcmax_part, &ctx->list_count,
+                    &ctx->list_wave_len, &ctx->list_wave_start, &ctx->list,
                     &ctx->ext_pos, &ctx->ws[0], &ctx->ws[1], &ctx->ws_owner[0],
                     &ctx->ws_owner[1], &ctx->ext_rel};
   for (DevBuf *b : bufs)
@@ -361,6 +364,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
                            const double *rc, int64_t n, dcm_box box, double cell_edge,
                            double rc_bound, int prec, int32_t *cell_of, int32_t *cell_start) {
   if (!ctx) return DCM_ERR_INVALID;
+  ctx->list_n = -1;
   DCM_TRY(check_n(ctx, n));
   DCM_TRY(check_box(ctx, box));
   if (n > 0 && (!x || !y || !z || !rc))
@@ -472,6 +476,8 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
     ctx->cell_box.L[a] = box.L[a];
   }
   ctx->cell_n = n;
+  ctx->list_n = -1;  // a list belongs to the build it was made on
+  ctx->cells_moved = false;
   ctx->cell_prec = prec;
   ctx->cell_rel = rel;
   ctx->rc_bound = rc_cap;
@@ -488,11 +494,20 @@ dcm_status dcm_cell_dims(const dcm_ctx *ctx, int32_t n_cells[3], double cell_len
   return DCM_OK;
 }
 
-dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_flags,
-                      double *fx, double *fy, double *fz, double *energy, double *virial,
-                      int32_t *nnbr, uint64_t *npairs) {
+namespace {
+// dcm_forces and dcm_forces_list: the cell walk, or the Verlet list of the
+// current cell build
+dcm_status forces_impl(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_flags, double *fx,
+                       double *fy, double *fz, double *energy, double *virial, int32_t *nnbr,
+                       uint64_t *npairs, bool use_list) {
   if (!ctx) return DCM_ERR_INVALID;
   if (ctx->cell_n < 0) return fail(ctx, DCM_ERR_INVALID, "dcm_forces before dcm_build_cells");
+  if (use_list && ctx->list_n != ctx->cell_n)
+    return fail(ctx, DCM_ERR_INVALID, "dcm_forces_list needs dcm_build_list after the cell build");
+  if (!use_list && ctx->cells_moved)
+    return fail(ctx, DCM_ERR_INVALID,
+                "dcm_forces after dcm_update_list: the particles have left their cells; build "
+                "the cells again");
   const int64_t n = ctx->cell_n;
   if (n > 0 && (!fx || !fy || !fz)) return fail(ctx, DCM_ERR_INVALID, "dcm_forces: null force");
   if (pair_rule != DCM_PAIR_OWN && pair_rule != DCM_PAIR_MAX)
@@ -543,12 +558,145 @@ dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_f
   a.status = ctx->d_status;
   hipEvent_t ev;
   timer_begin(ctx, "pair", &ev);
-  launch_pair(ctx->stream, a, pair_rule, prec);
+  if (use_list)
+    launch_pair_list(ctx->stream, a, prec, ptr<int32_t>(ctx->list_count),
+                     ptr<int32_t>(ctx->list_wave_start), ptr<int32_t>(ctx->list));
+  else
+    launch_pair(ctx->stream, a, pair_rule, prec);
   timer_end(ctx, "pair", ev);
   if (ev_flags & (DCM_EV_ENERGY | DCM_EV_VIRIAL | DCM_EV_COUNTS))
     launch_reduce_partials(ctx->stream, a.partials, blocks, lj.epsilon, ev_flags, energy, virial,
                            npairs);
-  return check_launch(ctx, "dcm_forces");
+  return check_launch(ctx, use_list ? "dcm_forces_list" : "dcm_forces");
+}
+}  // namespace
+
+dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_flags,
+                      double *fx, double *fy, double *fz, double *energy, double *virial,
+                      int32_t *nnbr, uint64_t *npairs) {
+  return forces_impl(ctx, lj, pair_rule, prec, ev_flags, fx, fy, fz, energy, virial, nnbr, npairs,
+                     false);
+}
+
+dcm_status dcm_build_list(dcm_ctx *ctx, double skin) {
+  if (!ctx) return DCM_ERR_INVALID;
+  if (ctx->cell_n < 0) return fail(ctx, DCM_ERR_INVALID, "dcm_build_list before dcm_build_cells");
+  const double edge = std::min(ctx->cell_len[0], std::min(ctx->cell_len[1], ctx->cell_len[2]));
+  if (!std::isfinite(skin) || skin < 0.0 || skin > edge)
+    return fail(ctx, DCM_ERR_INVALID, "skin must be in [0, cell edge]");
+  if (ctx->cells_moved)
+    return fail(ctx, DCM_ERR_INVALID,
+                "dcm_build_list after dcm_update_list: build the cells again first");
+  const int64_t n = ctx->cell_n, nw = list_waves(n);
+  DCM_TRY(ensure(ctx, ctx->list_count, std::max<int64_t>(n, 1) * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->list_wave_len, std::max<int64_t>(nw, 1) * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->list_wave_start, (nw + 1) * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->list_ref, std::max<int64_t>(n, 1) * sizeof(double4)));
+  DCM_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_elems(std::max<int64_t>(nw, 1)) * sizeof(int32_t)));
+  ListArgs a;
+  a.pos = ptr<double4>(ctx->sorted);
+  a.cell_start = ptr<int32_t>(ctx->cell_start);
+  a.ext_pos = ptr<double4>(ctx->ext_pos);
+  a.ext_start = ptr<int32_t>(ctx->ext_start);
+  a.n = n;
+  a.ext_cap = ctx->ext_cap;
+  for (int k = 0; k < 3; ++k) {
+    a.nc[k] = ctx->nc[k];
+    a.h[k] = ctx->halo[k];
+    a.ne[k] = ctx->nc[k] + 2 * ctx->halo[k];
+    a.len[k] = ctx->cell_len[k];
+    a.sc[k] = ctx->cell_scale[k];
+  }
+  a.rc_bound = ctx->rc_bound;
+  a.skin = skin;
+  a.count = ptr<int32_t>(ctx->list_count);
+  a.wave_len = ptr<int32_t>(ctx->list_wave_len);
+  a.wave_start = ptr<int32_t>(ctx->list_wave_start);
+  a.n_waves = nw;
+  a.list = nullptr;
+  a.list_cap = 0;
+  a.ref = ptr<double4>(ctx->list_ref);
+  a.status = ctx->d_status;
+  hipStream_t s = ctx->stream;
+  hipEvent_t ev;
+  timer_begin(ctx, "list", &ev);
+  ctx->list_n = -1;
+  if (n > 0) {
+    launch_list_count(s, a);
+    launch_exclusive_scan(s, ptr<int32_t>(ctx->list_wave_len), ptr<int32_t>(ctx->list_wave_start),
+                          nw, ptr<int32_t>(ctx->scan_tmp));
+    // the list's size, read back to size its buffer
+    if (hipMemcpyAsync(ctx->h_list_total, ptr<int32_t>(ctx->list_wave_start) + nw, sizeof(int32_t),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_build_list: size read-back failed");
+    const int64_t entries = 64 * (int64_t)*ctx->h_list_total;
+    DCM_TRY(ensure(ctx, ctx->list, std::max<int64_t>(entries, 1) * sizeof(int32_t)));
+    a.list = ptr<int32_t>(ctx->list);
+    a.list_cap = entries;
+    launch_list_fill(s, a);
+  }
+  timer_end(ctx, "list", ev);
+  DCM_TRY(check_launch(ctx, "dcm_build_list"));
+  ctx->list_n = n;
+  ctx->list_skin = skin;
+  return DCM_OK;
+}
+
+dcm_status dcm_update_list(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                           const double *rc, int64_t n, double *max_disp, double *min_slack,
+                           int32_t *valid) {
+  if (!ctx) return DCM_ERR_INVALID;
+  if (!valid) return fail(ctx, DCM_ERR_INVALID, "dcm_update_list: null valid");
+  *valid = 0;
+  if (ctx->cell_n < 0 || ctx->list_n != ctx->cell_n)
+    return fail(ctx, DCM_ERR_INVALID, "dcm_update_list needs dcm_build_list after the cell build");
+  if (n != ctx->cell_n)
+    return fail(ctx, DCM_ERR_INVALID, "dcm_update_list: n differs from the cell build");
+  if (n > 0 && (!x || !y || !z || !rc))
+    return fail(ctx, DCM_ERR_INVALID, "dcm_update_list: null pointer");
+  const int64_t blocks = list_update_blocks(n);
+  DCM_TRY(ensure(ctx, ctx->list_part, blocks * sizeof(double2)));
+  DCM_TRY(ensure(ctx, ctx->list_out, 2 * sizeof(double)));
+  hipStream_t s = ctx->stream;
+  hipEvent_t ev;
+  timer_begin(ctx, "list", &ev);
+  ctx->cells_moved = true;
+  double dmax = 0.0, slack = INFINITY;
+  if (n > 0) {
+    launch_list_update(s, x, y, z, rc, ptr<int32_t>(ctx->perm), ptr<double4>(ctx->list_ref), n,
+                       ctx->cell_box.L, ctx->rc_bound, ptr<double4>(ctx->sorted),
+                       ptr<double2>(ctx->list_part), ptr<double>(ctx->list_out), ctx->d_status);
+    launch_ext_refill(s, ptr<int32_t>(ctx->cell_start), ptr<int32_t>(ctx->ext_row_start),
+                      ptr<int32_t>(ctx->ext_row_lo), ptr<double4>(ctx->sorted), ctx->nc,
+                      ctx->halo, ctx->cell_box.L, ctx->ext_cap, ptr<double4>(ctx->ext_pos),
+                      ctx->d_status);
+  }
+  timer_end(ctx, "list", ev);
+  if (n > 0) {
+    if (hipMemcpyAsync(ctx->h_list_verdict, ptr<double>(ctx->list_out), 2 * sizeof(double),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_update_list: read-back failed");
+    dmax = ctx->h_list_verdict[0];
+    slack = ctx->h_list_verdict[1];
+  }
+  DCM_TRY(check_launch(ctx, "dcm_update_list"));
+  // every pair within r_c(i) now was within r_c(i) + 2 dmax <= R_i at the
+  // build; the margin covers the rounding of the distance tests
+  const double guard = 1e-12 * (ctx->rc_bound + ctx->list_skin);
+  const bool ok = (dmax == 0.0 && slack >= 0.0) || (slack - 2.0 * dmax >= guard);
+  *valid = ok ? 1 : 0;
+  if (max_disp) *max_disp = dmax;
+  if (min_slack) *min_slack = slack;
+  return DCM_OK;
+}
+
+dcm_status dcm_forces_list(dcm_ctx *ctx, dcm_lj lj, int prec, int ev_flags, double *fx,
+                           double *fy, double *fz, double *energy, double *virial, int32_t *nnbr,
+                           uint64_t *npairs) {
+  return forces_impl(ctx, lj, DCM_PAIR_OWN, prec, ev_flags, fx, fy, fz, energy, virial, nnbr,
+                     npairs, true);
 }
 
 dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,

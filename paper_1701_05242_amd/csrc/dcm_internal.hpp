@@ -116,6 +116,14 @@ struct dcm_ctx {
   // grid scratch
   dcm::DevBuf counts, gray, hist, seg_a, seg_b, seg, iface, dA, dB, dist, fsm_chg, fsm_flags;
   dcm::DevBuf ccl_label, ccl_size;  // bubble filter
+  // Verlet list of the last cell build
+  dcm::DevBuf list_count, list_wave_len, list_wave_start, list;
+  dcm::DevBuf list_ref, list_part, list_out;
+  int64_t list_n = -1;  // particles of the list (-1: none built)
+  double list_skin = 0.0;
+  int32_t *h_list_total = nullptr;  // pinned: entries / 64 of the last build
+  double *h_list_verdict = nullptr; // pinned: [displacement, slack] of the last update
+  bool cells_moved = false;  // positions replaced by dcm_update_list since the build
   // particle scratch
   dcm::DevBuf delta, rc, partials, ke, scalars;
   // cells
@@ -232,6 +240,12 @@ void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *s
                       int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
                       int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
                       uint32_t *status);
+// ghost images again from new positions of the same cells (the row tables of
+// the last build), without compact records
+void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
+                       const int32_t *row_lo, const double4 *sorted, const int32_t nc[3],
+                       const int32_t h[3], const double L[3], int64_t ext_cap, double4 *ext_pos,
+                       uint32_t *status);
 
 // k_pair.hip
 struct PairArgs {
@@ -261,6 +275,39 @@ struct PairArgs {
 };
 int pair_block_size();
 void launch_pair(hipStream_t s, const PairArgs &a, int rule, int prec);
+// forces over a Verlet list (k_list.hip layout), own-cutoff rule
+void launch_pair_list(hipStream_t s, const PairArgs &a, int prec, const int32_t *count,
+                      const int32_t *wave_start, const int32_t *list);
+
+// k_list.hip: Verlet list with a skin on the cells of the last build
+struct ListArgs {
+  const double4 *pos;        // sorted particles (x, y, z, rc)
+  const int32_t *cell_start;
+  const double4 *ext_pos;
+  const int32_t *ext_start;
+  int64_t n, ext_cap;
+  int32_t nc[3], h[3], ne[3];
+  double len[3], sc[3];
+  double rc_bound, skin;
+  int32_t *count;            // [n] list lengths
+  int32_t *wave_len;         // [n_waves] longest list of each wavefront
+  const int32_t *wave_start; // [n_waves + 1] exclusive scan of wave_len
+  int64_t n_waves;
+  int32_t *list;             // [list_cap]
+  int64_t list_cap;
+  double4 *ref;              // [n] build position and list radius R (count pass)
+  uint32_t *status;
+};
+int64_t list_waves(int64_t n);
+int64_t list_update_blocks(int64_t n);
+// new positions and cutoffs for the cells of the list's build (sorted order),
+// out[0] = largest displacement from the build, out[1] = smallest R - r_c
+void launch_list_update(hipStream_t s, const double *x, const double *y, const double *z,
+                        const double *rc, const int32_t *perm, const double4 *ref, int64_t n,
+                        const double L[3], double rc_cap, double4 *sorted, double2 *part,
+                        double *out, uint32_t *status);
+void launch_list_count(hipStream_t s, const ListArgs &a);
+void launch_list_fill(hipStream_t s, const ListArgs &a);
 
 struct BatchPairArgs {
   const SysGeom *sys;

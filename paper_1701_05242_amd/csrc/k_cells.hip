@@ -475,20 +475,43 @@ int64_t ext_row_scratch_elems(const int32_t nc[3], const int32_t h[3]) {
   return (int64_t)(nc[1] + 2 * h[1]) * (nc[2] + 2 * h[2]) + 1;
 }
 
-void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
-                      const int32_t nc[3], const int32_t h[3], const double L[3],
-                      int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
-                      int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
-                      uint32_t *status) {
+static ExtGeom ext_geom(const int32_t nc[3], const int32_t h[3], const double L[3]) {
   ExtGeom g;
-  int64_t next = 1;
   for (int a = 0; a < 3; ++a) {
     g.nc[a] = nc[a];
     g.h[a] = h[a];
     g.ne[a] = nc[a] + 2 * h[a];
     g.L[a] = L[a];
-    next *= g.ne[a];
   }
+  return g;
+}
+
+static void launch_ext_fill(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
+                            const int32_t *row_lo, const double4 *sorted, const ExtGeom &g,
+                            int64_t ext_cap, double4 *ext_pos, float4 *ext_rel,
+                            uint32_t *status) {
+  const int64_t nrows = (int64_t)g.ne[1] * g.ne[2];
+  int64_t b = ceil_div(nrows, 4);  // four rows per workgroup of 256
+  if (b > 16384) b = 16384;
+  hipLaunchKernelGGL(k_ext_fill, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
+                     row_lo, sorted, g, nrows, ext_cap, ext_pos, ext_rel, status);
+}
+
+void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
+                       const int32_t *row_lo, const double4 *sorted, const int32_t nc[3],
+                       const int32_t h[3], const double L[3], int64_t ext_cap, double4 *ext_pos,
+                       uint32_t *status) {
+  launch_ext_fill(s, cell_start, row_start, row_lo, sorted, ext_geom(nc, h, L), ext_cap, ext_pos,
+                  nullptr, status);
+}
+
+void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
+                      const int32_t nc[3], const int32_t h[3], const double L[3],
+                      int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
+                      int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
+                      uint32_t *status) {
+  const ExtGeom g = ext_geom(nc, h, L);
+  const int64_t next = (int64_t)g.ne[0] * g.ne[1] * g.ne[2];
   const int64_t nrows = (int64_t)g.ne[1] * g.ne[2];
   int64_t b = ceil_div(nrows, 256);
   if (b > 16384) b = 16384;
@@ -499,10 +522,7 @@ void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *s
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_ext_starts, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
                      row_lo, g, next, nrows, ext_start);
-  b = ceil_div(nrows, 4);  // four rows per workgroup of 256
-  if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_ext_fill, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
-                     row_lo, sorted, g, nrows, ext_cap, ext_pos, ext_rel, status);
+  launch_ext_fill(s, cell_start, row_start, row_lo, sorted, g, ext_cap, ext_pos, ext_rel, status);
 }
 
 }  // namespace dcm

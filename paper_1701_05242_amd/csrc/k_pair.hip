@@ -452,6 +452,46 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
   }
 }
 
+// Forces of the lane's particle to caller order (24 eps applied), its pair
+// count, and the block's deterministic partial sums E, W[6], pair count.
+template <int PREC>
+__device__ __forceinline__ void finish_block(const int32_t *perm, int64_t id0, double *fx,
+                                             double *fy, double *fz, int32_t *nnbr, int64_t s,
+                                             bool active, double eps, const Acc<PREC> &acc,
+                                             int cnt, double (*red)[kPartialSlots],
+                                             uint32_t *status, double *partial_out) {
+  if (active) {
+    const double c24 = 24.0 * eps;
+    const double Fx = c24 * acc.fx, Fy = c24 * acc.fy, Fz = c24 * acc.fz;
+    const int64_t i = perm[s] - id0;
+    fx[i] = Fx;
+    fy[i] = Fy;
+    fz[i] = Fz;
+    if (nnbr) nnbr[i] = cnt;
+    if (!finite3(Fx, Fy, Fz)) atomicOr(status, ST_NONFINITE_FORCE);
+  }
+  // deterministic block partials: E, W[6], pair count
+  double pv[kPartialSlots];
+  pv[0] = (double)acc.e * (2.0 * eps);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) pv[1 + k] = (double)acc.w[k] * (12.0 * eps);
+  pv[7] = (double)cnt;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kPartialSlots; ++k) {
+    double t = wave_sum(pv[k]);
+    if (lane == 0) red[wid][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPartialSlots) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPairBlock / 64; ++q) t += red[q][threadIdx.x];
+    partial_out[threadIdx.x] = t;
+  }
+}
+
+
 // One block of kPairBlock particles: sorted slot s for this lane (active if
 // it holds a particle).  Writes the forces and, from lanes 0..7, the block's
 // partial sums E, W[6], pair count to partial_out.  REL: FP32-mixed
@@ -535,35 +575,8 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
       sweep_rows<RULE, PREC, EVM, false>(v, active && redo, g, sig2, segs, acc, cnt, unused);
     }
   }
-  if (active) {
-    const double c24 = 24.0 * eps;
-    const double Fx = c24 * acc.fx, Fy = c24 * acc.fy, Fz = c24 * acc.fz;
-    const int64_t i = v.perm[s] - v.id0;
-    v.fx[i] = Fx;
-    v.fy[i] = Fy;
-    v.fz[i] = Fz;
-    if (v.nnbr) v.nnbr[i] = cnt;
-    if (!finite3(Fx, Fy, Fz)) atomicOr(status, ST_NONFINITE_FORCE);
-  }
-  // deterministic block partials: E, W[6], pair count
-  double pv[kPartialSlots];
-  pv[0] = (double)acc.e * (2.0 * eps);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) pv[1 + k] = (double)acc.w[k] * (12.0 * eps);
-  pv[7] = (double)cnt;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < kPartialSlots; ++k) {
-    double t = wave_sum(pv[k]);
-    if (lane == 0) red[wid][k] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x < kPartialSlots) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < kPairBlock / 64; ++q) t += red[q][threadIdx.x];
-    partial_out[threadIdx.x] = t;
-  }
+  finish_block<PREC>(v.perm, v.id0, v.fx, v.fy, v.fz, v.nnbr, s, active, eps, acc, cnt, red, status,
+                     partial_out);
 }
 
 template <int RULE, int PREC, int EVM, bool REL>
@@ -598,6 +611,79 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   v.nnbr = a.nnbr;
   pair_block<RULE, PREC, EVM, REL>(v, s, s < a.n, a.eps, a.sigma * a.sigma, segs, red, a.status,
                               a.partials + lblock * kPartialSlots);
+}
+
+// Forces from a Verlet list (Algorithm 2.3, own-cutoff rule): the lane's
+// list, entry k at wave_base + 64 k + lane, holds the candidates in the order
+// of the cell walk, so the included pairs and their order are those of
+// k_pair.
+template <int PREC, int EVM>
+__global__ __launch_bounds__(kPairBlock) void k_pair_list(PairArgs a, const int32_t *count,
+                                                          const int32_t *wave_start,
+                                                          const int32_t *list) {
+  __shared__ double red[kPairBlock / 64][kPartialSlots];
+  const int64_t s = blockIdx.x * (int64_t)kPairBlock + threadIdx.x;
+  const bool active = s < a.n;
+  Acc<PREC> acc;
+  int cnt = 0;
+  double xi = 0.0, yi = 0.0, zi = 0.0, rci = 0.0;
+  int len = 0;
+  if (active) {
+    const double4 pi = a.pos[s];
+    xi = pi.x;
+    yi = pi.y;
+    zi = pi.z;
+    rci = pi.w;
+    len = count[s];
+  }
+  const double rci2 = rci * rci, sig2 = a.sigma * a.sigma;
+  int wmax = len;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(wmax, off, 64);
+    wmax = o > wmax ? o : wmax;
+  }
+  // wavefronts past the last particle read the first list (their lanes are idle)
+  const int64_t w = (s >> 6) < ((a.n + 63) >> 6) ? (s >> 6) : 0;
+  const int32_t *mine = list + 64 * (int64_t)wave_start[w] + (s & 63);
+  // two entries per trip, each loaded a trip ahead of its use
+  int k = 0;
+  int ja = 0 < len ? mine[0] : 0;
+  double4 A = a.ext_pos[ja];
+  while (k < wmax) {
+    const int jb = k + 1 < len ? mine[64 * (int64_t)(k + 1)] : ja;
+    const double4 B = a.ext_pos[jb];
+    if (k < len) candidate<DCM_PAIR_OWN, PREC, EVM>(A, ja, -1, xi, yi, zi, rci, rci2, sig2, acc, cnt);
+    if (k + 1 >= wmax) break;
+    const int jc = k + 2 < len ? mine[64 * (int64_t)(k + 2)] : jb;
+    A = a.ext_pos[jc];
+    if (k + 1 < len)
+      candidate<DCM_PAIR_OWN, PREC, EVM>(B, jb, -1, xi, yi, zi, rci, rci2, sig2, acc, cnt);
+    ja = jc;
+    k += 2;
+  }
+  finish_block<PREC>(a.perm, 0, a.fx, a.fy, a.fz, a.nnbr, s, active, a.eps, acc, cnt, red,
+                     a.status, a.partials + blockIdx.x * kPartialSlots);
+}
+
+template <int PREC>
+static void launch_pair_list_ev(hipStream_t s, const PairArgs &a, const int32_t *count,
+                                const int32_t *wave_start, const int32_t *list, dim3 g, dim3 b) {
+  const int evm = ((a.ev_flags & DCM_EV_ENERGY) ? 1 : 0) | ((a.ev_flags & DCM_EV_VIRIAL) ? 2 : 0);
+  switch (evm) {
+    case 0: hipLaunchKernelGGL((k_pair_list<PREC, 0>), g, b, 0, s, a, count, wave_start, list); break;
+    case 1: hipLaunchKernelGGL((k_pair_list<PREC, 1>), g, b, 0, s, a, count, wave_start, list); break;
+    case 2: hipLaunchKernelGGL((k_pair_list<PREC, 2>), g, b, 0, s, a, count, wave_start, list); break;
+    default: hipLaunchKernelGGL((k_pair_list<PREC, 3>), g, b, 0, s, a, count, wave_start, list); break;
+  }
+}
+
+void launch_pair_list(hipStream_t s, const PairArgs &a, int prec, const int32_t *count,
+                      const int32_t *wave_start, const int32_t *list) {
+  const int64_t blocks = ceil_div(a.n, kPairBlock) > 0 ? ceil_div(a.n, kPairBlock) : 1;
+  dim3 g((unsigned)blocks), b(kPairBlock);
+  if (prec == DCM_FP64) launch_pair_list_ev<DCM_FP64>(s, a, count, wave_start, list, g, b);
+  else launch_pair_list_ev<DCM_FP32_MIXED>(s, a, count, wave_start, list, g, b);
 }
 
 // Batched form: a persistent grid takes work items (blocks of kPairBlock
