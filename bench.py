@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
     p.add_argument("--no-list", action="store_true", help="skip the Verlet-list leg")
-    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--table1", action="store_true",
                    help="only run the DCM-versus-static-cutoff timing of the paper's Table 1 "
                         "settings on the 1.2M-particle planar slab and print that as the line")
@@ -326,7 +326,8 @@ def cpu_baseline(s, seconds):
     rcg = oracle.rc_grid_for(s.rule, det["hv"])
     D, _ = oracle.fsm(det["nv"], det["hv"], det["seg"], det["iface"], rcg)
     rc = oracle.cutoffs(oracle.particle_distance(s.x, s.y, s.z, s.box, det["nv"], D), s.rule)
-    probe = workloads.sample_indices(s.n, 64, seed=7)
+    # a probe large enough that thread start-up does not dominate its time
+    probe = workloads.sample_indices(s.n, 512, seed=7)
     t0 = time.perf_counter()
     oracle.forces(s.x, s.y, s.z, rc, s.box, idx=probe)
     per_i = (time.perf_counter() - t0) / len(probe)
