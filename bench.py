@@ -43,6 +43,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
     p.add_argument("--no-list", action="store_true", help="skip the Verlet-list leg")
+    p.add_argument("--no-n3", action="store_true", help="skip the Newton's-third-law leg")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--table1", action="store_true",
                    help="only run the DCM-versus-static-cutoff timing of the paper's Table 1 "
@@ -314,6 +315,62 @@ def list_leg(s, dev, reps=5, skin=0.3):
     return out
 
 
+def n3_leg(s, dev, reps=3):
+    """The symmetric rule (r_ij <= max(rc_i, rc_j)) in FP64 on the same cells:
+    the plain traversal (every particle searches the largest cutoff) against
+    the Newton's-third-law form (each pair once, from the endpoint with the
+    larger cutoff, reactions added with atomics), and the own-cutoff rule
+    for reference.  Per form: average pair-kernel time ("pair" events) and
+    wall time of the whole dcm_forces call; pairs counted once per call."""
+    import torch
+
+    import paper_1701_05242_amd as dcm
+
+    f64 = dict(dtype=torch.float64, device=dev)
+    x, y, z = (torch.tensor(a, **f64) for a in (s.x, s.y, s.z))
+    grid = dcm.make_grid(s.box, s.h)
+    rule = dcm.make_rule(*s.rule)
+    nv = dcm.grid_voxels(grid)
+    seg = torch.zeros(nv, dtype=torch.uint8, device=dev)
+    iface = torch.zeros_like(seg)
+    dist = torch.zeros(nv, **f64)
+    rc = torch.zeros(s.n, **f64)
+    F = [torch.zeros(s.n, **f64) for _ in range(3)]
+    e = torch.zeros(1, **f64)
+    npairs = torch.zeros(1, dtype=torch.uint64, device=dev)
+    lj = dcm.make_lj()
+    ctx = dcm.dcm_create()
+    out = {"workload": s.name, "precision": "fp64", "cell_edge": 1.25}
+    try:
+        dcm.dcm_detect_interface(ctx, x, y, z, s.box, grid, seg, iface)
+        dcm.dcm_sweep_distance(ctx, seg, iface, grid, dcm.rc_grid_for(rule, grid), 64, dist)
+        dcm.dcm_assign_cutoffs(ctx, x, y, z, s.box, grid, dist, rule, rc)
+        dcm.dcm_build_cells(ctx, x, y, z, rc, s.box, 1.25, dcm.DCM_FP64, rc_bound=s.rule[1])
+        for name, pr in (("own", dcm.DCM_PAIR_OWN), ("max", dcm.DCM_PAIR_MAX),
+                         ("max_n3", dcm.DCM_PAIR_MAX_N3)):
+            call = lambda: dcm.dcm_forces(ctx, lj, *F, pair_rule=pr,
+                                          ev_flags=dcm.DCM_EV_ENERGY | dcm.DCM_EV_COUNTS,
+                                          energy=e, npairs=npairs)
+            call()
+            torch.cuda.synchronize()
+            dcm.dcm_set_profiling(ctx, True)
+            dcm.dcm_kernel_time(ctx, "pair")
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                call()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+            ms, k = dcm.dcm_kernel_time(ctx, "pair")
+            dcm.dcm_set_profiling(ctx, False)
+            out[name] = {"pair_kernel_ms": ms / max(k, 1), "call_ms": wall * 1e3,
+                         "pairs": int(npairs.cpu().numpy()[0])}
+        if dcm.dcm_sync_status(ctx) != dcm.DCM_OK:
+            raise RuntimeError(dcm.dcm_last_error(ctx))
+    finally:
+        dcm.dcm_destroy(ctx)
+    return out
+
+
 def cpu_baseline(s, seconds):
     """The oracle's O(N) per-particle sums on a seeded sample of particles."""
     import numpy as np
@@ -431,6 +488,10 @@ def main():
     if not args.no_list:
         vlist = list_leg(s, dev)
         print(f"[bench] verlet list {json.dumps(vlist)}", file=sys.stderr, flush=True)
+    n3 = None
+    if not args.no_n3:
+        n3 = n3_leg(s, dev)
+        print(f"[bench] newton3 {json.dumps(n3)}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(s, args.cpu_seconds)
@@ -470,6 +531,7 @@ def main():
             "pair_kernel_tflops": fp64_leg["pair_kernel_tflops"]},
         "batched": batched,
         "verlet_list": vlist,
+        "newton3": n3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -81,8 +81,15 @@ enum { DCM_FP64 = 0, DCM_FP32_MIXED = 1 };
 /* Which pairs interact.
  * DCM_PAIR_OWN (Algorithm 2.3): j acts on i iff r_ij < rc_i; Newton's third
  * law is not applied (Section 2.4), so sum_i F_i need not vanish.
- * DCM_PAIR_MAX: j and i interact iff r_ij <= max(rc_i, rc_j) (symmetric). */
-enum { DCM_PAIR_OWN = 0, DCM_PAIR_MAX = 1 };
+ * DCM_PAIR_MAX: j and i interact iff r_ij <= max(rc_i, rc_j) (symmetric).
+ * DCM_PAIR_MAX_N3: the pairs of DCM_PAIR_MAX, each evaluated once with
+ * Newton's third law (Section 2.4 and its footnotes on the trade-off): the
+ * endpoint with the larger cutoff (ties: the one sorted first) searches its
+ * own cutoff and adds the partner's reaction with atomics.  Results equal
+ * DCM_PAIR_MAX's up to FP64 summation order; the forces are not bitwise
+ * reproducible (atomic order), energy, virial and counts are.  dcm_forces
+ * and dcm_step only. */
+enum { DCM_PAIR_OWN = 0, DCM_PAIR_MAX = 1, DCM_PAIR_MAX_N3 = 2 };
 
 /* Optional outputs of dcm_forces. */
 enum { DCM_EV_ENERGY = 1, DCM_EV_VIRIAL = 2, DCM_EV_COUNTS = 4 };

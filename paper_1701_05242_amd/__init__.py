@@ -39,6 +39,7 @@ DCM_FP64 = 0
 DCM_FP32_MIXED = 1
 DCM_PAIR_OWN = 0
 DCM_PAIR_MAX = 1
+DCM_PAIR_MAX_N3 = 2
 DCM_EV_ENERGY = 1
 DCM_EV_VIRIAL = 2
 DCM_EV_COUNTS = 4

@@ -441,6 +441,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   // FP32-mixed builds also write the compact records the pair kernel reads
   const bool rel = prec == DCM_FP32_MIXED && halo[1] <= kRelMaxHalo && halo[2] <= kRelMaxHalo;
   if (rel) DCM_TRY(ensure(ctx, ctx->ext_rel, ext_cap * sizeof(float4)));
+  DCM_TRY(ensure(ctx, ctx->ext_src, ext_cap * sizeof(int32_t)));
   ctx->ext_cap = ext_cap;
   hipStream_t s = ctx->stream;
   hipEvent_t ev;
@@ -460,7 +461,8 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
                    ext_cap, ptr<int32_t>(ctx->ext_row_count), ptr<int32_t>(ctx->ext_row_start),
                    ptr<int32_t>(ctx->ext_row_lo), ptr<int32_t>(ctx->ext_start),
                    ptr<int32_t>(ctx->scan_tmp), ptr<double4>(ctx->ext_pos),
-                   rel ? ptr<float4>(ctx->ext_rel) : nullptr, ctx->d_status);
+                   rel ? ptr<float4>(ctx->ext_rel) : nullptr, ptr<int32_t>(ctx->ext_src),
+                   ctx->d_status);
   // exact ghost-extended count, read by a later build to size the buffer
   hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
                  hipMemcpyDeviceToHost, s);
@@ -510,7 +512,7 @@ dcm_status forces_impl(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_
                 "the cells again");
   const int64_t n = ctx->cell_n;
   if (n > 0 && (!fx || !fy || !fz)) return fail(ctx, DCM_ERR_INVALID, "dcm_forces: null force");
-  if (pair_rule != DCM_PAIR_OWN && pair_rule != DCM_PAIR_MAX)
+  if (pair_rule != DCM_PAIR_OWN && pair_rule != DCM_PAIR_MAX && pair_rule != DCM_PAIR_MAX_N3)
     return fail(ctx, DCM_ERR_INVALID, "unknown pair rule");
   if (prec != DCM_FP64 && prec != DCM_FP32_MIXED)
     return fail(ctx, DCM_ERR_INVALID, "unknown precision");
@@ -556,6 +558,19 @@ dcm_status forces_impl(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_
   a.nnbr = (ev_flags & DCM_EV_COUNTS) ? nnbr : nullptr;
   a.partials = ptr<double>(ctx->partials);
   a.status = ctx->d_status;
+  const bool n3 = pair_rule == DCM_PAIR_MAX_N3;
+  a.ext_src = ptr<int32_t>(ctx->ext_src);
+  a.n3_f = nullptr;
+  a.n3_cnt = nullptr;
+  if (n3) {
+    DCM_TRY(ensure(ctx, ctx->n3_f, std::max<int64_t>(n, 1) * sizeof(double4)));
+    DCM_TRY(ensure(ctx, ctx->n3_cnt, std::max<int64_t>(n, 1) * sizeof(int32_t)));
+    a.n3_f = ptr<double4>(ctx->n3_f);
+    a.n3_cnt = (ev_flags & DCM_EV_COUNTS) ? ptr<int32_t>(ctx->n3_cnt) : nullptr;
+    // zero sums (fill kernels, not memsets, so the calls stay capturable)
+    launch_fill_u32(ctx->stream, ptr<uint32_t>(ctx->n3_f), 0u, 8 * n);
+    if (a.n3_cnt) launch_fill_i32(ctx->stream, a.n3_cnt, 0, n);
+  }
   hipEvent_t ev;
   timer_begin(ctx, "pair", &ev);
   if (use_list)
@@ -564,6 +579,9 @@ dcm_status forces_impl(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_
   else
     launch_pair(ctx->stream, a, pair_rule, prec);
   timer_end(ctx, "pair", ev);
+  if (n3)
+    launch_n3_out(ctx->stream, a.n3_f, a.n3_cnt, a.perm, n, lj.epsilon, fx, fy, fz, a.nnbr,
+                  ctx->d_status);
   if (ev_flags & (DCM_EV_ENERGY | DCM_EV_VIRIAL | DCM_EV_COUNTS))
     launch_reduce_partials(ctx->stream, a.partials, blocks, lj.epsilon, ev_flags, energy, virial,
                            npairs);

@@ -130,6 +130,8 @@ struct dcm_ctx {
   dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp, rcmax_part;
   dcm::DevBuf ext_row_count, ext_row_start, ext_row_lo, ext_start, ext_pos;
   dcm::DevBuf ext_rel;  // FP32-mixed builds: compact cell-relative copy of ext_pos
+  dcm::DevBuf ext_src;  // sorted slot of each extended slot's particle
+  dcm::DevBuf n3_f, n3_cnt;  // Newton's-third-law forces and counts in sorted order
   int64_t ext_cap = 0;             // particles ext_pos can hold
   int32_t *h_ext_total = nullptr;  // pinned: ghost-extended count of the last build
   int32_t nc[3] = {0, 0, 0};
@@ -239,7 +241,7 @@ void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *s
                       const int32_t nc[3], const int32_t h[3], const double L[3],
                       int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
                       int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
-                      uint32_t *status);
+                      int32_t *ext_src, uint32_t *status);
 // ghost images again from new positions of the same cells (the row tables of
 // the last build), without compact records
 void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
@@ -272,9 +274,18 @@ struct PairArgs {
   int32_t *nnbr;
   double *partials;          // [blocks * kPartialSlots]
   uint32_t *status;
+  // rule DCM_PAIR_MAX_N3: source slots of ext_pos, and the sorted-order
+  // force and count sums the pairs' both endpoints are added to (zeroed)
+  const int32_t *ext_src;
+  double4 *n3_f;
+  int32_t *n3_cnt;           // null without DCM_EV_COUNTS
 };
 int pair_block_size();
 void launch_pair(hipStream_t s, const PairArgs &a, int rule, int prec);
+// rule DCM_PAIR_MAX_N3: sorted-order sums to caller order (24 eps applied)
+void launch_n3_out(hipStream_t s, const double4 *f, const int32_t *cnt, const int32_t *perm,
+                   int64_t n, double eps, double *fx, double *fy, double *fz, int32_t *nnbr,
+                   uint32_t *status);
 // forces over a Verlet list (k_list.hip layout), own-cutoff rule
 void launch_pair_list(hipStream_t s, const PairArgs &a, int prec, const int32_t *count,
                       const int32_t *wave_start, const int32_t *list);

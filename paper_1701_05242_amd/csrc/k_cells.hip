@@ -436,6 +436,7 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
                                                   int64_t nrows, int64_t cap,
                                                   double4 *__restrict__ ext_pos,
                                                   float4 *__restrict__ ext_rel,
+                                                  int32_t *__restrict__ ext_src,
                                                   uint32_t *status) {
   const double len[3] = {g.L[0] / (double)g.nc[0], g.L[1] / (double)g.nc[1],
                          g.L[2] / (double)g.nc[2]};
@@ -459,13 +460,15 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
         over = true;
         continue;
       }
-      double4 q = sorted[first + (P - p * T)];
+      const int src = first + (P - p * T);
+      double4 q = sorted[src];
       const int ex = slab_index(q.x, sc0, g.nc[0]) + p * g.nc[0];
       q.x = q.x + (double)p * g.L[0];
       q.y = q.y + sy;
       q.z = q.z + sz;
       ext_pos[o] = q;
       if (ext_rel) ext_rel[o] = rel_record(q, ex, r.ey, r.ez, len);
+      if (ext_src) ext_src[o] = src;
     }
     if (over) atomicOr(status, ST_GHOST_OVERFLOW);
   }
@@ -489,12 +492,12 @@ static ExtGeom ext_geom(const int32_t nc[3], const int32_t h[3], const double L[
 static void launch_ext_fill(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
                             const int32_t *row_lo, const double4 *sorted, const ExtGeom &g,
                             int64_t ext_cap, double4 *ext_pos, float4 *ext_rel,
-                            uint32_t *status) {
+                            int32_t *ext_src, uint32_t *status) {
   const int64_t nrows = (int64_t)g.ne[1] * g.ne[2];
   int64_t b = ceil_div(nrows, 4);  // four rows per workgroup of 256
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_ext_fill, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
-                     row_lo, sorted, g, nrows, ext_cap, ext_pos, ext_rel, status);
+                     row_lo, sorted, g, nrows, ext_cap, ext_pos, ext_rel, ext_src, status);
 }
 
 void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
@@ -502,14 +505,14 @@ void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *
                        const int32_t h[3], const double L[3], int64_t ext_cap, double4 *ext_pos,
                        uint32_t *status) {
   launch_ext_fill(s, cell_start, row_start, row_lo, sorted, ext_geom(nc, h, L), ext_cap, ext_pos,
-                  nullptr, status);
+                  nullptr, nullptr, status);
 }
 
 void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
                       const int32_t nc[3], const int32_t h[3], const double L[3],
                       int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
                       int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
-                      uint32_t *status) {
+                      int32_t *ext_src, uint32_t *status) {
   const ExtGeom g = ext_geom(nc, h, L);
   const int64_t next = (int64_t)g.ne[0] * g.ne[1] * g.ne[2];
   const int64_t nrows = (int64_t)g.ne[1] * g.ne[2];
@@ -522,7 +525,8 @@ void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *s
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_ext_starts, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
                      row_lo, g, next, nrows, ext_start);
-  launch_ext_fill(s, cell_start, row_start, row_lo, sorted, g, ext_cap, ext_pos, ext_rel, status);
+  launch_ext_fill(s, cell_start, row_start, row_lo, sorted, g, ext_cap, ext_pos, ext_rel, ext_src,
+                  status);
 }
 
 }  // namespace dcm

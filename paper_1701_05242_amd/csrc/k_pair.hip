@@ -67,10 +67,10 @@ __device__ __forceinline__ float recip_to_f32(double r2) {
 
 // One interacting pair with separation d (FP64) and r2.  The force factor
 // excludes 24 eps, the energy 4 eps / 2, the virial 24 eps / 2; they are
-// applied once per particle.
+// applied once per particle.  Returns the force factor (for a reaction).
 template <int PREC, int EVM>
-__device__ __forceinline__ void interact(Acc<PREC> &acc, double dx, double dy, double dz,
-                                         double r2, double sig2) {
+__device__ __forceinline__ double interact(Acc<PREC> &acc, double dx, double dy, double dz,
+                                           double r2, double sig2) {
   if constexpr (PREC == DCM_FP64) {
     double r2i = recip_newton2(r2);
     double s2 = sig2 * r2i;
@@ -89,6 +89,7 @@ __device__ __forceinline__ void interact(Acc<PREC> &acc, double dx, double dy, d
       acc.w[4] = fma(fdz, dx, acc.w[4]);
       acc.w[5] = fma(fdz, dy, acc.w[5]);
     }
+    return fp;
   } else {
     float r2i = recip_to_f32(r2);
     float s2 = (float)sig2 * r2i;
@@ -109,6 +110,7 @@ __device__ __forceinline__ void interact(Acc<PREC> &acc, double dx, double dy, d
       acc.w[4] = fmaf(fdz, dxf, acc.w[4]);
       acc.w[5] = fmaf(fdz, dyf, acc.w[5]);
     }
+    return fpd;
   }
 }
 
@@ -201,6 +203,9 @@ struct PairView {
   const unsigned long long *rc_all_bits;  // largest cutoff of the system (rule MAX)
   double *fx, *fy, *fz;
   int32_t *nnbr;
+  const int32_t *ext_src;        // rule DCM_PAIR_MAX_N3: source slot of each extended slot
+  double4 *n3_f;                 // ... and the sorted-order force and count sums
+  int32_t *n3_cnt;
 };
 
 // One lane's particle and search window.
@@ -211,7 +216,40 @@ struct LaneGeo {
   // the centre of the lane's cell
   double tin, margin, a0y, a0z;
   int zlo, zhi, ylo, yhi, cy, cz, self;
+  int slot;  // sorted slot of the lane's particle
 };
+
+// Newton's third law (rule MAX): a pair belongs to the endpoint with the
+// larger cutoff (ties: the smaller sorted slot), whose own cutoff is then the
+// pair's max(rc_i, rc_j), so the lane's own search radius finds every pair
+// it owns and each interacting pair is evaluated exactly once.  The partner's
+// reaction goes to the sorted-order sums with atomics.  A lane's own copy has
+// its own slot as source and is never owned.
+template <int PREC, int EVM>
+__device__ __forceinline__ void scan_n3(const uint2 (*segs)[kPairBlock], int nseg,
+                                        const PairView &v, const LaneGeo &g, double sig2,
+                                        Acc<PREC> &acc, int &cnt) {
+  const int lane_id = threadIdx.x;
+  for (int q = 0; q < nseg; ++q) {
+    const uint2 sg = segs[q][lane_id];
+    for (int j = (int)sg.x; j < (int)sg.y; ++j) {
+      const double4 pj = v.ext_pos[j];
+      const int src = v.ext_src[j];
+      const double dx = g.xi - pj.x, dy = g.yi - pj.y, dz = g.zi - pj.z;
+      const double r2 = (dx * dx + dy * dy) + dz * dz;
+      const bool owned = pj.w < g.rci || (pj.w == g.rci && src > g.slot);
+      if (owned && r2 <= g.rci2) {
+        const double fp = interact<PREC, EVM>(acc, dx, dy, dz, r2, sig2);
+        double *f = &v.n3_f[src].x;
+        unsafeAtomicAdd(f, -fp * dx);
+        unsafeAtomicAdd(f + 1, -fp * dy);
+        unsafeAtomicAdd(f + 2, -fp * dz);
+        if (v.n3_cnt) atomicAdd(&v.n3_cnt[src], 1);
+        ++cnt;
+      }
+    }
+  }
+}
 
 // One pair of the own-cutoff FP32-mixed kernel evaluated for every lane, the
 // result kept only where inc is set: the force of a lane without an
@@ -445,10 +483,38 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     if (nseg > 0) {
       if constexpr (REL)
         scan_rel<EVM>(segs, nseg, rs, g, v.len, sig2, acc, cnt, redo);
+      else if constexpr (RULE == DCM_PAIR_MAX_N3)
+        scan_n3<PREC, EVM>(segs, nseg, v, g, sig2, acc, cnt);
       else
         scan_ranges<RULE, PREC, EVM>(segs, nseg, v.ext_pos, g.self, g.xi, g.yi, g.zi, g.rci,
                                      g.rci2, sig2, acc, cnt);
     }
+  }
+}
+
+// The block's deterministic partial sums: E = e_scale * sum of the lanes'
+// energy terms, W = w_scale * virial terms, and the pair count.
+template <int PREC>
+__device__ __forceinline__ void block_partials(const Acc<PREC> &acc, int64_t cnt, double e_scale,
+                                               double w_scale, double (*red)[kPartialSlots],
+                                               double *partial_out) {
+  double pv[kPartialSlots];
+  pv[0] = (double)acc.e * e_scale;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) pv[1 + k] = (double)acc.w[k] * w_scale;
+  pv[7] = (double)cnt;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kPartialSlots; ++k) {
+    double t = wave_sum(pv[k]);
+    if (lane == 0) red[wid][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPartialSlots) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPairBlock / 64; ++q) t += red[q][threadIdx.x];
+    partial_out[threadIdx.x] = t;
   }
 }
 
@@ -470,27 +536,8 @@ __device__ __forceinline__ void finish_block(const int32_t *perm, int64_t id0, d
     if (nnbr) nnbr[i] = cnt;
     if (!finite3(Fx, Fy, Fz)) atomicOr(status, ST_NONFINITE_FORCE);
   }
-  // deterministic block partials: E, W[6], pair count
-  double pv[kPartialSlots];
-  pv[0] = (double)acc.e * (2.0 * eps);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) pv[1 + k] = (double)acc.w[k] * (12.0 * eps);
-  pv[7] = (double)cnt;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < kPartialSlots; ++k) {
-    double t = wave_sum(pv[k]);
-    if (lane == 0) red[wid][k] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x < kPartialSlots) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < kPairBlock / 64; ++q) t += red[q][threadIdx.x];
-    partial_out[threadIdx.x] = t;
-  }
+  block_partials<PREC>(acc, cnt, 2.0 * eps, 12.0 * eps, red, partial_out);
 }
-
 
 // One block of kPairBlock particles: sorted slot s for this lane (active if
 // it holds a particle).  Writes the forces and, from lanes 0..7, the block's
@@ -514,6 +561,7 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   g.zhi = g.yhi = -1;
   g.cy = g.cz = 0;
   g.self = -1;
+  g.slot = (int)s;
   if (active) {
     const double4 pi = v.pos[s];
     g.xi = pi.x;
@@ -575,8 +623,21 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
       sweep_rows<RULE, PREC, EVM, false>(v, active && redo, g, sig2, segs, acc, cnt, unused);
     }
   }
-  finish_block<PREC>(v.perm, v.id0, v.fx, v.fy, v.fz, v.nnbr, s, active, eps, acc, cnt, red, status,
-                     partial_out);
+  if constexpr (RULE == DCM_PAIR_MAX_N3) {
+    // partners add to this particle's sums too; each pair counts for both
+    // endpoints and carries its whole energy and virial
+    if (active) {
+      double *f = &v.n3_f[s].x;
+      unsafeAtomicAdd(f, acc.fx);
+      unsafeAtomicAdd(f + 1, acc.fy);
+      unsafeAtomicAdd(f + 2, acc.fz);
+      if (v.n3_cnt) atomicAdd(&v.n3_cnt[s], cnt);
+    }
+    block_partials<PREC>(acc, 2 * (int64_t)cnt, 4.0 * eps, 24.0 * eps, red, partial_out);
+  } else {
+    finish_block<PREC>(v.perm, v.id0, v.fx, v.fy, v.fz, v.nnbr, s, active, eps, acc, cnt, red,
+                       status, partial_out);
+  }
 }
 
 template <int RULE, int PREC, int EVM, bool REL>
@@ -609,6 +670,9 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   v.fy = a.fy;
   v.fz = a.fz;
   v.nnbr = a.nnbr;
+  v.ext_src = a.ext_src;
+  v.n3_f = a.n3_f;
+  v.n3_cnt = a.n3_cnt;
   pair_block<RULE, PREC, EVM, REL>(v, s, s < a.n, a.eps, a.sigma * a.sigma, segs, red, a.status,
                               a.partials + lblock * kPartialSlots);
 }
@@ -730,6 +794,9 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
     v.fy = g.fy;
     v.fz = g.fz;
     v.nnbr = g.nnbr;
+    v.ext_src = nullptr;
+    v.n3_f = nullptr;
+    v.n3_cnt = nullptr;
     const int64_t local = first + threadIdx.x;
     pair_block<RULE, PREC, EVM, REL>(v, g.p0 + local, local < g.n, a.eps, sig2, segs, red,
                                      a.status,
@@ -755,10 +822,44 @@ void launch_pair(hipStream_t s, const PairArgs &a, int rule, int prec) {
     if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_OWN, DCM_FP64, false>(s, a, g, b);
     else if (a.ext_rel) launch_pair_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true>(s, a, g, b);
     else launch_pair_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, false>(s, a, g, b);
-  } else {
+  } else if (rule == DCM_PAIR_MAX) {
     if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_MAX, DCM_FP64, false>(s, a, g, b);
     else launch_pair_ev<DCM_PAIR_MAX, DCM_FP32_MIXED, false>(s, a, g, b);
+  } else {
+    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_MAX_N3, DCM_FP64, false>(s, a, g, b);
+    else launch_pair_ev<DCM_PAIR_MAX_N3, DCM_FP32_MIXED, false>(s, a, g, b);
   }
+}
+
+// Rule DCM_PAIR_MAX_N3: the sorted-order sums (complete once the pair kernel
+// has finished) to caller order.
+__global__ __launch_bounds__(256) void k_n3_out(const double4 *__restrict__ f,
+                                                const int32_t *__restrict__ cnt,
+                                                const int32_t *__restrict__ perm, int64_t n,
+                                                double c24, double *__restrict__ fx,
+                                                double *__restrict__ fy, double *__restrict__ fz,
+                                                int32_t *__restrict__ nnbr, uint32_t *status) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
+       s += (int64_t)gridDim.x * blockDim.x) {
+    const double4 F = f[s];
+    const double Fx = c24 * F.x, Fy = c24 * F.y, Fz = c24 * F.z;
+    const int i = perm[s];
+    fx[i] = Fx;
+    fy[i] = Fy;
+    fz[i] = Fz;
+    if (nnbr) nnbr[i] = cnt[s];
+    if (!finite3(Fx, Fy, Fz)) atomicOr(status, ST_NONFINITE_FORCE);
+  }
+}
+
+void launch_n3_out(hipStream_t s, const double4 *f, const int32_t *cnt, const int32_t *perm,
+                   int64_t n, double eps, double *fx, double *fy, double *fz, int32_t *nnbr,
+                   uint32_t *status) {
+  if (n <= 0) return;
+  int64_t b = ceil_div(n, 256);
+  if (b > 16384) b = 16384;
+  hipLaunchKernelGGL(k_n3_out, dim3((unsigned)b), dim3(256), 0, s, f, cnt, perm, n, 24.0 * eps,
+                     fx, fy, fz, nnbr, status);
 }
 
 template <int RULE, int PREC, bool REL>
