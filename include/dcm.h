@@ -9,7 +9,10 @@
  *   cutoff-limited fast-sweeping distances     (Section 2.2, Algorithm 2.1)
  *   per-particle cutoffs from the distances    (Section 2.2)
  *   linked-cell binning with small cells       (Section 2.3, Algorithm 2.2)
- *   dynamic-cutoff Lennard-Jones forces        (Section 2.4, Algorithm 2.3, Eqs. 2-3)
+ *   Verlet lists with a skin, reused over steps (Section 2.3, Algorithm 2.2)
+ *   dynamic-cutoff Lennard-Jones forces        (Section 2.4, Algorithm 2.3, Eqs. 2-3),
+ *     optionally with Newton's third law       (Section 2.4)
+ *   many independent systems in one pass       (Section 2.4, dynamic scheduling)
  *   velocity Verlet integration                (Section 2, Fig. 3 box 5)
  *
  * Conventions shared by every entry point
@@ -20,7 +23,9 @@
  *   periodic box [0, L_a); inputs outside it are wrapped on the fly.
  * - Every call is asynchronous on the context's HIP stream.  Scalar outputs
  *   (energies, virials, counters) are device scalars.  No call synchronises
- *   the stream except dcm_sync_status, dcm_create and dcm_destroy.
+ *   the stream except dcm_sync_status, dcm_create, dcm_destroy,
+ *   dcm_build_list and dcm_update_list (they read a size or a verdict back),
+ *   and dcm_forces_batched when it tunes the cell edge of a new batch.
  * - Scratch memory (grid buffers, cells, sorted copies, partial sums) is owned
  *   by the context and grown on demand; growing it allocates device memory,
  *   so call each entry point once with its largest sizes before capturing it
@@ -222,7 +227,10 @@ dcm_status dcm_cell_dims(const dcm_ctx *ctx, int32_t n_cells[3], double cell_len
  *   DCM_EV_COUNTS: nnbr[i] = number of j acting on i (int32 [n]), *npairs =
  *                  number of interacting ordered pairs (uint64).
  * Pointers for unrequested outputs may be NULL.  energy/virial/npairs are
- * device scalars.  The energy and virial sums are deterministic. */
+ * device scalars.  The energy and virial sums are deterministic; so are the
+ * forces, except under DCM_PAIR_MAX_N3 (atomic reactions).
+ * Errors: DCM_ERR_INVALID before a cell build, after dcm_update_list, or for
+ * an unknown rule or precision. */
 dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_flags,
                       double *fx, double *fy, double *fz, double *energy, double *virial,
                       int32_t *nnbr, uint64_t *npairs);
@@ -319,8 +327,9 @@ typedef struct {
  * replay it (the arrays' contents may change between calls, their addresses
  * and sizes may not).  Work is ordered after earlier work on the context's
  * stream and before later work on it.
- * Limits: sum of n below 2^24.  Device-detected conditions (non-finite
- * input or force, cutoffs above rc_bound) as for the single-system calls. */
+ * Limits: sum of n below 2^24; pair_rule DCM_PAIR_OWN or DCM_PAIR_MAX.
+ * Device-detected conditions (non-finite input or force, cutoffs above
+ * rc_bound) as for the single-system calls. */
 dcm_status dcm_forces_batched(dcm_ctx *ctx, int32_t nsys, const dcm_system *sys, dcm_lj lj,
                               int pair_rule, int prec, int ev_flags, int use_graph);
 
