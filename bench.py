@@ -11,7 +11,10 @@ Printed (one JSON line): pair interactions per second over the whole step,
 force evaluations per second, the pair kernel's achieved rate against the
 VALU roofline (HIP events around every pair launch inside the timed region),
 the FP64 path's figures on the same workload, and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+on a bounded sample of the same workload.  Context beside them: the same
+step with re-detection every 10 steps, the 64-system batched form, Verlet
+lists against the cell walk, and the symmetric rule with and without
+Newton's third law.
 """
 from __future__ import annotations
 
@@ -54,7 +57,7 @@ def parse():
     return p.parse_args()
 
 
-def run_leg(s, prec, steps, warmup, dev):
+def run_leg(s, prec, steps, warmup, dev, redetect=1):
     import torch
 
     import paper_1701_05242_amd as dcm
@@ -73,7 +76,7 @@ def run_leg(s, prec, steps, warmup, dev):
         dcm.dcm_step(ctx, *pos, *vel, *frc, s.box, lj, rule, grid, rcg, 0.005, 0, prec=prec, rc=rc)
         if warmup:
             dcm.dcm_step(ctx, *pos, *vel, *frc, s.box, lj, rule, grid, rcg, 0.005, warmup,
-                         prec=prec, redetect_every=1, rc=rc)
+                         prec=prec, redetect_every=redetect, rc=rc)
         if dcm.dcm_sync_status(ctx) != dcm.DCM_OK:
             raise RuntimeError(dcm.dcm_last_error(ctx))
 
@@ -93,7 +96,7 @@ def run_leg(s, prec, steps, warmup, dev):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         dcm.dcm_step(ctx, *pos, *vel, *frc, s.box, lj, rule, grid, rcg, 0.005, steps,
-                     prec=prec, redetect_every=1, step0=warmup, rc=rc)
+                     prec=prec, redetect_every=redetect, step0=warmup, rc=rc)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         fam_ms = {fam: dcm.dcm_kernel_time(ctx, fam)
@@ -480,6 +483,10 @@ def main():
     if not args.no_fp64 and prec != dcm.DCM_FP64:
         fp64_leg = run_leg(s, dcm.DCM_FP64, max(3, args.steps // 4), 1, dev)
         print(f"[bench] fp64 leg {json.dumps(fp64_leg)}", file=sys.stderr, flush=True)
+    every10 = None
+    if not args.no_fp64:
+        every10 = run_leg(s, prec, args.steps, args.warmup, dev, redetect=10)
+        print(f"[bench] re-detect every 10 {json.dumps(every10)}", file=sys.stderr, flush=True)
     batched = None
     if not args.no_batched:
         batched = batched_leg(args.steps, dev)
@@ -529,6 +536,9 @@ def main():
             "force_evals_per_s": fp64_leg["force_evals"],
             "pair_kernel_ms": fp64_leg["avg_pair_ms"],
             "pair_kernel_tflops": fp64_leg["pair_kernel_tflops"]},
+        "redetect_every_10": None if every10 is None else {
+            "value": every10["pair_rate"], "ms_per_step": every10["ms_per_step"],
+            "force_evals_per_s": every10["force_evals"]},
         "batched": batched,
         "verlet_list": vlist,
         "newton3": n3,

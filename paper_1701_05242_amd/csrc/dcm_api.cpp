@@ -365,6 +365,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
                            double rc_bound, int prec, int32_t *cell_of, int32_t *cell_start) {
   if (!ctx) return DCM_ERR_INVALID;
   ctx->list_n = -1;
+  ctx->ext_src_ok = false;
   DCM_TRY(check_n(ctx, n));
   DCM_TRY(check_box(ctx, box));
   if (n > 0 && (!x || !y || !z || !rc))
@@ -441,7 +442,6 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   // FP32-mixed builds also write the compact records the pair kernel reads
   const bool rel = prec == DCM_FP32_MIXED && halo[1] <= kRelMaxHalo && halo[2] <= kRelMaxHalo;
   if (rel) DCM_TRY(ensure(ctx, ctx->ext_rel, ext_cap * sizeof(float4)));
-  DCM_TRY(ensure(ctx, ctx->ext_src, ext_cap * sizeof(int32_t)));
   ctx->ext_cap = ext_cap;
   hipStream_t s = ctx->stream;
   hipEvent_t ev;
@@ -461,8 +461,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
                    ext_cap, ptr<int32_t>(ctx->ext_row_count), ptr<int32_t>(ctx->ext_row_start),
                    ptr<int32_t>(ctx->ext_row_lo), ptr<int32_t>(ctx->ext_start),
                    ptr<int32_t>(ctx->scan_tmp), ptr<double4>(ctx->ext_pos),
-                   rel ? ptr<float4>(ctx->ext_rel) : nullptr, ptr<int32_t>(ctx->ext_src),
-                   ctx->d_status);
+                   rel ? ptr<float4>(ctx->ext_rel) : nullptr, nullptr, ctx->d_status);
   // exact ghost-extended count, read by a later build to size the buffer
   hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
                  hipMemcpyDeviceToHost, s);
@@ -480,6 +479,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   ctx->cell_n = n;
   ctx->list_n = -1;  // a list belongs to the build it was made on
   ctx->cells_moved = false;
+  ctx->ext_src_ok = false;
   ctx->cell_prec = prec;
   ctx->cell_rel = rel;
   ctx->rc_bound = rc_cap;
@@ -559,10 +559,19 @@ dcm_status forces_impl(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_
   a.partials = ptr<double>(ctx->partials);
   a.status = ctx->d_status;
   const bool n3 = pair_rule == DCM_PAIR_MAX_N3;
-  a.ext_src = ptr<int32_t>(ctx->ext_src);
+  a.ext_src = nullptr;
   a.n3_f = nullptr;
   a.n3_cnt = nullptr;
   if (n3) {
+    // the ghosts' source slots, made once per cell build
+    if (!ctx->ext_src_ok) {
+      DCM_TRY(ensure(ctx, ctx->ext_src, ctx->ext_cap * sizeof(int32_t)));
+      launch_ext_src(ctx->stream, ptr<int32_t>(ctx->cell_start), ptr<int32_t>(ctx->ext_row_start),
+                     ptr<int32_t>(ctx->ext_row_lo), ctx->nc, ctx->halo, ctx->cell_box.L,
+                     ctx->ext_cap, ptr<int32_t>(ctx->ext_src), ctx->d_status);
+      ctx->ext_src_ok = true;
+    }
+    a.ext_src = ptr<int32_t>(ctx->ext_src);
     DCM_TRY(ensure(ctx, ctx->n3_f, std::max<int64_t>(n, 1) * sizeof(double4)));
     DCM_TRY(ensure(ctx, ctx->n3_cnt, std::max<int64_t>(n, 1) * sizeof(int32_t)));
     a.n3_f = ptr<double4>(ctx->n3_f);

@@ -130,7 +130,8 @@ struct dcm_ctx {
   dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp, rcmax_part;
   dcm::DevBuf ext_row_count, ext_row_start, ext_row_lo, ext_start, ext_pos;
   dcm::DevBuf ext_rel;  // FP32-mixed builds: compact cell-relative copy of ext_pos
-  dcm::DevBuf ext_src;  // sorted slot of each extended slot's particle
+  dcm::DevBuf ext_src;  // sorted slot of each extended slot's particle (on demand)
+  bool ext_src_ok = false;  // ext_src belongs to the current cell build
   dcm::DevBuf n3_f, n3_cnt;  // Newton's-third-law forces and counts in sorted order
   int64_t ext_cap = 0;             // particles ext_pos can hold
   int32_t *h_ext_total = nullptr;  // pinned: ghost-extended count of the last build
@@ -242,6 +243,10 @@ void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *s
                       int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
                       int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
                       int32_t *ext_src, uint32_t *status);
+// source sorted slot of every extended slot of the last build (row tables)
+void launch_ext_src(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
+                    const int32_t *row_lo, const int32_t nc[3], const int32_t h[3],
+                    const double L[3], int64_t ext_cap, int32_t *ext_src, uint32_t *status);
 // ghost images again from new positions of the same cells (the row tables of
 // the last build), without compact records
 void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,

@@ -428,7 +428,8 @@ __global__ __launch_bounds__(256) void k_ext_starts(const int32_t *__restrict__ 
 
 // Copy of every extended row, one wavefront per row.  Writes stop at the
 // buffer's capacity; running past it flags an overflow (the pair kernel then
-// refuses to read ghost ranges beyond the capacity).
+// refuses to read ghost ranges beyond the capacity).  Each of ext_pos,
+// ext_rel and ext_src (the source's sorted slot) is written when not null.
 __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ cell_start,
                                                   const int32_t *__restrict__ row_start,
                                                   const int32_t *__restrict__ row_lo,
@@ -461,6 +462,8 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
         continue;
       }
       const int src = first + (P - p * T);
+      if (ext_src) ext_src[o] = src;
+      if (!ext_pos) continue;
       double4 q = sorted[src];
       const int ex = slab_index(q.x, sc0, g.nc[0]) + p * g.nc[0];
       q.x = q.x + (double)p * g.L[0];
@@ -468,7 +471,6 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
       q.z = q.z + sz;
       ext_pos[o] = q;
       if (ext_rel) ext_rel[o] = rel_record(q, ex, r.ey, r.ez, len);
-      if (ext_src) ext_src[o] = src;
     }
     if (over) atomicOr(status, ST_GHOST_OVERFLOW);
   }
@@ -498,6 +500,13 @@ static void launch_ext_fill(hipStream_t s, const int32_t *cell_start, const int3
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_ext_fill, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
                      row_lo, sorted, g, nrows, ext_cap, ext_pos, ext_rel, ext_src, status);
+}
+
+void launch_ext_src(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
+                    const int32_t *row_lo, const int32_t nc[3], const int32_t h[3],
+                    const double L[3], int64_t ext_cap, int32_t *ext_src, uint32_t *status) {
+  launch_ext_fill(s, cell_start, row_start, row_lo, nullptr, ext_geom(nc, h, L), ext_cap, nullptr,
+                  nullptr, ext_src, status);
 }
 
 void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
