@@ -211,10 +211,10 @@ struct PairView {
 // One lane's particle and search window.
 struct LaneGeo {
   double xi, yi, zi, rci, rci2, R2, guard;
-  // compact records: a rebuilt r^2 below tin is surely inside the cutoff, one
-  // within margin of rci2 cannot be decided; a0y, a0z are yi, zi relative to
-  // the centre of the lane's cell
-  double tin, margin, a0y, a0z;
+  // compact records, all FP32: the lane's position relative to the centre of
+  // its own cell (a0), that cell's x index + 1/2 (wc), the cell edges, rc^2,
+  // and the band around it within which an FP32 r^2 cannot decide a pair
+  float a0x, a0y, a0z, wc, lenf[3], rc2f, margin;
   int zlo, zhi, ylo, yhi, cy, cz, self;
   int slot;  // sorted slot of the lane's particle
 };
@@ -251,35 +251,35 @@ __device__ __forceinline__ void scan_n3(const uint2 (*segs)[kPairBlock], int nse
   }
 }
 
-// One pair of the own-cutoff FP32-mixed kernel evaluated for every lane, the
-// result kept only where inc is set: the force of a lane without an
-// interaction in this step is computed and discarded instead of branched
-// around (the wavefront executes it anyway whenever any lane interacts).
+// One pair of the own-cutoff FP32-mixed kernel on compact records, evaluated
+// for every lane with the result kept only where inc is set: the force of a
+// lane without an interaction in this step is computed and discarded instead
+// of branched around (the wavefront executes it anyway whenever any lane
+// interacts).  FP32 separations and r^2.
 template <int EVM>
-__device__ __forceinline__ void interact_masked(Acc<DCM_FP32_MIXED> &acc, double dx, double dy,
-                                                double dz, double r2, double sig2, bool inc) {
-  const float r2i = recip_to_f32(r2);
-  const float s2 = (float)sig2 * r2i;
+__device__ __forceinline__ void interact_rel(Acc<DCM_FP32_MIXED> &acc, float dx, float dy, float dz,
+                                             float r2, float sig2, bool inc) {
+  const float r2i = __builtin_amdgcn_rcpf(r2);
+  const float s2 = sig2 * r2i;
   const float s6 = s2 * s2 * s2;
   const float fpv = s6 * fmaf(2.0f, s6, -1.0f) * r2i;
   const float fp = inc ? fpv : 0.0f;
   const double fpd = (double)fp;
-  acc.fx = fma(fpd, dx, acc.fx);
-  acc.fy = fma(fpd, dy, acc.fy);
-  acc.fz = fma(fpd, dz, acc.fz);
+  acc.fx = fma(fpd, (double)dx, acc.fx);
+  acc.fy = fma(fpd, (double)dy, acc.fy);
+  acc.fz = fma(fpd, (double)dz, acc.fz);
   if constexpr ((EVM & 1) != 0) {
     const float et = s6 * (s6 - 1.0f);
     acc.e += inc ? et : 0.0f;
   }
   if constexpr ((EVM & 2) != 0) {
-    const float dxf = (float)dx, dyf = (float)dy, dzf = (float)dz;
-    const float fdx = fp * dxf, fdy = fp * dyf, fdz = fp * dzf;
-    acc.w[0] = fmaf(fdx, dxf, acc.w[0]);
-    acc.w[1] = fmaf(fdy, dyf, acc.w[1]);
-    acc.w[2] = fmaf(fdz, dzf, acc.w[2]);
-    acc.w[3] = fmaf(fdy, dxf, acc.w[3]);
-    acc.w[4] = fmaf(fdz, dxf, acc.w[4]);
-    acc.w[5] = fmaf(fdz, dyf, acc.w[5]);
+    const float fdx = fp * dx, fdy = fp * dy, fdz = fp * dz;
+    acc.w[0] = fmaf(fdx, dx, acc.w[0]);
+    acc.w[1] = fmaf(fdy, dy, acc.w[1]);
+    acc.w[2] = fmaf(fdz, dz, acc.w[2]);
+    acc.w[3] = fmaf(fdy, dx, acc.w[3]);
+    acc.w[4] = fmaf(fdz, dx, acc.w[4]);
+    acc.w[5] = fmaf(fdz, dy, acc.w[5]);
   }
 }
 
@@ -297,17 +297,18 @@ __device__ __forceinline__ float4 load_rel(__amdgpu_buffer_rsrc_t rs, int j) {
 // Flat loop over the compact-record candidates of this lane's first nseg
 // listed rows (FP32-mixed, own-cutoff rule).  A list entry is (first slot,
 // length | (row y - cy) << 16 | (row z - cz) << 24), the offsets as signed
-// bytes; the lane's own slot is never listed.  Separations are rebuilt in
-// FP64 from the cell-centre-relative FP32 record; a pair whose rebuilt r^2
-// lies within the proven error margin of the cutoff cannot be decided here
-// and marks the lane for the exact pass.  The stream is advanced with
-// selects, two register sets take turns so that every record is loaded a
-// full candidate before its use.
+// bytes; the lane's own slot is never listed.  Separations are formed in
+// FP32 between the two cell-centre-relative positions, the candidate's cell
+// k cells away: d = (a0 - k len) - rel.  A pair whose FP32 r^2 lies within
+// the lane's proven error band around rc^2 is decided from its FP64 record
+// instead (rare: the band is ~1e-5 sigma^2 wide).  The stream is advanced
+// with selects, two register sets take turns so that every record is loaded
+// a full candidate before its use.
 template <int EVM>
 __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int nseg,
-                                         __amdgpu_buffer_rsrc_t rs, const LaneGeo &g,
-                                         const double len[3], double sig2,
-                                         Acc<DCM_FP32_MIXED> &acc, int &cnt, bool &redo) {
+                                         __amdgpu_buffer_rsrc_t rs,
+                                         const double4 *__restrict__ ext_pos, const LaneGeo &g,
+                                         float sig2, Acc<DCM_FP32_MIXED> &acc, int &cnt) {
   const int lane_id = threadIdx.x;
   const int last = nseg - 1;
   const uint2 s0 = segs[0][lane_id];
@@ -327,17 +328,25 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int ns
     t = tag;
     return ok ? j : -1;
   };
-  bool amb = false;
-  auto eval = [&](const float4 &r, uint32_t t) {
+  auto eval = [&](const float4 &r, uint32_t t, int jr) {
     const int dyc = (int)(t << 8) >> 24, dzc = (int)t >> 24;
-    const double ay = fma(-(double)dyc, len[1], g.a0y);
-    const double az = fma(-(double)dzc, len[2], g.a0z);
-    const double dx = fma(-(double)r.w, len[0], g.xi) - (double)r.x;
-    const double dy = ay - (double)r.y, dz = az - (double)r.z;
-    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-    const bool inc = r2 < g.tin;
-    amb |= fabs(r2 - g.rci2) <= g.margin;
-    interact_masked<EVM>(acc, dx, dy, dz, r2, sig2, inc);
+    const float ay = fmaf(-(float)dyc, g.lenf[1], g.a0y);
+    const float az = fmaf(-(float)dzc, g.lenf[2], g.a0z);
+    float dx = fmaf(-(r.w - g.wc), g.lenf[0], g.a0x) - r.x;
+    float dy = ay - r.y, dz = az - r.z;
+    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    bool inc = r2 < g.rc2f;
+    if (fabsf(r2 - g.rc2f) <= g.margin) {
+      const double4 q = ext_pos[jr];
+      const double ex = g.xi - q.x, ey = g.yi - q.y, ez = g.zi - q.z;
+      const double e2 = (ex * ex + ey * ey) + ez * ez;
+      inc = e2 < g.rci2;
+      dx = (float)ex;
+      dy = (float)ey;
+      dz = (float)ez;
+      r2 = (float)e2;
+    }
+    interact_rel<EVM>(acc, dx, dy, dz, r2, sig2, inc);
     cnt += inc ? 1 : 0;
   };
   int ja = j;
@@ -348,19 +357,18 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int ns
     float4 B = load_rel(rs, jb >= 0 ? jb : ja);
     uint32_t tc = 0;
     const int jc = jb >= 0 ? advance(tc) : -1;
-    eval(A, ta);
+    eval(A, ta, ja);
     if (jb < 0) break;
     A = load_rel(rs, jc >= 0 ? jc : jb);
     uint32_t td = 0;
     const int jd = jc >= 0 ? advance(td) : -1;
-    eval(B, tb);
+    eval(B, tb, jb);
     if (jc < 0) break;
     ja = jc;
     ta = tc;
     jb = jd;
     tb = td;
   }
-  redo |= amb;
 }
 
 // Walk this lane's rows (fill a list, scan it, repeat) for a lane with run
@@ -482,7 +490,7 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     }
     if (nseg > 0) {
       if constexpr (REL)
-        scan_rel<EVM>(segs, nseg, rs, g, v.len, sig2, acc, cnt, redo);
+        scan_rel<EVM>(segs, nseg, rs, v.ext_pos, g, (float)sig2, acc, cnt);
       else if constexpr (RULE == DCM_PAIR_MAX_N3)
         scan_n3<PREC, EVM>(segs, nseg, v, g, sig2, acc, cnt);
       else
@@ -556,7 +564,8 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   const int nex = v.ne[0], ney = v.ne[1];
   LaneGeo g;
   g.xi = g.yi = g.zi = g.rci = g.rci2 = g.R2 = g.guard = 0.0;
-  g.tin = g.margin = g.a0y = g.a0z = 0.0;
+  g.a0x = g.a0y = g.a0z = g.wc = g.rc2f = g.margin = 0.0f;
+  g.lenf[0] = g.lenf[1] = g.lenf[2] = 0.0f;
   g.zlo = g.ylo = 0;
   g.zhi = g.yhi = -1;
   g.cy = g.cz = 0;
@@ -580,24 +589,36 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
     g.guard = 1e-9 * (v.len[0] + v.len[1] + v.len[2]);
     const double Rg = R + g.guard;
     g.R2 = Rg * Rg;
-    if constexpr (REL) {
-      // With per-coordinate errors d <= rel_delta, |rebuilt r^2 - r^2| <=
-      // E(r) = 2 sqrt(3) r d + 3 d^2 (+ FP64 rounding of r^2).  A pair with
-      // r^2 < rc^2 has r <= rc, so its rebuilt r^2 stays below rc^2 + E(rc);
-      // a pair with r^2 >= rc^2 has a rebuilt r^2 of at least rc^2 - E(rc),
-      // as r^2 - E(r) grows with r.  A margin of twice E(rc) therefore decides
-      // every pair with |rebuilt r^2 - rc^2| > margin exactly as the FP64
-      // records would.
-      const double d = v.rel_delta, r = Rg;
-      g.margin = 2.0 * (3.4641016151377548 * r * d + 3.0 * d * d + 1e-15 * r * r);
-      g.tin = g.rci2 - g.margin;
-    }
     const int cx = slab_index(g.xi, v.sc[0], nx);
     g.cy = slab_index(g.yi, v.sc[1], ny);
     g.cz = slab_index(g.zi, v.sc[2], nz);
     if constexpr (REL) {
-      g.a0y = g.yi - ((double)g.cy + 0.5) * v.len[1];
-      g.a0z = g.zi - ((double)g.cz + 0.5) * v.len[2];
+      g.a0x = (float)(g.xi - ((double)cx + 0.5) * v.len[0]);
+      g.a0y = (float)(g.yi - ((double)g.cy + 0.5) * v.len[1]);
+      g.a0z = (float)(g.zi - ((double)g.cz + 0.5) * v.len[2]);
+      g.wc = (float)cx + 0.5f;
+      double lmax = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        g.lenf[k] = (float)v.len[k];
+        lmax = v.len[k] > lmax ? v.len[k] : lmax;
+      }
+      g.rc2f = (float)g.rci2;
+      // Error of an FP32 separation component against the exact one, with
+      // u = 2^-24 and a candidate at most k cells away (|k| len <= Rg + len):
+      // a0 rounded (u len), len rounded (u |k| len), a0 - k len rounded
+      // (u (Rg + 2 len)), the final difference rounded (u (Rg + 3 len)), and
+      // the record's own error rel_delta; so del <= u (3 Rg + 7 len) + rel_delta.
+      // For a pair within rc + 1 (the only ones whose side of rc^2 is in
+      // question), |FP32 r^2 - FP64 r^2| <= E = 2 sqrt(3) (rc+1) del + 3 del^2
+      // + 3 u (rc+1)^2 (the three roundings of r^2).  Outside a band of
+      // E + u rc^2 (rc^2's own rounding) around the FP32 rc^2 the FP32 test
+      // decides as the FP64 one; the band kept is twice that.
+      const double u = 0x1p-24, rr = g.rci + 1.0;
+      const double del = u * (3.0 * Rg + 7.0 * lmax) + v.rel_delta + 1e-12;
+      const double E = 3.4641016151377548 * rr * del + 3.0 * del * del + 3.01 * u * rr * rr +
+                       1e-12 * rr * rr;
+      g.margin = (float)(2.0 * (E + u * g.rci2)) * (1.0f + 0x1p-20f);
     }
     // the halo holds ceil(rc_bound/len) + 1 cells, so these stay inside it
     g.zlo = clampi((int)floor((g.zi - Rg) * v.sc[2]), -hz, nz + hz - 1);
@@ -612,8 +633,8 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   bool redo = false;
   sweep_rows<RULE, PREC, EVM, REL>(v, active, g, sig2, segs, acc, cnt, redo);
   if constexpr (REL) {
-    // rare: lanes with a pair too close to their cutoff to decide from the
-    // compact records start over on the FP64 records
+    // rare: lanes with a row longer than a list entry can describe start
+    // over on the FP64 records
     if (__syncthreads_or(redo ? 1 : 0)) {
       if (redo) {
         acc = Acc<PREC>();
