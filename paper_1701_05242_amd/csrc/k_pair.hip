@@ -211,11 +211,13 @@ struct PairView {
 // One lane's particle and search window.
 struct LaneGeo {
   double xi, yi, zi, rci, rci2, R2, guard;
-  // compact records, all FP32: the lane's position relative to the centre of
-  // its own cell (a0), that cell's x index + 1/2 (wc), the cell edges, rc^2,
-  // and the band around it within which an FP32 r^2 cannot decide a pair
-  float a0x, a0y, a0z, wc, lenf[3], rc2f, margin;
-  int zlo, zhi, ylo, yhi, cy, cz, self;
+  // FP32 geometry: the lane's position relative to the centre of its own
+  // cell (a0), the cell edges and their inverses, the squared search radius
+  // with the row-selection guard fguard added (fR2); for compact records also
+  // the cell's x index + 1/2 (wc), rc^2 and the band around it within which
+  // an FP32 r^2 cannot decide a pair
+  float a0x, a0y, a0z, lenf[3], invf[3], fR2, fguard, wc, rc2f, margin;
+  int zlo, zhi, ylo, yhi, cx, cy, cz, self;
   int slot;  // sorted slot of the lane's particle
 };
 
@@ -371,6 +373,20 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int ns
   }
 }
 
+// Distance from the lane (a0 from the centre of its cell) to the near face of
+// the cell d cells away along one axis, less the guard; 0 for its own cell.
+__device__ __forceinline__ float face_gap(int d, float a0, float len, float guard) {
+  const float ad = (float)(d < 0 ? -d : d);
+  const float e = fmaf(ad - 0.5f, len, d < 0 ? a0 : -a0) - guard;
+  return (d == 0 || e < 0.0f) ? 0.0f : e;
+}
+
+// Offset from the lane's cell of the cell holding the point p (p relative to
+// the lane's cell centre).
+__device__ __forceinline__ int cell_off(float p, float inv) {
+  return (int)floorf(fmaf(p, inv, 0.5f));
+}
+
 // Walk this lane's rows (fill a list, scan it, repeat) for a lane with run
 // set.  REL: compact records (FP32-mixed, own-cutoff rule); else the FP64
 // records.
@@ -384,20 +400,23 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
   const int ny = v.nc[1];
   // rows are walked plane by plane (z), each plane's rows limited to the
   // y range its circle of radius sqrt(R^2 - ez^2) can reach
+  // (row selection in FP32 relative to the lane's cell: the guard outweighs
+  // every rounding, so rows and cells are only ever added, never dropped)
   int zc = g.zlo, yc = 0, ylo_c = 0, yhi_c = -1;
-  double ez2c = 0.0;
+  float remz_c = 0.0f;
+  // extended-cell index of row (y, z) at x = 0 is rowbase(z) + y nex; the
+  // extended grid has fewer than 2^30 cells, so 32-bit indices suffice
+  int rowbase_c = 0;
+  const int own_row = ((g.cz + hz) * ney + (g.cy + hy)) * nex + hx;
   auto plane = [&](int z) -> bool {
-    double ez = 0.0;
-    if (z < g.cz) ez = g.zi - (double)(z + 1) * v.len[2];
-    else if (z > g.cz) ez = (double)z * v.len[2] - g.zi;
-    ez = ez > g.guard ? ez - g.guard : 0.0;
-    const double remz = g.R2 - ez * ez;
-    if (remz < 0.0) return false;
-    // half-width, rounded up generously (it only selects rows)
-    const double w = (double)(sqrtf((float)remz) * 1.00001f) + g.guard;
-    ylo_c = clampi((int)floor((g.yi - w) * v.sc[1]), -hy, ny + hy - 1);
-    yhi_c = clampi((int)floor((g.yi + w) * v.sc[1]), -hy, ny + hy - 1);
-    ez2c = ez * ez;
+    const float ez = face_gap(z - g.cz, g.a0z, g.lenf[2], g.fguard);
+    const float remz = fmaf(-ez, ez, g.fR2);
+    if (remz < 0.0f) return false;
+    const float w = __builtin_amdgcn_sqrtf(remz) + g.fguard;
+    ylo_c = clampi(g.cy + cell_off(g.a0y - w, g.invf[1]), -hy, ny + hy - 1);
+    yhi_c = clampi(g.cy + cell_off(g.a0y + w, g.invf[1]), -hy, ny + hy - 1);
+    remz_c = remz;
+    rowbase_c = ((z + hz) * ney + hy) * nex + hx;
     return true;
   };
   bool rows_left = false;
@@ -408,6 +427,16 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
         break;
       }
   yc = ylo_c;
+  // cell starts through a buffer resource: 32-bit offsets, and an offset past
+  // the array reads 0 instead of touching memory
+  // (sizes and offsets are unsigned 32-bit: up to 2^30 cells of 4 bytes)
+  const int64_t start_bytes = ((int64_t)v.ne[0] * v.ne[1] * v.ne[2] + 1) * 4;
+  const __amdgpu_buffer_rsrc_t rs_start = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)v.ext_start, (short)0,
+      (int)(start_bytes > 0xffffffffll ? 0xffffffffu : (uint32_t)start_bytes), kBufferWord3);
+  auto load_start = [&](int idx) -> int {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(rs_start, (int)((uint32_t)idx << 2), 0, 0);
+  };
   __amdgpu_buffer_rsrc_t rs;
   if constexpr (REL)
     rs = __builtin_amdgcn_make_buffer_rsrc((void *)v.ext_rel, (short)0,
@@ -424,8 +453,8 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
       bool ok[kFillRows];
 #pragma unroll
       for (int k = 0; k < kFillRows; ++k) {
-        const int zcur = zc, ycur = yc;
-        const double ez2 = ez2c;
+        const int zcur = zc, ycur = yc, rowbase = rowbase_c;
+        const float remz = remz_c;
         bool in = rows_left;
         if (rows_left && ++yc > yhi_c) {
           bool more = false;
@@ -437,21 +466,17 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
           if (more) yc = ylo_c;
           else rows_left = false;
         }
-        double ey = 0.0;
-        if (ycur < g.cy) ey = g.yi - (double)(ycur + 1) * v.len[1];
-        else if (ycur > g.cy) ey = (double)ycur * v.len[1] - g.yi;
-        ey = ey > g.guard ? ey - g.guard : 0.0;
-        const double rem = g.R2 - ez2 - ey * ey;
-        in = in && rem >= 0.0;
-        // chord half-width, rounded up generously (it only selects cells)
-        const double w = in ? (double)(sqrtf((float)rem) * 1.00001f) + g.guard : 0.0;
-        const int xlo = clampi((int)floor((g.xi - w) * v.sc[0]), -hx, nx + hx - 1);
-        const int xhi = clampi((int)floor((g.xi + w) * v.sc[0]), -hx, nx + hx - 1);
+        const float ey = face_gap(ycur - g.cy, g.a0y, g.lenf[1], g.fguard);
+        const float rem = fmaf(-ey, ey, remz);
+        in = in && rem >= 0.0f;
+        // chord half-width, widened by the guard (it only selects cells)
+        const float w = in ? __builtin_amdgcn_sqrtf(rem) + g.fguard : 0.0f;
+        const int xlo = clampi(g.cx + cell_off(g.a0x - w, g.invf[0]), -hx, nx + hx - 1);
+        const int xhi = clampi(g.cx + cell_off(g.a0x + w, g.invf[0]), -hx, nx + hx - 1);
         // a row that is not taken still reads (its own cell row's) starts
-        const int zs = in ? zcur : g.cz, ys = in ? ycur : g.cy;
-        const int32_t *es = v.ext_start + ((int64_t)(zs + hz) * ney + (ys + hy)) * nex + hx;
-        j0[k] = es[xlo];
-        j1[k] = es[xhi + 1];
+        const int row = in ? rowbase + ycur * nex : own_row;
+        j0[k] = load_start(row + xlo);
+        j1[k] = load_start(row + xhi + 1);
         rz[k] = zcur;
         ry[k] = ycur;
         ok[k] = in;
@@ -564,8 +589,10 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   const int nex = v.ne[0], ney = v.ne[1];
   LaneGeo g;
   g.xi = g.yi = g.zi = g.rci = g.rci2 = g.R2 = g.guard = 0.0;
-  g.a0x = g.a0y = g.a0z = g.wc = g.rc2f = g.margin = 0.0f;
+  g.a0x = g.a0y = g.a0z = g.wc = g.rc2f = g.margin = g.fR2 = g.fguard = 0.0f;
   g.lenf[0] = g.lenf[1] = g.lenf[2] = 0.0f;
+  g.invf[0] = g.invf[1] = g.invf[2] = 0.0f;
+  g.cx = 0;
   g.zlo = g.ylo = 0;
   g.zhi = g.yhi = -1;
   g.cy = g.cz = 0;
@@ -590,19 +617,29 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
     const double Rg = R + g.guard;
     g.R2 = Rg * Rg;
     const int cx = slab_index(g.xi, v.sc[0], nx);
+    g.cx = cx;
     g.cy = slab_index(g.yi, v.sc[1], ny);
     g.cz = slab_index(g.zi, v.sc[2], nz);
-    if constexpr (REL) {
-      g.a0x = (float)(g.xi - ((double)cx + 0.5) * v.len[0]);
-      g.a0y = (float)(g.yi - ((double)g.cy + 0.5) * v.len[1]);
-      g.a0z = (float)(g.zi - ((double)g.cz + 0.5) * v.len[2]);
-      g.wc = (float)cx + 0.5f;
-      double lmax = 0.0;
+    g.a0x = (float)(g.xi - ((double)cx + 0.5) * v.len[0]);
+    g.a0y = (float)(g.yi - ((double)g.cy + 0.5) * v.len[1]);
+    g.a0z = (float)(g.zi - ((double)g.cz + 0.5) * v.len[2]);
+    double lmax = 0.0;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        g.lenf[k] = (float)v.len[k];
-        lmax = v.len[k] > lmax ? v.len[k] : lmax;
-      }
+    for (int k = 0; k < 3; ++k) {
+      g.lenf[k] = (float)v.len[k];
+      g.invf[k] = (float)v.sc[k];
+      lmax = v.len[k] > lmax ? v.len[k] : lmax;
+    }
+    // FP32 row selection: every quantity it forms is below ~Rg + 2 len, so its
+    // roundings (and the hardware square root's ulp) stay below ~1e-6 (Rg + len);
+    // the guard, 4e-6 (Rg + len), widens
+    // every face distance and chord beyond them, and raises R^2 by
+    // 2 Rg fguard, far above the ~4 u R^2 rounding of R^2 - ez^2 - ey^2
+    g.fguard = (float)(4e-6 * (Rg + lmax));
+    const double Rf = Rg + (double)g.fguard;
+    g.fR2 = (float)(Rf * Rf) * (1.0f + 0x1p-20f);
+    if constexpr (REL) {
+      g.wc = (float)cx + 0.5f;
       g.rc2f = (float)g.rci2;
       // Error of an FP32 separation component against the exact one, with
       // u = 2^-24 and a candidate at most k cells away (|k| len <= Rg + len):
