@@ -141,6 +141,34 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Column sums of `rows` rows of S doubles (row r at p + r S) by one
+// workgroup of NT threads, in a fixed order: thread t adds rows t, t + NT, ...
+// in turn, each wavefront sums its lanes with shuffles, and thread 0 adds
+// the wavefronts in order.  Every thread must call it; thread 0 gets out[].
+template <int NT, int S>
+__device__ __forceinline__ void sum_rows(const double *__restrict__ p, int64_t rows,
+                                         double (*red)[S], double *out) {
+  double v[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) v[k] = 0.0;
+  for (int64_t r = threadIdx.x; r < rows; r += NT)
+#pragma unroll
+    for (int k = 0; k < S; ++k) v[k] += p[r * S + k];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const double t = wave_sum(v[k]);
+    if (lane == 0) red[wid][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < S; ++k) {
+      double t = red[0][k];
+      for (int w = 1; w < NT / 64; ++w) t += red[w][k];
+      out[k] = t;
+    }
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -30,6 +30,7 @@ enum : uint32_t {
 constexpr int kHistBins = 4096;       // gray values (27-window counts) must stay below this
 constexpr int kMajorityMaxPasses = 16;
 constexpr int kPartialSlots = 8;      // per-block partial sums: E, W[6], pair count
+constexpr int kReduceThreads = 1024;  // workgroup that sums the block partials
 constexpr int kReorderEvery = 8;      // dcm_step re-sorts its working copies this often
 // the pair kernel addresses the ghost-extended array with 32-bit byte offsets
 constexpr int64_t kMaxExtSlots = (int64_t(1) << 27) - 1;
@@ -386,6 +387,9 @@ void launch_permute_scatter(hipStream_t s, const PermFields &f, const int32_t *o
 // k_verlet.hip
 void launch_kick(hipStream_t s, double *vx, double *vy, double *vz, const double *fx,
                  const double *fy, const double *fz, int64_t n, double c);
+void launch_kick_kick_drift(hipStream_t s, double *x, double *y, double *z, double *vx,
+                            double *vy, double *vz, const double *fx, const double *fy,
+                            const double *fz, int64_t n, double c, double dt, const double L[3]);
 void launch_kick_drift(hipStream_t s, double *x, double *y, double *z, double *vx, double *vy,
                        double *vz, const double *fx, const double *fy, const double *fz,
                        int64_t n, double c, double dt, const double L[3]);

@@ -248,29 +248,16 @@ __global__ __launch_bounds__(kBatchBlock) void kb_ext_fill(
 
 // One workgroup per system sums the system's work-item partials in a fixed
 // order (the same order as the single-system reduction over its blocks).
-__global__ __launch_bounds__(256) void kb_reduce(const SysGeom *__restrict__ sys,
-                                                 const double *__restrict__ partials,
-                                                 int ev_flags) {
+// (the same summation as the single-system reduction, so a system's sums
+// are bit for bit those of dcm_forces on the same cells)
+__global__ __launch_bounds__(kReduceThreads) void kb_reduce(const SysGeom *__restrict__ sys,
+                                                            const double *__restrict__ partials,
+                                                            int ev_flags) {
   const SysGeom &g = sys[blockIdx.x];
-  __shared__ double red[4][kPartialSlots];
-  double v[kPartialSlots];
-#pragma unroll
-  for (int k = 0; k < kPartialSlots; ++k) v[k] = 0.0;
-  const double *p = partials + g.item0 * kPartialSlots;
-  for (int64_t t = threadIdx.x; t < g.nitems; t += 256)
-#pragma unroll
-    for (int k = 0; k < kPartialSlots; ++k) v[k] += p[t * kPartialSlots + k];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < kPartialSlots; ++k) {
-    double t = wave_sum(v[k]);
-    if (lane == 0) red[wid][k] = t;
-  }
-  __syncthreads();
+  __shared__ double red[kReduceThreads / 64][kPartialSlots];
+  double t[kPartialSlots];
+  sum_rows<kReduceThreads, kPartialSlots>(partials + g.item0 * kPartialSlots, g.nitems, red, t);
   if (threadIdx.x == 0) {
-    double t[kPartialSlots];
-    for (int k = 0; k < kPartialSlots; ++k)
-      t[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
     if (g.energy && (ev_flags & DCM_EV_ENERGY)) *g.energy = t[0];
     if (g.virial && (ev_flags & DCM_EV_VIRIAL))
       for (int k = 0; k < 6; ++k) g.virial[k] = t[1 + k];
@@ -325,7 +312,8 @@ void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64
 void launch_batch_reduce(hipStream_t s, const SysGeom *sys, int32_t nsys,
                          const double *partials, int ev_flags) {
   if (nsys <= 0) return;
-  hipLaunchKernelGGL(kb_reduce, dim3((unsigned)nsys), dim3(256), 0, s, sys, partials, ev_flags);
+  hipLaunchKernelGGL(kb_reduce, dim3((unsigned)nsys), dim3(kReduceThreads), 0, s, sys, partials,
+                     ev_flags);
 }
 
 }  // namespace dcm

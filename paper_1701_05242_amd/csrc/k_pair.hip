@@ -974,28 +974,13 @@ void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int pr
 
 // Sum the block partials in a fixed order (one workgroup), so the energy,
 // virial and pair count do not depend on scheduling.
-__global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ partials,
-                                                         int64_t blocks, int ev_flags,
-                                                         double *energy, double *virial,
-                                                         uint64_t *npairs) {
-  __shared__ double red[4][kPartialSlots];
-  double v[kPartialSlots];
-#pragma unroll
-  for (int k = 0; k < kPartialSlots; ++k) v[k] = 0.0;
-  for (int64_t b = threadIdx.x; b < blocks; b += 256)
-#pragma unroll
-    for (int k = 0; k < kPartialSlots; ++k) v[k] += partials[b * kPartialSlots + k];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < kPartialSlots; ++k) {
-    double t = wave_sum(v[k]);
-    if (lane == 0) red[wid][k] = t;
-  }
-  __syncthreads();
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(
+    const double *__restrict__ partials, int64_t blocks, int ev_flags, double *energy,
+    double *virial, uint64_t *npairs) {
+  __shared__ double red[kReduceThreads / 64][kPartialSlots];
+  double t[kPartialSlots];
+  sum_rows<kReduceThreads, kPartialSlots>(partials, blocks, red, t);
   if (threadIdx.x == 0) {
-    double t[kPartialSlots];
-    for (int k = 0; k < kPartialSlots; ++k)
-      t[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
     if (energy && (ev_flags & DCM_EV_ENERGY)) *energy = t[0];
     if (virial && (ev_flags & DCM_EV_VIRIAL))
       for (int k = 0; k < 6; ++k) virial[k] = t[1 + k];
@@ -1006,8 +991,8 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
 void launch_reduce_partials(hipStream_t s, const double *partials, int64_t blocks, double eps,
                             int ev_flags, double *energy, double *virial, uint64_t *npairs) {
   (void)eps;
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, blocks, ev_flags,
-                     energy, virial, npairs);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kReduceThreads), 0, s, partials, blocks,
+                     ev_flags, energy, virial, npairs);
 }
 
 }  // namespace dcm

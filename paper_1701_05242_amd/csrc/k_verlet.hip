@@ -38,6 +38,29 @@ __global__ __launch_bounds__(256) void k_kick_drift(
   }
 }
 
+// The closing kick of one step and the opening kick and drift of the next
+// in one pass over the particles: the same operations in the same order as
+// k_kick followed by k_kick_drift, without the round trip of v through HBM.
+__global__ __launch_bounds__(256) void k_kick_kick_drift(
+    double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
+    double *__restrict__ vx, double *__restrict__ vy, double *__restrict__ vz,
+    const double *__restrict__ fx, const double *__restrict__ fy, const double *__restrict__ fz,
+    int64_t n, double c, double dt, double Lx, double Ly, double Lz) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double gx = c * fx[i], gy = c * fy[i], gz = c * fz[i];
+    const double a = (vx[i] + gx) + gx;
+    const double b = (vy[i] + gy) + gy;
+    const double d = (vz[i] + gz) + gz;
+    vx[i] = a;
+    vy[i] = b;
+    vz[i] = d;
+    x[i] = wrap_coord(x[i] + dt * a, Lx);
+    y[i] = wrap_coord(y[i] + dt * b, Ly);
+    z[i] = wrap_coord(z[i] + dt * d, Lz);
+  }
+}
+
 static unsigned grid_for(int64_t n) {
   int64_t b = ceil_div(n, 256);
   if (b < 1) b = 1;
@@ -57,6 +80,14 @@ void launch_kick_drift(hipStream_t s, double *x, double *y, double *z, double *v
   if (n <= 0) return;
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(n)), dim3(256), 0, s, x, y, z, vx, vy, vz, fx,
                      fy, fz, n, c, dt, L[0], L[1], L[2]);
+}
+
+void launch_kick_kick_drift(hipStream_t s, double *x, double *y, double *z, double *vx,
+                            double *vy, double *vz, const double *fx, const double *fy,
+                            const double *fz, int64_t n, double c, double dt, const double L[3]) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_kick_kick_drift, dim3(grid_for(n)), dim3(256), 0, s, x, y, z, vx, vy, vz,
+                     fx, fy, fz, n, c, dt, L[0], L[1], L[2]);
 }
 
 // Kinetic energy sum_i m v_i^2 / 2: fixed-size grid of block partials, then
