@@ -210,14 +210,14 @@ struct PairView {
 
 // One lane's particle and search window.
 struct LaneGeo {
-  double xi, yi, zi, rci, rci2, R2, guard;
+  double xi, yi, zi, rci, rci2;
   // FP32 geometry: the lane's position relative to the centre of its own
   // cell (a0), the cell edges and their inverses, the squared search radius
   // with the row-selection guard fguard added (fR2); for compact records also
   // the cell's x index + 1/2 (wc), rc^2 and the band around it within which
   // an FP32 r^2 cannot decide a pair
   float a0x, a0y, a0z, lenf[3], invf[3], fR2, fguard, wc, rc2f, margin;
-  int zlo, zhi, ylo, yhi, cx, cy, cz, self;
+  int zlo, zhi, cx, cy, cz, self;
   int slot;  // sorted slot of the lane's particle
 };
 
@@ -588,13 +588,13 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   const int hx = v.h[0], hy = v.h[1], hz = v.h[2];
   const int nex = v.ne[0], ney = v.ne[1];
   LaneGeo g;
-  g.xi = g.yi = g.zi = g.rci = g.rci2 = g.R2 = g.guard = 0.0;
+  g.xi = g.yi = g.zi = g.rci = g.rci2 = 0.0;
   g.a0x = g.a0y = g.a0z = g.wc = g.rc2f = g.margin = g.fR2 = g.fguard = 0.0f;
   g.lenf[0] = g.lenf[1] = g.lenf[2] = 0.0f;
   g.invf[0] = g.invf[1] = g.invf[2] = 0.0f;
   g.cx = 0;
-  g.zlo = g.ylo = 0;
-  g.zhi = g.yhi = -1;
+  g.zlo = 0;
+  g.zhi = -1;
   g.cy = g.cz = 0;
   g.self = -1;
   g.slot = (int)s;
@@ -613,9 +613,7 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
     g.rci2 = g.rci * g.rci;
     // search radius widened by a hair: rounding in the cell geometry can
     // only add candidates, never drop one
-    g.guard = 1e-9 * (v.len[0] + v.len[1] + v.len[2]);
-    const double Rg = R + g.guard;
-    g.R2 = Rg * Rg;
+    const double Rg = R + 1e-9 * (v.len[0] + v.len[1] + v.len[2]);
     const int cx = slab_index(g.xi, v.sc[0], nx);
     g.cx = cx;
     g.cy = slab_index(g.yi, v.sc[1], ny);
@@ -660,8 +658,6 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
     // the halo holds ceil(rc_bound/len) + 1 cells, so these stay inside it
     g.zlo = clampi((int)floor((g.zi - Rg) * v.sc[2]), -hz, nz + hz - 1);
     g.zhi = clampi((int)floor((g.zi + Rg) * v.sc[2]), -hz, nz + hz - 1);
-    g.ylo = clampi((int)floor((g.yi - Rg) * v.sc[1]), -hy, ny + hy - 1);
-    g.yhi = clampi((int)floor((g.yi + Rg) * v.sc[1]), -hy, ny + hy - 1);
     // this particle's own copy in the extended array
     const int real_cell = (g.cz * ny + g.cy) * nx + cx;
     const int ext_cell = ((g.cz + hz) * ney + (g.cy + hy)) * nex + (cx + hx);
