@@ -164,18 +164,7 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
 dcm_status dcm_destroy(dcm_ctx *ctx) {
   if (!ctx) return DCM_ERR_INVALID;
   hipStreamSynchronize(ctx->stream);
-  DevBuf *bufs[] = {&ctx->ccl_label, &ctx->ccl_size, &ctx->fsm_flags, &ctx->fsm_chg,  &ctx->counts,   &ctx->gray,      &ctx->hist,      &ctx->seg_a,
-                    &ctx->seg_b,    &ctx->seg,       &ctx->iface,     &ctx->dA,
-                    &ctx->dB,       &ctx->dist,      &ctx->delta,     &ctx->rc,
-                    &ctx->partials, &ctx->ke,        &ctx->cell_of,   &ctx->cell_count,
-                    &ctx->cell_start, &ctx->cell_fill, &ctx->perm,    &ctx->sorted,
-                    &ctx->scan_tmp, &ctx->scalars, &ctx->ext_row_count, &ctx->ext_row_start,
-                    &ctx->ext_row_lo, &ctx->ext_start, &ctx->rcmax_part, &ctx->list_count,
-                    &ctx->list_wave_len, &ctx->list_wave_start, &ctx->list,
-                    &ctx->ext_pos, &ctx->ws[0], &ctx->ws[1], &ctx->ws_owner[0],
-                    &ctx->ws_owner[1], &ctx->ext_rel};
-  for (DevBuf *b : bufs)
-    if (b->p) hipFree(b->p);
+  // the context's device buffers go with it
   batch_free(ctx);
   for (auto &kv : ctx->timers)
     for (auto &pr : kv.second.pending) {
@@ -397,6 +386,8 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   if (n >= (int64_t(1) << 24))
     return fail(ctx, DCM_ERR_RANGE, "the pair kernel supports fewer than 2^24 particles");
   DCM_TRY(ensure(ctx, ctx->perm, n * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->sort_tmp, std::max<int64_t>(n, 1) * sizeof(int32_t)));
+  DCM_TRY(ensure(ctx, ctx->sort_list, cell_sort_list_elems(n) * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->sorted, n * sizeof(double4)));
   int32_t *cof = cell_of;
   if (!cof) {
@@ -454,7 +445,8 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   launch_fill_i32(s, ptr<int32_t>(ctx->cell_fill), 0, ncell);
   launch_cell_scatter(s, cof, n, ptr<int32_t>(ctx->cell_start), ptr<int32_t>(ctx->cell_fill),
                       ptr<int32_t>(ctx->perm));
-  launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, ptr<int32_t>(ctx->perm));
+  launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, ptr<int32_t>(ctx->perm),
+                   ptr<int32_t>(ctx->sort_tmp), ptr<int32_t>(ctx->sort_list), &ctx->ctl->big_cells);
   launch_gather(s, x, y, z, rc, ptr<int32_t>(ctx->perm), n, box.L, rc_cap,
                 ptr<double4>(ctx->sorted));
   launch_ext_build(s, ptr<int32_t>(ctx->cell_start), ptr<double4>(ctx->sorted), nc, halo, box.L,
@@ -529,8 +521,12 @@ dcm_status forces_impl(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_
   a.cell_start = ptr<int32_t>(ctx->cell_start);
   a.perm = ptr<int32_t>(ctx->perm);
   a.ext_pos = ptr<double4>(ctx->ext_pos);
-  // FP32-mixed own-cutoff forces on an FP32-mixed build read the compact records
-  const bool rel = ctx->cell_rel && prec == DCM_FP32_MIXED && pair_rule == DCM_PAIR_OWN;
+  // FP32-mixed own-cutoff forces on an FP32-mixed build read the compact
+  // records, if the cells are narrow enough for their precision
+  const double max_len =
+      std::max(ctx->cell_len[0], std::max(ctx->cell_len[1], ctx->cell_len[2]));
+  const bool rel = ctx->cell_rel && prec == DCM_FP32_MIXED && pair_rule == DCM_PAIR_OWN &&
+                   max_len <= kRelMaxEdgeSigma * lj.sigma;
   a.ext_rel = rel ? ptr<float4>(ctx->ext_rel) : nullptr;
   double span = 0.0;  // largest coordinate magnitude in the extended grid
   for (int k = 0; k < 3; ++k)

@@ -41,11 +41,13 @@ struct BatchState {
   std::vector<int32_t> queue;
   int64_t n_total = 0, cells_total = 0, ext_cells_total = 0, ext_rows_total = 0, ext_cap = 0;
   bool rel_ok = true;  // every system's halos fit the compact records
+  double max_len = 0.0;  // widest cell edge of any system
   size_t off_geo = 0, off_items = 0, off_eblk = 0, off_rblk = 0, off_queue = 0, table_bytes = 0;
   std::vector<unsigned char> table_host;
   // device memory
   DevBuf tables, cell_of, cell_count, cell_fill, cell_start, perm, sorted, scan_tmp, row_count,
-      row_start, row_lo, ext_start, ext_pos, ext_rel, partials, rcmax, rcmax_part, head;
+      row_start, row_lo, ext_start, ext_pos, ext_rel, partials, rcmax, rcmax_part, head,
+      sort_tmp, sort_list;
   // recorded graph
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -97,6 +99,7 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   int64_t p0 = 0, cell0 = 0, ext_cell0 = 0, row0 = 0;
   double ext_bound = 0.0;
   B.rel_ok = true;
+  B.max_len = 0.0;
   for (int32_t b = 0; b < nsys; ++b) {
     const dcm_system &d = B.desc[b];
     SysGeom &g = B.geo[b];
@@ -140,6 +143,7 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
     for (int a = 0; a < 3; ++a) span = std::max(span, g.L[a] + 2.0 * g.h[a] * g.len[a]);
     g.rel_delta = rel_record_delta(g.len, span);
     if (g.h[1] > kRelMaxHalo || g.h[2] > kRelMaxHalo) B.rel_ok = false;
+    for (int a = 0; a < 3; ++a) B.max_len = std::max(B.max_len, g.len[a]);
     g.p0 = p0;
     g.cell0 = cell0;
     g.ext_cell0 = ext_cell0;
@@ -210,6 +214,10 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   if ((st = ensure(ctx, B.cell_count, sizeof(int32_t) * B.cells_total)) != DCM_OK) return st;
   if ((st = ensure(ctx, B.cell_fill, sizeof(int32_t) * B.cells_total)) != DCM_OK) return st;
   if ((st = ensure(ctx, B.cell_start, sizeof(int32_t) * (B.cells_total + 1))) != DCM_OK) return st;
+  if ((st = ensure(ctx, B.sort_tmp, sizeof(int32_t) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
+    return st;
+  if ((st = ensure(ctx, B.sort_list, sizeof(int32_t) * cell_sort_list_elems(B.n_total))) != DCM_OK)
+    return st;
   if ((st = ensure(ctx, B.perm, sizeof(int32_t) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
     return st;
   if ((st = ensure(ctx, B.sorted, sizeof(double4) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
@@ -232,7 +240,8 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   if ((st = ensure(ctx, B.rcmax_part, sizeof(unsigned long long) * std::max<int64_t>(nitems, 1))) !=
       DCM_OK)
     return st;
-  if ((st = ensure(ctx, B.head, sizeof(uint32_t))) != DCM_OK) return st;
+  // work-queue head and the cell sort's count of large cells
+  if ((st = ensure(ctx, B.head, 2 * sizeof(uint32_t))) != DCM_OK) return st;
   // plans change rarely: a synchronous upload keeps the host copy free to
   // change as soon as this returns
   if (hipMemcpyAsync(B.tables.p, B.table_host.data(), B.table_bytes, hipMemcpyHostToDevice,
@@ -254,14 +263,15 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   const int32_t *queue = dptr<int32_t>(B.tables, B.off_queue);
   const int64_t nitems = (int64_t)B.items.size();
   // FP32-mixed own-cutoff forces read the compact records
-  float4 *rel = (B.rel_ok && prec == DCM_FP32_MIXED && rule == DCM_PAIR_OWN)
+  float4 *rel = (B.rel_ok && prec == DCM_FP32_MIXED && rule == DCM_PAIR_OWN &&
+                 B.max_len <= kRelMaxEdgeSigma * lj.sigma)
                     ? dptr<float4>(B.ext_rel)
                     : nullptr;
   hipEvent_t ev = nullptr;
   if (timed) timer_begin(ctx, "batch_cells", &ev);
   launch_fill_i32(s, dptr<int32_t>(B.cell_count), 0, B.cells_total);
   launch_fill_i32(s, dptr<int32_t>(B.cell_fill), 0, B.cells_total);
-  launch_fill_u32(s, dptr<uint32_t>(B.head), 0u, 1);
+  launch_fill_u32(s, dptr<uint32_t>(B.head), 0u, 2);
   launch_batch_cell_count(s, geo, nsys, items, nitems, dptr<int32_t>(B.cell_of),
                           dptr<int32_t>(B.cell_count), dptr<unsigned long long>(B.rcmax_part),
                           dptr<unsigned long long>(B.rcmax), ctx->d_status);
@@ -270,7 +280,9 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   launch_batch_cell_scatter(s, geo, items, nitems, dptr<int32_t>(B.cell_of),
                             dptr<int32_t>(B.cell_start), dptr<int32_t>(B.cell_fill),
                             dptr<int32_t>(B.perm));
-  launch_cell_sort(s, dptr<int32_t>(B.cell_start), B.cells_total, dptr<int32_t>(B.perm));
+  launch_cell_sort(s, dptr<int32_t>(B.cell_start), B.cells_total, dptr<int32_t>(B.perm),
+                   dptr<int32_t>(B.sort_tmp), dptr<int32_t>(B.sort_list),
+                   dptr<uint32_t>(B.head) + 1);
   launch_batch_gather(s, geo, items, nitems, dptr<int32_t>(B.perm), dptr<double4>(B.sorted));
   launch_batch_ext(s, geo, eblk, (int64_t)B.eblk.size(), dptr<int2>(B.tables, B.off_rblk),
                    (int64_t)B.rblk.size(), dptr<int32_t>(B.cell_start), dptr<double4>(B.sorted),
@@ -361,11 +373,6 @@ void batch_free(dcm_ctx *ctx) {
   BatchState *B = ctx->batch;
   if (!B) return;
   B->drop_graph();
-  DevBuf *bufs[] = {&B->tables,    &B->cell_of,   &B->cell_count, &B->cell_fill, &B->cell_start,
-                    &B->perm,      &B->sorted,    &B->scan_tmp,   &B->row_count, &B->row_start, &B->row_lo, &B->ext_start,
-                    &B->ext_pos,   &B->ext_rel,   &B->partials,  &B->rcmax,    &B->rcmax_part,      &B->head};
-  for (DevBuf *b : bufs)
-    if (b->p) hipFree(b->p);
   if (B->cap) hipStreamDestroy(B->cap);
   delete B;
   ctx->batch = nullptr;

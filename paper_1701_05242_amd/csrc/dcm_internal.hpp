@@ -50,6 +50,11 @@ inline double rel_record_delta(const double len[3], double span) {
 // the compact-record path packs a row's cell offset from the lane's cell in
 // 8 bits, so it needs halos of at most this many cells
 constexpr int kRelMaxHalo = 127;
+// Compact records only for cells at most this many LJ sigma wide: their FP32
+// positions relative to cell centres err by up to ~2^-24 times the edge, and
+// the force of a close pair amplifies a separation error ~14-fold, so wider
+// cells would push FP32-mixed forces past 1e-5; those read the FP64 records.
+constexpr double kRelMaxEdgeSigma = 2.0;
 
 // Device-resident control block: scalars produced and consumed on the device
 // so that no stage needs a host round trip.
@@ -66,13 +71,22 @@ struct Ctl {
   // maj_chg2[p] (differs from state p-2)
   uint32_t maj_chg1[kMajorityMaxPasses + 2];
   uint32_t maj_chg2[kMajorityMaxPasses + 2];
-  // cells: largest cutoff seen (bit pattern of a non-negative double)
+  // cells: largest cutoff seen (bit pattern of a non-negative double), and
+  // the number of cells too large for a one-thread sort (zeroed with it)
   unsigned long long rc_max_bits;
+  uint32_t big_cells;
 };
 
+// Device allocation owned by its holder (freed when the holder goes).
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() {
+    if (p) hipFree(p);
+  }
 };
 
 struct Timer {
@@ -129,6 +143,7 @@ struct dcm_ctx {
   dcm::DevBuf delta, rc, partials, ke, scalars;
   // cells
   dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp, rcmax_part;
+  dcm::DevBuf sort_tmp, sort_list;  // large-cell sort: scratch entries and the cells' list
   dcm::DevBuf ext_row_count, ext_row_start, ext_row_lo, ext_start, ext_pos;
   dcm::DevBuf ext_rel;  // FP32-mixed builds: compact cell-relative copy of ext_pos
   dcm::DevBuf ext_src;  // sorted slot of each extended slot's particle (on demand)
@@ -233,7 +248,11 @@ void launch_exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64
 int64_t scan_tmp_elems(int64_t n);
 void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
                          const int32_t *cell_start, int32_t *cell_fill, int32_t *perm);
-void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell, int32_t *perm);
+// sort each cell's entries of perm by value; tmp holds n entries, big_list
+// cell_sort_list_elems(n), big_count must be 0 on entry
+void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell, int32_t *perm,
+                      int32_t *tmp, int32_t *big_list, uint32_t *big_count);
+int64_t cell_sort_list_elems(int64_t n);
 void launch_gather(hipStream_t s, const double *x, const double *y, const double *z,
                    const double *rc, const int32_t *perm, int64_t n, const double L[3],
                    double rc_cap, double4 *sorted);

@@ -132,6 +132,7 @@ __global__ __launch_bounds__(1024) void k_reduce_rcmax(const unsigned long long 
     for (int w = 1; w < 16; ++w) m = wmax[w] > m ? wmax[w] : m;
     m = wmax[0] > m ? wmax[0] : m;
     ctl->rc_max_bits = m;
+    ctl->big_cells = 0u;  // for the cell sort that follows
   }
 }
 
@@ -315,11 +316,23 @@ void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
 
 // Atomic slots give an arbitrary order inside a cell; sort each cell's
 // entries by caller index so the layout (and every FP sum) is reproducible.
+// A thread sorts a cell of at most kSmallCell entries by insertion; larger
+// cells go to a list that whole workgroups sort (k_cell_sort_big).
+constexpr int kSmallCell = 32;
+constexpr int kSortChunk = 4096;  // entries a workgroup sorts at once in LDS
+constexpr int kBigSortBlocks = 256;
+
 __global__ __launch_bounds__(256) void k_cell_sort(const int32_t *__restrict__ cell_start,
-                                                   int64_t ncell, int32_t *perm) {
+                                                   int64_t ncell, int32_t *perm,
+                                                   int32_t *__restrict__ big_list,
+                                                   uint32_t *big_count) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
     int a = cell_start[c], b = cell_start[c + 1];
+    if (b - a > kSmallCell) {
+      big_list[atomicAdd(big_count, 1u)] = (int32_t)c;
+      continue;
+    }
     for (int p = a + 1; p < b; ++p) {
       int key = perm[p];
       int q = p - 1;
@@ -332,12 +345,84 @@ __global__ __launch_bounds__(256) void k_cell_sort(const int32_t *__restrict__ c
   }
 }
 
-void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell, int32_t *perm) {
+// One workgroup per listed cell: chunks of kSortChunk entries are sorted in
+// LDS (bitonic), then runs are merged pairwise, each entry moving to its own
+// offset in its run plus the count of smaller keys in the partner run (keys
+// are distinct caller indices), ping-ponging between perm and tmp.
+__global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t *__restrict__ cell_start,
+                                                       int32_t *perm, int32_t *tmp,
+                                                       const int32_t *__restrict__ big_list,
+                                                       const uint32_t *big_count) {
+  __shared__ int32_t buf[kSortChunk];
+  const int tid = threadIdx.x;
+  const uint32_t nbig = *big_count;
+  for (uint32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
+    const int64_t c = big_list[q];
+    const int a = cell_start[c], n = cell_start[c + 1] - a;
+    for (int c0 = 0; c0 < n; c0 += kSortChunk) {
+      const int len = n - c0 < kSortChunk ? n - c0 : kSortChunk;
+      int P = 1;
+      while (P < len) P <<= 1;
+      for (int i = tid; i < P; i += 256) buf[i] = i < len ? perm[a + c0 + i] : 0x7fffffff;
+      __syncthreads();
+      for (int k = 2; k <= P; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int i = tid; i < P; i += 256) {
+            const int l = i ^ j;
+            if (l > i) {
+              const int u = buf[i], w = buf[l];
+              if ((u > w) == ((i & k) == 0)) {
+                buf[i] = w;
+                buf[l] = u;
+              }
+            }
+          }
+          __syncthreads();
+        }
+      for (int i = tid; i < len; i += 256) perm[a + c0 + i] = buf[i];
+      __syncthreads();
+    }
+    int32_t *src = perm + a, *dst = tmp + a;
+    for (int L = kSortChunk; L < n; L <<= 1) {
+      for (int p = tid; p < n; p += 256) {
+        const int r = p / L, off = p - r * L;
+        const int x = src[p];
+        const int o = (r ^ 1) * L;  // partner run
+        int lo = 0, hi = 0;
+        if (o < n) {
+          hi = n - o < L ? n - o : L;
+          while (lo < hi) {  // count of partner keys below x
+            const int m = (lo + hi) >> 1;
+            if (src[o + m] < x) lo = m + 1;
+            else hi = m;
+          }
+        }
+        dst[(r & ~1) * L + off + lo] = x;
+      }
+      __syncthreads();
+      int32_t *t = src;
+      src = dst;
+      dst = t;
+    }
+    if (src != perm + a) {
+      for (int p = tid; p < n; p += 256) perm[a + p] = src[p];
+      __syncthreads();
+    }
+  }
+}
+
+void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell, int32_t *perm,
+                      int32_t *tmp, int32_t *big_list, uint32_t *big_count) {
   int64_t b = ceil_div(ncell, 256);
   if (b < 1) b = 1;
   if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)b), dim3(256), 0, s, cell_start, ncell, perm);
+  hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)b), dim3(256), 0, s, cell_start, ncell, perm,
+                     big_list, big_count);
+  hipLaunchKernelGGL(k_cell_sort_big, dim3(kBigSortBlocks), dim3(256), 0, s, cell_start, perm,
+                     tmp, big_list, big_count);
 }
+
+int64_t cell_sort_list_elems(int64_t n) { return n / (kSmallCell + 1) + 1; }
 
 // Sorted copy (x, y, z, rc) with positions wrapped into the box.
 __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ x,

@@ -286,6 +286,52 @@ def test_fp32_mixed_pairs_at_the_cutoff():
         assert emax <= 1e-5 and erms <= 1e-5
 
 
+def dense_rod_system(seed):
+    """A 120 x 80 x 40 sigma rod of the workloads' liquid (FCC at density 0.8,
+    each site jittered by U(-0.05, 0.05)) filling two rows of 40-sigma cells of
+    a 120^3 box, cutoff 8."""
+    rng = np.random.default_rng(seed)
+    ext = np.array([120.0, 80.0, 40.0])
+    n = np.rint(ext / (4.0 / 0.8) ** (1.0 / 3.0)).astype(int)
+    a = ext / n
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]]) + 0.25
+    c = np.stack(np.meshgrid(*(np.arange(k) for k in n), indexing="ij"), -1).reshape(-1, 1, 3)
+    P = ((c + basis[None]) * a).reshape(-1, 3)
+    P += rng.uniform(-0.05, 0.05, P.shape)
+    z0 = np.zeros(len(P))
+    s = workloads.System("rod", P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy(), z0, z0, z0,
+                         (120.0, 120.0, 120.0))
+    return s, np.full(s.n, 8.0)
+
+
+def test_forty_sigma_cells_and_rows_of_100k_candidates():
+    """Cells 40 sigma wide: a lane near both a y and an x cell boundary scans
+    the other cell row of the rod across two x cells, ~100 K candidates in one
+    row.  Compact FP32 records would be too coarse at this cell size, so
+    FP32-mixed forces read the FP64 records and must still meet 1e-5."""
+    print("[gpu] dense rod in 40-sigma cells", flush=True)
+    s, rc = dense_rod_system(21)
+    cell = 40.0
+    # the other row's particles in two x cells number more than 65535
+    other = (s.y >= cell) & (s.x < 2 * cell)
+    assert other.sum() > 65535
+    to_xb = np.abs(((s.x + cell / 2) % cell) - cell / 2)
+    near = np.flatnonzero((to_xb < 7.0) & (s.y > cell - 7.0) & (s.y < cell))[::97]
+    idx = np.unique(np.concatenate([workloads.sample_indices(s.n, 128, seed=21), near]))
+    ref = oracle.forces(s.x, s.y, s.z, rc, s.box, idx=idx)
+    full = {}
+    for prec, tol in ((dcm.DCM_FP64, 1e-12), (dcm.DCM_FP32_MIXED, 1e-5)):
+        got = gpu_forces(s, rc, prec=prec, edge=40.0, rc_bound=8.0)
+        assert got["status"] == dcm.DCM_OK
+        assert got["dims"][0] == [3, 3, 3]
+        full[prec] = got
+        np.testing.assert_array_equal(got["nnbr"][idx], ref["nnbr"])
+        emax, erms = force_errors(got["F"][idx], _ref_F(ref))
+        print(f"[gpu]   prec={prec} err_max={emax:.3e} err_rms={erms:.3e}", flush=True)
+        assert emax <= tol and erms <= tol, (prec, emax, erms)
+    np.testing.assert_array_equal(full[dcm.DCM_FP32_MIXED]["nnbr"], full[dcm.DCM_FP64]["nnbr"])
+
+
 def test_static_cutoff_reduces_to_eq3_and_balances():
     s = workloads.make("slab_small")
     rc = np.full(s.n, 3.0)
