@@ -79,11 +79,11 @@ typedef struct { int32_t n[3]; double h[3]; } dcm_grid;
 /* Arithmetic of the pair kernel.
  * DCM_FP64: all FP64.
  * DCM_FP32_MIXED: the Lennard-Jones terms in FP32, per-particle force sums
- * and the global energy/virial in FP64.  Under DCM_PAIR_OWN, separations
- * and r^2 are FP32 too, from 16-byte cell-relative records; a pair whose FP32
- * r^2 lies within a proven error band of rc^2 is decided in FP64, so the
- * pairs included are exactly those of DCM_FP64.  Under the other rules the
- * separations and r^2 are FP64. */
+ * and the global energy/virial in FP64.  Under DCM_PAIR_OWN with cells at
+ * most 2 sigma wide, separations and r^2 are FP32 too, from 16-byte
+ * cell-relative records; a pair whose FP32 r^2 lies within a proven error
+ * band of rc^2 is decided in FP64, so the pairs included are exactly those
+ * of DCM_FP64.  Otherwise the separations and r^2 are FP64. */
 enum { DCM_FP64 = 0, DCM_FP32_MIXED = 1 };
 
 /* Which pairs interact.
