@@ -332,6 +332,33 @@ def test_forty_sigma_cells_and_rows_of_100k_candidates():
     np.testing.assert_array_equal(full[dcm.DCM_FP32_MIXED]["nnbr"], full[dcm.DCM_FP64]["nnbr"])
 
 
+@pytest.mark.parametrize("f", [0.34, 1.7])
+def test_lj_parameters_scale(f):
+    """The small slab scaled by f (box, positions, cutoffs) with sigma = f and
+    epsilon = 0.7: the oracle with the same parameters, and the reduced-unit
+    law F(f x; eps, sigma = f) = (eps / f) F(x; 1, 1) (Eq. 3 depends on r only
+    through r / sigma)."""
+    base = workloads.make("slab_small")
+    rc = ref_detect("slab_small")["rc"]
+    s = workloads.System("scaled", base.x * f, base.y * f, base.z * f, base.vx, base.vy, base.vz,
+                         tuple(L * f for L in base.box))
+    eps = 0.7
+    ref = oracle.forces(s.x, s.y, s.z, rc * f, s.box, eps=eps, sigma=f)
+    unit = oracle.forces(base.x, base.y, base.z, rc, base.box)
+    np.testing.assert_array_equal(ref["nnbr"], unit["nnbr"])
+    emax, _ = force_errors(_ref_F(ref), _ref_F(unit) * (eps / f))
+    assert emax <= 1e-12
+    for prec, tol in ((dcm.DCM_FP64, 1e-12), (dcm.DCM_FP32_MIXED, 1e-5)):
+        got = gpu_forces(s, rc * f, prec=prec, edge=1.25 * f, eps=eps, sigma=f,
+                         rc_bound=float(np.max(rc)) * f)
+        assert got["status"] == dcm.DCM_OK
+        np.testing.assert_array_equal(got["nnbr"], ref["nnbr"])
+        emax, erms = force_errors(got["F"], _ref_F(ref))
+        assert emax <= tol and erms <= tol, (prec, emax, erms)
+        assert abs(got["E"] - ref["E"]) <= tol * abs(ref["E"])
+        assert rel(got["W"], ref["W"]) <= tol
+
+
 def test_static_cutoff_reduces_to_eq3_and_balances():
     s = workloads.make("slab_small")
     rc = np.full(s.n, 3.0)

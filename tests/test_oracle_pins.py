@@ -217,6 +217,26 @@ def test_translation_and_permutation_invariance(orc):
     assert L.shape == (3,)
 
 
+def test_forces_scale_with_sigma_and_epsilon(orc):
+    """Eq. 3 depends on r only through r / sigma: scaling positions, box and
+    cutoffs by f with sigma = f multiplies forces by eps / f, the energy by
+    eps and the virial by eps, and keeps every neighbour count."""
+    s = workloads.make("slab_small")
+    rng = np.random.default_rng(12)
+    rc = rng.uniform(2.5, 6.0, s.n)
+    idx = np.arange(0, s.n, 29)
+    a = orc.forces(s.x, s.y, s.z, rc, s.box, idx=idx)
+    for f, eps in ((0.34, 0.7), (1.7, 2.5)):
+        b = orc.forces(s.x * f, s.y * f, s.z * f, rc * f, tuple(L * f for L in s.box), eps=eps,
+                       sigma=f, idx=idx)
+        np.testing.assert_array_equal(a["nnbr"], b["nnbr"])
+        scale = max(np.max(np.abs(a[k])) for k in ("fx", "fy", "fz"))
+        for k in ("fx", "fy", "fz"):
+            np.testing.assert_allclose(b[k], a[k] * (eps / f), rtol=0, atol=1e-12 * scale * eps / f)
+        assert b["E"] == pytest.approx(a["E"] * eps, rel=1e-12)
+        np.testing.assert_allclose(b["W"], np.asarray(a["W"]) * eps, rtol=1e-11, atol=1e-12)
+
+
 def test_large_cutoff_converges_to_full_sum(orc):
     """Eq. 2 vs Eq. 3: with rc beyond the half-diagonal every minimum image
     pair is included, and the truncation error shrinks as rc grows."""
