@@ -12,8 +12,17 @@
 // contiguous index range and a separation is a plain difference.  A lane
 // writes its rows' ranges into a private LDS list, then runs one flat loop
 // over all their candidates, so lanes with different row lengths never wait
-// for each other row by row.  No Newton-3 update is made (Section 2.4): a
-// lane writes only its own particle.
+// for each other row by row.
+//
+// Rules: own cutoff (Algorithm 2.3) and the symmetric max(rc_i, rc_j), both
+// without a Newton-3 update (Section 2.4), so a lane writes only its own
+// particle; and the symmetric rule with Newton's third law, where each pair
+// is evaluated once and the partner's reaction is added with atomics.
+// Precisions: FP64 records (32 B per candidate); for FP32-mixed own-cutoff
+// forces on narrow cells, 16-byte cell-relative records with FP32
+// separations, the pairs inside a proven error band of the cutoff decided
+// from the FP64 record.  Also here: forces over a stored Verlet list, the
+// persistent batched form, and the fixed-order reduction of block partials.
 #include "dcm_device.hpp"
 #include "dcm_internal.hpp"
 
