@@ -266,23 +266,21 @@ __device__ __forceinline__ void scan_n3(const uint2 (*segs)[kPairBlock], int nse
 // for every lane with the result kept only where inc is set: the force of a
 // lane without an interaction in this step is computed and discarded instead
 // of branched around (the wavefront executes it anyway whenever any lane
-// interacts).  FP32 separations and r^2.
+// interacts).  FP32 separations and r^2.  The mask is applied once, to 1/r^2:
+// a masked pair then has s6 = 0 and adds exactly zero force, energy and
+// virial, whatever its r^2 (an unmasked pair at r = 0 stays non-finite).
 template <int EVM>
 __device__ __forceinline__ void interact_rel(Acc<DCM_FP32_MIXED> &acc, float dx, float dy, float dz,
                                              float r2, float sig2, bool inc) {
-  const float r2i = __builtin_amdgcn_rcpf(r2);
+  const float r2i = inc ? __builtin_amdgcn_rcpf(r2) : 0.0f;
   const float s2 = sig2 * r2i;
   const float s6 = s2 * s2 * s2;
-  const float fpv = s6 * fmaf(2.0f, s6, -1.0f) * r2i;
-  const float fp = inc ? fpv : 0.0f;
+  const float fp = s6 * fmaf(2.0f, s6, -1.0f) * r2i;
   const double fpd = (double)fp;
   acc.fx = fma(fpd, (double)dx, acc.fx);
   acc.fy = fma(fpd, (double)dy, acc.fy);
   acc.fz = fma(fpd, (double)dz, acc.fz);
-  if constexpr ((EVM & 1) != 0) {
-    const float et = s6 * (s6 - 1.0f);
-    acc.e += inc ? et : 0.0f;
-  }
+  if constexpr ((EVM & 1) != 0) acc.e += fmaf(s6, s6, -s6);
   if constexpr ((EVM & 2) != 0) {
     const float fdx = fp * dx, fdy = fp * dy, fdz = fp * dz;
     acc.w[0] = fmaf(fdx, dx, acc.w[0]);
@@ -306,38 +304,38 @@ __device__ __forceinline__ float4 load_rel(__amdgpu_buffer_rsrc_t rs, int j) {
 }
 
 // Flat loop over the compact-record candidates of this lane's first nseg
-// listed rows (FP32-mixed, own-cutoff rule).  A list entry is (first slot,
-// length | (row y - cy) << 16 | (row z - cz) << 24), the offsets as signed
-// bytes; the lane's own slot is never listed.  Separations are formed in
-// FP32 between the two cell-centre-relative positions, the candidate's cell
-// k cells away: d = (a0 - k len) - rel.  A pair whose FP32 r^2 lies within
-// the lane's proven error band around rc^2 is decided from its FP64 record
-// instead (rare: the band is ~1e-5 sigma^2 wide).  The stream is advanced
-// with selects, two register sets take turns so that every record is loaded
-// a full candidate before its use.
+// listed rows, total candidates in all (FP32-mixed, own-cutoff rule).  A list
+// entry is (first slot, length | (row y - cy) << 16 | (row z - cz) << 24),
+// the offsets as signed bytes, the length at least 1; the lane's own slot is
+// never listed.  Separations are formed in FP32 between the two
+// cell-centre-relative positions, the candidate's cell k cells away:
+// d = (a0 - k len) - rel.  A pair whose FP32 r^2 lies within the lane's proven
+// error band around rc^2 is decided from its FP64 record instead (rare: the
+// band is ~1e-5 sigma^2 wide).  The stream advances with selects and ends on
+// the lane's candidate count; the next entry is read ahead (clamped to the
+// last, so every slot read is a listed one), and two register sets take
+// turns so that every record is loaded a full candidate before its use.
 template <int EVM>
-__device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int nseg,
+__device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int nseg, int total,
                                          __amdgpu_buffer_rsrc_t rs,
                                          const double4 *__restrict__ ext_pos, const LaneGeo &g,
                                          float sig2, Acc<DCM_FP32_MIXED> &acc, int &cnt) {
   const int lane_id = threadIdx.x;
   const int last = nseg - 1;
   const uint2 s0 = segs[0][lane_id];
-  int j = (int)s0.x, jend = (int)s0.x + (int)(s0.y & 0xffffu), sidx = 1;
+  int j = (int)s0.x, jend = (int)s0.x + (int)(s0.y & 0xffffu), sidx = last < 1 ? last : 1;
   uint32_t tag = s0.y;
-  uint2 nx = segs[last < 1 ? last : 1][lane_id];
-  // next candidate of the stream and its row tag; -1 once exhausted
-  auto advance = [&](uint32_t &t) -> int {
+  uint2 nx = segs[sidx][lane_id];
+  // move to the next candidate of the stream (past the end: the last entry's
+  // slots again, never evaluated)
+  auto advance = [&]() {
     const int jn = j + 1;
     const bool sw = jn >= jend;
-    const bool ok = !sw || sidx < nseg;
     j = sw ? (int)nx.x : jn;
     jend = sw ? (int)nx.x + (int)(nx.y & 0xffffu) : jend;
     tag = sw ? nx.y : tag;
-    sidx = sw ? sidx + 1 : sidx;
-    nx = segs[sidx < last ? sidx : last][lane_id];
-    t = tag;
-    return ok ? j : -1;
+    sidx = sw ? (sidx < last ? sidx + 1 : last) : sidx;
+    nx = segs[sidx][lane_id];
   };
   auto eval = [&](const float4 &r, uint32_t t, int jr) {
     const int dyc = (int)(t << 8) >> 24, dzc = (int)t >> 24;
@@ -360,25 +358,24 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int ns
     interact_rel<EVM>(acc, dx, dy, dz, r2, sig2, inc);
     cnt += inc ? 1 : 0;
   };
+  int left = total;
   int ja = j;
-  uint32_t ta = tag, tb = 0;
+  uint32_t ta = tag;
   float4 A = load_rel(rs, ja);
-  int jb = advance(tb);
+  advance();
   while (true) {
-    float4 B = load_rel(rs, jb >= 0 ? jb : ja);
-    uint32_t tc = 0;
-    const int jc = jb >= 0 ? advance(tc) : -1;
+    const int jb = j;
+    const uint32_t tb = tag;
+    const float4 B = load_rel(rs, jb);
+    advance();
     eval(A, ta, ja);
-    if (jb < 0) break;
-    A = load_rel(rs, jc >= 0 ? jc : jb);
-    uint32_t td = 0;
-    const int jd = jc >= 0 ? advance(td) : -1;
+    if (--left == 0) break;
+    ja = j;
+    ta = tag;
+    A = load_rel(rs, ja);
+    advance();
     eval(B, tb, jb);
-    if (jc < 0) break;
-    ja = jc;
-    ta = tc;
-    jb = jd;
-    tb = td;
+    if (--left == 0) break;
   }
 }
 
@@ -455,7 +452,7 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     // ---- fill: append the ranges of the next rows to this lane's list,
     // kFillRows rows at a time: the two ext_start reads of all of them are
     // issued before the first is used, so their latencies overlap
-    int nseg = 0;
+    int nseg = 0, total = 0;
     // a row adds at most two entries (compact records: the own row is split)
     while (rows_left && nseg <= kSegCap - kFillRows - 1) {
       int j0[kFillRows], j1[kFillRows], rz[kFillRows], ry[kFillRows];
@@ -508,11 +505,13 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
           if (e1 > a0) {
             segs[nseg][lane_id] = make_uint2((uint32_t)a0, (uint32_t)(e1 - a0) | rowtag);
             ++nseg;
+            total += e1 - a0;
           }
           if (own && a1 > g.self + 1) {
             segs[nseg][lane_id] =
                 make_uint2((uint32_t)(g.self + 1), (uint32_t)(a1 - g.self - 1) | rowtag);
             ++nseg;
+            total += a1 - g.self - 1;
           }
         } else {
           if (a1 > a0) {
@@ -524,7 +523,7 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     }
     if (nseg > 0) {
       if constexpr (REL)
-        scan_rel<EVM>(segs, nseg, rs, v.ext_pos, g, (float)sig2, acc, cnt);
+        scan_rel<EVM>(segs, nseg, total, rs, v.ext_pos, g, (float)sig2, acc, cnt);
       else if constexpr (RULE == DCM_PAIR_MAX_N3)
         scan_n3<PREC, EVM>(segs, nseg, v, g, sig2, acc, cnt);
       else
