@@ -41,6 +41,8 @@ constexpr int kXcdGroup = DCM_PAIR_XCD_GROUP;
 #define DCM_PAIR_FILL 2
 #endif
 constexpr int kFillRows = DCM_PAIR_FILL;  // cell rows whose starts are read together
+static_assert(kSegCap >= kFillRows + 4,
+              "a chunk holds a batch of rows, a sentinel and a look-ahead entry");
 int pair_block_size() { return kPairBlock; }
 
 // Per-lane accumulators.
@@ -307,34 +309,34 @@ __device__ __forceinline__ float4 load_rel(__amdgpu_buffer_rsrc_t rs, int j) {
 // listed rows, total candidates in all (FP32-mixed, own-cutoff rule).  A list
 // entry is (first slot, length | (row y - cy) << 16 | (row z - cz) << 24),
 // the offsets as signed bytes, the length at least 1; the lane's own slot is
-// never listed.  Separations are formed in FP32 between the two
-// cell-centre-relative positions, the candidate's cell k cells away:
-// d = (a0 - k len) - rel.  A pair whose FP32 r^2 lies within the lane's proven
-// error band around rc^2 is decided from its FP64 record instead (rare: the
-// band is ~1e-5 sigma^2 wide).  The stream advances with selects and ends on
-// the lane's candidate count; the next entry is read ahead (clamped to the
-// last, so every slot read is a listed one), and two register sets take
-// turns so that every record is loaded a full candidate before its use.
+// never listed.  Entry nseg is a sentinel (slot 0, length 65535) and entry
+// nseg + 1 exists, so the stream needs no bounds: it moves at most one entry
+// past the last row (into the sentinel) before the candidate count ends it.
+// Separations are formed in FP32 between the two cell-centre-relative
+// positions, the candidate's cell k cells away: d = (a0 - k len) - rel.  A
+// pair whose FP32 r^2 lies within the lane's proven error band around rc^2 is
+// decided from its FP64 record instead (rare: the band is ~1e-5 sigma^2
+// wide).  The stream advances with selects, and two register sets take turns
+// so that every record is loaded a full candidate before its use.
 template <int EVM>
-__device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int nseg, int total,
+__device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int total,
                                          __amdgpu_buffer_rsrc_t rs,
                                          const double4 *__restrict__ ext_pos, const LaneGeo &g,
                                          float sig2, Acc<DCM_FP32_MIXED> &acc, int &cnt) {
   const int lane_id = threadIdx.x;
-  const int last = nseg - 1;
   const uint2 s0 = segs[0][lane_id];
-  int j = (int)s0.x, jend = (int)s0.x + (int)(s0.y & 0xffffu), sidx = last < 1 ? last : 1;
+  int j = (int)s0.x, jend = (int)s0.x + (int)(s0.y & 0xffffu), sidx = 1;
   uint32_t tag = s0.y;
-  uint2 nx = segs[sidx][lane_id];
-  // move to the next candidate of the stream (past the end: the last entry's
-  // slots again, never evaluated)
+  uint2 nx = segs[1][lane_id];
+  // move to the next candidate of the stream (past the last row: slots of the
+  // sentinel, never evaluated)
   auto advance = [&]() {
     const int jn = j + 1;
     const bool sw = jn >= jend;
     j = sw ? (int)nx.x : jn;
     jend = sw ? (int)nx.x + (int)(nx.y & 0xffffu) : jend;
     tag = sw ? nx.y : tag;
-    sidx = sw ? (sidx < last ? sidx + 1 : last) : sidx;
+    sidx += sw ? 1 : 0;
     nx = segs[sidx][lane_id];
   };
   auto eval = [&](const float4 &r, uint32_t t, int jr) {
@@ -356,7 +358,7 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int ns
       r2 = (float)e2;
     }
     interact_rel<EVM>(acc, dx, dy, dz, r2, sig2, inc);
-    cnt += inc ? 1 : 0;
+    if constexpr ((EVM & 4) != 0) cnt += inc ? 1 : 0;
   };
   int left = total;
   int ja = j;
@@ -453,8 +455,9 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     // kFillRows rows at a time: the two ext_start reads of all of them are
     // issued before the first is used, so their latencies overlap
     int nseg = 0, total = 0;
-    // a row adds at most two entries (compact records: the own row is split)
-    while (rows_left && nseg <= kSegCap - kFillRows - 1) {
+    // a row adds at most two entries (compact records: the own row is split,
+    // and two entries stay free for the sentinel and the look-ahead)
+    while (rows_left && nseg <= kSegCap - kFillRows - (REL ? 3 : 1)) {
       int j0[kFillRows], j1[kFillRows], rz[kFillRows], ry[kFillRows];
       bool ok[kFillRows];
 #pragma unroll
@@ -522,9 +525,10 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
       }
     }
     if (nseg > 0) {
-      if constexpr (REL)
-        scan_rel<EVM>(segs, nseg, total, rs, v.ext_pos, g, (float)sig2, acc, cnt);
-      else if constexpr (RULE == DCM_PAIR_MAX_N3)
+      if constexpr (REL) {
+        segs[nseg][lane_id] = make_uint2(0u, 0xffffu);
+        scan_rel<EVM>(segs, total, rs, v.ext_pos, g, (float)sig2, acc, cnt);
+      } else if constexpr (RULE == DCM_PAIR_MAX_N3)
         scan_n3<PREC, EVM>(segs, nseg, v, g, sig2, acc, cnt);
       else
         scan_ranges<RULE, PREC, EVM>(segs, nseg, v.ext_pos, g.self, g.xi, g.yi, g.zi, g.rci,
@@ -866,30 +870,37 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
   }
 }
 
-template <int RULE, int PREC, bool REL>
-static void launch_pair_ev(hipStream_t s, const PairArgs &a, dim3 g, dim3 b) {
-  const int evm = ((a.ev_flags & DCM_EV_ENERGY) ? 1 : 0) | ((a.ev_flags & DCM_EV_VIRIAL) ? 2 : 0);
-  switch (evm) {
-    case 0: hipLaunchKernelGGL((k_pair<RULE, PREC, 0, REL>), g, b, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_pair<RULE, PREC, 1, REL>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pair<RULE, PREC, 2, REL>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pair<RULE, PREC, 3, REL>), g, b, 0, s, a); break;
+// Evaluation-mode bits of the kernels: 1 energy, 2 virial, 4 pair counts.
+// The compact-record kernels count only when asked (bit 4); the others always
+// count, so their modes stop at 3.
+static int ev_mode(int ev_flags, bool rel) {
+  return ((ev_flags & DCM_EV_ENERGY) ? 1 : 0) | ((ev_flags & DCM_EV_VIRIAL) ? 2 : 0) |
+         ((rel && (ev_flags & DCM_EV_COUNTS)) ? 4 : 0);
+}
+
+template <int RULE, int PREC, bool REL, int E = 0>
+static void launch_pair_ev(hipStream_t s, const PairArgs &a, dim3 g, dim3 b, int evm) {
+  if constexpr (E < (REL ? 8 : 4)) {
+    if (evm == E) hipLaunchKernelGGL((k_pair<RULE, PREC, E, REL>), g, b, 0, s, a);
+    else launch_pair_ev<RULE, PREC, REL, E + 1>(s, a, g, b, evm);
   }
 }
 
 void launch_pair(hipStream_t s, const PairArgs &a, int rule, int prec) {
   const int64_t blocks = ceil_div(a.n, kPairBlock) > 0 ? ceil_div(a.n, kPairBlock) : 1;
   dim3 g((unsigned)blocks), b(kPairBlock);
+  const int evm = ev_mode(a.ev_flags, false);
   if (rule == DCM_PAIR_OWN) {
-    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_OWN, DCM_FP64, false>(s, a, g, b);
-    else if (a.ext_rel) launch_pair_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true>(s, a, g, b);
-    else launch_pair_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, false>(s, a, g, b);
+    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_OWN, DCM_FP64, false>(s, a, g, b, evm);
+    else if (a.ext_rel)
+      launch_pair_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true>(s, a, g, b, ev_mode(a.ev_flags, true));
+    else launch_pair_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, false>(s, a, g, b, evm);
   } else if (rule == DCM_PAIR_MAX) {
-    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_MAX, DCM_FP64, false>(s, a, g, b);
-    else launch_pair_ev<DCM_PAIR_MAX, DCM_FP32_MIXED, false>(s, a, g, b);
+    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_MAX, DCM_FP64, false>(s, a, g, b, evm);
+    else launch_pair_ev<DCM_PAIR_MAX, DCM_FP32_MIXED, false>(s, a, g, b, evm);
   } else {
-    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_MAX_N3, DCM_FP64, false>(s, a, g, b);
-    else launch_pair_ev<DCM_PAIR_MAX_N3, DCM_FP32_MIXED, false>(s, a, g, b);
+    if (prec == DCM_FP64) launch_pair_ev<DCM_PAIR_MAX_N3, DCM_FP64, false>(s, a, g, b, evm);
+    else launch_pair_ev<DCM_PAIR_MAX_N3, DCM_FP32_MIXED, false>(s, a, g, b, evm);
   }
 }
 
@@ -924,14 +935,12 @@ void launch_n3_out(hipStream_t s, const double4 *f, const int32_t *cnt, const in
                      fx, fy, fz, nnbr, status);
 }
 
-template <int RULE, int PREC, bool REL>
-static void launch_pair_batched_ev(hipStream_t s, const BatchPairArgs &a, dim3 g, dim3 b) {
-  const int evm = ((a.ev_flags & DCM_EV_ENERGY) ? 1 : 0) | ((a.ev_flags & DCM_EV_VIRIAL) ? 2 : 0);
-  switch (evm) {
-    case 0: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 0, REL>), g, b, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 1, REL>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 2, REL>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pair_batched<RULE, PREC, 3, REL>), g, b, 0, s, a); break;
+template <int RULE, int PREC, bool REL, int E = 0>
+static void launch_pair_batched_ev(hipStream_t s, const BatchPairArgs &a, dim3 g, dim3 b,
+                                   int evm) {
+  if constexpr (E < (REL ? 8 : 4)) {
+    if (evm == E) hipLaunchKernelGGL((k_pair_batched<RULE, PREC, E, REL>), g, b, 0, s, a);
+    else launch_pair_batched_ev<RULE, PREC, REL, E + 1>(s, a, g, b, evm);
   }
 }
 
@@ -944,7 +953,7 @@ static int64_t persistent_grid(int rule, int prec, int64_t nitems) {
     const void *fn;
     if (rule == DCM_PAIR_OWN)
       fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP64, 3, false>
-                            : (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP32_MIXED, 3, true>;
+                            : (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP32_MIXED, 7, true>;
     else
       fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP64, 3, false>
                             : (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP32_MIXED, 3, false>;
@@ -966,13 +975,16 @@ static int64_t persistent_grid(int rule, int prec, int64_t nitems) {
 void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int prec) {
   if (a.nitems <= 0) return;
   dim3 g((unsigned)persistent_grid(rule, prec, a.nitems)), b(kPairBlock);
+  const int evm = ev_mode(a.ev_flags, false);
   if (rule == DCM_PAIR_OWN) {
-    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP64, false>(s, a, g, b);
-    else if (a.ext_rel) launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true>(s, a, g, b);
-    else launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, false>(s, a, g, b);
+    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP64, false>(s, a, g, b, evm);
+    else if (a.ext_rel)
+      launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true>(s, a, g, b,
+                                                                 ev_mode(a.ev_flags, true));
+    else launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, false>(s, a, g, b, evm);
   } else {
-    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP64, false>(s, a, g, b);
-    else launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP32_MIXED, false>(s, a, g, b);
+    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP64, false>(s, a, g, b, evm);
+    else launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP32_MIXED, false>(s, a, g, b, evm);
   }
 }
 
