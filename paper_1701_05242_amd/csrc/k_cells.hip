@@ -490,24 +490,33 @@ __global__ __launch_bounds__(256) void k_ext_rows(const int32_t *__restrict__ ce
 }
 
 // ext_start of every extended cell (and of one past the last) from the row
-// starts.
+// starts, one wavefront per extended row with the row's values uniform.  Cell
+// u of the unwrapped row lies p = floor(u / n_x) periods away; with a halo of
+// at most n_x cells, u is in [-n_x, 2 n_x) and p in {-1, 0, 1}.
 __global__ __launch_bounds__(256) void k_ext_starts(const int32_t *__restrict__ cell_start,
                                                     const int32_t *__restrict__ row_start,
                                                     const int32_t *__restrict__ row_lo,
                                                     ExtGeom g, int64_t next, int64_t nrows,
                                                     int32_t *__restrict__ ext_start) {
-  // next < 2^30 (checked at build), so 32-bit index arithmetic suffices
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e <= (int)next; e += gridDim.x * blockDim.x) {
-    if (e == (int)next) {
-      ext_start[e] = row_start[nrows];
-      continue;
-    }
-    const int row = e / g.ne[0];
-    const int ex = e - row * g.ne[0];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(
+      (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6));
+  const int nwaves = (int)(((int64_t)gridDim.x * blockDim.x) >> 6);
+  if (wave == 0 && lane == 0) ext_start[next] = row_start[nrows];
+  const int nx = g.nc[0], hx = g.h[0], nex = g.ne[0];
+  const bool near = hx <= nx;
+  // next < 2^30 (checked at build), so 32-bit cell indices suffice
+  for (int row = wave; row < (int)nrows; row += nwaves) {
     const ExtRow r = ext_row(g, row);
-    const int64_t T = cell_start[r.r0 + g.nc[0]] - cell_start[r.r0];
-    const int64_t f = row_prefix(cell_start, r.r0, g.nc[0], T, ex - g.h[0]);
-    ext_start[e] = (int32_t)(row_start[row] + (f - row_lo[row]));
+    const int c0 = cell_start[r.r0];
+    const int64_t T = cell_start[r.r0 + nx] - c0;
+    const int64_t base = (int64_t)row_start[row] - row_lo[row];
+    int32_t *__restrict__ out = ext_start + (int64_t)row * nex;
+    for (int ex = lane; ex < nex; ex += 64) {
+      const int u = ex - hx;
+      const int p = near ? (u < 0 ? -1 : (u >= nx ? 1 : 0)) : floor_div(u, nx);
+      out[ex] = (int32_t)(base + p * T + (cell_start[r.r0 + (u - p * nx)] - c0));
+    }
   }
 }
 
@@ -528,10 +537,14 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
                          g.L[2] / (double)g.nc[2]};
   const double sc0 = (double)g.nc[0] / g.L[0];
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t row = wave; row < nrows; row += nwaves) {
-    const ExtRow r = ext_row(g, (int)row);
+  const int wave = __builtin_amdgcn_readfirstlane(
+      (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6));
+  const int nwaves = (int)(((int64_t)gridDim.x * blockDim.x) >> 6);
+  // with a halo of at most n_x cells a row's unwrapped prefixes P lie in
+  // [-T, 2T), so the period floor(P / T) is -1, 0 or 1
+  const bool near = g.h[0] <= g.nc[0];
+  for (int row = wave; row < (int)nrows; row += nwaves) {
+    const ExtRow r = ext_row(g, row);
     const int first = cell_start[r.r0];
     const int T = cell_start[r.r0 + g.nc[0]] - first;
     const int64_t o0 = row_start[row], cnt = row_start[row + 1] - o0;
@@ -540,7 +553,8 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
     bool over = false;
     for (int k = lane; k < cnt; k += 64) {
       const int P = lo + k;
-      const int p = floor_div(P, T);  // cnt > 0 implies T > 0
+      // cnt > 0 implies T > 0
+      const int p = near ? (P < 0 ? -1 : (P >= T ? 1 : 0)) : floor_div(P, T);
       const int64_t o = o0 + k;
       if (o >= cap) {
         over = true;
@@ -615,7 +629,8 @@ void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *s
   hipLaunchKernelGGL(k_ext_rows, dim3((unsigned)b), dim3(256), 0, s, cell_start, g, nrows,
                      row_count, row_lo);
   launch_exclusive_scan(s, row_count, row_start, nrows, scan_tmp);
-  b = ceil_div(next + 1, 256);
+  b = ceil_div(nrows, 4);  // four rows per workgroup of 256
+  if (b < 1) b = 1;
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_ext_starts, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
                      row_lo, g, next, nrows, ext_start);

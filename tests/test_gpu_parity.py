@@ -187,7 +187,9 @@ def test_forces_match_oracle(name, rule, prec):
     assert rel(got["W"], ref["W"]) <= tol
 
 
-@pytest.mark.parametrize("edge", [0.0, 0.7, 1.9, 3.3])
+# 7.0: one cell across x and y (13.4 sigma), so the halo of two cells is
+# wider than the grid and the ghost rows wrap the box more than once
+@pytest.mark.parametrize("edge", [0.0, 0.7, 1.9, 3.3, 7.0])
 def test_forces_independent_of_cell_edge_and_deterministic(edge):
     s = workloads.make("slab_small")
     rc = ref_detect("slab_small")["rc"]
