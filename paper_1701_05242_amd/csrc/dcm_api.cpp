@@ -779,13 +779,19 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     for (int k = 0; k < WFIELDS; ++k) W[k] = field(cur, k);
   };
   bind();
-  // reorder the working copies into the order of the last cell build
+  // reorder the working copies into the order of the last cell build.  Only
+  // the fields read before the next force pass rewrites them move: positions
+  // and velocities, and the forces when the next step opens with its own kick
+  // (an energy series is recorded); delta and rc are always recomputed.
   auto reorder = [&]() {
     PermFields f;
-    f.nf = WFIELDS;
+    f.nf = 0;
     for (int k = 0; k < WFIELDS; ++k) {
-      f.src[k] = field(cur, k);
-      f.dst[k] = field(1 - cur, k);
+      const bool force = k == WFX || k == WFY || k == WFZ;
+      if (k == WDELTA || k == WRC || (force && !energy_series)) continue;
+      f.src[f.nf] = field(cur, k);
+      f.dst[f.nf] = field(1 - cur, k);
+      ++f.nf;
     }
     launch_permute_gather(s, f, ptr<int32_t>(ctx->perm), owner(cur), owner(1 - cur), n);
     cur = 1 - cur;

@@ -478,6 +478,31 @@ def test_verlet_trajectory_tracks_oracle():
     assert host(es)[-1] == pytest.approx(ke, rel=1e-9)
 
 
+@pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
+def test_step_without_energy_series_repeats_the_recorded_run(prec):
+    """Without an energy series dcm_step fuses the closing and opening kicks
+    and keeps fewer fields in step between its reorderings; with one it runs
+    every kick on its own.  Both perform the same arithmetic, so 20 steps
+    (reorderings after steps 1, 8 and 16) must give the same state bit for
+    bit: positions, velocities, forces, cutoffs and distances."""
+    print(f"[gpu] dcm_step with and without an energy series prec={prec}", flush=True)
+    s = workloads.make("slab_small")
+    grid = dcm.make_grid(s.box, s.h)
+    rule = dcm.make_rule(*s.rule)
+    rcg = dcm.rc_grid_for(rule, grid)
+    out = []
+    for series in (True, False):
+        st = [dev(a) for a in (s.x, s.y, s.z, s.vx, s.vy, s.vz)]
+        st += [torch.zeros(s.n, **F64) for _ in range(5)]  # forces, delta, rc
+        es = torch.zeros(40, **F64) if series else None
+        with Ctx() as ctx:
+            dcm.dcm_step(ctx, *st[:9], s.box, dcm.make_lj(), rule, grid, rcg, 0.005, 20,
+                         prec=prec, redetect_every=3, energy_series=es, delta=st[9], rc=st[10])
+            assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
+        out.append(np.stack([host(t) for t in st], 1))
+    np.testing.assert_array_equal(out[0], out[1])
+
+
 def test_large_slab_sampled_parity():
     """The large slab in the benchmark's configuration (FP32-mixed, automatic
     cells): every cutoff bit-exact, forces on a seeded sample of particles
