@@ -141,11 +141,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Column sums of `rows` rows of S doubles (row r at p + r S) by one
-// workgroup of NT threads, in a fixed order: thread t adds rows t, t + NT, ...
-// in turn, each wavefront sums its lanes with shuffles, and thread 0 adds
-// the wavefronts in order.  Every thread must call it; thread 0 gets out[].
-template <int NT, int S>
+// Sums of the first S columns of `rows` rows of STRIDE doubles (row r at
+// p + r STRIDE) by one workgroup of NT threads, in a fixed order: thread t
+// adds rows t, t + NT, ... in turn, each wavefront sums its lanes with
+// shuffles, and thread 0 adds the wavefronts in order.  A column's sum does
+// not depend on S.  Every thread must call it; thread 0 gets out[].
+template <int NT, int S, int STRIDE = S>
 __device__ __forceinline__ void sum_rows(const double *__restrict__ p, int64_t rows,
                                          double (*red)[S], double *out) {
   double v[S];
@@ -153,7 +154,7 @@ __device__ __forceinline__ void sum_rows(const double *__restrict__ p, int64_t r
   for (int k = 0; k < S; ++k) v[k] = 0.0;
   for (int64_t r = threadIdx.x; r < rows; r += NT)
 #pragma unroll
-    for (int k = 0; k < S; ++k) v[k] += p[r * S + k];
+    for (int k = 0; k < S; ++k) v[k] += p[r * STRIDE + k];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < S; ++k) {

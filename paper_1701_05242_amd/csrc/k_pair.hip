@@ -29,10 +29,21 @@
 namespace dcm {
 
 constexpr int kPairBlock = 256;
+// Row ranges per lane per chunk (LDS: 8 B each): FP64-record kernels, and
+// compact-record kernels, whose cheaper candidates gain more from the higher
+// occupancy of a smaller list (measured on the large slab).
 #ifndef DCM_PAIR_SEGCAP
 #define DCM_PAIR_SEGCAP 24
 #endif
-constexpr int kSegCap = DCM_PAIR_SEGCAP;  // row ranges per lane per chunk (LDS: 8 B each)
+#ifndef DCM_PAIR_SEGCAP_REL
+#define DCM_PAIR_SEGCAP_REL 16
+#endif
+constexpr int kSegCap = DCM_PAIR_SEGCAP;
+constexpr int kSegCapRel = DCM_PAIR_SEGCAP_REL;
+template <bool REL>
+constexpr int seg_cap() {
+  return REL ? kSegCapRel : kSegCap;
+}
 #ifndef DCM_PAIR_XCD_GROUP
 #define DCM_PAIR_XCD_GROUP 16
 #endif
@@ -41,7 +52,7 @@ constexpr int kXcdGroup = DCM_PAIR_XCD_GROUP;
 #define DCM_PAIR_FILL 2
 #endif
 constexpr int kFillRows = DCM_PAIR_FILL;  // cell rows whose starts are read together
-static_assert(kSegCap >= kFillRows + 4,
+static_assert(kSegCap >= kFillRows + 4 && kSegCapRel >= kFillRows + 4,
               "a chunk holds a batch of rows, a sentinel and a look-ahead entry");
 int pair_block_size() { return kPairBlock; }
 
@@ -397,8 +408,8 @@ __device__ __forceinline__ int cell_off(float p, float inv) {
 
 // Walk this lane's rows (fill a list, scan it, repeat) for a lane with run
 // set.  REL: compact records (FP32-mixed, own-cutoff rule); else the FP64
-// records.
-template <int RULE, int PREC, int EVM, bool REL>
+// records.  CAP: the row capacity of segs.
+template <int RULE, int PREC, int EVM, bool REL, int CAP>
 __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const LaneGeo &g,
                                            double sig2, uint2 (*segs)[kPairBlock],
                                            Acc<PREC> &acc, int &cnt, bool &redo) {
@@ -457,7 +468,7 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     int nseg = 0, total = 0;
     // a row adds at most two entries (compact records: the own row is split,
     // and two entries stay free for the sentinel and the look-ahead)
-    while (rows_left && nseg <= kSegCap - kFillRows - (REL ? 3 : 1)) {
+    while (rows_left && nseg <= CAP - kFillRows - (REL ? 3 : 1)) {
       int j0[kFillRows], j1[kFillRows], rz[kFillRows], ry[kFillRows];
       bool ok[kFillRows];
 #pragma unroll
@@ -588,7 +599,8 @@ __device__ __forceinline__ void finish_block(const int32_t *perm, int64_t id0, d
 // it holds a particle).  Writes the forces and, from lanes 0..7, the block's
 // partial sums E, W[6], pair count to partial_out.  REL: FP32-mixed
 // own-cutoff evaluation on compact records, then the lanes that met an
-// undecidable pair are recomputed from the FP64 records.
+// undecidable pair are recomputed from the FP64 records.  segs holds
+// seg_cap<REL>() rows.
 template <int RULE, int PREC, int EVM, bool REL>
 __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool active, double eps,
                                            double sig2, uint2 (*segs)[kPairBlock],
@@ -676,7 +688,7 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
     g.self = v.ext_start[ext_cell] + (int)(s - v.cell_start[real_cell]);
   }
   bool redo = false;
-  sweep_rows<RULE, PREC, EVM, REL>(v, active, g, sig2, segs, acc, cnt, redo);
+  sweep_rows<RULE, PREC, EVM, REL, seg_cap<REL>()>(v, active, g, sig2, segs, acc, cnt, redo);
   if constexpr (REL) {
     // rare: lanes with a row longer than a list entry can describe start
     // over on the FP64 records
@@ -686,7 +698,8 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
         cnt = 0;
       }
       bool unused = false;
-      sweep_rows<RULE, PREC, EVM, false>(v, active && redo, g, sig2, segs, acc, cnt, unused);
+      sweep_rows<RULE, PREC, EVM, false, seg_cap<REL>()>(v, active && redo, g, sig2, segs, acc,
+                                                        cnt, unused);
     }
   }
   if constexpr (RULE == DCM_PAIR_MAX_N3) {
@@ -708,7 +721,7 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
 
 template <int RULE, int PREC, int EVM, bool REL>
 __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
-  __shared__ uint2 segs[kSegCap][kPairBlock];
+  __shared__ uint2 segs[seg_cap<REL>()][kPairBlock];
   __shared__ double red[kPairBlock / 64][kPartialSlots];
   const int64_t lblock = xcd_block(blockIdx.x, gridDim.x, kXcdGroup);
   const int64_t s = lblock * kPairBlock + threadIdx.x;
@@ -821,7 +834,7 @@ void launch_pair_list(hipStream_t s, const PairArgs &a, int prec, const int32_t 
 // workgroup leaves the loop once the queue head passes the item count.
 template <int RULE, int PREC, int EVM, bool REL>
 __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
-  __shared__ uint2 segs[kSegCap][kPairBlock];
+  __shared__ uint2 segs[seg_cap<REL>()][kPairBlock];
   __shared__ double red[kPairBlock / 64][kPartialSlots];
   __shared__ int32_t next_item;
   const double sig2 = a.sigma * a.sigma;
@@ -989,26 +1002,36 @@ void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int pr
 }
 
 // Sum the block partials in a fixed order (one workgroup), so the energy,
-// virial and pair count do not depend on scheduling.
+// virial and pair count do not depend on scheduling.  ONLY_E: the energy
+// alone (slot 0 of each block), the same sum as in the full reduction.
+template <bool ONLY_E>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(
     const double *__restrict__ partials, int64_t blocks, int ev_flags, double *energy,
     double *virial, uint64_t *npairs) {
-  __shared__ double red[kReduceThreads / 64][kPartialSlots];
-  double t[kPartialSlots];
-  sum_rows<kReduceThreads, kPartialSlots>(partials, blocks, red, t);
+  constexpr int S = ONLY_E ? 1 : kPartialSlots;
+  __shared__ double red[kReduceThreads / 64][S];
+  double t[S];
+  sum_rows<kReduceThreads, S, kPartialSlots>(partials, blocks, red, t);
   if (threadIdx.x == 0) {
     if (energy && (ev_flags & DCM_EV_ENERGY)) *energy = t[0];
-    if (virial && (ev_flags & DCM_EV_VIRIAL))
-      for (int k = 0; k < 6; ++k) virial[k] = t[1 + k];
-    if (npairs && (ev_flags & DCM_EV_COUNTS)) *npairs = (uint64_t)t[7];
+    if constexpr (!ONLY_E) {
+      if (virial && (ev_flags & DCM_EV_VIRIAL))
+        for (int k = 0; k < 6; ++k) virial[k] = t[1 + k];
+      if (npairs && (ev_flags & DCM_EV_COUNTS)) *npairs = (uint64_t)t[7];
+    }
   }
 }
 
 void launch_reduce_partials(hipStream_t s, const double *partials, int64_t blocks, double eps,
                             int ev_flags, double *energy, double *virial, uint64_t *npairs) {
   (void)eps;
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kReduceThreads), 0, s, partials, blocks,
-                     ev_flags, energy, virial, npairs);
+  const bool only_e = !(ev_flags & (DCM_EV_VIRIAL | DCM_EV_COUNTS)) || (!virial && !npairs);
+  if (only_e)
+    hipLaunchKernelGGL(k_reduce_partials<true>, dim3(1), dim3(kReduceThreads), 0, s, partials,
+                       blocks, ev_flags, energy, virial, npairs);
+  else
+    hipLaunchKernelGGL(k_reduce_partials<false>, dim3(1), dim3(kReduceThreads), 0, s, partials,
+                       blocks, ev_flags, energy, virial, npairs);
 }
 
 }  // namespace dcm
