@@ -254,7 +254,7 @@ dcm_status dcm_detect_interface_opts(dcm_ctx *ctx, const double *x, const double
     return fail(ctx, DCM_ERR_INVALID, "dcm_detect_interface: null pointer");
   if (!std::isfinite(split)) return fail(ctx, DCM_ERR_INVALID, "split must be finite");
   DCM_TRY(ensure(ctx, ctx->gray, nvox * sizeof(uint32_t)));
-  DCM_TRY(ensure(ctx, ctx->hist, kHistBins * sizeof(uint32_t)));
+  DCM_TRY(ensure(ctx, ctx->hist, (size_t)kHistCopies * kHistBins * sizeof(uint32_t)));
   DCM_TRY(ensure(ctx, ctx->seg_a, phase_bits_words(grid.n) * sizeof(uint32_t)));
   DCM_TRY(ensure(ctx, ctx->seg_b, phase_bits_words(grid.n) * sizeof(uint32_t)));
   if (opts->min_volume > 0) {
@@ -271,10 +271,10 @@ dcm_status dcm_detect_interface_opts(dcm_ctx *ctx, const double *x, const double
   hipEvent_t ev;
   timer_begin(ctx, "detect", &ev);
   launch_fill_u32(s, counts, 0u, nvox);
-  launch_fill_u32(s, ptr<uint32_t>(ctx->hist), 0u, kHistBins);
+  launch_fill_u32(s, ptr<uint32_t>(ctx->hist), 0u, (int64_t)kHistCopies * kHistBins);
   launch_bin_density(s, x, y, z, n, box.L, grid.n, sc, counts, ctx->d_status);
-  launch_gray(s, counts, ptr<uint32_t>(ctx->gray), grid.n);
-  launch_hist(s, ptr<uint32_t>(ctx->gray), nvox, ptr<uint32_t>(ctx->hist), ctx->d_status);
+  launch_gray_hist(s, counts, ptr<uint32_t>(ctx->gray), grid.n, ptr<uint32_t>(ctx->hist),
+                   ctx->d_status);
   if (split <= 0.0)
     launch_otsu(s, ptr<uint32_t>(ctx->hist), nvox, ctx->ctl, threshold_out, ctx->d_status);
   launch_threshold(s, ptr<uint32_t>(ctx->gray), grid.n, split, ctx->ctl,

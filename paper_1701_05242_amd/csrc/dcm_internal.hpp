@@ -28,6 +28,7 @@ enum : uint32_t {
 };
 
 constexpr int kHistBins = 4096;       // gray values (27-window counts) must stay below this
+constexpr int kHistCopies = 32;      // histogram copies the gray-value workgroups add into
 constexpr int kMajorityMaxPasses = 16;
 constexpr int kPartialSlots = 8;      // per-block partial sums: E, W[6], pair count
 constexpr int kReduceThreads = 1024;  // workgroup that sums the block partials
@@ -196,9 +197,8 @@ void launch_clear_status(hipStream_t s, uint32_t *st);
 void launch_bin_density(hipStream_t s, const double *x, const double *y, const double *z,
                         int64_t n, const double L[3], const int32_t nv[3], const double sc[3],
                         uint32_t *counts, uint32_t *status);
-void launch_gray(hipStream_t s, const uint32_t *counts, uint32_t *gray, const int32_t nv[3]);
-void launch_hist(hipStream_t s, const uint32_t *gray, int64_t nvox, uint32_t *hist,
-                 uint32_t *status);
+void launch_gray_hist(hipStream_t s, const uint32_t *counts, uint32_t *gray, const int32_t nv[3],
+                      uint32_t *hist, uint32_t *status);
 void launch_otsu(hipStream_t s, const uint32_t *hist, int64_t nvox, Ctl *ctl, int32_t *t_out,
                  uint32_t *status);
 // phase maps of the majority passes are bit-packed: ceil(nx/32) words per

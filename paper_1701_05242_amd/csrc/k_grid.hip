@@ -3,16 +3,16 @@
 // regularisation -> interface marking.  All stages are integer stencils or
 // exact integer sums, so their results are bit-for-bit deterministic.
 //
-// The 27-point stencils run on 3-D tiles staged in LDS (64 x 4 x 4 outputs
-// per workgroup, one-voxel periodic halo) and sum separably: along x into LDS,
-// then over the 3 x 3 (y, z) window, so each output costs 3 + 9 LDS reads.
+// The gray value's 27-point window runs on 64 x 4 columns of (x, y) outputs
+// that march through z with the (x, y) halo of each plane staged in LDS; the
+// interface marking reads 64 x 4 x 4 tiles.
 #include "dcm_device.hpp"
 #include "dcm_internal.hpp"
 
 namespace dcm {
 
 constexpr int SX = 64, SY = 4, SZ = 4;                 // stencil tile (outputs)
-constexpr int HX = SX + 2, HY = SY + 2, HZ = SZ + 2;   // with halo
+constexpr int HX = SX + 2, HY = SY + 2;                // with halo
 
 // periodic index for a coordinate within one period of [0, n)
 __device__ __forceinline__ int wrap_near(int i, int n) {
@@ -68,122 +68,105 @@ static dim3 stencil_grid(const int32_t nv[3]) {
               (unsigned)ceil_div(nv[2], SZ));
 }
 
-// Stage the haloed tile of `src` (periodic) into LDS.
-template <typename T, typename S>
-__device__ __forceinline__ void load_tile(S (&tile)[HZ][HY][HX], const T *__restrict__ src,
-                                          int x0, int y0, int z0, int nx, int ny, int nz) {
-  const int tid = threadIdx.y * SX + threadIdx.x;
-  for (int e = tid; e < HZ * HY * HX; e += SX * SY) {
-    const int lz = e / (HY * HX);
-    const int r = e - lz * (HY * HX);
-    const int ly = r / HX;
-    const int lx = r - ly * HX;
-    const int gx = wrap_near(x0 + lx - 1, nx);
-    const int gy = wrap_near(y0 + ly - 1, ny);
-    const int gz = wrap_near(z0 + lz - 1, nz);
-    tile[lz][ly][lx] = (S)src[((int64_t)gz * ny + gy) * nx + gx];
-  }
-}
-
-// 27-window sum at output (lx, ly, lz) of the tile from the x-summed plane.
-template <typename S>
-__device__ __forceinline__ S sum_yz(const S (&sx)[HZ][HY][SX], int lx, int ly, int lz) {
-  S s = 0;
-#pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy) s += sx[lz + dz][ly + dy][lx];
-  return s;
-}
-
-template <typename S>
-__device__ __forceinline__ void sum_x(S (&sx)[HZ][HY][SX], const S (&tile)[HZ][HY][HX]) {
-  const int tid = threadIdx.y * SX + threadIdx.x;
-  for (int e = tid; e < HZ * HY * SX; e += SX * SY) {
-    const int lz = e / (HY * SX);
-    const int r = e - lz * (HY * SX);
-    const int ly = r / SX;
-    const int lx = r - ly * SX;
-    sx[lz][ly][lx] = tile[lz][ly][lx] + tile[lz][ly][lx + 1] + tile[lz][ly][lx + 2];
-  }
-}
-
-// --------------------------------------------------- gray value (Fig. 4b)
-// gray[v] = sum of counts over the periodic 3x3x3 window of v.
-__global__ __launch_bounds__(256) void k_gray(const uint32_t *__restrict__ counts,
-                                              uint32_t *__restrict__ gray, int nx, int ny,
-                                              int nz) {
-  __shared__ uint32_t tile[HZ][HY][HX];
-  __shared__ uint32_t sx[HZ][HY][SX];
-  const int x0 = blockIdx.x * SX, y0 = blockIdx.y * SY, z0 = blockIdx.z * SZ;
-  load_tile(tile, counts, x0, y0, z0, nx, ny, nz);
-  __syncthreads();
-  sum_x(sx, tile);
-  __syncthreads();
-  const int lx = threadIdx.x, ly = threadIdx.y;
-  const int gx = x0 + lx, gy = y0 + ly;
-  if (gx >= nx || gy >= ny) return;
-#pragma unroll
-  for (int lz = 0; lz < SZ; ++lz) {
-    const int gz = z0 + lz;
-    if (gz < nz) gray[((int64_t)gz * ny + gy) * nx + gx] = sum_yz(sx, lx, ly, lz);
-  }
-}
-
-void launch_gray(hipStream_t s, const uint32_t *counts, uint32_t *gray, const int32_t nv[3]) {
-  hipLaunchKernelGGL(k_gray, stencil_grid(nv), dim3(SX, SY), 0, s, counts, gray, nv[0], nv[1],
-                     nv[2]);
-}
-
-// Histogram of the gray values: a private LDS histogram per workgroup, merged
-// once into the global one.  Each lane reads four voxels at a time.  The
-// low-density phase puts most voxels into the first few bins: a lane counts
-// those in registers and adds them to the LDS histogram once at the end;
-// every other voxel takes one LDS atomic (lanes that hit the same bin are
-// serialised by the LDS itself).
+// --------------------------------------- gray value and histogram (Fig. 4b)
+// gray[v] = sum of counts over the periodic 3x3x3 window of v, and the
+// histogram of the gray values, in one pass.  A workgroup owns a 64 x 4
+// column of (x, y) outputs and marches through kGrayZ planes of z (32: fewer
+// workgroups merge fewer private histograms, measured 41 us against 50 us
+// for 16 and 47 us for 64 on the 160 x 160 x 400 grid): each plane
+// of counts is staged in LDS with its one-voxel (x, y) halo and summed over
+// the 3 x 3 window of each output, and the sums of three consecutive planes
+// give the gray value of the middle one.  A plane is read once per column
+// (1.55 words per output with the halo) instead of three times.
+//
+// Histogram: a private LDS histogram per workgroup, merged once into one of
+// kHistCopies global copies (the split sums them).  The low-density phase puts most voxels into the first few
+// bins: a lane counts those in registers and adds them to the LDS histogram
+// at the end; every other voxel takes one LDS atomic (lanes that hit the same
+// bin are serialised by the LDS itself).  Counts are exact integers, so the
+// histogram does not depend on the order of the additions.
+#ifndef DCM_GRAY_Z
+#define DCM_GRAY_Z 32
+#endif
+constexpr int kGrayZ = DCM_GRAY_Z;
 constexpr int kHistLow = 3;
 
-__global__ __launch_bounds__(256) void k_hist(const uint32_t *__restrict__ gray, int64_t nvox,
-                                              uint32_t *hist, uint32_t *status) {
+__global__ __launch_bounds__(SX * SY) void k_gray_hist(const uint32_t *__restrict__ counts,
+                                                     uint32_t *__restrict__ gray, int nx, int ny,
+                                                     int nz, uint32_t *hist, uint32_t *status) {
+  __shared__ uint32_t plane[HY][HX];
   __shared__ uint32_t lh[kHistBins];
-  for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) lh[b] = 0u;
-  __syncthreads();
+  const int tid = threadIdx.y * SX + threadIdx.x;
+  for (int b = tid; b < kHistBins; b += SX * SY) lh[b] = 0u;
+  const int x0 = blockIdx.x * SX, y0 = blockIdx.y * SY, z0 = blockIdx.z * kGrayZ;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool mine = gx < nx && gy < ny;
+  const int zend = z0 + kGrayZ < nz ? z0 + kGrayZ : nz;
   uint32_t low[kHistLow] = {0u, 0u, 0u};
   bool over = false;
-  auto add = [&](uint32_t g) {
-#pragma unroll
-    for (int k = 0; k < kHistLow; ++k) low[k] += g == (uint32_t)k ? 1u : 0u;
-    if (g >= (uint32_t)kHistLow) {
-      if (g < (uint32_t)kHistBins) atomicAdd(&lh[g], 1u);
-      else over = true;
-    }
+  uint32_t s0 = 0u, s1 = 0u;  // 3 x 3 sums of the two planes before plane z
+  // this thread's (at most two) elements of a haloed plane; the next plane's
+  // are read while the current one is summed
+  static_assert(HY * HX <= 2 * SX * SY, "two elements per thread cover a plane");
+  const int e1 = tid + SX * SY;
+  const int py0 = tid / HX, px0 = tid - py0 * HX, py1 = e1 / HX, px1 = e1 - py1 * HX;
+  const bool has0 = tid < HY * HX, has1 = e1 < HY * HX;
+  const int64_t off0 = has0 ? (int64_t)wrap_near(y0 + py0 - 1, ny) * nx + wrap_near(x0 + px0 - 1, nx) : 0;
+  const int64_t off1 = has1 ? (int64_t)wrap_near(y0 + py1 - 1, ny) * nx + wrap_near(x0 + px1 - 1, nx) : 0;
+  const int64_t pstride = (int64_t)ny * nx;
+  auto fetch = [&](int z, uint32_t &v0, uint32_t &v1) {
+    const uint32_t *src = counts + wrap_near(z, nz) * pstride;
+    v0 = has0 ? src[off0] : 0u;
+    v1 = has1 ? src[off1] : 0u;
   };
-  const int64_t nq = nvox >> 2;  // whole uint4 groups (gray is 16-byte aligned)
-  const uint4 *g4 = reinterpret_cast<const uint4 *>(gray);
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const uint4 v = g4[q];
-    add(v.x);
-    add(v.y);
-    add(v.z);
-    add(v.w);
+  uint32_t n0, n1;
+  fetch(z0 - 1, n0, n1);
+  // plane z is read for z = z0 - 1 .. zend; output plane z - 1 once three
+  // planes are summed
+  for (int z = z0 - 1; z <= zend; ++z) {
+    __syncthreads();  // the previous plane has been summed (and lh cleared)
+    if (has0) plane[py0][px0] = n0;
+    if (has1) plane[py1][px1] = n1;
+    __syncthreads();
+    if (z < zend) fetch(z + 1, n0, n1);
+    uint32_t s2 = 0u;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) s2 += plane[ly + dy][lx + dx];
+    if (z > z0 && mine) {
+      const uint32_t g = s0 + s1 + s2;
+      gray[((int64_t)(z - 1) * ny + gy) * nx + gx] = g;
+#pragma unroll
+      for (int k = 0; k < kHistLow; ++k) low[k] += g == (uint32_t)k ? 1u : 0u;
+      if (g >= (uint32_t)kHistLow) {
+        if (g < (uint32_t)kHistBins) atomicAdd(&lh[g], 1u);
+        else over = true;
+      }
+    }
+    s0 = s1;
+    s1 = s2;
   }
-  if (blockIdx.x == 0 && threadIdx.x < (nvox & 3)) add(gray[(nq << 2) + threadIdx.x]);
   if (over) atomicOr(status, ST_HIST_RANGE);
 #pragma unroll
   for (int k = 0; k < kHistLow; ++k)
     if (low[k]) atomicAdd(&lh[k], low[k]);
   __syncthreads();
-  for (int b = threadIdx.x; b < kHistBins; b += blockDim.x)
-    if (lh[b]) atomicAdd(&hist[b], lh[b]);
+  // workgroups spread their merges over kHistCopies copies of the histogram,
+  // so the few bins of the liquid are not all added into one address
+  const int64_t bid = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  uint32_t *dst = hist + (bid % kHistCopies) * kHistBins;
+  for (int b = tid; b < kHistBins; b += SX * SY)
+    if (lh[b]) atomicAdd(&dst[b], lh[b]);
 }
 
-void launch_hist(hipStream_t s, const uint32_t *gray, int64_t nvox, uint32_t *hist,
-                 uint32_t *status) {
-  int64_t b = ceil_div(nvox, 256 * 16);
-  if (b < 1) b = 1;
-  if (b > 2048) b = 2048;
-  hipLaunchKernelGGL(k_hist, dim3((unsigned)b), dim3(256), 0, s, gray, nvox, hist, status);
+void launch_gray_hist(hipStream_t s, const uint32_t *counts, uint32_t *gray, const int32_t nv[3],
+                      uint32_t *hist, uint32_t *status) {
+  const dim3 g((unsigned)ceil_div(nv[0], SX), (unsigned)ceil_div(nv[1], SY),
+               (unsigned)ceil_div(nv[2], kGrayZ));
+  hipLaunchKernelGGL(k_gray_hist, g, dim3(SX, SY), 0, s, counts, gray, nv[0], nv[1], nv[2], hist,
+                     status);
 }
 
 // ------------------------------ two-phase split of the gray values (Eq. 4)
@@ -191,7 +174,7 @@ void launch_hist(hipStream_t s, const uint32_t *gray, int64_t nvox, uint32_t *hi
 // constant two-phase energy with no length term is smallest where
 // S0^2/n0 + S1^2/n1 is largest (S, n: exact integer sum and count of each
 // phase); ties go to the smallest t.  One workgroup of 1024 threads owns 4
-// consecutive histogram bins each.
+// consecutive histogram bins each (summed over the histogram's copies).
 __global__ __launch_bounds__(1024) void k_otsu(const uint32_t *__restrict__ hist, Ctl *ctl,
                                                int32_t *t_out, uint32_t *status) {
   __shared__ long long sc[1024];
@@ -205,7 +188,9 @@ __global__ __launch_bounds__(1024) void k_otsu(const uint32_t *__restrict__ hist
   long long lc = 0, ls = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    c[q] = (long long)hist[t0 + q];
+    c[q] = 0;
+#pragma unroll 8
+    for (int k = 0; k < kHistCopies; ++k) c[q] += (long long)hist[k * kHistBins + t0 + q];
     sm[q] = c[q] * (long long)(t0 + q);
     lc += c[q];
     ls += sm[q];
