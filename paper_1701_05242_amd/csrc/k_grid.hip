@@ -186,11 +186,20 @@ __global__ __launch_bounds__(1024) void k_otsu(const uint32_t *__restrict__ hist
   const int t0 = tid * 4;
   long long c[4], sm[4];
   long long lc = 0, ls = 0;
+  // this thread's 4 bins summed over the copies (16-byte loads; a bin holds
+  // at most the voxel count, below 2^31)
+  uint4 h = make_uint4(0u, 0u, 0u, 0u);
+  for (int k = 0; k < kHistCopies; ++k) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(hist + k * kHistBins + t0);
+    h.x += v.x;
+    h.y += v.y;
+    h.z += v.z;
+    h.w += v.w;
+  }
+  const uint32_t hv[4] = {h.x, h.y, h.z, h.w};
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    c[q] = 0;
-#pragma unroll 8
-    for (int k = 0; k < kHistCopies; ++k) c[q] += (long long)hist[k * kHistBins + t0 + q];
+    c[q] = (long long)hv[q];
     sm[q] = c[q] * (long long)(t0 + q);
     lc += c[q];
     ls += sm[q];
