@@ -101,6 +101,44 @@ def test_detect_fixed_split_and_degenerate_flag():
     assert host(iface).sum() == 0
 
 
+def thin_layer_system(box, seed):
+    """A dense layer (density 0.8, z in [0.3, 0.6) of the box) in a gas of
+    density 0.05, uniform random positions."""
+    rng = np.random.default_rng(seed)
+    L = np.asarray(box, dtype=float)
+    dense = rng.uniform(0, 1, (int(0.8 * 0.3 * L.prod()), 3)) * [L[0], L[1], 0.3 * L[2]]
+    dense[:, 2] += 0.3 * L[2]
+    gas = rng.uniform(0, 1, (int(0.05 * L.prod()), 3)) * L
+    P = np.concatenate([dense, gas])
+    return P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy()
+
+
+# (1, 70, 9) and (70, 2, 33) voxels: the 27-window wraps onto the same voxels;
+# (130, 6, 65): x not a multiple of the 64-voxel column, z a partial chunk
+@pytest.mark.parametrize("box", [(3.0, 5.0, 40.0), (1.2, 70.0, 9.0), (70.0, 2.4, 33.0),
+                                 (130.0, 6.0, 65.0)])
+def test_detect_on_thin_and_ragged_grids(box):
+    print(f"[gpu] detect on a thin or ragged grid {box}", flush=True)
+    x, y, z = thin_layer_system(box, int(sum(box) * 10))
+    ref = oracle.detect_interface(x, y, z, box, 1.0)
+    grid = dcm.make_grid(box, 1.0)
+    nv = dcm.grid_voxels(grid)
+    assert list(grid.n) == list(ref["nv"])
+    counts = torch.zeros(nv, dtype=torch.uint32, device=DEV)
+    seg = torch.zeros(nv, dtype=torch.uint8, device=DEV)
+    iface = torch.zeros(nv, dtype=torch.uint8, device=DEV)
+    thr = torch.zeros(1, dtype=torch.int32, device=DEV)
+    with Ctx() as ctx:
+        dcm.dcm_detect_interface(ctx, dev(x), dev(y), dev(z), box, grid, seg, iface,
+                                 counts=counts, threshold_out=thr)
+        code = dcm.dcm_sync_status(ctx)
+    assert code == (dcm.DCM_ERR_DEGENERATE if ref["degenerate"] else dcm.DCM_OK)
+    np.testing.assert_array_equal(host(counts), ref["counts"])
+    assert int(host(thr)[0]) == ref["threshold"]
+    np.testing.assert_array_equal(host(seg), ref["seg"])
+    np.testing.assert_array_equal(host(iface), ref["iface"])
+
+
 @pytest.mark.parametrize("name", GRIDS)
 def test_sweep_distance_matches_fsm(name):
     print(f"[gpu] sweep {name}", flush=True)
