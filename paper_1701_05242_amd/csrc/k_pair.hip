@@ -29,9 +29,11 @@
 namespace dcm {
 
 constexpr int kPairBlock = 256;
-// Row ranges per lane per chunk (LDS: 8 B each): FP64-record kernels, and
-// compact-record kernels, whose cheaper candidates gain more from the higher
-// occupancy of a smaller list (measured on the large slab).
+// Row ranges per lane per chunk (LDS: 8 B each), for the kernels reading FP64
+// records and for those reading compact records.  A smaller list allows more
+// resident workgroups: the compact-record kernels, with cheaper candidates,
+// gain from that, while the FP64 kernels, bound by their gathers, lose
+// (measured on the large slab).
 #ifndef DCM_PAIR_SEGCAP
 #define DCM_PAIR_SEGCAP 24
 #endif
@@ -326,8 +328,8 @@ __device__ __forceinline__ float4 load_rel(__amdgpu_buffer_rsrc_t rs, int j) {
 // Separations are formed in FP32 between the two cell-centre-relative
 // positions, the candidate's cell k cells away: d = (a0 - k len) - rel.  A
 // pair whose FP32 r^2 lies within the lane's proven error band around rc^2 is
-// decided from its FP64 record instead (rare: the band is ~1e-5 sigma^2
-// wide).  The stream advances with selects, and two register sets take turns
+// decided from its FP64 record instead (rare: the band is 3e-5 to 2e-4
+// sigma^2 wide for cutoffs of 2.5 to 8 sigma).  The stream advances with selects, and two register sets take turns
 // so that every record is loaded a full candidate before its use.
 template <int EVM>
 __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int total,
