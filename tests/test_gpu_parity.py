@@ -241,6 +241,43 @@ def test_forces_independent_of_cell_edge_and_deterministic(edge):
     assert again["E"] == got["E"]
 
 
+@pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
+def test_evaluation_flags_do_not_change_results(prec):
+    """Pair counts, energy and virial are optional outputs: the compact-record
+    kernel counts pairs only when asked, and an energy-only call reduces only
+    the energy.  Forces must not depend on which outputs are asked for, and
+    each output must be the same bit for bit whichever others come with it."""
+    s = workloads.make("slab_medium")
+    rc = ref_detect("slab_medium")["rc"]
+    x, y, z, r = dev(s.x), dev(s.y), dev(s.z), dev(rc)
+    E, V, C = dcm.DCM_EV_ENERGY, dcm.DCM_EV_VIRIAL, dcm.DCM_EV_COUNTS
+    out = {}
+    with Ctx() as ctx:
+        # 1.25-sigma cells: FP32-mixed runs the compact-record kernel
+        dcm.dcm_build_cells(ctx, x, y, z, r, s.box, 1.25, prec, rc_bound=s.rule[1])
+        for flags in (0, E, E | V, E | C, V | C, E | V | C):
+            f = [torch.zeros(s.n, **F64) for _ in range(3)]
+            e = torch.zeros(1, **F64)
+            w = torch.zeros(6, **F64)
+            nn = torch.zeros(s.n, dtype=torch.int32, device=DEV)
+            npairs = torch.zeros(1, dtype=torch.uint64, device=DEV)
+            dcm.dcm_forces(ctx, dcm.make_lj(), *f, prec=prec, ev_flags=flags, energy=e, virial=w,
+                           nnbr=nn, npairs=npairs)
+            assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
+            out[flags] = (np.stack([host(t) for t in f], 1), float(host(e)[0]), host(w),
+                          host(nn), int(host(npairs)[0]))
+    full = out[E | V | C]
+    for flags, (F, e, w, nn, npairs) in out.items():
+        np.testing.assert_array_equal(F, full[0])
+        if flags & E:
+            assert e == full[1]
+        if flags & V:
+            np.testing.assert_array_equal(w, full[2])
+        if flags & C:
+            np.testing.assert_array_equal(nn, full[3])
+            assert npairs == full[4] == int(full[3].sum())
+
+
 def test_tiny_box_every_axis_wraps():
     """A box smaller than the cutoff stencil: every cell is visited once and the
     minimum image is taken per pair."""
