@@ -248,3 +248,29 @@ def test_batched_edge_cases():
             dcm.dcm_forces_batched(ctx, arr, lj, ev_flags=dcm.DCM_EV_ENERGY)
         assert err.value.code == dcm.DCM_ERR_INVALID
         assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
+
+
+@pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
+def test_batched_evaluation_flags_do_not_change_results(prec):
+    """As for single systems: each system's forces do not depend on which
+    outputs are asked for, and each output is the same bit for bit whichever
+    others come with it (the compact-record kernel counts pairs only when
+    asked)."""
+    systems = small_batch()
+    rcs = [oracle_rc("small", b) for b in range(len(systems))]
+    E, V, C = dcm.DCM_EV_ENERGY, dcm.DCM_EV_VIRIAL, dcm.DCM_EV_COUNTS
+    out = {}
+    for flags in (0, E, E | C, EV_ALL):
+        batch = device_batch(systems, rcs, edge=1.25)
+        with Ctx() as ctx:
+            dcm.dcm_forces_batched(ctx, batch, dcm.make_lj(), prec=prec, ev_flags=flags)
+            assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
+        out[flags] = [results(d) for d in batch]
+    for flags, res in out.items():
+        for r, full in zip(res, out[EV_ALL]):
+            np.testing.assert_array_equal(r["F"], full["F"])
+            if flags & E:
+                assert r["E"] == full["E"]
+            if flags & C:
+                np.testing.assert_array_equal(r["nnbr"], full["nnbr"])
+                assert r["npairs"] == full["npairs"] == int(full["nnbr"].sum())
