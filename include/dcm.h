@@ -285,7 +285,8 @@ dcm_status dcm_forces_list(dcm_ctx *ctx, dcm_lj lj, int prec, int ev_flags, doub
  * step does v += dt/(2m) F; x += dt v (wrapped); re-detect the interface and
  * re-sweep the distances when (step0 + s + 1) % redetect_every == 0 or no
  * distance field exists yet; re-assign cutoffs and rebuild cells (every
- * step); recompute F; v += dt/(2m) F.
+ * step; cell edge rc_min / 2, for DCM_FP32_MIXED at most 2 sigma so that the
+ * compact records apply); recompute F; v += dt/(2m) F.
  * energy_series (double [2*nsteps], optional): potential and kinetic energy
  * after each step.  delta/rc (double [n], optional) receive the last
  * distances and cutoffs. */

@@ -831,13 +831,17 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     for (int a = 0; a < 3; ++a) ctx->field_n[a] = grid.n[a];
     return DCM_OK;
   };
+  const double step_cell_edge =
+      prec == DCM_FP32_MIXED ? std::min(0.5 * rule.rc_min, kRelMaxEdgeSigma * lj.sigma)
+                             : 0.5 * rule.rc_min;
   // cutoffs, cells and forces of the working copies; the forces land in the
   // working order (the cells map sorted slots back to it)
   auto forces = [&](double *e_out) -> dcm_status {
     DCM_TRY(dcm_assign_cutoffs(ctx, W[WX], W[WY], W[WZ], n, box, grid, ptr<double>(ctx->dist),
                                rule, W[WDELTA], W[WRC]));
-    // small cells (Section 2.3): half the smallest cutoff
-    DCM_TRY(dcm_build_cells(ctx, W[WX], W[WY], W[WZ], W[WRC], n, box, 0.5 * rule.rc_min,
+    // small cells (Section 2.3): half the smallest cutoff, and for FP32-mixed
+    // forces at most the widest cell the compact records serve
+    DCM_TRY(dcm_build_cells(ctx, W[WX], W[WY], W[WZ], W[WRC], n, box, step_cell_edge,
                             rule.rc_max, prec, nullptr, nullptr));
     return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, W[WFX], W[WFY], W[WFZ],
                       e_out ? e_out : scal, nullptr, nullptr, nullptr);
