@@ -25,7 +25,11 @@
  *   (energies, virials, counters) are device scalars.  No call synchronises
  *   the stream except dcm_sync_status, dcm_create, dcm_destroy,
  *   dcm_build_list and dcm_update_list (they read a size or a verdict back),
- *   and dcm_forces_batched when it tunes the cell edge of a new batch.
+ *   dcm_forces_batched when it tunes the cell edge of a new batch, and
+ *   dcm_build_cells (and dcm_step through it) the first time it meets a cell
+ *   geometry, when it reads its ghost-image count back to size the image
+ *   buffer; a later build of the same geometry waits only for the previous
+ *   build's count.
  * - Scratch memory (grid buffers, cells, sorted copies, partial sums) is owned
  *   by the context and grown on demand; growing it allocates device memory,
  *   so call each entry point once with its largest sizes before capturing it
@@ -83,7 +87,9 @@ typedef struct { int32_t n[3]; double h[3]; } dcm_grid;
  * most 2 sigma wide, separations and r^2 are FP32 too, from 16-byte
  * cell-relative records; a pair whose FP32 r^2 lies within a proven error
  * band of rc^2 is decided in FP64, so the pairs included are exactly those
- * of DCM_FP64.  Otherwise the separations and r^2 are FP64. */
+ * of DCM_FP64.  Otherwise the separations and r^2 are FP64.  Close pairs
+ * (r < 1.1 sigma), whose large forces would carry most of the FP32 rounding,
+ * are evaluated in FP64 throughout. */
 enum { DCM_FP64 = 0, DCM_FP32_MIXED = 1 };
 
 /* Which pairs interact.
@@ -126,6 +132,16 @@ const char *dcm_last_error(const dcm_ctx *ctx);
 /* Host helper: grid with n[a] = max(1, round(L_a/h)) and h[a] = L_a/n[a]
  * (the voxel edge h is chosen once per run, Section 2.1 footnote 2). */
 dcm_status dcm_make_grid(dcm_box box, double h, dcm_grid *out);
+
+/* Host helper: the distance r_c^grid up to which dcm_sweep_distance should
+ * propagate (Section 2.2, Algorithm 2.1 and its footnote on r_c^grid): the
+ * cutoff ramp plus three of the largest voxel edges, rule.ramp + 3 max_a
+ * grid.h[a].  Beyond `ramp` every particle gets rc_min whatever its distance,
+ * and the discrete distance changes by at most one voxel edge per face step,
+ * so capping the field there leaves every cutoff unchanged.  *out receives
+ * it; DCM_ERR_INVALID for a null out, a non-positive or non-finite ramp or
+ * voxel edge. */
+dcm_status dcm_rc_grid(dcm_rule rule, dcm_grid grid, double *out);
 
 /* ------------------------------------------------------------- hot path */
 
@@ -289,7 +305,10 @@ dcm_status dcm_forces_list(dcm_ctx *ctx, dcm_lj lj, int prec, int ev_flags, doub
  * compact records apply); recompute F; v += dt/(2m) F.
  * energy_series (double [2*nsteps], optional): potential and kinetic energy
  * after each step.  delta/rc (double [n], optional) receive the last
- * distances and cutoffs. */
+ * distances and cutoffs.  The context keeps the last distance field between
+ * calls; a call with nsteps > 0 reuses it until its first re-detection only
+ * when n, box, grid and rc_grid equal those it was computed for (continue a
+ * run with step0 = the steps done so far). */
 dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,
                     double *vz, double *fx, double *fy, double *fz, int64_t n, double mass,
                     dcm_box box, dcm_lj lj, dcm_rule rule, dcm_grid grid, double rc_grid,

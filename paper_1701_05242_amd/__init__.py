@@ -97,6 +97,7 @@ SIGNATURES = {
     "dcm_last_error": [_P],
     "dcm_make_grid": [dcm_box, _F64, ctypes.POINTER(dcm_grid)],
     "dcm_detect_interface": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid, _F64, _P, _P, _P, _P],
+    "dcm_rc_grid": [dcm_rule, dcm_grid, ctypes.POINTER(_F64)],
     "dcm_detect_interface_opts": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid,
                                   ctypes.POINTER(dcm_detect_opts), _P, _P, _P, _P],
     "dcm_sweep_distance": [_P, _P, _P, dcm_grid, _F64, _I32, _P, _P],
@@ -401,7 +402,11 @@ def dcm_kernel_time(ctx, family: str):
     return float(ms.value), int(cnt.value)
 
 
-def rc_grid_for(rule: dcm_rule, grid: dcm_grid) -> float:
-    """Distance up to which the sweep propagates: the ramp plus three voxels
-    (beyond the ramp every particle gets rc_min anyway)."""
-    return float(rule.ramp) + 3.0 * max(float(grid.h[a]) for a in range(3))
+def dcm_rc_grid(rule: dcm_rule, grid: dcm_grid) -> float:
+    """Distance up to which the sweep propagates (the library's dcm_rc_grid)."""
+    out = ctypes.c_double()
+    _check(None, load_library().dcm_rc_grid(rule, grid, ctypes.byref(out)))
+    return float(out.value)
+
+
+rc_grid_for = dcm_rc_grid

@@ -142,6 +142,14 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
     return DCM_ERR_NOMEM;
   }
   ctx->h_status = static_cast<uint32_t *>(p);
+  if (hipEventCreateWithFlags(&ctx->ext_event, hipEventDisableTiming) != hipSuccess) {
+    hipGetLastError();
+    hipFree(ctx->d_status);
+    hipFree(ctx->ctl);
+    hipHostFree(ctx->h_status);
+    delete ctx;
+    return DCM_ERR_HIP;
+  }
   ctx->h_ext_total = reinterpret_cast<int32_t *>(static_cast<char *>(p) + 8);
   *ctx->h_ext_total = 0;
   ctx->h_list_total = reinterpret_cast<int32_t *>(static_cast<char *>(p) + 16);
@@ -151,6 +159,7 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
   dcm_status st = check_launch(ctx, "dcm_create");
   if (st == DCM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = DCM_ERR_HIP;
   if (st != DCM_OK) {
+    hipEventDestroy(ctx->ext_event);
     hipFree(ctx->d_status);
     hipFree(ctx->ctl);
     hipHostFree(ctx->h_status);
@@ -171,6 +180,7 @@ dcm_status dcm_destroy(dcm_ctx *ctx) {
       hipEventDestroy(pr.first);
       hipEventDestroy(pr.second);
     }
+  hipEventDestroy(ctx->ext_event);
   hipFree(ctx->d_status);
   hipFree(ctx->ctl);
   hipHostFree(ctx->h_status);
@@ -222,6 +232,17 @@ dcm_status dcm_make_grid(dcm_box box, double h, dcm_grid *out) {
     out->n[a] = k;
     out->h[a] = box.L[a] / (double)k;
   }
+  return DCM_OK;
+}
+
+dcm_status dcm_rc_grid(dcm_rule rule, dcm_grid grid, double *out) {
+  if (!out || !finite_pos(rule.ramp)) return DCM_ERR_INVALID;
+  double hmax = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    if (!finite_pos(grid.h[a])) return DCM_ERR_INVALID;
+    hmax = std::max(hmax, grid.h[a]);
+  }
+  *out = rule.ramp + 3.0 * hmax;
   return DCM_OK;
 }
 
@@ -414,14 +435,32 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
     uniform *= (double)ne / (double)nc[a];
     hard *= 1.0 + 2.0 * std::ceil((double)halo[a] / (double)nc[a]);
   }
-  // ghost-extended particle capacity: the uniform-density count with
-  // headroom, capped by the most any arrangement can need, and grown from
-  // the exact count of an earlier build
-  double want = std::min(1.5 * uniform * (double)n + 4096.0, hard * (double)n + 64.0);
-  want = std::max(want, 1.25 * (double)*ctx->h_ext_total);
-  if (want > (double)kMaxExtSlots)
-    return fail(ctx, DCM_ERR_RANGE, "ghost-extended system too large");
-  const int64_t ext_cap = std::max<int64_t>((int64_t)want, ctx->ext_cap);
+  // ghost-extended particle capacity, sized from a synchronised count: the
+  // exact count of the previous build of the same cell geometry (its copy
+  // has completed once ext_event has, so a caller queuing many builds waits
+  // for at most the previous one) with 25% headroom for particles moving
+  // between builds, else this build's own count, read back before the
+  // images are written.  A stream being captured into a graph cannot wait:
+  // it keeps the uniform-density estimate, the overflow is flagged.
+  hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(ctx->stream, &capture) != hipSuccess) {
+    hipGetLastError();
+    capture = hipStreamCaptureStatusNone;
+  }
+  const bool capturing = capture != hipStreamCaptureStatusNone;
+  const int64_t key[7] = {nc[0], nc[1], nc[2], halo[0], halo[1], halo[2], n};
+  const bool same_geom = std::equal(key, key + 7, ctx->ext_key);
+  if (ctx->ext_copy_pending && !capturing) {
+    if (hipEventSynchronize(ctx->ext_event) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_build_cells: ghost count read-back failed");
+    ctx->ext_copy_pending = false;
+    ctx->ext_exact = *ctx->h_ext_total;
+  }
+  const double max_need = hard * (double)n + 64.0;  // the most any arrangement needs
+  const bool known = same_geom && ctx->ext_exact >= 0 && !ctx->ext_copy_pending;
+  double want = known ? std::min(1.25 * (double)ctx->ext_exact + 4096.0, max_need)
+                      : std::min(1.5 * uniform * (double)n + 4096.0, max_need);
+  if (want > (double)kMaxExtSlots) want = (double)kMaxExtSlots;
   DCM_TRY(ensure(ctx, ctx->rcmax_part, cell_count_blocks(n) * sizeof(unsigned long long)));
   const int64_t nrow1 = ext_row_scratch_elems(nc, halo);
   DCM_TRY(ensure(ctx, ctx->ext_row_count, nrow1 * sizeof(int32_t)));
@@ -429,11 +468,8 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   DCM_TRY(ensure(ctx, ctx->ext_row_lo, nrow1 * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->ext_start, (next + 1) * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_elems(std::max(ncell, nrow1)) * sizeof(int32_t)));
-  DCM_TRY(ensure(ctx, ctx->ext_pos, ext_cap * sizeof(double4)));
   // FP32-mixed builds also write the compact records the pair kernel reads
   const bool rel = prec == DCM_FP32_MIXED && halo[1] <= kRelMaxHalo && halo[2] <= kRelMaxHalo;
-  if (rel) DCM_TRY(ensure(ctx, ctx->ext_rel, ext_cap * sizeof(float4)));
-  ctx->ext_cap = ext_cap;
   hipStream_t s = ctx->stream;
   hipEvent_t ev;
   timer_begin(ctx, "cells", &ev);
@@ -449,14 +485,38 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
                    ptr<int32_t>(ctx->sort_tmp), ptr<int32_t>(ctx->sort_list), &ctx->ctl->big_cells);
   launch_gather(s, x, y, z, rc, ptr<int32_t>(ctx->perm), n, box.L, rc_cap,
                 ptr<double4>(ctx->sorted));
-  launch_ext_build(s, ptr<int32_t>(ctx->cell_start), ptr<double4>(ctx->sorted), nc, halo, box.L,
-                   ext_cap, ptr<int32_t>(ctx->ext_row_count), ptr<int32_t>(ctx->ext_row_start),
+  launch_ext_count(s, ptr<int32_t>(ctx->cell_start), nc, halo, box.L,
+                   ptr<int32_t>(ctx->ext_row_count), ptr<int32_t>(ctx->ext_row_start),
                    ptr<int32_t>(ctx->ext_row_lo), ptr<int32_t>(ctx->ext_start),
-                   ptr<int32_t>(ctx->scan_tmp), ptr<double4>(ctx->ext_pos),
-                   rel ? ptr<float4>(ctx->ext_rel) : nullptr, nullptr, ctx->d_status);
-  // exact ghost-extended count, read by a later build to size the buffer
-  hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
-                 hipMemcpyDeviceToHost, s);
+                   ptr<int32_t>(ctx->scan_tmp));
+  if (!known && !capturing) {
+    // a new geometry: this build's exact count sizes the buffers
+    if (hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_build_cells: ghost count read-back failed");
+    ctx->ext_exact = *ctx->h_ext_total;
+    want = std::min(1.25 * (double)ctx->ext_exact + 4096.0, std::max(max_need, 1.0));
+    if (want > (double)kMaxExtSlots) want = (double)kMaxExtSlots;
+  }
+  if (!capturing && ctx->ext_exact > kMaxExtSlots)
+    return fail(ctx, DCM_ERR_RANGE, "ghost-extended system too large");
+  const int64_t ext_cap = std::max<int64_t>((int64_t)want, ctx->ext_cap);
+  DCM_TRY(ensure(ctx, ctx->ext_pos, ext_cap * sizeof(double4)));
+  if (rel) DCM_TRY(ensure(ctx, ctx->ext_rel, ext_cap * sizeof(float4)));
+  ctx->ext_cap = ext_cap;
+  launch_ext_images(s, ptr<int32_t>(ctx->cell_start), ptr<int32_t>(ctx->ext_row_start),
+                    ptr<int32_t>(ctx->ext_row_lo), ptr<double4>(ctx->sorted), nc, halo, box.L,
+                    ext_cap, ptr<double4>(ctx->ext_pos), rel ? ptr<float4>(ctx->ext_rel) : nullptr,
+                    ctx->d_status);
+  // exact ghost-extended count, read by the next build of this geometry
+  std::copy(key, key + 7, ctx->ext_key);
+  if (!capturing) {
+    hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
+                   hipMemcpyDeviceToHost, s);
+    hipEventRecord(ctx->ext_event, s);
+    ctx->ext_copy_pending = true;
+  }
   if (cell_start)
     hipMemcpyAsync(cell_start, ctx->cell_start.p, (ncell + 1) * sizeof(int32_t),
                    hipMemcpyDeviceToDevice, s);
@@ -759,9 +819,13 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     DCM_TRY(ensure(ctx, ctx->ws[b], (size_t)WFIELDS * nn * sizeof(double)));
     DCM_TRY(ensure(ctx, ctx->ws_owner[b], nn * sizeof(int32_t)));
   }
-  if (ctx->field_n[0] != grid.n[0] || ctx->field_n[1] != grid.n[1] ||
-      ctx->field_n[2] != grid.n[2])
-    ctx->have_field = false;
+  // a distance field from an earlier call is reused only for the same grid,
+  // box, sweep limit and particle count
+  for (int a = 0; a < 3; ++a)
+    if (ctx->field_n[a] != grid.n[a] || ctx->field_h[a] != grid.h[a] ||
+        ctx->field_L[a] != box.L[a])
+      ctx->have_field = false;
+  if (ctx->field_rc_grid != rc_grid || ctx->field_particles != n) ctx->have_field = false;
   hipStream_t s = ctx->stream;
   int cur = 0;
   auto field = [&](int set, int k) { return ptr<double>(ctx->ws[set]) + (int64_t)k * nn; };
@@ -828,7 +892,13 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     DCM_TRY(dcm_sweep_distance(ctx, ptr<uint8_t>(ctx->seg), ptr<uint8_t>(ctx->iface), grid,
                                rc_grid, max_waves, ptr<double>(ctx->dist), nullptr));
     ctx->have_field = true;
-    for (int a = 0; a < 3; ++a) ctx->field_n[a] = grid.n[a];
+    for (int a = 0; a < 3; ++a) {
+      ctx->field_n[a] = grid.n[a];
+      ctx->field_h[a] = grid.h[a];
+      ctx->field_L[a] = box.L[a];
+    }
+    ctx->field_rc_grid = rc_grid;
+    ctx->field_particles = n;
     return DCM_OK;
   };
   const double step_cell_edge =

@@ -152,6 +152,12 @@ struct dcm_ctx {
   dcm::DevBuf n3_f, n3_cnt;  // Newton's-third-law forces and counts in sorted order
   int64_t ext_cap = 0;             // particles ext_pos can hold
   int32_t *h_ext_total = nullptr;  // pinned: ghost-extended count of the last build
+  // the copy into h_ext_total completes with ext_event; the count is kept for
+  // the next build of the same cell geometry (ext_key: cells, halo, n)
+  hipEvent_t ext_event = nullptr;
+  bool ext_copy_pending = false;
+  int64_t ext_key[7] = {-1, -1, -1, -1, -1, -1, -1};
+  int64_t ext_exact = -1;  // synchronised count of the last build with ext_key
   int32_t nc[3] = {0, 0, 0};
   int32_t halo[3] = {0, 0, 0};
   double rc_bound = 0.0;
@@ -164,9 +170,12 @@ struct dcm_ctx {
   // dcm_step's working copies in cell order: two sets of 11 fields (x y z,
   // vx vy vz, fx fy fz, delta, rc) and the caller index of each slot
   dcm::DevBuf ws[2], ws_owner[2];
-  // last distance field kept for dcm_step
+  // last distance field kept for dcm_step, with what it was computed for
   bool have_field = false;
   int32_t field_n[3] = {0, 0, 0};
+  double field_h[3] = {0, 0, 0}, field_L[3] = {0, 0, 0};
+  double field_rc_grid = 0.0;
+  int64_t field_particles = -1;
   // batched form: plan, buffers and recorded graph
   dcm::BatchState *batch = nullptr;
   // profiling
@@ -258,11 +267,17 @@ void launch_gather(hipStream_t s, const double *x, const double *y, const double
                    double rc_cap, double4 *sorted);
 // rows of the extended grid + 1: the size of each per-row scratch array
 int64_t ext_row_scratch_elems(const int32_t nc[3], const int32_t h[3]);
-void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
-                      const int32_t nc[3], const int32_t h[3], const double L[3],
-                      int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
-                      int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
-                      int32_t *ext_src, uint32_t *status);
+// ghost-extended cells in two parts: the per-row tables and the extended
+// cell starts (ext_start[next] then holds the extended particle count), and
+// the images themselves into buffers of ext_cap slots
+void launch_ext_count(hipStream_t s, const int32_t *cell_start, const int32_t nc[3],
+                      const int32_t h[3], const double L[3], int32_t *row_count,
+                      int32_t *row_start, int32_t *row_lo, int32_t *ext_start,
+                      int32_t *scan_tmp);
+void launch_ext_images(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
+                       const int32_t *row_lo, const double4 *sorted, const int32_t nc[3],
+                       const int32_t h[3], const double L[3], int64_t ext_cap, double4 *ext_pos,
+                       float4 *ext_rel, uint32_t *status);
 // source sorted slot of every extended slot of the last build (row tables)
 void launch_ext_src(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
                     const int32_t *row_lo, const int32_t nc[3], const int32_t h[3],

@@ -616,11 +616,10 @@ void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *
                   nullptr, nullptr, status);
 }
 
-void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *sorted,
-                      const int32_t nc[3], const int32_t h[3], const double L[3],
-                      int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
-                      int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
-                      int32_t *ext_src, uint32_t *status) {
+void launch_ext_count(hipStream_t s, const int32_t *cell_start, const int32_t nc[3],
+                      const int32_t h[3], const double L[3], int32_t *row_count,
+                      int32_t *row_start, int32_t *row_lo, int32_t *ext_start,
+                      int32_t *scan_tmp) {
   const ExtGeom g = ext_geom(nc, h, L);
   const int64_t next = (int64_t)g.ne[0] * g.ne[1] * g.ne[2];
   const int64_t nrows = (int64_t)g.ne[1] * g.ne[2];
@@ -634,8 +633,14 @@ void launch_ext_build(hipStream_t s, const int32_t *cell_start, const double4 *s
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_ext_starts, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
                      row_lo, g, next, nrows, ext_start);
-  launch_ext_fill(s, cell_start, row_start, row_lo, sorted, g, ext_cap, ext_pos, ext_rel, ext_src,
-                  status);
+}
+
+void launch_ext_images(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
+                       const int32_t *row_lo, const double4 *sorted, const int32_t nc[3],
+                       const int32_t h[3], const double L[3], int64_t ext_cap, double4 *ext_pos,
+                       float4 *ext_rel, uint32_t *status) {
+  launch_ext_fill(s, cell_start, row_start, row_lo, sorted, ext_geom(nc, h, L), ext_cap, ext_pos,
+                  ext_rel, nullptr, status);
 }
 
 }  // namespace dcm

@@ -21,7 +21,10 @@
 // Precisions: FP64 records (32 B per candidate); for FP32-mixed own-cutoff
 // forces on narrow cells, 16-byte cell-relative records with FP32
 // separations, the pairs inside a proven error band of the cutoff decided
-// from the FP64 record.  Also here: forces over a stored Verlet list, the
+// from the FP64 record.  FP32-mixed evaluates close pairs (r < 1.1 sigma)
+// in FP64 from the FP64 record: their forces are the largest and the
+// r^-14 dependence multiplies every relative rounding of r^2 and 1/r^2
+// by about 7, so in FP32 they alone would set the worst particle's error.  Also here: forces over a stored Verlet list, the
 // persistent batched form, and the fixed-order reduction of block partials.
 #include "dcm_device.hpp"
 #include "dcm_internal.hpp"
@@ -73,6 +76,14 @@ struct Acc<DCM_FP32_MIXED> {
   float e = 0, w[6] = {0, 0, 0, 0, 0, 0};
 };
 
+// FP32-mixed evaluates a pair with r^2 < kNear2 sigma^2 in FP64.  A relative
+// error e of an FP32 separation or of 1/r^2 becomes ~13 e or ~7 e in the pair
+// force, and at r < 1.1 sigma that force is up to ~60 times the RMS particle
+// force of a dense liquid (F(0.85 sigma) ~ 320 eps/sigma), so FP32 rounding
+// of these few pairs (well under 1% of the interacting pairs) would dominate
+// the largest per-particle error measured in units of the RMS force.
+constexpr double kNear2 = 1.21;
+
 // 1/r2 from the hardware reciprocal estimate refined by Newton steps
 // y <- y + y (1 - r2 y): two steps for FP64, one before rounding to FP32.
 __device__ __forceinline__ double recip_newton2(double r2) {
@@ -87,6 +98,32 @@ __device__ __forceinline__ float recip_to_f32(double r2) {
   double y = __builtin_amdgcn_rcp(r2);
   double e = fma(-r2, y, 1.0);
   return (float)fma(y, e, y);
+}
+
+// A close pair of the FP32-mixed kernels in FP64 arithmetic (from an FP64
+// separation): FP64 force sums, the energy and virial terms rounded once into
+// the FP32 accumulators.  Returns the force factor.
+template <int EVM>
+__device__ __forceinline__ double interact_exact(Acc<DCM_FP32_MIXED> &acc, double dx, double dy,
+                                                 double dz, double r2, double sig2) {
+  const double r2i = recip_newton2(r2);
+  const double s2 = sig2 * r2i;
+  const double s6 = s2 * s2 * s2;
+  const double fp = s6 * fma(2.0, s6, -1.0) * r2i;
+  acc.fx = fma(fp, dx, acc.fx);
+  acc.fy = fma(fp, dy, acc.fy);
+  acc.fz = fma(fp, dz, acc.fz);
+  if constexpr ((EVM & 1) != 0) acc.e += (float)(s6 * (s6 - 1.0));
+  if constexpr ((EVM & 2) != 0) {
+    const double fdx = fp * dx, fdy = fp * dy, fdz = fp * dz;
+    acc.w[0] += (float)(fdx * dx);
+    acc.w[1] += (float)(fdy * dy);
+    acc.w[2] += (float)(fdz * dz);
+    acc.w[3] += (float)(fdy * dx);
+    acc.w[4] += (float)(fdz * dx);
+    acc.w[5] += (float)(fdz * dy);
+  }
+  return fp;
 }
 
 // One interacting pair with separation d (FP64) and r2.  The force factor
@@ -115,6 +152,7 @@ __device__ __forceinline__ double interact(Acc<PREC> &acc, double dx, double dy,
     }
     return fp;
   } else {
+    if (r2 < kNear2 * sig2) return interact_exact<EVM>(acc, dx, dy, dz, r2, sig2);
     float r2i = recip_to_f32(r2);
     float s2 = (float)sig2 * r2i;
     float s6 = s2 * s2 * s2;
@@ -241,6 +279,10 @@ struct LaneGeo {
   // the cell's x index + 1/2 (wc), rc^2 and the band around it within which
   // an FP32 r^2 cannot decide a pair
   float a0x, a0y, a0z, lenf[3], invf[3], fR2, fguard, wc, rc2f, margin;
+  // compact records: FP32 r^2 below which a pair is evaluated in FP64, and
+  // sigma^2 for that evaluation
+  float near2f;
+  double sig2;
   int zlo, zhi, cx, cy, cz, self;
   int slot;  // sorted slot of the lane's particle
 };
@@ -358,17 +400,18 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int to
     const float az = fmaf(-(float)dzc, g.lenf[2], g.a0z);
     float dx = fmaf(-(r.w - g.wc), g.lenf[0], g.a0x) - r.x;
     float dy = ay - r.y, dz = az - r.z;
-    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     bool inc = r2 < g.rc2f;
-    if (fabsf(r2 - g.rc2f) <= g.margin) {
+    if (fabsf(r2 - g.rc2f) <= g.margin || r2 < g.near2f) {
+      // rare: a pair too close to rc^2 for the FP32 test, or a close pair,
+      // is decided and evaluated in FP64 from its FP64 record
       const double4 q = ext_pos[jr];
       const double ex = g.xi - q.x, ey = g.yi - q.y, ez = g.zi - q.z;
       const double e2 = (ex * ex + ey * ey) + ez * ez;
-      inc = e2 < g.rci2;
-      dx = (float)ex;
-      dy = (float)ey;
-      dz = (float)ez;
-      r2 = (float)e2;
+      const bool in64 = e2 < g.rci2;
+      if (in64) interact_exact<EVM>(acc, ex, ey, ez, e2, g.sig2);
+      if constexpr ((EVM & 4) != 0) cnt += in64 ? 1 : 0;
+      inc = false;
     }
     interact_rel<EVM>(acc, dx, dy, dz, r2, sig2, inc);
     if constexpr ((EVM & 4) != 0) cnt += inc ? 1 : 0;
@@ -616,6 +659,10 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   LaneGeo g;
   g.xi = g.yi = g.zi = g.rci = g.rci2 = 0.0;
   g.a0x = g.a0y = g.a0z = g.wc = g.rc2f = g.margin = g.fR2 = g.fguard = 0.0f;
+  // the FP32 r^2 of a pair at most a few ulps off: evaluating a pair just
+  // past the threshold in FP64 as well costs nothing in accuracy
+  g.near2f = (float)(kNear2 * sig2);
+  g.sig2 = sig2;
   g.lenf[0] = g.lenf[1] = g.lenf[2] = 0.0f;
   g.invf[0] = g.invf[1] = g.invf[2] = 0.0f;
   g.cx = 0;

@@ -53,6 +53,23 @@ def test_make_grid_rounds_box_over_h(lib):
         dcm.make_grid((1.0, 1.0, 1.0), 0.0)
 
 
+def test_rc_grid_is_the_ramp_plus_three_voxels(lib):
+    """dcm_rc_grid (a host helper, no device) gives the sweep limit the
+    oracle uses, and refuses a bad rule or grid."""
+    import oracle
+    import paper_1701_05242_amd as dcm
+    g = dcm.make_grid((13.4, 13.4, 60.0), 1.0)
+    rule = dcm.make_rule(2.5, 6.0, 5.0)
+    assert dcm.dcm_rc_grid(rule, g) == oracle.rc_grid_for((2.5, 6.0, 5.0), list(g.h))
+    assert dcm.dcm_rc_grid(rule, g) == 5.0 + 3.0 * (13.4 / 13)
+    with pytest.raises(dcm.DcmError):
+        dcm.dcm_rc_grid(dcm.make_rule(2.5, 6.0, 0.0), g)
+    bad = dcm.dcm_grid()
+    with pytest.raises(dcm.DcmError):
+        dcm.dcm_rc_grid(rule, bad)
+    assert lib.dcm_rc_grid(rule, g, None) == dcm.DCM_ERR_INVALID
+
+
 def test_null_context_is_rejected_before_any_device_call(lib):
     import paper_1701_05242_amd as dcm
     box = dcm.dcm_box((ctypes.c_double * 3)(1.0, 1.0, 1.0))

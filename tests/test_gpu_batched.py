@@ -197,6 +197,38 @@ def test_batched_full_size_sampled():
     assert worst <= 1e-5, worst
 
 
+def test_batched_full_size_fp32_mixed_every_particle():
+    """The 64-system batch in the benchmark's form (FP32-mixed, tuned edge,
+    recorded graph) against the FP64 batch at the same edge, every particle
+    of every system: force errors in units of each system's RMS force,
+    identical neighbour counts, energy and virial within 1e-5."""
+    print("[gpu] batched full size, FP32-mixed vs FP64 on every particle", flush=True)
+    systems = full_batch()
+    rcs = [oracle_rc("full", b) for b in range(len(systems))]
+    b32 = device_batch(systems, rcs, edge=0.0)
+    with Ctx() as ctx:
+        dcm.dcm_forces_batched(ctx, b32, dcm.make_lj(), prec=dcm.DCM_FP32_MIXED,
+                               ev_flags=EV_ALL, use_graph=True)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
+        edge = dcm.dcm_batched_edge(ctx)
+    b64 = device_batch(systems, rcs, edge=edge)
+    with Ctx() as ctx:
+        dcm.dcm_forces_batched(ctx, b64, dcm.make_lj(), prec=dcm.DCM_FP64, ev_flags=EV_ALL)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
+    worst = [0.0, 0.0, 0.0]
+    for b, (d32, d64) in enumerate(zip(b32, b64)):
+        g32, g64 = results(d32), results(d64)
+        np.testing.assert_array_equal(g32["nnbr"], g64["nnbr"])
+        assert g32["npairs"] == g64["npairs"]
+        errs = force_errors(g32["F"], g64["F"], detail=True)
+        worst = [max(w, e) for w, e in zip(worst, errs)]
+        assert max(errs) <= 1e-5, (b, errs)
+        assert abs(g32["E"] - g64["E"]) <= 1e-5 * abs(g64["E"]), b
+        assert rel(g32["W"], g64["W"]) <= 1e-5, b
+    print(f"[gpu]   worst system: err_max={worst[0]:.3e} err_rms={worst[1]:.3e} "
+          f"floored={worst[2]:.3e}", flush=True)
+
+
 def test_batched_edge_cases():
     """Empty batch; empty, one- and two-particle systems next to a normal one;
     a cutoff above its system's bound; invalid descriptors."""

@@ -70,8 +70,11 @@ def test_n3_against_the_plain_max_rule(edge):
     b = gpu_forces(s, rc, rule=N3, edge=edge)
     np.testing.assert_array_equal(a["nnbr"], b["nnbr"])
     assert a["npairs"] == b["npairs"]
-    emax, _ = force_errors(b["F"], a["F"])
-    assert emax <= 1e-13
+    # the same FP64 pair terms summed in another order (reactions arrive by
+    # atomics): the worst particle, whose force is ~60 F_rms, differs by a few
+    # ulps of its own force, i.e. ~3e-13 F_rms -- within the FP64 bar
+    emax, erms = force_errors(b["F"], a["F"])
+    assert emax <= 1e-12 and erms <= 1e-13
     assert abs(a["E"] - b["E"]) <= 1e-13 * abs(a["E"])
     assert rel(b["W"], a["W"]) <= 1e-13
     # Newton's third law: the reactions cancel the actions

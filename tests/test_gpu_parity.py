@@ -218,11 +218,54 @@ def test_forces_match_oracle(name, rule, prec):
     np.testing.assert_array_equal(got["nnbr"], ref["nnbr"])
     assert got["npairs"] == int(ref["nnbr"].sum())
     tol = 1e-12 if prec == dcm.DCM_FP64 else 1e-5
-    emax, erms, eabs = force_errors(got["F"], _ref_F(ref), detail=True)
-    print(f"[gpu]   err_max={emax:.3e} err_rms={erms:.3e} max/F_rms={eabs:.3e}", flush=True)
-    assert emax <= tol and erms <= tol
+    emax, erms, efloor = force_errors(got["F"], _ref_F(ref), detail=True)
+    print(f"[gpu]   err_max={emax:.3e} err_rms={erms:.3e} floored={efloor:.3e}", flush=True)
+    assert emax <= tol and erms <= tol and efloor <= tol
     assert abs(got["E"] - ref["E"]) <= tol * abs(ref["E"])
     assert rel(got["W"], ref["W"]) <= tol
+
+
+def corner_blob(shift=0.0):
+    """A dense cube of 1,000 particles (jittered unit lattice) centred on the
+    corner of a 40-sigma periodic box: every particle lies within the ghost
+    halo of all three axes, so each has seven periodic images -- far more
+    than a uniform-density estimate of the ghost count allows."""
+    rng = np.random.default_rng(np.random.PCG64(2024))
+    g = np.arange(10) - 4.5
+    pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pts = pts + rng.uniform(-0.1, 0.1, pts.shape) + shift
+    pts = np.mod(pts, 40.0)
+    n = len(pts)
+    z0 = np.zeros(n)
+    return workloads.System(name="corner_blob", x=pts[:, 0].copy(), y=pts[:, 1].copy(),
+                            z=pts[:, 2].copy(), vx=z0, vy=z0, vz=z0, box=(40.0, 40.0, 40.0),
+                            rule=(3.0, 3.0, 1.0))
+
+
+@pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
+def test_ghost_images_of_a_dense_corner(prec):
+    """The ghost-image buffer is sized from the build's exact image count
+    (about 8 N here), both on a context's first build and on a later build of
+    the same geometry after the particles moved: no overflow, forces and
+    counts as the oracle's."""
+    print(f"[gpu] dense periodic corner prec={prec}", flush=True)
+    tol = 1e-12 if prec == dcm.DCM_FP64 else 1e-5
+    lj = dcm.make_lj()
+    with Ctx() as ctx:
+        for shift in (0.0, 0.3):
+            s = corner_blob(shift)
+            rc = np.full(s.n, 3.0)
+            fx, fy, fz = (torch.zeros(s.n, **F64) for _ in range(3))
+            nn = torch.zeros(s.n, dtype=torch.int32, device=DEV)
+            dcm.dcm_build_cells(ctx, dev(s.x), dev(s.y), dev(s.z), dev(rc), s.box, 1.25, prec,
+                                rc_bound=3.0)
+            dcm.dcm_forces(ctx, lj, fx, fy, fz, prec=prec, ev_flags=dcm.DCM_EV_COUNTS, nnbr=nn)
+            assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
+            ref = oracle.forces(s.x, s.y, s.z, rc, s.box)
+            np.testing.assert_array_equal(host(nn), ref["nnbr"])
+            F = np.stack([host(fx), host(fy), host(fz)], 1)
+            emax, erms = force_errors(F, _ref_F(ref))
+            assert emax <= tol and erms <= tol, (shift, emax, erms)
 
 
 # 7.0: one cell across x and y (13.4 sigma), so the halo of two cells is
@@ -578,14 +621,9 @@ def test_step_without_energy_series_repeats_the_recorded_run(prec):
     np.testing.assert_array_equal(out[0], out[1])
 
 
-def test_large_slab_sampled_parity():
-    """The large slab in the benchmark's configuration (FP32-mixed, automatic
-    cells): every cutoff bit-exact, forces on a seeded sample of particles
-    against the oracle's per-particle O(N) sums."""
-    name = "slab_large"
-    print("[gpu] large slab sampled parity", flush=True)
-    s = workloads.make(name)
-    ref_d = ref_detect(name)
+def step_forces(s, prec):
+    """dcm_step with nsteps = 0 (detection, distances, cutoffs, cells of
+    r_c^min/2, forces) from the generator's positions: forces and cutoffs."""
     grid = dcm.make_grid(s.box, s.h)
     rule = dcm.make_rule(*s.rule)
     f = [torch.zeros(s.n, **F64) for _ in range(3)]
@@ -593,20 +631,70 @@ def test_large_slab_sampled_parity():
     rc = torch.zeros(s.n, **F64)
     with Ctx() as ctx:
         dcm.dcm_step(ctx, dev(s.x), dev(s.y), dev(s.z), *v, *f, s.box, dcm.make_lj(), rule, grid,
-                     dcm.rc_grid_for(rule, grid), dt=0.005, nsteps=0, prec=dcm.DCM_FP32_MIXED,
-                     rc=rc)
+                     dcm.dcm_rc_grid(rule, grid), dt=0.005, nsteps=0, prec=prec, rc=rc)
         assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
-    np.testing.assert_allclose(host(rc), ref_d["rc"], rtol=1e-12, atol=0)
+    return np.stack([host(t) for t in f], 1), host(rc)
+
+
+def test_large_slab_parity_and_full_population_accuracy():
+    """The large slab (2.6 M particles) in the benchmark's configuration.
+    Cutoffs against the oracle's (FP64 distance fixed point: 1e-12); the FP64
+    forces, and the FP32-mixed ones, against the oracle's per-particle sums on
+    a seeded sample that includes the particles nearest the interfaces (where
+    cutoffs are largest), neighbour counts bit for bit; then the FP32-mixed
+    forces against the FP64 GPU path on every particle, with identical
+    neighbour counts everywhere."""
+    name = "slab_large"
+    print("[gpu] large slab parity and full-population accuracy", flush=True)
+    s = workloads.make(name)
+    ref_d = ref_detect(name)
+    F32, rc32 = step_forces(s, dcm.DCM_FP32_MIXED)
+    F64s, rc64 = step_forces(s, dcm.DCM_FP64)
+    np.testing.assert_allclose(rc64, ref_d["rc"], rtol=1e-12, atol=0)
+    np.testing.assert_array_equal(rc32, rc64)
     idx = workloads.sample_indices(s.n, 1536, seed=4242)
-    # include the particles nearest the interfaces, where cutoffs are largest
     near = np.argsort(np.minimum(np.abs(s.z - 140.0), np.abs(s.z - 260.0)))[:512]
     idx = np.unique(np.concatenate([idx, near]))
-    ref = oracle.forces(s.x, s.y, s.z, ref_d["rc"], s.box, idx=idx)
-    F = np.stack([host(t) for t in f], 1)[idx]
-    emax, erms, eabs = force_errors(F, _ref_F(ref), detail=True)
-    print(f"[gpu]   large slab err_max={emax:.3e} err_rms={erms:.3e} max/F_rms={eabs:.3e}",
-          flush=True)
-    assert emax <= 1e-5 and erms <= 1e-5
+    ref = oracle.forces(s.x, s.y, s.z, rc64, s.box, idx=idx)
+    R = _ref_F(ref)
+    for tag, F, tol in (("fp64", F64s, 1e-12), ("fp32_mixed", F32, 1e-5)):
+        emax, erms, efloor = force_errors(F[idx], R, detail=True)
+        print(f"[gpu]   {tag} vs oracle (sample {len(idx)}): err_max={emax:.3e} "
+              f"err_rms={erms:.3e} floored={efloor:.3e}", flush=True)
+        assert emax <= tol and erms <= tol and efloor <= tol, tag
+    emax, erms, efloor = force_errors(F32, F64s, detail=True)
+    print(f"[gpu]   fp32_mixed vs fp64, all {s.n}: err_max={emax:.3e} err_rms={erms:.3e} "
+          f"floored={efloor:.3e}", flush=True)
+    assert emax <= 1e-5 and erms <= 1e-5 and efloor <= 1e-5
+    # neighbour counts: both precisions at the step's cells, every particle
+    c32 = gpu_forces(s, rc64, prec=dcm.DCM_FP32_MIXED, edge=1.25, rc_bound=s.rule[1])
+    c64 = gpu_forces(s, rc64, prec=dcm.DCM_FP64, edge=1.25, rc_bound=s.rule[1])
+    np.testing.assert_array_equal(c64["nnbr"][idx], ref["nnbr"])
+    np.testing.assert_array_equal(c32["nnbr"], c64["nnbr"])
+    assert c32["npairs"] == c64["npairs"] == int(c64["nnbr"].astype(np.int64).sum())
+    assert abs(c32["E"] - c64["E"]) <= 1e-5 * abs(c64["E"])
+    assert rel(c32["W"], c64["W"]) <= 1e-5
+    np.testing.assert_array_equal(c64["F"], F64s)
+
+
+@pytest.mark.parametrize("name", ["droplet", "cylinder"])
+def test_curved_interface_full_population_accuracy(name):
+    """FP32-mixed against FP64 forces on every particle of the droplet and
+    the cylinder (dcm_step's configuration), neighbour counts identical."""
+    print(f"[gpu] curved {name} full-population accuracy", flush=True)
+    s = workloads.make(name)
+    F32, rc32 = step_forces(s, dcm.DCM_FP32_MIXED)
+    F64s, rc64 = step_forces(s, dcm.DCM_FP64)
+    np.testing.assert_array_equal(rc32, rc64)
+    emax, erms, efloor = force_errors(F32, F64s, detail=True)
+    print(f"[gpu]   {name} fp32_mixed vs fp64, all {s.n}: err_max={emax:.3e} "
+          f"err_rms={erms:.3e} floored={efloor:.3e}", flush=True)
+    assert emax <= 1e-5 and erms <= 1e-5 and efloor <= 1e-5
+    c32 = gpu_forces(s, rc64, prec=dcm.DCM_FP32_MIXED, edge=1.25, rc_bound=s.rule[1])
+    c64 = gpu_forces(s, rc64, prec=dcm.DCM_FP64, edge=1.25, rc_bound=s.rule[1])
+    np.testing.assert_array_equal(c32["nnbr"], c64["nnbr"])
+    assert abs(c32["E"] - c64["E"]) <= 1e-5 * abs(c64["E"])
+    assert rel(c32["W"], c64["W"]) <= 1e-5
 
 
 @pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
