@@ -74,6 +74,11 @@ template <>
 struct Acc<DCM_FP32_MIXED> {
   double fx = 0, fy = 0, fz = 0;
   float e = 0, w[6] = {0, 0, 0, 0, 0, 0};
+  // the compact-record loop's FP32 force sums, added into fx, fy, fz after
+  // each chunk of rows (they collect only pairs beyond the close range,
+  // each below ~2.5 eps/sigma, so FP32 sums of a chunk lose nothing that
+  // the FP32 pair terms themselves keep)
+  float px = 0, py = 0, pz = 0;
 };
 
 // FP32-mixed evaluates a pair with r^2 < kNear2 sigma^2 in FP64.  A relative
@@ -83,6 +88,13 @@ struct Acc<DCM_FP32_MIXED> {
 // of these few pairs (well under 1% of the interacting pairs) would dominate
 // the largest per-particle error measured in units of the RMS force.
 constexpr double kNear2 = 1.21;
+// The compact-record loop queues its close pairs (their extended slots) in a
+// per-lane LDS list of kNearCap entries and evaluates them from the FP64
+// records after each chunk of rows, so the wavefront never waits on a record
+// gather inside the candidate loop.  A lane with more queued pairs in one
+// chunk (a dense liquid has a handful within 1.1 sigma per particle) starts
+// over on the FP64 records.
+constexpr int kNearCap = 6;
 
 // 1/r2 from the hardware reciprocal estimate refined by Newton steps
 // y <- y + y (1 - r2 y): two steps for FP64, one before rounding to FP32.
@@ -323,7 +335,8 @@ __device__ __forceinline__ void scan_n3(const uint2 (*segs)[kPairBlock], int nse
 // for every lane with the result kept only where inc is set: the force of a
 // lane without an interaction in this step is computed and discarded instead
 // of branched around (the wavefront executes it anyway whenever any lane
-// interacts).  FP32 separations and r^2.  The mask is applied once, to 1/r^2:
+// interacts).  FP32 separations, r^2 and force sums (added into the FP64 sums
+// after each chunk of rows).  The mask is applied once, to 1/r^2:
 // a masked pair then has s6 = 0 and adds exactly zero force, energy and
 // virial, whatever its r^2 (an unmasked pair at r = 0 stays non-finite).
 template <int EVM>
@@ -333,10 +346,9 @@ __device__ __forceinline__ void interact_rel(Acc<DCM_FP32_MIXED> &acc, float dx,
   const float s2 = sig2 * r2i;
   const float s6 = s2 * s2 * s2;
   const float fp = s6 * fmaf(2.0f, s6, -1.0f) * r2i;
-  const double fpd = (double)fp;
-  acc.fx = fma(fpd, (double)dx, acc.fx);
-  acc.fy = fma(fpd, (double)dy, acc.fy);
-  acc.fz = fma(fpd, (double)dz, acc.fz);
+  acc.px = fmaf(fp, dx, acc.px);
+  acc.py = fmaf(fp, dy, acc.py);
+  acc.pz = fmaf(fp, dz, acc.pz);
   if constexpr ((EVM & 1) != 0) acc.e += fmaf(s6, s6, -s6);
   if constexpr ((EVM & 2) != 0) {
     const float fdx = fp * dx, fdy = fp * dy, fdz = fp * dz;
@@ -369,15 +381,17 @@ __device__ __forceinline__ float4 load_rel(__amdgpu_buffer_rsrc_t rs, int j) {
 // past the last row (into the sentinel) before the candidate count ends it.
 // Separations are formed in FP32 between the two cell-centre-relative
 // positions, the candidate's cell k cells away: d = (a0 - k len) - rel.  A
-// pair whose FP32 r^2 lies within the lane's proven error band around rc^2 is
-// decided from its FP64 record instead (rare: the band is 3e-5 to 2e-4
-// sigma^2 wide for cutoffs of 2.5 to 8 sigma).  The stream advances with selects, and two register sets take turns
-// so that every record is loaded a full candidate before its use.
+// close pair, and a pair whose FP32 r^2 lies within the lane's proven error
+// band around rc^2, is queued in nearq (nq entries; row kNearCap takes the
+// overflow) for flush_near, which decides and evaluates it in FP64.  The
+// stream advances with selects, and two register sets take turns so that
+// every record is loaded a full candidate before its use.
 template <int EVM>
 __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int total,
                                          __amdgpu_buffer_rsrc_t rs,
                                          const double4 *__restrict__ ext_pos, const LaneGeo &g,
-                                         float sig2, Acc<DCM_FP32_MIXED> &acc, int &cnt) {
+                                         float sig2, Acc<DCM_FP32_MIXED> &acc, int &cnt,
+                                         int32_t (*nearq)[kPairBlock], int &nq) {
   const int lane_id = threadIdx.x;
   const uint2 s0 = segs[0][lane_id];
   int j = (int)s0.x, jend = (int)s0.x + (int)(s0.y & 0xffffu), sidx = 1;
@@ -401,17 +415,13 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int to
     float dx = fmaf(-(r.w - g.wc), g.lenf[0], g.a0x) - r.x;
     float dy = ay - r.y, dz = az - r.z;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    bool inc = r2 < g.rc2f;
-    if (fabsf(r2 - g.rc2f) <= g.margin || r2 < g.near2f) {
-      // rare: a pair too close to rc^2 for the FP32 test, or a close pair,
-      // is decided and evaluated in FP64 from its FP64 record
-      const double4 q = ext_pos[jr];
-      const double ex = g.xi - q.x, ey = g.yi - q.y, ez = g.zi - q.z;
-      const double e2 = (ex * ex + ey * ey) + ez * ez;
-      const bool in64 = e2 < g.rci2;
-      if (in64) interact_exact<EVM>(acc, ex, ey, ez, e2, g.sig2);
-      if constexpr ((EVM & 4) != 0) cnt += in64 ? 1 : 0;
-      inc = false;
+    // a close pair, or one too near rc^2 for the FP32 test (rare: the band
+    // is 3e-5 to 2e-4 sigma^2 wide), waits for flush_near
+    const bool exact = r2 < g.near2f || fabsf(r2 - g.rc2f) <= g.margin;
+    const bool inc = r2 < g.rc2f && !exact;
+    if (exact) {
+      nearq[nq < kNearCap ? nq : kNearCap][lane_id] = jr;
+      ++nq;
     }
     interact_rel<EVM>(acc, dx, dy, dz, r2, sig2, inc);
     if constexpr ((EVM & 4) != 0) cnt += inc ? 1 : 0;
@@ -437,6 +447,30 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int to
   }
 }
 
+// The queued pairs of the lane (the first min(nq, kNearCap)), decided and
+// evaluated in FP64 from their FP64 records, two records in flight.
+template <int EVM>
+__device__ __forceinline__ void flush_near(const int32_t (*nearq)[kPairBlock], int nq,
+                                           const double4 *__restrict__ ext_pos, const LaneGeo &g,
+                                           Acc<DCM_FP32_MIXED> &acc, int &cnt) {
+  const int lane_id = threadIdx.x;
+  const int m = nq < kNearCap ? nq : kNearCap;
+  auto one = [&](const double4 &q) {
+    const double ex = g.xi - q.x, ey = g.yi - q.y, ez = g.zi - q.z;
+    const double e2 = (ex * ex + ey * ey) + ez * ez;
+    const bool in64 = e2 < g.rci2;
+    if (in64) interact_exact<EVM>(acc, ex, ey, ez, e2, g.sig2);
+    if constexpr ((EVM & 4) != 0) cnt += in64 ? 1 : 0;
+  };
+  for (int k = 0; k < m; k += 2) {
+    const double4 q0 = ext_pos[nearq[k][lane_id]];
+    const bool two = k + 1 < m;
+    const double4 q1 = ext_pos[nearq[two ? k + 1 : k][lane_id]];
+    one(q0);
+    if (two) one(q1);
+  }
+}
+
 // Distance from the lane (a0 from the centre of its cell) to the near face of
 // the cell d cells away along one axis, less the guard; 0 for its own cell.
 __device__ __forceinline__ float face_gap(int d, float a0, float len, float guard) {
@@ -457,7 +491,8 @@ __device__ __forceinline__ int cell_off(float p, float inv) {
 template <int RULE, int PREC, int EVM, bool REL, int CAP>
 __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const LaneGeo &g,
                                            double sig2, uint2 (*segs)[kPairBlock],
-                                           Acc<PREC> &acc, int &cnt, bool &redo) {
+                                           int32_t (*nearq)[kPairBlock], Acc<PREC> &acc,
+                                           int &cnt, bool &redo) {
   const int lane_id = threadIdx.x;
   const int nx = v.nc[0], hx = v.h[0], hy = v.h[1], hz = v.h[2];
   const int nex = v.ne[0], ney = v.ne[1];
@@ -583,7 +618,14 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     if (nseg > 0) {
       if constexpr (REL) {
         segs[nseg][lane_id] = make_uint2(0u, 0xffffu);
-        scan_rel<EVM>(segs, total, rs, v.ext_pos, g, (float)sig2, acc, cnt);
+        int nq = 0;
+        scan_rel<EVM>(segs, total, rs, v.ext_pos, g, (float)sig2, acc, cnt, nearq, nq);
+        if (nq > kNearCap) redo = true;  // more close pairs than the queue holds
+        flush_near<EVM>(nearq, nq, v.ext_pos, g, acc, cnt);
+        acc.fx += (double)acc.px;
+        acc.fy += (double)acc.py;
+        acc.fz += (double)acc.pz;
+        acc.px = acc.py = acc.pz = 0.0f;
       } else if constexpr (RULE == DCM_PAIR_MAX_N3)
         scan_n3<PREC, EVM>(segs, nseg, v, g, sig2, acc, cnt);
       else
@@ -649,6 +691,7 @@ __device__ __forceinline__ void finish_block(const int32_t *perm, int64_t id0, d
 template <int RULE, int PREC, int EVM, bool REL>
 __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool active, double eps,
                                            double sig2, uint2 (*segs)[kPairBlock],
+                                           int32_t (*nearq)[kPairBlock],
                                            double (*red)[kPartialSlots], uint32_t *status,
                                            double *partial_out) {
   Acc<PREC> acc;
@@ -737,18 +780,20 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
     g.self = v.ext_start[ext_cell] + (int)(s - v.cell_start[real_cell]);
   }
   bool redo = false;
-  sweep_rows<RULE, PREC, EVM, REL, seg_cap<REL>()>(v, active, g, sig2, segs, acc, cnt, redo);
+  sweep_rows<RULE, PREC, EVM, REL, seg_cap<REL>()>(v, active, g, sig2, segs, nearq, acc, cnt,
+                                                   redo);
   if constexpr (REL) {
-    // rare: lanes with a row longer than a list entry can describe start
-    // over on the FP64 records
+    // rare: lanes with a row longer than a list entry can describe, or with
+    // more close pairs in one chunk than their queue holds, start over on
+    // the FP64 records
     if (__syncthreads_or(redo ? 1 : 0)) {
       if (redo) {
         acc = Acc<PREC>();
         cnt = 0;
       }
       bool unused = false;
-      sweep_rows<RULE, PREC, EVM, false, seg_cap<REL>()>(v, active && redo, g, sig2, segs, acc,
-                                                        cnt, unused);
+      sweep_rows<RULE, PREC, EVM, false, seg_cap<REL>()>(v, active && redo, g, sig2, segs, nearq,
+                                                        acc, cnt, unused);
     }
   }
   if constexpr (RULE == DCM_PAIR_MAX_N3) {
@@ -771,6 +816,7 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
 template <int RULE, int PREC, int EVM, bool REL>
 __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   __shared__ uint2 segs[seg_cap<REL>()][kPairBlock];
+  __shared__ int32_t nearq[REL ? kNearCap + 1 : 1][kPairBlock];
   __shared__ double red[kPairBlock / 64][kPartialSlots];
   const int64_t lblock = xcd_block(blockIdx.x, gridDim.x, kXcdGroup);
   const int64_t s = lblock * kPairBlock + threadIdx.x;
@@ -801,7 +847,8 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   v.ext_src = a.ext_src;
   v.n3_f = a.n3_f;
   v.n3_cnt = a.n3_cnt;
-  pair_block<RULE, PREC, EVM, REL>(v, s, s < a.n, a.eps, a.sigma * a.sigma, segs, red, a.status,
+  pair_block<RULE, PREC, EVM, REL>(v, s, s < a.n, a.eps, a.sigma * a.sigma, segs, nearq, red,
+                                   a.status,
                               a.partials + lblock * kPartialSlots);
 }
 
@@ -884,6 +931,7 @@ void launch_pair_list(hipStream_t s, const PairArgs &a, int prec, const int32_t 
 template <int RULE, int PREC, int EVM, bool REL>
 __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
   __shared__ uint2 segs[seg_cap<REL>()][kPairBlock];
+  __shared__ int32_t nearq[REL ? kNearCap + 1 : 1][kPairBlock];
   __shared__ double red[kPairBlock / 64][kPartialSlots];
   __shared__ int32_t next_item;
   const double sig2 = a.sigma * a.sigma;
@@ -926,7 +974,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
     v.n3_f = nullptr;
     v.n3_cnt = nullptr;
     const int64_t local = first + threadIdx.x;
-    pair_block<RULE, PREC, EVM, REL>(v, g.p0 + local, local < g.n, a.eps, sig2, segs, red,
+    pair_block<RULE, PREC, EVM, REL>(v, g.p0 + local, local < g.n, a.eps, sig2, segs, nearq, red,
                                      a.status,
                                 a.partials + (int64_t)item * kPartialSlots);
   }

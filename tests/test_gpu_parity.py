@@ -268,6 +268,62 @@ def test_ghost_images_of_a_dense_corner(prec):
             assert emax <= tol and erms <= tol, (shift, emax, erms)
 
 
+def crowded_centres():
+    """Dilute gas (density 0.05) holding a few tight clusters: a centre with
+    eight neighbours at the corners of a cube, all 0.95-1.05 sigma away (more
+    close pairs in reach than the compact-record queue holds), plus a pair
+    at 0.9 sigma."""
+    rng = np.random.default_rng(np.random.PCG64(31))
+    L = 18.0
+    pts = [rng.uniform(0.0, L, (int(0.05 * L ** 3), 3))]
+    corners = np.array([[a, b, c] for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)], float)
+    for centre in ((4.0, 4.0, 4.0), (13.0, 5.0, 11.0), (9.0, 14.0, 6.0)):
+        c = np.asarray(centre)
+        r = rng.uniform(0.95, 1.05, (8, 1))
+        pts.append(c[None, :])
+        pts.append(c + corners / np.sqrt(3.0) * r)
+    pts.append(np.array([[15.0, 15.0, 15.0], [15.9, 15.0, 15.0]]))
+    pts = np.concatenate(pts)
+    # keep the gas away from the clusters (at least 1.2 sigma)
+    clusters = pts[int(0.05 * L ** 3):]
+    gas = pts[:int(0.05 * L ** 3)]
+    d = gas[:, None, :] - clusters[None, :, :]
+    d -= L * np.rint(d / L)
+    gas = gas[np.min(np.linalg.norm(d, axis=2), axis=1) > 1.2]
+    keep = []
+    for p in gas:  # and from each other (at least 0.9 sigma)
+        if keep:
+            e = np.asarray(keep) - p
+            e -= L * np.rint(e / L)
+            if np.min(np.linalg.norm(e, axis=1)) < 0.9:
+                continue
+        keep.append(p)
+    pts = np.mod(np.concatenate([np.asarray(keep), clusters]), L)
+    n = len(pts)
+    z0 = np.zeros(n)
+    return workloads.System(name="crowded", x=pts[:, 0].copy(), y=pts[:, 1].copy(),
+                            z=pts[:, 2].copy(), vx=z0, vy=z0, vz=z0, box=(L, L, L),
+                            rule=(2.5, 6.0, 5.0))
+
+
+@pytest.mark.parametrize("edge", [0.9, 1.25, 2.0])
+def test_fp32_mixed_many_close_pairs(edge):
+    """Particles with more close pairs than the compact-record kernel queues
+    (they start over on the FP64 records) next to ordinary ones: counts bit
+    for bit and forces within the FP32-mixed bar against the oracle."""
+    print(f"[gpu] crowded close pairs edge={edge}", flush=True)
+    s = crowded_centres()
+    rc = workloads.uniform_cutoffs(s.n, 2.5, 6.0, seed=37)
+    got = gpu_forces(s, rc, prec=dcm.DCM_FP32_MIXED, edge=edge, rc_bound=6.0)
+    assert got["status"] == dcm.DCM_OK
+    ref = oracle.forces(s.x, s.y, s.z, rc, s.box)
+    np.testing.assert_array_equal(got["nnbr"], ref["nnbr"])
+    emax, erms, efloor = force_errors(got["F"], _ref_F(ref), detail=True)
+    assert emax <= 1e-5 and erms <= 1e-5 and efloor <= 1e-5, (emax, erms)
+    assert abs(got["E"] - ref["E"]) <= 1e-5 * abs(ref["E"])
+    assert rel(got["W"], ref["W"]) <= 1e-5
+
+
 # 7.0: one cell across x and y (13.4 sigma), so the halo of two cells is
 # wider than the grid and the ghost rows wrap the box more than once
 @pytest.mark.parametrize("edge", [0.0, 0.7, 1.9, 3.3, 7.0])
