@@ -195,6 +195,27 @@ dcm_status dcm_detect_interface_opts(dcm_ctx *ctx, const double *x, const double
                                      const dcm_detect_opts *opts, uint32_t *counts,
                                      uint8_t *seg, uint8_t *iface, int32_t *threshold_out);
 
+/* Interface detection that allocates nothing, for callers that cannot
+ * allocate device memory: code being captured into a HIP graph, tight serving
+ * loops, harnesses that forbid allocation.  Arguments, outputs and results
+ * are those of dcm_detect_interface (bit for bit).  Its scratch -- the
+ * gray-value histogram copies (512 KiB), the gray values (4 N_v bytes), two
+ * bit-packed phase maps (N_y N_z ceil(N_x/32) words each) and, when counts is
+ * NULL, the voxel counts (4 N_v bytes) -- lives in one static 32 MiB device
+ * array per GPU, which the library holds until the process ends (its address
+ * is looked up when the first context is created on that GPU).  That bounds
+ * the grid: about 7.7 M voxels with a caller counts array, 4.0 M without
+ * (fewer when N_x is far below a multiple of 32); larger grids return
+ * DCM_ERR_RANGE before anything is enqueued.  Every call
+ * on a GPU shares that one array and leaves its contents behind (the call
+ * clears what must start at zero itself): calls that overlap on one GPU --
+ * from other streams, contexts or threads -- race and must be serialised by
+ * the caller. */
+dcm_status dcm_detect_interface_noalloc(dcm_ctx *ctx, const double *x, const double *y,
+                                        const double *z, int64_t n, dcm_box box, dcm_grid grid,
+                                        double split, uint32_t *counts, uint8_t *seg,
+                                        uint8_t *iface, int32_t *threshold_out);
+
 /* Box-interface distances (Section 2.2, Algorithm 2.1).  Interface and
  * low-density voxels start at 0, the rest at +infinity; the first-order
  * Godunov upwind update of |grad d| = 1 is applied to every voxel in

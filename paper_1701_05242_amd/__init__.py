@@ -98,6 +98,8 @@ SIGNATURES = {
     "dcm_make_grid": [dcm_box, _F64, ctypes.POINTER(dcm_grid)],
     "dcm_detect_interface": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid, _F64, _P, _P, _P, _P],
     "dcm_rc_grid": [dcm_rule, dcm_grid, ctypes.POINTER(_F64)],
+    "dcm_detect_interface_noalloc": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid, _F64, _P, _P, _P,
+                                     _P],
     "dcm_detect_interface_opts": [_P, _P, _P, _P, _I64, dcm_box, dcm_grid,
                                   ctypes.POINTER(dcm_detect_opts), _P, _P, _P, _P],
     "dcm_sweep_distance": [_P, _P, _P, dcm_grid, _F64, _I32, _P, _P],
@@ -224,6 +226,19 @@ def dcm_detect_interface(ctx, x, y, z, box, grid: dcm_grid, seg, iface, split: f
     nv = grid_voxels(grid)
     f64 = torch.float64
     code = load_library().dcm_detect_interface(
+        ctx, _ptr(x, f64, "x", n), _ptr(y, f64, "y", n), _ptr(z, f64, "z", n), n, _box(box),
+        grid, float(split), _ptr(counts, torch.uint32, "counts", nv),
+        _ptr(seg, torch.uint8, "seg", nv), _ptr(iface, torch.uint8, "iface", nv),
+        _ptr(threshold_out, torch.int32, "threshold_out", 1))
+    _check(ctx, code)
+
+
+def dcm_detect_interface_noalloc(ctx, x, y, z, box, grid: dcm_grid, seg, iface,
+                                 split: float = 0.0, counts=None, threshold_out=None) -> None:
+    n = x.numel()
+    nv = grid_voxels(grid)
+    f64 = torch.float64
+    code = load_library().dcm_detect_interface_noalloc(
         ctx, _ptr(x, f64, "x", n), _ptr(y, f64, "y", n), _ptr(z, f64, "z", n), n, _box(box),
         grid, float(split), _ptr(counts, torch.uint32, "counts", nv),
         _ptr(seg, torch.uint8, "seg", nv), _ptr(iface, torch.uint8, "iface", nv),

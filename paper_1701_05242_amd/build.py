@@ -26,7 +26,8 @@ FLAGS = [
     "-Wall", "-Wno-unused-command-line-argument",
 ]
 SOURCES = ["k_common.hip", "k_grid.hip", "k_fsm.hip", "k_cells.hip", "k_pair.hip",
-           "k_order.hip", "k_verlet.hip", "k_batch.hip", "k_ccl.hip", "k_list.hip", "dcm_api.cpp", "dcm_batch.cpp"]
+           "k_order.hip", "k_verlet.hip", "k_batch.hip", "k_ccl.hip", "k_list.hip", "dcm_noalloc.hip",
+           "dcm_api.cpp", "dcm_batch.cpp"]
 
 
 def _compile(src: str) -> str:

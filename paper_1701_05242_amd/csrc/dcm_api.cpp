@@ -64,6 +64,67 @@ void timer_end(dcm_ctx *ctx, const char *family, hipEvent_t ev) {
   ctx->timers[family].pending.push_back({ev, e2});
 }
 
+dcm_status detect_check(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                        int64_t n, const dcm_box &box, const dcm_grid &grid,
+                        const dcm_detect_opts *opts, const uint8_t *seg, const uint8_t *iface,
+                        int64_t *nvox) {
+  if (!ctx) return DCM_ERR_INVALID;
+  if (!opts) return fail(ctx, DCM_ERR_INVALID, "dcm_detect_interface_opts: null opts");
+  const double split = opts->split, nu = opts->nu;
+  if (!std::isfinite(nu)) return fail(ctx, DCM_ERR_INVALID, "nu must be finite");
+  if (nu >= 0.0 && split > 0.0)
+    return fail(ctx, DCM_ERR_INVALID, "a length-term weight needs the two-phase split (split <= 0)");
+  if (opts->min_volume < 0 || opts->min_volume >= (int64_t(1) << 31))
+    return fail(ctx, DCM_ERR_INVALID, "min_volume must be in [0, 2^31)");
+  if (n < 0) return fail(ctx, DCM_ERR_INVALID, "particle count must be >= 0");
+  if (n >= (int64_t(1) << 31) - 1) return fail(ctx, DCM_ERR_RANGE, "particle count >= 2^31 - 1");
+  for (int a = 0; a < 3; ++a)
+    if (!(std::isfinite(box.L[a]) && box.L[a] > 0.0))
+      return fail(ctx, DCM_ERR_INVALID, "box lengths must be > 0");
+  int64_t v = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (grid.n[a] < 1 || !(std::isfinite(grid.h[a]) && grid.h[a] > 0.0))
+      return fail(ctx, DCM_ERR_INVALID, "grid needs n >= 1 and h > 0 on every axis");
+    v *= grid.n[a];
+    if (v >= (int64_t(1) << 31)) return fail(ctx, DCM_ERR_RANGE, "grid has 2^31 or more voxels");
+  }
+  *nvox = v;
+  if ((n > 0 && (!x || !y || !z)) || !seg || !iface)
+    return fail(ctx, DCM_ERR_INVALID, "dcm_detect_interface: null pointer");
+  if (!std::isfinite(split)) return fail(ctx, DCM_ERR_INVALID, "split must be finite");
+  return DCM_OK;
+}
+
+dcm_status detect_enqueue(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                          int64_t n, const dcm_box &box, const dcm_grid &grid,
+                          const dcm_detect_opts &opts, const DetectScratch &sc, uint8_t *seg,
+                          uint8_t *iface, int32_t *threshold_out, bool timed) {
+  const int64_t nvox = (int64_t)grid.n[0] * grid.n[1] * grid.n[2];
+  const double sc3[3] = {(double)grid.n[0] / box.L[0], (double)grid.n[1] / box.L[1],
+                         (double)grid.n[2] / box.L[2]};
+  hipStream_t s = ctx->stream;
+  hipEvent_t ev = nullptr;
+  if (timed) timer_begin(ctx, "detect", &ev);
+  launch_fill_u32(s, sc.counts, 0u, nvox);
+  launch_fill_u32(s, sc.hist, 0u, (int64_t)kHistCopies * kHistBins);
+  launch_bin_density(s, x, y, z, n, box.L, grid.n, sc3, sc.counts, ctx->d_status);
+  launch_gray_hist(s, sc.counts, sc.gray, grid.n, sc.hist, ctx->d_status);
+  if (opts.split <= 0.0) launch_otsu(s, sc.hist, nvox, ctx->ctl, threshold_out, ctx->d_status);
+  launch_threshold(s, sc.gray, grid.n, opts.split, ctx->ctl, sc.seg_a, threshold_out);
+  for (int p = 1; p <= kMajorityMaxPasses; ++p) {
+    if (opts.nu < 0.0)
+      launch_majority_pass(s, sc.seg_a, sc.seg_b, grid.n, p, kMajorityMaxPasses, ctx->ctl);
+    else
+      launch_potts_pass(s, sc.seg_a, sc.seg_b, sc.gray, grid.n, opts.nu, p, ctx->ctl);
+  }
+  launch_interface(s, sc.seg_a, sc.seg_b, grid.n, ctx->ctl, seg, iface);
+  if (opts.min_volume > 0)
+    launch_bubble_filter(s, grid.n, opts.min_volume, seg, iface, sc.ccl_label, sc.ccl_size,
+                         ctx->d_status);
+  if (timed) timer_end(ctx, "detect", ev);
+  return check_launch(ctx, "dcm_detect_interface");
+}
+
 }  // namespace dcm
 
 namespace {
@@ -157,6 +218,9 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
   launch_clear_status(ctx->stream, ctx->d_status);
   launch_reset_ctl(ctx->stream, ctx->ctl);
   dcm_status st = check_launch(ctx, "dcm_create");
+  // the device address of this GPU's no-allocation scratch array, once per
+  // device (dcm_noalloc.hip)
+  if (st == DCM_OK) st = noalloc_scratch_setup(ctx->device, &ctx->err);
   if (st == DCM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = DCM_ERR_HIP;
   if (st != DCM_OK) {
     hipEventDestroy(ctx->ext_event);
@@ -259,21 +323,9 @@ dcm_status dcm_detect_interface_opts(dcm_ctx *ctx, const double *x, const double
                                      const double *z, int64_t n, dcm_box box, dcm_grid grid,
                                      const dcm_detect_opts *opts, uint32_t *counts,
                                      uint8_t *seg, uint8_t *iface, int32_t *threshold_out) {
-  if (!ctx) return DCM_ERR_INVALID;
-  if (!opts) return fail(ctx, DCM_ERR_INVALID, "dcm_detect_interface_opts: null opts");
-  const double split = opts->split, nu = opts->nu;
-  if (!std::isfinite(nu)) return fail(ctx, DCM_ERR_INVALID, "nu must be finite");
-  if (nu >= 0.0 && split > 0.0)
-    return fail(ctx, DCM_ERR_INVALID, "a length-term weight needs the two-phase split (split <= 0)");
-  if (opts->min_volume < 0 || opts->min_volume >= (int64_t(1) << 31))
-    return fail(ctx, DCM_ERR_INVALID, "min_volume must be in [0, 2^31)");
   int64_t nvox = 0;
-  DCM_TRY(check_n(ctx, n));
-  DCM_TRY(check_box(ctx, box));
-  DCM_TRY(check_grid(ctx, grid, &nvox));
-  if ((n > 0 && (!x || !y || !z)) || !seg || !iface)
-    return fail(ctx, DCM_ERR_INVALID, "dcm_detect_interface: null pointer");
-  if (!std::isfinite(split)) return fail(ctx, DCM_ERR_INVALID, "split must be finite");
+  DCM_TRY(detect_check(ctx, x, y, z, n, box, grid, opts, seg, iface, &nvox));
+  DetectScratch sc;
   DCM_TRY(ensure(ctx, ctx->gray, nvox * sizeof(uint32_t)));
   DCM_TRY(ensure(ctx, ctx->hist, (size_t)kHistCopies * kHistBins * sizeof(uint32_t)));
   DCM_TRY(ensure(ctx, ctx->seg_a, phase_bits_words(grid.n) * sizeof(uint32_t)));
@@ -281,40 +333,19 @@ dcm_status dcm_detect_interface_opts(dcm_ctx *ctx, const double *x, const double
   if (opts->min_volume > 0) {
     DCM_TRY(ensure(ctx, ctx->ccl_label, nvox * sizeof(int32_t)));
     DCM_TRY(ensure(ctx, ctx->ccl_size, nvox * sizeof(int32_t)));
+    sc.ccl_label = ptr<int32_t>(ctx->ccl_label);
+    sc.ccl_size = ptr<int32_t>(ctx->ccl_size);
   }
   if (!counts) {
     DCM_TRY(ensure(ctx, ctx->counts, nvox * sizeof(uint32_t)));
     counts = ptr<uint32_t>(ctx->counts);
   }
-  const double sc[3] = {(double)grid.n[0] / box.L[0], (double)grid.n[1] / box.L[1],
-                        (double)grid.n[2] / box.L[2]};
-  hipStream_t s = ctx->stream;
-  hipEvent_t ev;
-  timer_begin(ctx, "detect", &ev);
-  launch_fill_u32(s, counts, 0u, nvox);
-  launch_fill_u32(s, ptr<uint32_t>(ctx->hist), 0u, (int64_t)kHistCopies * kHistBins);
-  launch_bin_density(s, x, y, z, n, box.L, grid.n, sc, counts, ctx->d_status);
-  launch_gray_hist(s, counts, ptr<uint32_t>(ctx->gray), grid.n, ptr<uint32_t>(ctx->hist),
-                   ctx->d_status);
-  if (split <= 0.0)
-    launch_otsu(s, ptr<uint32_t>(ctx->hist), nvox, ctx->ctl, threshold_out, ctx->d_status);
-  launch_threshold(s, ptr<uint32_t>(ctx->gray), grid.n, split, ctx->ctl,
-                   ptr<uint32_t>(ctx->seg_a), threshold_out);
-  for (int p = 1; p <= kMajorityMaxPasses; ++p) {
-    if (nu < 0.0)
-      launch_majority_pass(s, ptr<uint32_t>(ctx->seg_a), ptr<uint32_t>(ctx->seg_b), grid.n, p,
-                           kMajorityMaxPasses, ctx->ctl);
-    else
-      launch_potts_pass(s, ptr<uint32_t>(ctx->seg_a), ptr<uint32_t>(ctx->seg_b),
-                        ptr<uint32_t>(ctx->gray), grid.n, nu, p, ctx->ctl);
-  }
-  launch_interface(s, ptr<uint32_t>(ctx->seg_a), ptr<uint32_t>(ctx->seg_b), grid.n, ctx->ctl, seg,
-                   iface);
-  if (opts->min_volume > 0)
-    launch_bubble_filter(s, grid.n, opts->min_volume, seg, iface, ptr<int32_t>(ctx->ccl_label),
-                         ptr<int32_t>(ctx->ccl_size), ctx->d_status);
-  timer_end(ctx, "detect", ev);
-  return check_launch(ctx, "dcm_detect_interface");
+  sc.counts = counts;
+  sc.gray = ptr<uint32_t>(ctx->gray);
+  sc.hist = ptr<uint32_t>(ctx->hist);
+  sc.seg_a = ptr<uint32_t>(ctx->seg_a);
+  sc.seg_b = ptr<uint32_t>(ctx->seg_b);
+  return detect_enqueue(ctx, x, y, z, n, box, grid, *opts, sc, seg, iface, threshold_out, true);
 }
 
 dcm_status dcm_sweep_distance(dcm_ctx *ctx, const uint8_t *seg, const uint8_t *iface,

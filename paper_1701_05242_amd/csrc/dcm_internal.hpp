@@ -185,6 +185,27 @@ struct dcm_ctx {
 
 namespace dcm {
 
+// ---- interface detection in parts (dcm_api.cpp): argument checks, and the
+// launches on given scratch buffers (counts, gray values, histogram copies,
+// the two bit-packed phase maps; the bubble filter's labels and sizes when
+// opts.min_volume > 0)
+struct DetectScratch {
+  uint32_t *counts = nullptr, *gray = nullptr, *hist = nullptr, *seg_a = nullptr,
+           *seg_b = nullptr;
+  int32_t *ccl_label = nullptr, *ccl_size = nullptr;
+};
+dcm_status detect_check(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                        int64_t n, const dcm_box &box, const dcm_grid &grid,
+                        const dcm_detect_opts *opts, const uint8_t *seg, const uint8_t *iface,
+                        int64_t *nvox);
+dcm_status detect_enqueue(dcm_ctx *ctx, const double *x, const double *y, const double *z,
+                          int64_t n, const dcm_box &box, const dcm_grid &grid,
+                          const dcm_detect_opts &opts, const DetectScratch &sc, uint8_t *seg,
+                          uint8_t *iface, int32_t *threshold_out, bool timed);
+// dcm_noalloc.hip: look up (once per device) the device address of the
+// static scratch array of dcm_detect_interface_noalloc
+dcm_status noalloc_scratch_setup(int device, std::string *err);
+
 // ---- context helpers (dcm_api.cpp)
 dcm_status fail(dcm_ctx *ctx, dcm_status code, const std::string &msg);
 dcm_status ensure(dcm_ctx *ctx, DevBuf &b, size_t bytes);
