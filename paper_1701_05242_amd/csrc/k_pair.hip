@@ -36,12 +36,14 @@ constexpr int kPairBlock = 256;
 // records and for those reading compact records.  A smaller list allows more
 // resident workgroups: the compact-record kernels, with cheaper candidates,
 // gain from that, while the FP64 kernels, bound by their gathers, lose
-// (measured on the large slab).
+// (measured on the large slab).  The compact-record kernels also hold their
+// close-pair queue (kNearCap + 1 entries of 4 B); with 14 row entries both
+// fit in the 40 KB of LDS that keeps four workgroups on a compute unit.
 #ifndef DCM_PAIR_SEGCAP
 #define DCM_PAIR_SEGCAP 24
 #endif
 #ifndef DCM_PAIR_SEGCAP_REL
-#define DCM_PAIR_SEGCAP_REL 16
+#define DCM_PAIR_SEGCAP_REL 14
 #endif
 constexpr int kSegCap = DCM_PAIR_SEGCAP;
 constexpr int kSegCapRel = DCM_PAIR_SEGCAP_REL;
@@ -91,10 +93,11 @@ constexpr double kNear2 = 1.21;
 // The compact-record loop queues its close pairs (their extended slots) in a
 // per-lane LDS list of kNearCap entries and evaluates them from the FP64
 // records after each chunk of rows, so the wavefront never waits on a record
-// gather inside the candidate loop.  A lane with more queued pairs in one
-// chunk (a dense liquid has a handful within 1.1 sigma per particle) starts
-// over on the FP64 records.
-constexpr int kNearCap = 6;
+// gather inside the candidate loop.  The lane's own slot passes through the
+// queue too.  A lane with more queued pairs in one chunk starts over on the
+// FP64 records: an equilibrated LJ liquid at density 0.8 has 3.3 neighbours
+// within 1.1 sigma on average and at most 9 or 10 (measured).
+constexpr int kNearCap = 10;
 
 // 1/r2 from the hardware reciprocal estimate refined by Newton steps
 // y <- y + y (1 - r2 y): two steps for FP64, one before rounding to FP32.
@@ -255,7 +258,7 @@ __device__ __forceinline__ void scan_ranges(const uint2 (*segs)[kPairBlock], int
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) {
-  return v < lo ? lo : (v > hi ? hi : v);
+  return min(max(v, lo), hi);  // one v_med3_i32 (lo <= hi)
 }
 
 // Everything one lane needs to find and sum its particle's neighbours; the
@@ -291,6 +294,10 @@ struct LaneGeo {
   // the cell's x index + 1/2 (wc), rc^2 and the band around it within which
   // an FP32 r^2 cannot decide a pair
   float a0x, a0y, a0z, lenf[3], invf[3], fR2, fguard, wc, rc2f, margin;
+  // per axis: the distances (plus the guard) from the lane to the far faces
+  // of its cell's positive (gp) and negative (gm) neighbours less one cell,
+  // 0.5 len +- a0 + guard, and the lane's offset in cell units, a0/len + 1/2
+  float gp[3], gm[3], ac[3];
   // compact records: FP32 r^2 below which a pair is evaluated in FP64, and
   // sigma^2 for that evaluation
   float near2f;
@@ -463,26 +470,29 @@ __device__ __forceinline__ void flush_near(const int32_t (*nearq)[kPairBlock], i
     if constexpr ((EVM & 4) != 0) cnt += in64 ? 1 : 0;
   };
   for (int k = 0; k < m; k += 2) {
-    const double4 q0 = ext_pos[nearq[k][lane_id]];
-    const bool two = k + 1 < m;
-    const double4 q1 = ext_pos[nearq[two ? k + 1 : k][lane_id]];
-    one(q0);
-    if (two) one(q1);
+    // the lane's own slot (queued at separation 0) is skipped unread
+    const int j0 = nearq[k][lane_id];
+    const int j1 = k + 1 < m ? nearq[k + 1][lane_id] : g.self;
+    const bool u0 = j0 != g.self, u1 = j1 != g.self;
+    double4 q0, q1;
+    if (u0) q0 = ext_pos[j0];
+    if (u1) q1 = ext_pos[j1];
+    if (u0) one(q0);
+    if (u1) one(q1);
   }
 }
 
-// Distance from the lane (a0 from the centre of its cell) to the near face of
-// the cell d cells away along one axis, less the guard; 0 for its own cell.
-__device__ __forceinline__ float face_gap(int d, float a0, float len, float guard) {
-  const float ad = (float)(d < 0 ? -d : d);
-  const float e = fmaf(ad - 0.5f, len, d < 0 ? a0 : -a0) - guard;
-  return (d == 0 || e < 0.0f) ? 0.0f : e;
+// Distance from the lane to the near face of the cell d cells away along axis
+// a, less the guard; 0 for its own cell (gp, gm > 0 make that value negative).
+__device__ __forceinline__ float face_gap(int d, const LaneGeo &g, int a) {
+  const float e = fmaf(fabsf((float)d), g.lenf[a], -(d > 0 ? g.gp[a] : g.gm[a]));
+  return fmaxf(e, 0.0f);
 }
 
-// Offset from the lane's cell of the cell holding the point p (p relative to
-// the lane's cell centre).
-__device__ __forceinline__ int cell_off(float p, float inv) {
-  return (int)floorf(fmaf(p, inv, 0.5f));
+// Offset from the lane's cell of the cell holding the point a0 + p along
+// axis a.
+__device__ __forceinline__ int cell_off(float p, const LaneGeo &g, int a) {
+  return (int)floorf(fmaf(p, g.invf[a], g.ac[a]));
 }
 
 // Walk this lane's rows (fill a list, scan it, repeat) for a lane with run
@@ -508,12 +518,12 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
   int rowbase_c = 0;
   const int own_row = ((g.cz + hz) * ney + (g.cy + hy)) * nex + hx;
   auto plane = [&](int z) -> bool {
-    const float ez = face_gap(z - g.cz, g.a0z, g.lenf[2], g.fguard);
+    const float ez = face_gap(z - g.cz, g, 2);
     const float remz = fmaf(-ez, ez, g.fR2);
     if (remz < 0.0f) return false;
     const float w = __builtin_amdgcn_sqrtf(remz) + g.fguard;
-    ylo_c = clampi(g.cy + cell_off(g.a0y - w, g.invf[1]), -hy, ny + hy - 1);
-    yhi_c = clampi(g.cy + cell_off(g.a0y + w, g.invf[1]), -hy, ny + hy - 1);
+    ylo_c = clampi(g.cy + cell_off(-w, g, 1), -hy, ny + hy - 1);
+    yhi_c = clampi(g.cy + cell_off(w, g, 1), -hy, ny + hy - 1);
     remz_c = remz;
     rowbase_c = ((z + hz) * ney + hy) * nex + hx;
     return true;
@@ -546,9 +556,9 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     // kFillRows rows at a time: the two ext_start reads of all of them are
     // issued before the first is used, so their latencies overlap
     int nseg = 0, total = 0;
-    // a row adds at most two entries (compact records: the own row is split,
-    // and two entries stay free for the sentinel and the look-ahead)
-    while (rows_left && nseg <= CAP - kFillRows - (REL ? 3 : 1)) {
+    // a row adds at most one entry (compact records: two entries stay free
+    // for the sentinel and the look-ahead)
+    while (rows_left && nseg <= CAP - kFillRows - (REL ? 2 : 1)) {
       int j0[kFillRows], j1[kFillRows], rz[kFillRows], ry[kFillRows];
       bool ok[kFillRows];
 #pragma unroll
@@ -566,15 +576,15 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
           if (more) yc = ylo_c;
           else rows_left = false;
         }
-        const float ey = face_gap(ycur - g.cy, g.a0y, g.lenf[1], g.fguard);
+        const float ey = face_gap(ycur - g.cy, g, 1);
         const float rem = fmaf(-ey, ey, remz);
         in = in && rem >= 0.0f;
         // chord half-width, widened by the guard (it only selects cells)
         const float w = in ? __builtin_amdgcn_sqrtf(rem) + g.fguard : 0.0f;
-        const int xlo = clampi(g.cx + cell_off(g.a0x - w, g.invf[0]), -hx, nx + hx - 1);
-        const int xhi = clampi(g.cx + cell_off(g.a0x + w, g.invf[0]), -hx, nx + hx - 1);
+        const int xlo = clampi(g.cx + cell_off(-w, g, 0), -hx, nx + hx - 1);
+        const int xhi = clampi(g.cx + cell_off(w, g, 0), -hx, nx + hx - 1);
         // a row that is not taken still reads (its own cell row's) starts
-        const int row = in ? rowbase + ycur * nex : own_row;
+        const int row = in ? rowbase + __mul24(ycur, nex) : own_row;
         j0[k] = load_start(row + xlo);
         j1[k] = load_start(row + xhi + 1);
         rz[k] = zcur;
@@ -587,25 +597,20 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
         const int a0 = j0[k];
         const int a1 = j1[k] > v.ext_cap ? (int)v.ext_cap : j1[k];  // overflow (flagged at build)
         if constexpr (REL) {
+          // the lane's own slot stays in its row: at separation 0 it is
+          // queued like a close pair, and flush_near drops it
           const uint32_t rowtag = ((uint32_t)(uint8_t)(ry[k] - g.cy) << 16) |
                                   ((uint32_t)(uint8_t)(rz[k] - g.cz) << 24);
-          const bool own = g.self >= a0 && g.self < a1;
-          const int e1 = own ? g.self : a1;
+          const int len = a1 - a0;
           // entries hold at most 65535 slots; a longer row goes to the exact pass
-          if (e1 - a0 > 65535 || (own && a1 - g.self - 1 > 65535)) {
+          if (len > 65535) {
             redo = true;
             continue;
           }
-          if (e1 > a0) {
-            segs[nseg][lane_id] = make_uint2((uint32_t)a0, (uint32_t)(e1 - a0) | rowtag);
+          if (len > 0) {
+            segs[nseg][lane_id] = make_uint2((uint32_t)a0, (uint32_t)len | rowtag);
             ++nseg;
-            total += e1 - a0;
-          }
-          if (own && a1 > g.self + 1) {
-            segs[nseg][lane_id] =
-                make_uint2((uint32_t)(g.self + 1), (uint32_t)(a1 - g.self - 1) | rowtag);
-            ++nseg;
-            total += a1 - g.self - 1;
+            total += len;
           }
         } else {
           if (a1 > a0) {
@@ -708,6 +713,7 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   g.sig2 = sig2;
   g.lenf[0] = g.lenf[1] = g.lenf[2] = 0.0f;
   g.invf[0] = g.invf[1] = g.invf[2] = 0.0f;
+  for (int k = 0; k < 3; ++k) g.gp[k] = g.gm[k] = g.ac[k] = 0.0f;
   g.cx = 0;
   g.zlo = 0;
   g.zhi = -1;
@@ -750,6 +756,13 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
     // every face distance and chord beyond them, and raises R^2 by
     // 2 Rg fguard, far above the ~4 u R^2 rounding of R^2 - ez^2 - ey^2
     g.fguard = (float)(4e-6 * (Rg + lmax));
+    const float a0[3] = {g.a0x, g.a0y, g.a0z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      g.gp[k] = fmaf(0.5f, g.lenf[k], a0[k]) + g.fguard;
+      g.gm[k] = fmaf(0.5f, g.lenf[k], -a0[k]) + g.fguard;
+      g.ac[k] = fmaf(a0[k], g.invf[k], 0.5f);
+    }
     const double Rf = Rg + (double)g.fguard;
     g.fR2 = (float)(Rf * Rf) * (1.0f + 0x1p-20f);
     if constexpr (REL) {
