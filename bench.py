@@ -398,32 +398,66 @@ def n3_leg(s, dev, reps=3):
 
 
 def cpu_baseline(s, seconds):
-    """The oracle's O(N) per-particle sums on a seeded sample of particles."""
+    """The oracle's O(N) per-particle sums on a seeded sample of particles at
+    all host threads (the reported CPU baseline) and at one thread, and the
+    CPU cell-list DCM of the paper (Algorithms 2.2-2.3, OpenMP dynamic,20):
+    the whole system at all threads, a seeded sample at one thread.  Every leg
+    runs on the oracle's own cutoffs."""
     import numpy as np
 
     import oracle
     import workloads
 
     oracle.build(force=False)
+    threads = oracle.num_threads()
     det = oracle.detect_interface(s.x, s.y, s.z, s.box, s.h)
     rcg = oracle.rc_grid_for(s.rule, det["hv"])
     D, _ = oracle.fsm(det["nv"], det["hv"], det["seg"], det["iface"], rcg)
     rc = oracle.cutoffs(oracle.particle_distance(s.x, s.y, s.z, s.box, det["nv"], D), s.rule)
-    # a probe large enough that thread start-up does not dominate its time
-    probe = workloads.sample_indices(s.n, 512, seed=7)
-    t0 = time.perf_counter()
-    oracle.forces(s.x, s.y, s.z, rc, s.box, idx=probe)
-    per_i = (time.perf_counter() - t0) / len(probe)
-    k = int(max(64, min(s.n, seconds / max(per_i, 1e-9))))
-    idx = workloads.sample_indices(s.n, k, seed=8)
-    t0 = time.perf_counter()
-    out = oracle.forces(s.x, s.y, s.z, rc, s.box, idx=idx)
-    dt = time.perf_counter() - t0
-    pairs = int(np.sum(out["nnbr"]))
-    return dict(value=pairs / dt, unit="pair-interactions/s", cores=oracle.num_threads(),
-                kind="oracle",
+
+    def oracle_leg(budget, seed):
+        # a probe large enough that thread start-up does not dominate its time
+        probe = workloads.sample_indices(s.n, 512, seed=7)
+        t0 = time.perf_counter()
+        oracle.forces(s.x, s.y, s.z, rc, s.box, idx=probe)
+        per_i = (time.perf_counter() - t0) / len(probe)
+        k = int(max(64, min(s.n, budget / max(per_i, 1e-9))))
+        idx = workloads.sample_indices(s.n, k, seed=seed)
+        t0 = time.perf_counter()
+        out = oracle.forces(s.x, s.y, s.z, rc, s.box, idx=idx)
+        dt = time.perf_counter() - t0
+        pairs = int(np.sum(out["nnbr"]))
+        return k, pairs, dt
+
+    k, pairs, dt = oracle_leg(seconds, 8)
+    main = dict(value=pairs / dt, unit="pair-interactions/s", cores=threads, kind="oracle",
                 sample=f"O(N^2) oracle force sums for {k} seeded particles of {s.name} "
                        f"(all {s.n} j each), {pairs} interacting pairs in {dt:.1f} s")
+    detail = {}
+    edge = float(s.rule[0])  # small bins: the smallest cutoff (Section 2.3)
+    g = oracle.cpu_cells_forces(s.x, s.y, s.z, rc, s.box, edge)
+    detail["cell_list_all_threads"] = dict(
+        threads=threads, pair_rate=g["pairs"] / (g["t_build"] + g["t_force"]),
+        force_evals_per_s=1.0 / (g["t_build"] + g["t_force"]), list_build_s=g["t_build"],
+        force_loop_s=g["t_force"], pairs=g["pairs"],
+        sample=f"whole system ({s.n} particles), bins of {edge:g} sigma")
+    oracle.set_threads(1)
+    try:
+        k1, pairs1, dt1 = oracle_leg(max(2.0, seconds / 3.0), 9)
+        detail["oracle_1_thread"] = dict(
+            threads=1, pair_rate=pairs1 / dt1,
+            sample=f"{k1} seeded particles (all {s.n} j each), {pairs1} pairs in {dt1:.1f} s")
+        m = min(s.n, max(1000, int(0.04 * s.n)))
+        idx = workloads.sample_indices(s.n, m, seed=10)
+        g1 = oracle.cpu_cells_forces(s.x, s.y, s.z, rc, s.box, edge, idx=idx)
+        t1 = g1["t_build"] + g1["t_force"]
+        detail["cell_list_1_thread"] = dict(
+            threads=1, pair_rate=g1["pairs"] / t1, list_build_s=g1["t_build"],
+            force_loop_s=g1["t_force"], pairs=g1["pairs"],
+            sample=f"{m} seeded particles' lists and forces, bins of {edge:g} sigma")
+    finally:
+        oracle.set_threads(threads)
+    return main, detail
 
 
 def copy_calibration(mib):
@@ -522,10 +556,11 @@ def main():
     if not args.no_n3:
         n3 = n3_leg(s, dev)
         print(f"[bench] newton3 {json.dumps(n3)}", file=sys.stderr, flush=True)
-    cpu = None
+    cpu = cpu_detail = None
     if not args.no_cpu:
-        cpu = cpu_baseline(s, args.cpu_seconds)
-        print(f"[bench] cpu {json.dumps(cpu)}", file=sys.stderr, flush=True)
+        cpu, cpu_detail = cpu_baseline(s, args.cpu_seconds)
+        print(f"[bench] cpu {json.dumps(cpu)} {json.dumps(cpu_detail)}", file=sys.stderr,
+              flush=True)
     achieved = main_leg["pair_kernel_tflops"]
     # the vector peak of the arithmetic the pair kernel computes in
     peak = VALU_PEAK_FP32 if prec == dcm.DCM_FP32_MIXED else VALU_PEAK_FP64
@@ -570,6 +605,7 @@ def main():
         "verlet_list": vlist,
         "newton3": n3,
         "cpu_baseline": cpu,
+        "cpu_baselines": cpu_detail,
     }
     print(json.dumps(line), flush=True)
 

@@ -17,7 +17,10 @@ paper it follows:
   assignment, Section 2.2;
 * ``cells`` -- linked cells, Section 2.3;
 * ``forces`` -- Eqs. 2-3 and Algorithm 2.3 as an O(N^2) minimum-image sum;
-* ``kick`` / ``drift`` -- velocity Verlet, Fig. 3 box 5.
+* ``kick`` / ``drift`` -- velocity Verlet, Fig. 3 box 5;
+* ``cpu_cells_forces`` -- the CPU cell-list baseline (``cpu_cells.c``:
+  Algorithms 2.2-2.3 with OpenMP dynamic scheduling, Section 2.4), timed by
+  the benchmark for context and checked against ``forces``.
 
 Every function here is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` against closed forms, invariants and brute force.
@@ -34,6 +37,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dcm_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_CELLS_SRC = os.path.join(_HERE, "cpu_cells.c")
+_CELLS_PATH = os.path.join(_HERE, "libcpucells.so")
 _CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-msse4.1",
            "-fPIC", "-shared", "-std=c99", "-Wall"]
 
@@ -44,11 +49,13 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile dcm_oracle.c into liboracle.so next to it (gcc)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", *_CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
+    """Compile dcm_oracle.c into liboracle.so and the CPU cell-list baseline
+    cpu_cells.c into libcpucells.so next to them (gcc)."""
+    for src, path in ((_SRC, _LIB_PATH), (_CELLS_SRC, _CELLS_PATH)):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", *_CFLAGS, "-o", tmp, src, "-lm"])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
@@ -269,6 +276,48 @@ def forces(x, y, z, rc, box, eps: float = 1.0, sigma: float = 1.0, rule: int = R
                        float(sigma), int(rule), pidx, m, _p(fx), _p(fy), _p(fz), _p(nn),
                        _p(e), _p(w))
     return dict(fx=fx, fy=fy, fz=fz, nnbr=nn, E=float(e[0]), W=w)
+
+
+_cells_lib = None
+
+
+def cpu_cells_forces(x, y, z, rc, box, bin_edge: float, eps: float = 1.0, sigma: float = 1.0,
+                     idx: Optional[Sequence[int]] = None) -> dict:
+    """CPU cell-list baseline (cpu_cells.c): Algorithm 2.2's per-step list on
+    bins of edge >= bin_edge (the smallest cutoff: small bins, Section 2.3),
+    then Algorithm 2.3's force loop, both OpenMP dynamic,20 (Section 2.4).
+    Returns fx, fy, fz, nnbr (per listed i), E (half the listed i's pair
+    energies), pairs, and the seconds of the list build and of the force
+    loop.  Throughput context for the benchmark, checked against forces()."""
+    global _cells_lib
+    if _cells_lib is None:
+        if not os.path.exists(_CELLS_PATH):
+            build(force=True)
+        lib = ctypes.CDLL(_CELLS_PATH)
+        P = ctypes.c_void_p
+        lib.cpu_cells_forces.restype = ctypes.c_int64
+        lib.cpu_cells_forces.argtypes = [ctypes.c_int64, P, P, P, P, P, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
+                                         P, P, P, P, P, P, P]
+        _cells_lib = lib
+    x, y, z, rc = _f64(x), _f64(y), _f64(z), _f64(rc)
+    n = x.size
+    if idx is None:
+        m, pidx = n, None
+    else:
+        idx_arr = np.ascontiguousarray(idx, dtype=np.int64)
+        m, pidx = idx_arr.size, _p(idx_arr)
+    fx, fy, fz = (np.zeros(m, np.float64) for _ in range(3))
+    nn = np.zeros(m, np.int32)
+    out = np.zeros(3, np.float64)
+    pairs = _cells_lib.cpu_cells_forces(n, _p(x), _p(y), _p(z), _p(rc), _p(_box(box)),
+                                        float(bin_edge), float(eps), float(sigma), pidx, m,
+                                        _p(fx), _p(fy), _p(fz), _p(nn), _p(out[0:]),
+                                        _p(out[1:]), _p(out[2:]))
+    if pairs < 0:
+        raise MemoryError("cpu_cells_forces: out of memory")
+    return dict(fx=fx, fy=fy, fz=fz, nnbr=nn, E=float(out[0]), pairs=int(pairs),
+                t_build=float(out[1]), t_force=float(out[2]))
 
 
 def kick(v, f, dt: float, mass: float = 1.0):
