@@ -74,6 +74,7 @@ def run_leg(s, prec, steps, warmup, dev, redetect=1):
     ctx = dcm.dcm_create()
     try:
         dcm.dcm_step(ctx, *pos, *vel, *frc, s.box, lj, rule, grid, rcg, 0.005, 0, prec=prec, rc=rc)
+        cell_len = dcm.dcm_cell_dims(ctx)[1]  # the step's tuned cell edge
         if warmup:
             dcm.dcm_step(ctx, *pos, *vel, *frc, s.box, lj, rule, grid, rcg, 0.005, warmup,
                          prec=prec, redetect_every=redetect, rc=rc)
@@ -112,7 +113,7 @@ def run_leg(s, prec, steps, warmup, dev, redetect=1):
     pairs = 0.5 * (pairs_before + pairs_after)
     pair_ms, pair_launches = fam_ms["pair"]
     avg_pair_s = pair_ms / max(pair_launches, 1) / 1e3
-    return dict(wall=wall, ms_per_step=wall / steps * 1e3, pairs_per_step=pairs,
+    return dict(wall=wall, ms_per_step=wall / steps * 1e3, pairs_per_step=pairs, cell_len=cell_len,
                 pair_rate=pairs * steps / wall, force_evals=steps / wall,
                 avg_pair_ms=avg_pair_s * 1e3,
                 pair_kernel_tflops=pairs * FLOP_PER_PAIR_FE / avg_pair_s / 1e12,
@@ -581,7 +582,7 @@ def main():
                                f"N={s.n}, rc {s.rule[0]:g}-{s.rule[1]:g}, full DCM step "
                                "(re-detect every step)",
                    "n_particles": s.n, "pairs_per_step": main_leg["pairs_per_step"],
-                   "precision": args.prec},
+                   "precision": args.prec, "tuned_cell_edge": main_leg["cell_len"]},
         "force_evals_per_s": main_leg["force_evals"],
         "stage_ms": main_leg["stage_ms"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,

@@ -25,11 +25,12 @@
  *   (energies, virials, counters) are device scalars.  No call synchronises
  *   the stream except dcm_sync_status, dcm_create, dcm_destroy,
  *   dcm_build_list and dcm_update_list (they read a size or a verdict back),
- *   dcm_forces_batched when it tunes the cell edge of a new batch, and
- *   dcm_build_cells (and dcm_step through it) the first time it meets a cell
- *   geometry, when it reads its ghost-image count back to size the image
- *   buffer; a later build of the same geometry waits only for the previous
- *   build's count.
+ *   dcm_forces_batched when it tunes the cell edge of a new batch,
+ *   dcm_build_cells with cell_edge < 0 and dcm_step when they tune the cell
+ *   edge of a new system shape, and dcm_build_cells (and dcm_step through it)
+ *   the first time it meets a cell geometry, when it reads its ghost-image
+ *   count back to size the image buffer; a later build of the same geometry
+ *   waits only for the previous build's count.
  * - Scratch memory (grid buffers, cells, sorted copies, partial sums) is owned
  *   by the context and grown on demand; growing it allocates device memory,
  *   so call each entry point once with its largest sizes before capturing it
@@ -236,8 +237,14 @@ dcm_status dcm_assign_cutoffs(dcm_ctx *ctx, const double *x, const double *y,
                               double *rc);
 
 /* Linked cells (Section 2.3).  Cells of edge L_a/n_a with
- * n_a = floor(L_a/cell_edge) (cell_edge <= 0: a default of about two
- * particles per cell at the mean density), cell c = (c_z*n_y + c_y)*n_x + c_x.
+ * n_a = floor(L_a/cell_edge), cell c = (c_z*n_y + c_y)*n_x + c_x.
+ * cell_edge == 0: a default of about two particles per cell at the mean
+ * density.  cell_edge < 0: a measured choice among 1/3, 0.4, 1/2 and 0.6 of
+ * the smallest cutoff (for DCM_FP32_MIXED at most 2, the widest cell its
+ * compact records serve at sigma = 1): the first such call for a system
+ * shape (device, n, box, smallest cutoff, rc_bound, prec) times a cell build
+ * and a force pass (own rule, eps = sigma = 1) at each and synchronises; the
+ * choice is kept for the rest of the process.
  * Particles are sorted by cell (stable: ascending caller index within a cell)
  * into context-owned copies of (x, y, z, rc) that dcm_forces reads, together
  * with periodic ghost images of the cells within rc_bound of the box faces.
@@ -322,8 +329,12 @@ dcm_status dcm_forces_list(dcm_ctx *ctx, dcm_lj lj, int prec, int ev_flags, doub
  * step does v += dt/(2m) F; x += dt v (wrapped); re-detect the interface and
  * re-sweep the distances when (step0 + s + 1) % redetect_every == 0 or no
  * distance field exists yet; re-assign cutoffs and rebuild cells (every
- * step; cell edge rc_min / 2, for DCM_FP32_MIXED at most 2 sigma so that the
- * compact records apply); recompute F; v += dt/(2m) F.
+ * step); recompute F; v += dt/(2m) F.  The cell edge is a measured choice
+ * among 1/3, 0.4, 1/2 and 0.6 of rc_min (for DCM_FP32_MIXED at most 2 sigma,
+ * so that the compact records apply): the first call for a system shape
+ * (device, n, box, rc_min, rc_max, prec, pair_rule, sigma) in the process
+ * times a cell build and a force pass at each, synchronising once; later
+ * calls and contexts reuse the choice (dcm_cell_dims reports it).
  * energy_series (double [2*nsteps], optional): potential and kinetic energy
  * after each step.  delta/rc (double [n], optional) receive the last
  * distances and cutoffs.  The context keeps the last distance field between

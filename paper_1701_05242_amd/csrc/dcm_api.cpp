@@ -5,6 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "dcm_internal.hpp"
 
@@ -165,6 +169,79 @@ dcm_status check_n(dcm_ctx *ctx, int64_t n) {
     dcm_status st_ = (expr);           \
     if (st_ != DCM_OK) return st_;     \
   } while (0)
+
+// ---- cell-edge tuner (Section 2.3, small cells): the edge of the linked
+// cells is chosen among fractions of a reference cutoff r_ref (the smallest
+// cutoff) by timing a cell build plus a force pass at each, and remembered
+// for the rest of the process per system shape (device, particle count, box,
+// cutoff range, precision, rule, sigma), so that every context of a process
+// makes the same choice for the same system.
+std::mutex g_edge_mu;
+std::map<std::vector<double>, double> g_edge_cache;
+
+// r_ref/3, 0.4 r_ref, r_ref/2, 0.6 r_ref, each at most cap (the widest cell
+// the compact FP32 records serve, for FP32-mixed forces); repeats dropped
+std::vector<double> edge_candidates(double r_ref, double cap) {
+  std::vector<double> c;
+  for (double f : {1.0 / 3.0, 0.4, 0.5, 0.6}) {
+    const double e = std::min(f * r_ref, cap);
+    if (c.empty() || std::fabs(e - c.back()) > 1e-12 * e) c.push_back(e);
+  }
+  return c;
+}
+
+bool edge_cached(const std::vector<double> &key, double *edge) {
+  std::lock_guard<std::mutex> lock(g_edge_mu);
+  auto it = g_edge_cache.find(key);
+  if (it == g_edge_cache.end()) return false;
+  *edge = it->second;
+  return true;
+}
+
+// Times run(edge) (a cell build plus a force pass, enqueued on the context's
+// stream) once untimed and twice timed per candidate; synchronises.
+dcm_status tune_edge(dcm_ctx *ctx, const std::vector<double> &key,
+                     const std::vector<double> &cands,
+                     const std::function<dcm_status(double)> &run, double *best) {
+  if (edge_cached(key, best)) return DCM_OK;
+  double pick = cands.front();
+  if (cands.size() > 1) {
+    const bool prof = ctx->profile;
+    ctx->profile = false;  // the trials are not part of any kernel family's time
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      hipGetLastError();
+      if (e0) hipEventDestroy(e0);
+      ctx->profile = prof;
+      return fail(ctx, DCM_ERR_HIP, "cell-edge tuner: event creation failed");
+    }
+    float best_ms = INFINITY;
+    dcm_status st = DCM_OK;
+    for (double e : cands) {
+      if ((st = run(e)) != DCM_OK) break;  // first run: buffers grow, caches warm
+      hipEventRecord(e0, ctx->stream);
+      if ((st = run(e)) != DCM_OK || (st = run(e)) != DCM_OK) break;
+      hipEventRecord(e1, ctx->stream);
+      float ms = 0.0f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(ctx, DCM_ERR_HIP, "cell-edge tuner: timing failed");
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        pick = e;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->profile = prof;
+    if (st != DCM_OK) return st;
+  }
+  std::lock_guard<std::mutex> lock(g_edge_mu);
+  auto it = g_edge_cache.emplace(key, pick).first;  // a concurrent tuning may have won
+  *best = it->second;
+  return DCM_OK;
+}
 
 }  // namespace
 
@@ -416,10 +493,34 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   if (!std::isfinite(cell_edge)) return fail(ctx, DCM_ERR_INVALID, "cell_edge must be finite");
   if (!std::isfinite(rc_bound)) return fail(ctx, DCM_ERR_INVALID, "rc_bound must be finite");
   double edge = cell_edge;
-  if (edge <= 0.0) {
+  if (edge == 0.0) {
     // about two particles per cell at the mean density
     double vol = box.L[0] * box.L[1] * box.L[2];
     edge = std::cbrt(2.0 * vol / (double)std::max<int64_t>(n, 1));
+  } else if (edge < 0.0) {
+    // measured choice among fractions of the smallest cutoff
+    DCM_TRY(ensure(ctx, ctx->scalars, 16 * sizeof(double)));
+    double *d_min = ptr<double>(ctx->scalars) + 15;
+    launch_min_f64(ctx->stream, rc, n, d_min);
+    double r_ref = 0.0;
+    if (hipMemcpyAsync(&r_ref, d_min, sizeof(double), hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_build_cells: cutoff read-back failed");
+    const double half = 0.5 * std::min(box.L[0], std::min(box.L[1], box.L[2]));
+    if (!(r_ref > 0.0) || !std::isfinite(r_ref)) r_ref = rc_bound > 0.0 ? rc_bound : half;
+    const std::vector<double> key = {(double)ctx->device, (double)n, box.L[0], box.L[1],
+                                     box.L[2], r_ref, rc_bound, (double)prec, 1.0};
+    const double cap = prec == DCM_FP32_MIXED ? kRelMaxEdgeSigma : INFINITY;
+    const int64_t nn = std::max<int64_t>(n, 1);
+    DCM_TRY(ensure(ctx, ctx->tune_f, 3 * nn * sizeof(double)));
+    double *f = ptr<double>(ctx->tune_f);
+    auto run = [&](double e) -> dcm_status {
+      DCM_TRY(dcm_build_cells(ctx, x, y, z, rc, n, box, e, rc_bound, prec, nullptr, nullptr));
+      return dcm_forces(ctx, dcm_lj{1.0, 1.0}, DCM_PAIR_OWN, prec, DCM_EV_ENERGY, f, f + nn,
+                        f + 2 * nn, ptr<double>(ctx->scalars) + 14, nullptr, nullptr, nullptr);
+    };
+    DCM_TRY(tune_edge(ctx, key, edge_candidates(r_ref, cap), run, &edge));
   }
   int32_t nc[3];
   int64_t ncell = 1;
@@ -489,9 +590,17 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   }
   const double max_need = hard * (double)n + 64.0;  // the most any arrangement needs
   const bool known = same_geom && ctx->ext_exact >= 0 && !ctx->ext_copy_pending;
-  double want = known ? std::min(1.25 * (double)ctx->ext_exact + 4096.0, max_need)
-                      : std::min(1.5 * uniform * (double)n + 4096.0, max_need);
-  if (want > (double)kMaxExtSlots) want = (double)kMaxExtSlots;
+  // the buffer grows to 1.25 x the exact count (+4096) only when it holds
+  // less than 1.1 x (+1024), so a count creeping up between builds does not
+  // reallocate it every time
+  auto sizes = [&](double exact, double *need, double *want) {
+    *need = std::min(std::min(1.1 * exact + 1024.0, max_need), (double)kMaxExtSlots);
+    *want = std::min(std::min(1.25 * exact + 4096.0, max_need), (double)kMaxExtSlots);
+  };
+  double need = 0.0, want = 0.0;
+  if (known) sizes((double)ctx->ext_exact, &need, &want);
+  else need = want = std::min(std::min(1.5 * uniform * (double)n + 4096.0, max_need),
+                              (double)kMaxExtSlots);
   DCM_TRY(ensure(ctx, ctx->rcmax_part, cell_count_blocks(n) * sizeof(unsigned long long)));
   const int64_t nrow1 = ext_row_scratch_elems(nc, halo);
   DCM_TRY(ensure(ctx, ctx->ext_row_count, nrow1 * sizeof(int32_t)));
@@ -527,12 +636,11 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
         hipStreamSynchronize(s) != hipSuccess)
       return fail(ctx, DCM_ERR_HIP, "dcm_build_cells: ghost count read-back failed");
     ctx->ext_exact = *ctx->h_ext_total;
-    want = std::min(1.25 * (double)ctx->ext_exact + 4096.0, std::max(max_need, 1.0));
-    if (want > (double)kMaxExtSlots) want = (double)kMaxExtSlots;
+    sizes((double)ctx->ext_exact, &need, &want);
   }
   if (!capturing && ctx->ext_exact > kMaxExtSlots)
     return fail(ctx, DCM_ERR_RANGE, "ghost-extended system too large");
-  const int64_t ext_cap = std::max<int64_t>((int64_t)want, ctx->ext_cap);
+  const int64_t ext_cap = (double)ctx->ext_cap >= need ? ctx->ext_cap : (int64_t)want;
   DCM_TRY(ensure(ctx, ctx->ext_pos, ext_cap * sizeof(double4)));
   if (rel) DCM_TRY(ensure(ctx, ctx->ext_rel, ext_cap * sizeof(float4)));
   ctx->ext_cap = ext_cap;
@@ -932,16 +1040,30 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     ctx->field_particles = n;
     return DCM_OK;
   };
-  const double step_cell_edge =
-      prec == DCM_FP32_MIXED ? std::min(0.5 * rule.rc_min, kRelMaxEdgeSigma * lj.sigma)
-                             : 0.5 * rule.rc_min;
+  // small cells (Section 2.3): a measured choice between a third and 0.6 of
+  // the smallest cutoff, for FP32-mixed forces at most the widest cell the
+  // compact records serve (tuned on the first cell build of this system
+  // shape in the process, then remembered)
+  double step_cell_edge = 0.0;
+  const std::vector<double> edge_key = {
+      (double)ctx->device, (double)n,  box.L[0],        box.L[1],          box.L[2],
+      rule.rc_min,         rule.rc_max, (double)prec,   (double)pair_rule, lj.sigma};
+  const std::vector<double> edge_cands = edge_candidates(
+      rule.rc_min, prec == DCM_FP32_MIXED ? kRelMaxEdgeSigma * lj.sigma : INFINITY);
   // cutoffs, cells and forces of the working copies; the forces land in the
   // working order (the cells map sorted slots back to it)
   auto forces = [&](double *e_out) -> dcm_status {
     DCM_TRY(dcm_assign_cutoffs(ctx, W[WX], W[WY], W[WZ], n, box, grid, ptr<double>(ctx->dist),
                                rule, W[WDELTA], W[WRC]));
-    // small cells (Section 2.3): half the smallest cutoff, and for FP32-mixed
-    // forces at most the widest cell the compact records serve
+    if (step_cell_edge <= 0.0) {
+      auto run = [&](double e) -> dcm_status {
+        DCM_TRY(dcm_build_cells(ctx, W[WX], W[WY], W[WZ], W[WRC], n, box, e, rule.rc_max, prec,
+                                nullptr, nullptr));
+        return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, W[WFX], W[WFY], W[WFZ], scal,
+                          nullptr, nullptr, nullptr);
+      };
+      DCM_TRY(tune_edge(ctx, edge_key, edge_cands, run, &step_cell_edge));
+    }
     DCM_TRY(dcm_build_cells(ctx, W[WX], W[WY], W[WZ], W[WRC], n, box, step_cell_edge,
                             rule.rc_max, prec, nullptr, nullptr));
     return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, W[WFX], W[WFY], W[WFZ],

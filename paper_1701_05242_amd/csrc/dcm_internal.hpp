@@ -142,6 +142,7 @@ struct dcm_ctx {
   bool cells_moved = false;  // positions replaced by dcm_update_list since the build
   // particle scratch
   dcm::DevBuf delta, rc, partials, ke, scalars;
+  dcm::DevBuf tune_f;  // forces of the cell-edge tuner's trial passes (dcm_build_cells)
   // cells
   dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp, rcmax_part;
   dcm::DevBuf sort_tmp, sort_list;  // large-cell sort: scratch entries and the cells' list
@@ -221,6 +222,7 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n);
 void launch_fill_i32(hipStream_t s, int32_t *p, int32_t v, int64_t n);
 void launch_reset_ctl(hipStream_t s, Ctl *ctl);
+void launch_min_f64(hipStream_t s, const double *v, int64_t n, double *out);
 void launch_clear_status(hipStream_t s, uint32_t *st);
 
 // k_grid.hip

@@ -56,6 +56,34 @@ void launch_fill_u64(hipStream_t s, unsigned long long *p, unsigned long long v,
   hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
 }
 
+// Smallest finite non-negative value of v[0..n) into *out (+inf if none):
+// one workgroup, for the one-off reductions of the cell-edge tuner.
+__global__ __launch_bounds__(1024) void k_min_f64(const double *__restrict__ v, int64_t n,
+                                                  double *out) {
+  __shared__ double wmin[16];
+  double m = __builtin_huge_val();
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double x = v[i];
+    if (x >= 0.0 && x < m) m = x;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(m, off, 64);
+    m = o < m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) m = wmin[w] < m ? wmin[w] : m;
+    m = wmin[0] < m ? wmin[0] : m;
+    *out = m;
+  }
+}
+
+void launch_min_f64(hipStream_t s, const double *v, int64_t n, double *out) {
+  hipLaunchKernelGGL(k_min_f64, dim3(1), dim3(1024), 0, s, v, n, out);
+}
+
 void launch_reset_ctl(hipStream_t s, Ctl *ctl) {
   hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, s, ctl);
 }

@@ -376,6 +376,27 @@ __device__ __forceinline__ void x_neighbours(uint32_t lw, uint32_t w, uint32_t r
   c = (w >> 1) | (lastw ? ((rw & 1u) << top) : (rw << 31));
 }
 
+// Add the x-window sums (a + w + c per bit) of one row into the bit-sliced
+// 5-bit counters c0..c4 of a 27-window count.
+__device__ __forceinline__ void add_row_window(uint32_t a, uint32_t w, uint32_t c, uint32_t &c0,
+                                               uint32_t &c1, uint32_t &c2, uint32_t &c3,
+                                               uint32_t &c4) {
+  // x-window sum a + w + c as two bit slices
+  const uint32_t h0 = a ^ w ^ c;
+  const uint32_t h1 = (a & w) | (c & (a ^ w));
+  // add the 2-bit number (h1 h0) into the 5-bit counter
+  const uint32_t k0 = c0 & h0;
+  c0 ^= h0;
+  const uint32_t t1 = c1 ^ h1;
+  const uint32_t k1 = (c1 & h1) | (k0 & t1);
+  c1 = t1 ^ k0;
+  const uint32_t k2 = c2 & k1;
+  c2 ^= k1;
+  const uint32_t k3 = c3 & k2;
+  c3 ^= k2;
+  c4 ^= k3;
+}
+
 // One lane per word: the 27-window count of each of its 32 voxels as a
 // bit-sliced 5-bit number (c0..c4), then [count >= 14].
 __global__ __launch_bounds__(256) void k_majority(uint32_t *buf0, uint32_t *buf1, int nx, int ny,
@@ -409,20 +430,7 @@ __global__ __launch_bounds__(256) void k_majority(uint32_t *buf0, uint32_t *buf1
         if (dz == 0 && dy == 0) prev = w;
         uint32_t a, c;
         x_neighbours(r[kl], w, r[kr], first, lastw, top, a, c);
-        // x-window sum a + w + c as two bit slices
-        const uint32_t h0 = a ^ w ^ c;
-        const uint32_t h1 = (a & w) | (c & (a ^ w));
-        // add the 2-bit number (h1 h0) into the 5-bit counter
-        const uint32_t k0 = c0 & h0;
-        c0 ^= h0;
-        const uint32_t t1 = c1 ^ h1;
-        const uint32_t k1 = (c1 & h1) | (k0 & t1);
-        c1 = t1 ^ k0;
-        const uint32_t k2 = c2 & k1;
-        c2 ^= k1;
-        const uint32_t k3 = c3 & k2;
-        c3 ^= k2;
-        c4 ^= k3;
+        add_row_window(a, w, c, c0, c1, c2, c3, c4);
       }
     }
     // count >= 14: 16..27 have c4 set, 14 and 15 are 0111x

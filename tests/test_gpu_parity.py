@@ -324,6 +324,32 @@ def test_fp32_mixed_many_close_pairs(edge):
     assert rel(got["W"], ref["W"]) <= 1e-5
 
 
+@pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
+def test_tuned_cell_edge(prec):
+    """cell_edge < 0: the edge is one of the tuner's candidates (fractions of
+    the smallest cutoff, at most 2 sigma for FP32-mixed), the same on a second
+    context, and the forces are the oracle's."""
+    print(f"[gpu] tuned cell edge prec={prec}", flush=True)
+    s = workloads.make("slab_medium")
+    rc = ref_detect("slab_medium")["rc"]
+    r_ref = float(np.min(rc))
+    cands = sorted({min(f * r_ref, 2.0 if prec == dcm.DCM_FP32_MIXED else 1e9)
+                    for f in (1.0 / 3.0, 0.4, 0.5, 0.6)})
+    got = gpu_forces(s, rc, prec=prec, edge=-1.0, rc_bound=s.rule[1])
+    again = gpu_forces(s, rc, prec=prec, edge=-1.0, rc_bound=s.rule[1])
+    dims = got["dims"]
+    edge_used = [s.box[a] / dims[0][a] for a in range(3)]
+    assert any(all(int(np.floor(s.box[a] / c)) == dims[0][a] for a in range(3)) for c in cands), \
+        (dims, cands, edge_used)
+    assert again["dims"][0] == dims[0]
+    np.testing.assert_array_equal(again["F"], got["F"])
+    ref = ref_forces("slab_medium", dcm.DCM_PAIR_OWN)
+    np.testing.assert_array_equal(got["nnbr"], ref["nnbr"])
+    tol = 1e-12 if prec == dcm.DCM_FP64 else 1e-5
+    emax, erms = force_errors(got["F"], _ref_F(ref))
+    assert emax <= tol and erms <= tol
+
+
 # 7.0: one cell across x and y (13.4 sigma), so the halo of two cells is
 # wider than the grid and the ghost rows wrap the box more than once
 @pytest.mark.parametrize("edge", [0.0, 0.7, 1.9, 3.3, 7.0])
