@@ -47,6 +47,10 @@ def parse():
     p.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
     p.add_argument("--no-list", action="store_true", help="skip the Verlet-list leg")
     p.add_argument("--no-n3", action="store_true", help="skip the Newton's-third-law leg")
+    p.add_argument("--no-table1", action="store_true",
+                   help="skip the Table 1 analogue (DCM vs static cutoff, 1.2M-particle slab)")
+    p.add_argument("--no-curved", action="store_true",
+                   help="skip the droplet and cylinder legs (FP32-mixed and FP64)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--table1", action="store_true",
                    help="only run the DCM-versus-static-cutoff timing of the paper's Table 1 "
@@ -184,6 +188,29 @@ def table1_leg(steps, warmup, dev, prec):
                 workload=f"slab_table1: 120x120x250 LJ slab, N={s.n}, liquid 75 <= z < 175",
                 steps=steps, warmup=warmup, precision="fp32_mixed" if prec else "fp64",
                 redetect_every=10, rows=rows)
+
+
+def curved_leg(steps, warmup, dev):
+    """The curved-interface workloads (a droplet of radius 30 and a cylinder of
+    radius 25): the full DCM step with re-detection every step, FP32-mixed and
+    FP64."""
+    import workloads
+
+    out = {}
+    for name in ("droplet", "cylinder"):
+        s = workloads.make(name)
+        legs = {}
+        for tag, prec in (("fp32_mixed", 1), ("fp64", 0)):
+            r = run_leg(s, prec, steps, warmup, dev)
+            legs[tag] = {"ms_per_step": r["ms_per_step"], "pair_rate": r["pair_rate"],
+                         "pair_kernel_ms": r["avg_pair_ms"], "tuned_cell_edge": r["cell_len"]}
+        legs["n_particles"] = s.n
+        legs["pairs_per_step"] = r["pairs_per_step"]
+        legs["fp32_mixed_speedup_per_step"] = (legs["fp64"]["ms_per_step"] /
+                                               legs["fp32_mixed"]["ms_per_step"])
+        out[name] = legs
+        print(f"[bench] curved {name} {json.dumps(legs)}", file=sys.stderr, flush=True)
+    return out
 
 
 def batched_leg(steps, dev):
@@ -557,6 +584,12 @@ def main():
     if not args.no_n3:
         n3 = n3_leg(s, dev)
         print(f"[bench] newton3 {json.dumps(n3)}", file=sys.stderr, flush=True)
+    curved = None
+    if not args.no_curved:
+        curved = curved_leg(max(5, args.steps // 2), 2, dev)
+    table1 = None
+    if not args.no_table1:
+        table1 = table1_leg(max(5, args.steps // 2), 2, dev, prec)
     cpu = cpu_detail = None
     if not args.no_cpu:
         cpu, cpu_detail = cpu_baseline(s, args.cpu_seconds)
@@ -605,6 +638,8 @@ def main():
         "batched": batched,
         "verlet_list": vlist,
         "newton3": n3,
+        "curved": curved,
+        "table1": table1,
         "cpu_baseline": cpu,
         "cpu_baselines": cpu_detail,
     }
