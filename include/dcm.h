@@ -239,14 +239,16 @@ dcm_status dcm_assign_cutoffs(dcm_ctx *ctx, const double *x, const double *y,
 /* Linked cells (Section 2.3).  Cells of edge L_a/n_a with
  * n_a = floor(L_a/cell_edge), cell c = (c_z*n_y + c_y)*n_x + c_x.
  * cell_edge == 0: a default of about two particles per cell at the mean
- * density.  cell_edge < 0: a measured choice among 1/3, 0.4, 1/2 and 0.6 of
- * the smallest cutoff (for DCM_FP32_MIXED at most 2, the widest cell its
- * compact records serve at sigma = 1): the first such call for a system
+ * density.  cell_edge < 0: a measured choice among 1/3, 0.4, 1/2, 0.6, 0.7
+ * and 0.8 of the smallest cutoff (for DCM_FP32_MIXED at most the widest edge
+ * whose cells stay within 2, the widest cell its compact records serve at
+ * sigma = 1): the first such call for a system
  * shape (device, n, box, smallest cutoff, rc_bound, prec) times a cell build
  * and a force pass (own rule, eps = sigma = 1) at each and synchronises; the
  * choice is kept for the rest of the process.
- * Particles are sorted by cell (stable: ascending caller index within a cell)
- * into context-owned copies of (x, y, z, rc) that dcm_forces reads, together
+ * Particles are sorted by cell and, within a cell, by x (positions quantised
+ * to 2^-20 of the cell; ties in ascending caller index) into context-owned
+ * copies of (x, y, z, rc) that dcm_forces reads, together
  * with periodic ghost images of the cells within rc_bound of the box faces.
  * rc_bound is an upper bound on every cutoff (<= 0: half the shortest box
  * edge); larger cutoffs are clamped to it and flag DCM_ERR_RANGE, and so do
@@ -330,8 +332,9 @@ dcm_status dcm_forces_list(dcm_ctx *ctx, dcm_lj lj, int prec, int ev_flags, doub
  * re-sweep the distances when (step0 + s + 1) % redetect_every == 0 or no
  * distance field exists yet; re-assign cutoffs and rebuild cells (every
  * step); recompute F; v += dt/(2m) F.  The cell edge is a measured choice
- * among 1/3, 0.4, 1/2 and 0.6 of rc_min (for DCM_FP32_MIXED at most 2 sigma,
- * so that the compact records apply): the first call for a system shape
+ * among 1/3, 0.4, 1/2, 0.6, 0.7 and 0.8 of rc_min (for DCM_FP32_MIXED at most
+ * the widest edge whose cells stay within 2 sigma, so that the compact
+ * records apply): the first call for a system shape
  * (device, n, box, rc_min, rc_max, prec, pair_rule, sigma) in the process
  * times a cell build and a force pass at each, synchronising once; later
  * calls and contexts reuse the choice (dcm_cell_dims reports it).

@@ -179,12 +179,17 @@ dcm_status check_n(dcm_ctx *ctx, int64_t n) {
 std::mutex g_edge_mu;
 std::map<std::vector<double>, double> g_edge_cache;
 
-// r_ref/3, 0.4 r_ref, r_ref/2, 0.6 r_ref, each at most cap (the widest cell
-// the compact FP32 records serve, for FP32-mixed forces); repeats dropped
-std::vector<double> edge_candidates(double r_ref, double cap) {
+// f r_ref for f = 1/3, 0.4, 1/2, 0.6, 0.7, 0.8, each at most the widest
+// edge whose cells (of length L_a / floor(L_a / edge) >= edge) stay within
+// cap (the widest cell the compact FP32 records serve, for FP32-mixed
+// forces); repeats dropped
+std::vector<double> edge_candidates(double r_ref, double cap, const double L[3]) {
+  double top = cap;
+  if (std::isfinite(cap))
+    for (int a = 0; a < 3; ++a) top = std::min(top, L[a] / std::ceil(L[a] / cap));
   std::vector<double> c;
-  for (double f : {1.0 / 3.0, 0.4, 0.5, 0.6}) {
-    const double e = std::min(f * r_ref, cap);
+  for (double f : {1.0 / 3.0, 0.4, 0.5, 0.6, 0.7, 0.8}) {
+    const double e = std::min(f * r_ref, top);
     if (c.empty() || std::fabs(e - c.back()) > 1e-12 * e) c.push_back(e);
   }
   return c;
@@ -520,7 +525,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
       return dcm_forces(ctx, dcm_lj{1.0, 1.0}, DCM_PAIR_OWN, prec, DCM_EV_ENERGY, f, f + nn,
                         f + 2 * nn, ptr<double>(ctx->scalars) + 14, nullptr, nullptr, nullptr);
     };
-    DCM_TRY(tune_edge(ctx, key, edge_candidates(r_ref, cap), run, &edge));
+    DCM_TRY(tune_edge(ctx, key, edge_candidates(r_ref, cap, box.L), run, &edge));
   }
   int32_t nc[3];
   int64_t ncell = 1;
@@ -607,6 +612,14 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   DCM_TRY(ensure(ctx, ctx->ext_row_start, nrow1 * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->ext_row_lo, nrow1 * sizeof(int32_t)));
   DCM_TRY(ensure(ctx, ctx->ext_start, (next + 1) * sizeof(int32_t)));
+  // the trimming table (the pair walk's x trimming), unless the extended
+  // grid is too large for it
+  const bool qtab = next < kQStartMaxCells;
+  if (qtab) {
+    DCM_TRY(ensure(ctx, ctx->ext_sq, (next + 1) * sizeof(int2)));
+    DCM_TRY(ensure(ctx, ctx->qword, std::max<int64_t>(ncell, 1) * sizeof(uint32_t)));
+  }
+  DCM_TRY(ensure(ctx, ctx->xkey, std::max<int64_t>(n, 1) * sizeof(uint32_t)));
   DCM_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_elems(std::max(ncell, nrow1)) * sizeof(int32_t)));
   // FP32-mixed builds also write the compact records the pair kernel reads
   const bool rel = prec == DCM_FP32_MIXED && halo[1] <= kRelMaxHalo && halo[2] <= kRelMaxHalo;
@@ -615,20 +628,23 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   timer_begin(ctx, "cells", &ev);
   launch_fill_i32(s, ptr<int32_t>(ctx->cell_count), 0, ncell);
   launch_cell_count(s, x, y, z, rc, n, box.L, nc, sc, rc_cap, cof, ptr<int32_t>(ctx->cell_count),
-                    ptr<unsigned long long>(ctx->rcmax_part), ctx->ctl, ctx->d_status);
+                    ptr<unsigned long long>(ctx->rcmax_part), ptr<uint32_t>(ctx->xkey), ctx->ctl,
+                    ctx->d_status);
   launch_exclusive_scan(s, ptr<int32_t>(ctx->cell_count), ptr<int32_t>(ctx->cell_start), ncell,
                         ptr<int32_t>(ctx->scan_tmp));
   launch_fill_i32(s, ptr<int32_t>(ctx->cell_fill), 0, ncell);
   launch_cell_scatter(s, cof, n, ptr<int32_t>(ctx->cell_start), ptr<int32_t>(ctx->cell_fill),
                       ptr<int32_t>(ctx->perm));
-  launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, ptr<int32_t>(ctx->perm),
+  launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, cof, n, ptr<int32_t>(ctx->perm),
+                   ptr<uint32_t>(ctx->xkey), qtab ? ptr<uint32_t>(ctx->qword) : nullptr,
                    ptr<int32_t>(ctx->sort_tmp), ptr<int32_t>(ctx->sort_list), &ctx->ctl->big_cells);
-  launch_gather(s, x, y, z, rc, ptr<int32_t>(ctx->perm), n, box.L, rc_cap,
-                ptr<double4>(ctx->sorted));
+  launch_gather(s, x, y, z, rc, ptr<int32_t>(ctx->sort_tmp), n, box.L, rc_cap,
+                ptr<double4>(ctx->sorted), ptr<int32_t>(ctx->perm));
   launch_ext_count(s, ptr<int32_t>(ctx->cell_start), nc, halo, box.L,
                    ptr<int32_t>(ctx->ext_row_count), ptr<int32_t>(ctx->ext_row_start),
                    ptr<int32_t>(ctx->ext_row_lo), ptr<int32_t>(ctx->ext_start),
-                   ptr<int32_t>(ctx->scan_tmp));
+                   ptr<int32_t>(ctx->scan_tmp), qtab ? ptr<uint32_t>(ctx->qword) : nullptr,
+                   qtab ? ptr<int2>(ctx->ext_sq) : nullptr);
   if (!known && !capturing) {
     // a new geometry: this build's exact count sizes the buffers
     if (hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
@@ -673,6 +689,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   ctx->ext_src_ok = false;
   ctx->cell_prec = prec;
   ctx->cell_rel = rel;
+  ctx->cell_qtab = qtab;
   ctx->rc_bound = rc_cap;
   return check_launch(ctx, "dcm_build_cells");
 }
@@ -732,6 +749,7 @@ dcm_status forces_impl(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_
     span = std::max(span, ctx->cell_box.L[k] + 2.0 * ctx->halo[k] * ctx->cell_len[k]);
   a.rel_delta = rel_record_delta(ctx->cell_len, span);
   a.ext_start = ptr<int32_t>(ctx->ext_start);
+  a.ext_sq = ctx->cell_qtab ? ptr<int2>(ctx->ext_sq) : nullptr;
   a.n = n;
   a.ext_cap = ctx->ext_cap;
   for (int k = 0; k < 3; ++k) {
@@ -1040,7 +1058,7 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     ctx->field_particles = n;
     return DCM_OK;
   };
-  // small cells (Section 2.3): a measured choice between a third and 0.6 of
+  // small cells (Section 2.3): a measured choice between a third and 0.8 of
   // the smallest cutoff, for FP32-mixed forces at most the widest cell the
   // compact records serve (tuned on the first cell build of this system
   // shape in the process, then remembered)
@@ -1049,7 +1067,7 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
       (double)ctx->device, (double)n,  box.L[0],        box.L[1],          box.L[2],
       rule.rc_min,         rule.rc_max, (double)prec,   (double)pair_rule, lj.sigma};
   const std::vector<double> edge_cands = edge_candidates(
-      rule.rc_min, prec == DCM_FP32_MIXED ? kRelMaxEdgeSigma * lj.sigma : INFINITY);
+      rule.rc_min, prec == DCM_FP32_MIXED ? kRelMaxEdgeSigma * lj.sigma : INFINITY, box.L);
   // cutoffs, cells and forces of the working copies; the forces land in the
   // working order (the cells map sorted slots back to it)
   auto forces = [&](double *e_out) -> dcm_status {

@@ -14,7 +14,7 @@ namespace {
 
 constexpr int kItem = 256;  // particles per work item = pair kernel block
 // cell edges the tuner tries for systems that leave the edge to the library
-constexpr double kTuneEdges[] = {1.0, 1.15, 1.3, 1.5};
+constexpr double kTuneEdges[] = {1.0, 1.15, 1.3, 1.5, 1.75};
 
 template <typename T>
 T *dptr(const DevBuf &b, size_t byte_off = 0) {
@@ -47,7 +47,7 @@ struct BatchState {
   // device memory
   DevBuf tables, cell_of, cell_count, cell_fill, cell_start, perm, sorted, scan_tmp, row_count,
       row_start, row_lo, ext_start, ext_pos, ext_rel, partials, rcmax, rcmax_part, head,
-      sort_tmp, sort_list;
+      sort_tmp, sort_list, xkey, qword, ext_sq;
   // recorded graph
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -220,6 +220,11 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
     return st;
   if ((st = ensure(ctx, B.perm, sizeof(int32_t) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
     return st;
+  if ((st = ensure(ctx, B.xkey, sizeof(uint32_t) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
+    return st;
+  if ((st = ensure(ctx, B.qword, sizeof(uint32_t) * std::max<int64_t>(B.cells_total, 1))) !=
+      DCM_OK)
+    return st;
   if ((st = ensure(ctx, B.sorted, sizeof(double4) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
     return st;
   if ((st = ensure(ctx, B.scan_tmp,
@@ -231,6 +236,7 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   if ((st = ensure(ctx, B.row_lo, sizeof(int32_t) * (B.ext_rows_total + 1))) != DCM_OK) return st;
   if ((st = ensure(ctx, B.ext_start, sizeof(int32_t) * (B.ext_cells_total + 1))) != DCM_OK)
     return st;
+  if ((st = ensure(ctx, B.ext_sq, sizeof(int2) * (B.ext_cells_total + 1))) != DCM_OK) return st;
   if ((st = ensure(ctx, B.ext_pos, sizeof(double4) * B.ext_cap)) != DCM_OK) return st;
   if (B.rel_ok && (st = ensure(ctx, B.ext_rel, sizeof(float4) * B.ext_cap)) != DCM_OK) return st;
   if ((st = ensure(ctx, B.partials,
@@ -274,21 +280,25 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   launch_fill_u32(s, dptr<uint32_t>(B.head), 0u, 2);
   launch_batch_cell_count(s, geo, nsys, items, nitems, dptr<int32_t>(B.cell_of),
                           dptr<int32_t>(B.cell_count), dptr<unsigned long long>(B.rcmax_part),
-                          dptr<unsigned long long>(B.rcmax), ctx->d_status);
+                          dptr<unsigned long long>(B.rcmax), dptr<uint32_t>(B.xkey),
+                          ctx->d_status);
   launch_exclusive_scan(s, dptr<int32_t>(B.cell_count), dptr<int32_t>(B.cell_start),
                         B.cells_total, dptr<int32_t>(B.scan_tmp));
   launch_batch_cell_scatter(s, geo, items, nitems, dptr<int32_t>(B.cell_of),
                             dptr<int32_t>(B.cell_start), dptr<int32_t>(B.cell_fill),
                             dptr<int32_t>(B.perm));
-  launch_cell_sort(s, dptr<int32_t>(B.cell_start), B.cells_total, dptr<int32_t>(B.perm),
-                   dptr<int32_t>(B.sort_tmp), dptr<int32_t>(B.sort_list),
+  launch_cell_sort(s, dptr<int32_t>(B.cell_start), B.cells_total, dptr<int32_t>(B.cell_of),
+                   B.n_total, dptr<int32_t>(B.perm), dptr<uint32_t>(B.xkey),
+                   dptr<uint32_t>(B.qword), dptr<int32_t>(B.sort_tmp), dptr<int32_t>(B.sort_list),
                    dptr<uint32_t>(B.head) + 1);
-  launch_batch_gather(s, geo, items, nitems, dptr<int32_t>(B.perm), dptr<double4>(B.sorted));
+  launch_batch_gather(s, geo, items, nitems, dptr<int32_t>(B.sort_tmp), dptr<double4>(B.sorted),
+                      dptr<int32_t>(B.perm));
   launch_batch_ext(s, geo, eblk, (int64_t)B.eblk.size(), dptr<int2>(B.tables, B.off_rblk),
                    (int64_t)B.rblk.size(), dptr<int32_t>(B.cell_start), dptr<double4>(B.sorted),
                    B.ext_cells_total, B.ext_rows_total, B.ext_cap, dptr<int32_t>(B.row_count),
                    dptr<int32_t>(B.row_start), dptr<int32_t>(B.row_lo), dptr<int32_t>(B.ext_start),
-                   dptr<int32_t>(B.scan_tmp), dptr<double4>(B.ext_pos), rel, ctx->d_status);
+                   dptr<int32_t>(B.scan_tmp), dptr<double4>(B.ext_pos), rel,
+                   dptr<uint32_t>(B.qword), dptr<int2>(B.ext_sq), ctx->d_status);
   if (timed) timer_end(ctx, "batch_cells", ev);
   BatchPairArgs a;
   a.sys = geo;
@@ -302,6 +312,7 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   a.ext_pos = dptr<double4>(B.ext_pos);
   a.ext_rel = rel;
   a.ext_start = dptr<int32_t>(B.ext_start);
+  a.ext_sq = dptr<int2>(B.ext_sq);
   a.ext_cap = B.ext_cap;
   a.rc_max_bits = dptr<unsigned long long>(B.rcmax);
   a.eps = lj.epsilon;

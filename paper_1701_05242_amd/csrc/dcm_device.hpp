@@ -30,6 +30,16 @@ __device__ __forceinline__ int slab_index(double w, double scale, int n) {
   return c;
 }
 
+// x key of a particle in cell c of the slab grid (scale = n/L): its offset
+// into the cell, (w scale - c), in units of 2^-20 of the cell, clamped to
+// [0, 2^20).  Cells keep their particles in key order; quarter q of a cell
+// holds the keys [q 2^18, (q+1) 2^18).
+constexpr uint32_t kXKeyOne = 1u << 20;
+__device__ __forceinline__ uint32_t x_key(double w, double scale, int c) {
+  const double f = (w * scale - (double)c) * (double)kXKeyOne;
+  return f > 0.0 ? (f < (double)(kXKeyOne - 1) ? (uint32_t)f : kXKeyOne - 1) : 0u;
+}
+
 __device__ __forceinline__ int wrap_index(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;

@@ -145,6 +145,10 @@ struct dcm_ctx {
   dcm::DevBuf tune_f;  // forces of the cell-edge tuner's trial passes (dcm_build_cells)
   // cells
   dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp, rcmax_part;
+  // x key of every particle (within-cell order), quarter word of every real
+  // cell and (start, quarter word) of every extended cell (the pair walk's
+  // x trimming)
+  dcm::DevBuf xkey, qword, ext_sq;
   dcm::DevBuf sort_tmp, sort_list;  // large-cell sort: scratch entries and the cells' list
   dcm::DevBuf ext_row_count, ext_row_start, ext_row_lo, ext_start, ext_pos;
   dcm::DevBuf ext_rel;  // FP32-mixed builds: compact cell-relative copy of ext_pos
@@ -168,6 +172,7 @@ struct dcm_ctx {
   int64_t cell_n = -1;
   int cell_prec = 0;
   bool cell_rel = false;  // the last build wrote ext_rel
+  bool cell_qtab = false; // ... and the trimming table ext_sq
   // dcm_step's working copies in cell order: two sets of 11 fields (x y z,
   // vx vy vz, fx fy fz, delta, rc) and the caller index of each slot
   dcm::DevBuf ws[2], ws_owner[2];
@@ -274,29 +279,39 @@ int64_t cell_count_blocks(int64_t n);
 void launch_cell_count(hipStream_t s, const double *x, const double *y, const double *z,
                        const double *rc, int64_t n, const double L[3], const int32_t nc[3],
                        const double sc[3], double rc_cap, int32_t *cell_of, int32_t *cell_count,
-                       unsigned long long *block_max, Ctl *ctl, uint32_t *status);
+                       unsigned long long *block_max, uint32_t *xq, Ctl *ctl, uint32_t *status);
 void launch_exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64_t n,
                            int32_t *tmp);
 int64_t scan_tmp_elems(int64_t n);
 void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
                          const int32_t *cell_start, int32_t *cell_fill, int32_t *perm);
-// sort each cell's entries of perm by value; tmp holds n entries, big_list
-// cell_sort_list_elems(n), big_count must be 0 on entry
-void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell, int32_t *perm,
-                      int32_t *tmp, int32_t *big_list, uint32_t *big_count);
+// sorted_perm receives the entries of perm (particle ids in cell order, cell
+// c of particle id holding cell_of[id]) with each cell's sorted by (x key
+// xq[id], id); perm is left as scratch.  qword (null: none) receives the
+// cells' quarter words: bytes o1, o2, o3 (particles below 1/4, 1/2, 3/4 of
+// the cell along x) and the count, 0 for cells of more than 255.  big_list
+// holds cell_sort_list_elems(n) entries; big_count must be 0 on entry.
+void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell,
+                      const int32_t *cell_of, int64_t n, int32_t *perm, const uint32_t *xq,
+                      uint32_t *qword, int32_t *sorted_perm, int32_t *big_list,
+                      uint32_t *big_count);
 int64_t cell_sort_list_elems(int64_t n);
+// sorted copy (x, y, z, rc) in the order order[] of particle ids, which is
+// also copied to perm
 void launch_gather(hipStream_t s, const double *x, const double *y, const double *z,
-                   const double *rc, const int32_t *perm, int64_t n, const double L[3],
-                   double rc_cap, double4 *sorted);
+                   const double *rc, const int32_t *order, int64_t n, const double L[3],
+                   double rc_cap, double4 *sorted, int32_t *perm);
 // rows of the extended grid + 1: the size of each per-row scratch array
 int64_t ext_row_scratch_elems(const int32_t nc[3], const int32_t h[3]);
 // ghost-extended cells in two parts: the per-row tables and the extended
 // cell starts (ext_start[next] then holds the extended particle count), and
-// the images themselves into buffers of ext_cap slots
+// the images themselves into buffers of ext_cap slots.  ext_sq (null: none;
+// int2 [next + 1]) receives (ext_start, quarter word of the real cell) of
+// every extended cell and (extended count, 0) past the last.
 void launch_ext_count(hipStream_t s, const int32_t *cell_start, const int32_t nc[3],
                       const int32_t h[3], const double L[3], int32_t *row_count,
                       int32_t *row_start, int32_t *row_lo, int32_t *ext_start,
-                      int32_t *scan_tmp);
+                      int32_t *scan_tmp, const uint32_t *qword, int2 *ext_sq);
 void launch_ext_images(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,
                        const int32_t *row_lo, const double4 *sorted, const int32_t nc[3],
                        const int32_t h[3], const double L[3], int64_t ext_cap, double4 *ext_pos,
@@ -312,6 +327,10 @@ void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *
                        const int32_t h[3], const double L[3], int64_t ext_cap, double4 *ext_pos,
                        uint32_t *status);
 
+// Extended grids of at least this many cells get no trimming table (its
+// 32-bit byte offsets would overflow): their pair walks take whole end cells.
+constexpr int64_t kQStartMaxCells = int64_t(1) << 28;
+
 // k_pair.hip
 struct PairArgs {
   const double4 *pos;        // sorted real particles (x, y, z, rc), wrapped into the box
@@ -321,6 +340,7 @@ struct PairArgs {
   const float4 *ext_rel;     // compact cell-relative copy of ext_pos, or null
   double rel_delta;          // its per-coordinate error bound
   const int32_t *ext_start;  // extended cells [next + 1]
+  const int2 *ext_sq;        // (start, quarter word) of the extended cells [next + 1], or null
   int64_t n;
   int64_t ext_cap;           // capacity of ext_pos
   int32_t nc[3];
@@ -395,6 +415,7 @@ struct BatchPairArgs {
   const float4 *ext_rel;      // compact cell-relative copy of ext_pos, or null
   const double4 *ext_pos;
   const int32_t *ext_start;   // concatenated extended cells
+  const int2 *ext_sq;         // their (start, quarter word) [cells + 1], or null
   int64_t ext_cap;
   const unsigned long long *rc_max_bits;  // per system
   double eps, sigma;
@@ -410,18 +431,18 @@ void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int pr
 void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, int32_t nsys, const int2 *pblk,
                              int64_t npblk, int32_t *cell_of, int32_t *cell_count,
                              unsigned long long *block_max, unsigned long long *rc_max_bits,
-                             uint32_t *status);
+                             uint32_t *xq, uint32_t *status);
 void launch_batch_cell_scatter(hipStream_t s, const SysGeom *sys, const int2 *pblk,
                                int64_t npblk, const int32_t *cell_of, const int32_t *cell_start,
                                int32_t *cell_fill, int32_t *perm);
 void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
-                         const int32_t *perm, double4 *sorted);
+                         const int32_t *order, double4 *sorted, int32_t *perm);
 void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64_t neblk,
                       const int2 *rblk, int64_t nrblk, const int32_t *cell_start,
                       const double4 *sorted, int64_t next_total, int64_t nrows_total,
                       int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
                       int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
-                      uint32_t *status);
+                      const uint32_t *qword, int2 *ext_sq, uint32_t *status);
 void launch_batch_reduce(hipStream_t s, const SysGeom *sys, int32_t nsys,
                          const double *partials, int ev_flags);
 void launch_fill_u64(hipStream_t s, unsigned long long *p, unsigned long long v, int64_t n);

@@ -30,11 +30,13 @@ __device__ __forceinline__ ExtGeom ext_geom(const SysGeom &g) {
   return e;
 }
 
-// Cell of every particle (concatenated cell index), per-cell counts, and the
-// largest cutoff of each workgroup (reduced per system by kb_reduce_rcmax).
+// Cell of every particle (concatenated cell index), its x key, per-cell
+// counts, and the largest cutoff of each workgroup (reduced per system by
+// kb_reduce_rcmax).
 __global__ __launch_bounds__(kBatchBlock) void kb_cell_count(
     const SysGeom *__restrict__ sys, const int2 *__restrict__ pblk, int32_t *__restrict__ cell_of,
-    int32_t *count, unsigned long long *__restrict__ block_max, uint32_t *status) {
+    int32_t *count, unsigned long long *__restrict__ block_max, uint32_t *__restrict__ xq,
+    uint32_t *status) {
   int64_t first;
   const int b = block_system(pblk, first);
   const SysGeom &g = sys[b];
@@ -46,14 +48,18 @@ __global__ __launch_bounds__(kBatchBlock) void kb_cell_count(
     const double px = g.x[i], py = g.y[i], pz = g.z[i];
     double r = g.rc[i];
     int lc = 0;
+    uint32_t q = 0;
     if (finite3(px, py, pz)) {
-      const int cx = slab_index(wrap_coord(px, g.L[0]), g.sc[0], g.nc[0]);
+      const double wx = wrap_coord(px, g.L[0]);
+      const int cx = slab_index(wx, g.sc[0], g.nc[0]);
       const int cy = slab_index(wrap_coord(py, g.L[1]), g.sc[1], g.nc[1]);
       const int cz = slab_index(wrap_coord(pz, g.L[2]), g.sc[2], g.nc[2]);
       lc = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+      q = x_key(wx, g.sc[0], cx);
     } else {
       atomicOr(status, ST_NONFINITE_POS);
     }
+    xq[g.p0 + i] = q;
     if (!(r >= 0.0) || r > g.rc_cap) {
       atomicOr(status, ST_RC_RANGE);
       r = (r > g.rc_cap) ? g.rc_cap : 0.0;
@@ -118,18 +124,22 @@ __global__ __launch_bounds__(kBatchBlock) void kb_cell_scatter(
   if (valid) perm[cell_start[c] + slot] = (int32_t)(g.p0 + i);
 }
 
-// Sorted copy (x, y, z, rc) with positions wrapped into each system's box.
+// Sorted copy (x, y, z, rc) in the order order[] (concatenated ids, copied
+// to perm) with positions wrapped into each system's box.
 __global__ __launch_bounds__(kBatchBlock) void kb_gather(const SysGeom *__restrict__ sys,
                                                          const int2 *__restrict__ pblk,
-                                                         const int32_t *__restrict__ perm,
-                                                         double4 *__restrict__ sorted) {
+                                                         const int32_t *__restrict__ order,
+                                                         double4 *__restrict__ sorted,
+                                                         int32_t *__restrict__ perm) {
   int64_t first;
   const int b = block_system(pblk, first);
   const SysGeom &g = sys[b];
   const int64_t k = first + threadIdx.x;
   if (k >= g.n) return;
   const int64_t s = g.p0 + k;
-  const int64_t i = perm[s] - g.p0;
+  const int32_t id = order[s];
+  perm[s] = id;
+  const int64_t i = id - g.p0;
   const double px = g.x[i], py = g.y[i], pz = g.z[i];
   double4 o;
   if (finite3(px, py, pz)) {
@@ -181,11 +191,15 @@ __global__ __launch_bounds__(kBatchBlock) void kb_ext_starts(
     const SysGeom *__restrict__ sys, const int2 *__restrict__ eblk,
     const int32_t *__restrict__ cell_start, const int32_t *__restrict__ row_start,
     const int32_t *__restrict__ row_lo, int64_t next_total, int64_t nrows_total,
-    int32_t *__restrict__ ext_start) {
+    int32_t *__restrict__ ext_start, const uint32_t *__restrict__ qword,
+    int2 *__restrict__ ext_sq) {
   int64_t first;
   const int b = block_system(eblk, first);
   const SysGeom &g = sys[b];
-  if (blockIdx.x == 0 && threadIdx.x == 0) ext_start[next_total] = row_start[nrows_total];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ext_start[next_total] = row_start[nrows_total];
+    if (ext_sq) ext_sq[next_total] = make_int2(row_start[nrows_total], 0);
+  }
   const int64_t e = first + threadIdx.x;
   if (e >= ext_cells_of(g)) return;
   const int row = (int)(e / g.ne[0]);
@@ -194,7 +208,11 @@ __global__ __launch_bounds__(kBatchBlock) void kb_ext_starts(
   const int32_t *cs = cell_start + g.cell0;
   const int64_t T = cs[r.r0 + g.nc[0]] - cs[r.r0];
   const int64_t f = row_prefix(cs, r.r0, g.nc[0], T, ex - g.h[0]);
-  ext_start[g.ext_cell0 + e] = (int32_t)(row_start[g.row0 + row] + (f - row_lo[g.row0 + row]));
+  const int32_t st = (int32_t)(row_start[g.row0 + row] + (f - row_lo[g.row0 + row]));
+  ext_start[g.ext_cell0 + e] = st;
+  if (ext_sq)
+    ext_sq[g.ext_cell0 + e] =
+        make_int2(st, (int)qword[g.cell0 + r.r0 + wrap_index(ex - g.h[0], g.nc[0])]);
 }
 
 // One wavefront per row: workgroup w takes rows 4 (w mod 64) .. + 3 of row
@@ -268,10 +286,10 @@ __global__ __launch_bounds__(kReduceThreads) void kb_reduce(const SysGeom *__res
 void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, int32_t nsys, const int2 *pblk,
                              int64_t npblk, int32_t *cell_of, int32_t *cell_count,
                              unsigned long long *block_max, unsigned long long *rc_max_bits,
-                             uint32_t *status) {
+                             uint32_t *xq, uint32_t *status) {
   if (npblk > 0)
     hipLaunchKernelGGL(kb_cell_count, dim3((unsigned)npblk), dim3(kBatchBlock), 0, s, sys, pblk,
-                       cell_of, cell_count, block_max, status);
+                       cell_of, cell_count, block_max, xq, status);
   if (nsys > 0)
     hipLaunchKernelGGL(kb_reduce_rcmax, dim3((unsigned)nsys), dim3(256), 0, s, sys, block_max,
                        rc_max_bits);
@@ -286,10 +304,10 @@ void launch_batch_cell_scatter(hipStream_t s, const SysGeom *sys, const int2 *pb
 }
 
 void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
-                         const int32_t *perm, double4 *sorted) {
+                         const int32_t *order, double4 *sorted, int32_t *perm) {
   if (npblk <= 0) return;
-  hipLaunchKernelGGL(kb_gather, dim3((unsigned)npblk), dim3(kBatchBlock), 0, s, sys, pblk, perm,
-                     sorted);
+  hipLaunchKernelGGL(kb_gather, dim3((unsigned)npblk), dim3(kBatchBlock), 0, s, sys, pblk, order,
+                     sorted, perm);
 }
 
 void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64_t neblk,
@@ -297,13 +315,14 @@ void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64
                       const double4 *sorted, int64_t next_total, int64_t nrows_total,
                       int64_t ext_cap, int32_t *row_count, int32_t *row_start, int32_t *row_lo,
                       int32_t *ext_start, int32_t *scan_tmp, double4 *ext_pos, float4 *ext_rel,
-                      uint32_t *status) {
+                      const uint32_t *qword, int2 *ext_sq, uint32_t *status) {
   if (nrblk <= 0 || neblk <= 0) return;
   hipLaunchKernelGGL(kb_ext_rows, dim3((unsigned)nrblk), dim3(kBatchBlock), 0, s, sys, rblk,
                      cell_start, row_count, row_lo);
   launch_exclusive_scan(s, row_count, row_start, nrows_total, scan_tmp);
   hipLaunchKernelGGL(kb_ext_starts, dim3((unsigned)neblk), dim3(kBatchBlock), 0, s, sys, eblk,
-                     cell_start, row_start, row_lo, next_total, nrows_total, ext_start);
+                     cell_start, row_start, row_lo, next_total, nrows_total, ext_start, qword,
+                     ext_sq);
   hipLaunchKernelGGL(kb_ext_fill, dim3((unsigned)(nrblk * kFillGroups)), dim3(kBatchBlock), 0, s,
                      sys, rblk, cell_start, row_start, row_lo, sorted, ext_cap, ext_pos, ext_rel,
                      status);

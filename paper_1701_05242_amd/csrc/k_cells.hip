@@ -69,7 +69,8 @@ __global__ __launch_bounds__(256) void k_cell_count(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     const double *__restrict__ rc, int64_t n, double Lx, double Ly, double Lz, int nx, int ny,
     int nz, double sx, double sy, double sz, double rc_cap, int32_t *__restrict__ cell_of,
-    int32_t *count, unsigned long long *__restrict__ block_max, uint32_t *status) {
+    int32_t *count, unsigned long long *__restrict__ block_max, uint32_t *__restrict__ xq,
+    uint32_t *status) {
   unsigned long long rmax = 0;
   // uniform trip count: every lane reaches the run-aggregated atomic
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -79,14 +80,18 @@ __global__ __launch_bounds__(256) void k_cell_count(
     int c = 0;
     if (valid) {
       double px = x[i], py = y[i], pz = z[i], r = rc[i];
+      uint32_t q = 0;
       if (finite3(px, py, pz)) {
-        int cx = slab_index(wrap_coord(px, Lx), sx, nx);
+        const double wx = wrap_coord(px, Lx);
+        int cx = slab_index(wx, sx, nx);
         int cy = slab_index(wrap_coord(py, Ly), sy, ny);
         int cz = slab_index(wrap_coord(pz, Lz), sz, nz);
         c = (cz * ny + cy) * nx + cx;
+        q = x_key(wx, sx, cx);
       } else {
         atomicOr(status, ST_NONFINITE_POS);
       }
+      if (xq) xq[i] = q;
       // rc_cap: the build's bound on every cutoff (inclusive, below L/2)
       if (!(r >= 0.0) || r > rc_cap) {
         atomicOr(status, ST_RC_RANGE);
@@ -145,12 +150,12 @@ int64_t cell_count_blocks(int64_t n) {
 void launch_cell_count(hipStream_t s, const double *x, const double *y, const double *z,
                        const double *rc, int64_t n, const double L[3], const int32_t nc[3],
                        const double sc[3], double rc_cap, int32_t *cell_of, int32_t *cell_count,
-                       unsigned long long *block_max, Ctl *ctl, uint32_t *status) {
+                       unsigned long long *block_max, uint32_t *xq, Ctl *ctl, uint32_t *status) {
   const int64_t b = cell_count_blocks(n);
   if (n > 0)
     hipLaunchKernelGGL(k_cell_count, dim3((unsigned)b), dim3(256), 0, s, x, y, z, rc, n, L[0],
                        L[1], L[2], nc[0], nc[1], nc[2], sc[0], sc[1], sc[2], rc_cap, cell_of,
-                       cell_count, block_max, status);
+                       cell_count, block_max, xq, status);
   hipLaunchKernelGGL(k_reduce_rcmax, dim3(1), dim3(1024), 0, s, block_max, n > 0 ? b : 0, ctl);
 }
 
@@ -315,63 +320,143 @@ void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
 }
 
 // Atomic slots give an arbitrary order inside a cell; sort each cell's
-// entries by caller index so the layout (and every FP sum) is reproducible.
-// A thread sorts a cell of at most kSmallCell entries by insertion; larger
-// cells go to a list that whole workgroups sort (k_cell_sort_big).
+// entries by (x key, caller index) so the layout (and every FP sum) is
+// reproducible and each cell's particles are in x order.  Cells of at most
+// kSmallCell entries are ranked one thread per particle (k_cell_rank);
+// larger cells go to a list that whole workgroups sort (k_cell_sort_big).
 constexpr int kSmallCell = 32;
 constexpr int kSortChunk = 4096;  // entries a workgroup sorts at once in LDS
 constexpr int kBigSortBlocks = 256;
 
-__global__ __launch_bounds__(256) void k_cell_sort(const int32_t *__restrict__ cell_start,
-                                                   int64_t ncell, int32_t *perm,
-                                                   int32_t *__restrict__ big_list,
-                                                   uint32_t *big_count) {
+// Order of two particles of one cell: by x key, then by caller index (the
+// keys are x positions quantised to 2^-20 of the cell, so a cell's particles
+// end up in x order and every extended row is x-sorted).
+__device__ __forceinline__ uint64_t sort_key(const uint32_t *__restrict__ xq, int i) {
+  return ((uint64_t)xq[i] << 32) | (uint32_t)i;
+}
+
+// Quarter counts of a cell's particles along x: o1, o2, o3 = how many have x
+// keys below 1/4, 1/2, 3/4 of the cell (with the particles in key order, the
+// first slots of quarters 1, 2, 3 are a + o1, a + o2, a + o3).
+__device__ __forceinline__ void count_quarters(const uint32_t *__restrict__ xq,
+                                               const int32_t *__restrict__ perm, int p0, int p1,
+                                               int step, uint32_t &o1, uint32_t &o2,
+                                               uint32_t &o3) {
+  o1 = o2 = o3 = 0;
+  for (int p = p0; p < p1; p += step) {
+    const uint32_t q = xq[perm[p]];
+    o1 += q < kXKeyOne / 4 ? 1u : 0u;
+    o2 += q < kXKeyOne / 2 ? 1u : 0u;
+    o3 += q < 3 * (kXKeyOne / 4) ? 1u : 0u;
+  }
+}
+
+// A cell's quarter word: bytes o1, o2, o3 and the count n; 0 (no quarters)
+// for a cell of more than 255 particles.
+__device__ __forceinline__ uint32_t quarter_word(uint32_t o1, uint32_t o2, uint32_t o3,
+                                                 uint32_t n) {
+  return n > 255 ? 0u : (o1 | (o2 << 8) | (o3 << 16) | (n << 24));
+}
+
+// One thread per cell: a cell of more than kSmallCell particles goes to the
+// list that whole workgroups sort (k_cell_sort_big, which also writes its
+// quarter word); a smaller one gets its quarter word here.
+__global__ __launch_bounds__(256) void k_cell_small(const int32_t *__restrict__ cell_start,
+                                                    int64_t ncell,
+                                                    const int32_t *__restrict__ perm,
+                                                    const uint32_t *__restrict__ xq,
+                                                    uint32_t *__restrict__ qword,
+                                                    int32_t *__restrict__ big_list,
+                                                    uint32_t *big_count) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
-    int a = cell_start[c], b = cell_start[c + 1];
+    const int a = cell_start[c], b = cell_start[c + 1];
     if (b - a > kSmallCell) {
       big_list[atomicAdd(big_count, 1u)] = (int32_t)c;
       continue;
     }
-    for (int p = a + 1; p < b; ++p) {
-      int key = perm[p];
-      int q = p - 1;
-      while (q >= a && perm[q] > key) {
-        perm[q + 1] = perm[q];
-        --q;
-      }
-      perm[q + 1] = key;
+    if (qword) {
+      uint32_t o1, o2, o3;
+      count_quarters(xq, perm, a, b, 1, o1, o2, o3);
+      qword[c] = quarter_word(o1, o2, o3, (uint32_t)(b - a));
     }
+  }
+}
+
+// One thread per slot of the cell-scattered order perm: a particle of a
+// small cell moves to its cell's start plus its rank there (the count of the
+// cell's particles with smaller (x key, id)); a particle of a large cell
+// keeps its slot.  out receives the result; no thread waits on another.
+__global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ cell_start,
+                                                   const int32_t *__restrict__ cell_of,
+                                                   const int32_t *__restrict__ perm, int64_t n,
+                                                   const uint32_t *__restrict__ xq,
+                                                   int32_t *__restrict__ out) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int i = perm[p];
+    const int c = cell_of[i];
+    const int a = cell_start[c], b = cell_start[c + 1];
+    if (b - a > kSmallCell) {
+      out[p] = i;
+      continue;
+    }
+    const uint32_t ki = xq[i];
+    int r = 0;
+    for (int q = a; q < b; ++q) {
+      const int j = perm[q];
+      const uint32_t kj = xq[j];
+      r += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+    }
+    out[a + r] = i;
   }
 }
 
 // One workgroup per listed cell: chunks of kSortChunk entries are sorted in
 // LDS (bitonic), then runs are merged pairwise, each entry moving to its own
 // offset in its run plus the count of smaller keys in the partner run (keys
-// are distinct caller indices), ping-ponging between perm and tmp.
+// are distinct: they end in the caller index), ping-ponging between perm and
+// tmp.  Entries are caller indices; their keys are looked up (sort_key).
 __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t *__restrict__ cell_start,
                                                        int32_t *perm, int32_t *tmp,
+                                                       const uint32_t *__restrict__ xq,
+                                                       uint32_t *__restrict__ qword,
                                                        const int32_t *__restrict__ big_list,
                                                        const uint32_t *big_count) {
   __shared__ int32_t buf[kSortChunk];
+  __shared__ uint32_t qn[3];
   const int tid = threadIdx.x;
   const uint32_t nbig = *big_count;
   for (uint32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
     const int64_t c = big_list[q];
     const int a = cell_start[c], n = cell_start[c + 1] - a;
+    if (qword) {  // the counts do not depend on the order
+      if (tid < 3) qn[tid] = 0;
+      __syncthreads();
+      uint32_t o1, o2, o3;
+      count_quarters(xq, perm, a + tid, a + n, 256, o1, o2, o3);
+      atomicAdd(&qn[0], o1);
+      atomicAdd(&qn[1], o2);
+      atomicAdd(&qn[2], o3);
+      __syncthreads();
+      if (tid == 0) qword[c] = quarter_word(qn[0], qn[1], qn[2], (uint32_t)n);
+      __syncthreads();
+    }
     for (int c0 = 0; c0 < n; c0 += kSortChunk) {
       const int len = n - c0 < kSortChunk ? n - c0 : kSortChunk;
       int P = 1;
       while (P < len) P <<= 1;
-      for (int i = tid; i < P; i += 256) buf[i] = i < len ? perm[a + c0 + i] : 0x7fffffff;
+      // padding entries (-1) sort after every particle
+      for (int i = tid; i < P; i += 256) buf[i] = i < len ? perm[a + c0 + i] : -1;
       __syncthreads();
+      auto key = [&](int v) -> uint64_t { return v < 0 ? ~uint64_t(0) : sort_key(xq, v); };
       for (int k = 2; k <= P; k <<= 1)
         for (int j = k >> 1; j > 0; j >>= 1) {
           for (int i = tid; i < P; i += 256) {
             const int l = i ^ j;
             if (l > i) {
               const int u = buf[i], w = buf[l];
-              if ((u > w) == ((i & k) == 0)) {
+              if ((key(u) > key(w)) == ((i & k) == 0)) {
                 buf[i] = w;
                 buf[l] = u;
               }
@@ -387,13 +472,14 @@ __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t *__restrict
       for (int p = tid; p < n; p += 256) {
         const int r = p / L, off = p - r * L;
         const int x = src[p];
+        const uint64_t kx = sort_key(xq, x);
         const int o = (r ^ 1) * L;  // partner run
         int lo = 0, hi = 0;
         if (o < n) {
           hi = n - o < L ? n - o : L;
-          while (lo < hi) {  // count of partner keys below x
+          while (lo < hi) {  // count of partner keys below x's
             const int m = (lo + hi) >> 1;
-            if (src[o + m] < x) lo = m + 1;
+            if (sort_key(xq, src[o + m]) < kx) lo = m + 1;
             else hi = m;
           }
         }
@@ -411,15 +497,24 @@ __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t *__restrict
   }
 }
 
-void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell, int32_t *perm,
-                      int32_t *tmp, int32_t *big_list, uint32_t *big_count) {
+void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell,
+                      const int32_t *cell_of, int64_t n, int32_t *perm, const uint32_t *xq,
+                      uint32_t *qword, int32_t *sorted_perm, int32_t *big_list,
+                      uint32_t *big_count) {
   int64_t b = ceil_div(ncell, 256);
   if (b < 1) b = 1;
   if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)b), dim3(256), 0, s, cell_start, ncell, perm,
-                     big_list, big_count);
-  hipLaunchKernelGGL(k_cell_sort_big, dim3(kBigSortBlocks), dim3(256), 0, s, cell_start, perm,
-                     tmp, big_list, big_count);
+  hipLaunchKernelGGL(k_cell_small, dim3((unsigned)b), dim3(256), 0, s, cell_start, ncell, perm,
+                     xq, qword, big_list, big_count);
+  if (n > 0) {
+    int64_t bn = ceil_div(n, 256);
+    if (bn > 16384) bn = 16384;
+    hipLaunchKernelGGL(k_cell_rank, dim3((unsigned)bn), dim3(256), 0, s, cell_start, cell_of,
+                       perm, n, xq, sorted_perm);
+  }
+  // the large cells, in place in sorted_perm with perm as scratch
+  hipLaunchKernelGGL(k_cell_sort_big, dim3(kBigSortBlocks), dim3(256), 0, s, cell_start,
+                     sorted_perm, perm, xq, qword, big_list, big_count);
 }
 
 int64_t cell_sort_list_elems(int64_t n) { return n / (kSmallCell + 1) + 1; }
@@ -429,12 +524,14 @@ __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ x,
                                                 const double *__restrict__ y,
                                                 const double *__restrict__ z,
                                                 const double *__restrict__ rc,
-                                                const int32_t *__restrict__ perm, int64_t n,
+                                                const int32_t *__restrict__ order, int64_t n,
                                                 double Lx, double Ly, double Lz, double rc_cap,
-                                                double4 *__restrict__ sorted) {
+                                                double4 *__restrict__ sorted,
+                                                int32_t *__restrict__ perm) {
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
        s += (int64_t)gridDim.x * blockDim.x) {
-    int i = perm[s];
+    int i = order[s];
+    perm[s] = i;
     double px = x[i], py = y[i], pz = z[i];
     double4 o;
     if (finite3(px, py, pz)) {
@@ -451,13 +548,13 @@ __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ x,
 }
 
 void launch_gather(hipStream_t s, const double *x, const double *y, const double *z,
-                   const double *rc, const int32_t *perm, int64_t n, const double L[3],
-                   double rc_cap, double4 *sorted) {
+                   const double *rc, const int32_t *order, int64_t n, const double L[3],
+                   double rc_cap, double4 *sorted, int32_t *perm) {
   if (n <= 0) return;
   int64_t b = ceil_div(n, 256);
   if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)b), dim3(256), 0, s, x, y, z, rc, perm, n, L[0],
-                     L[1], L[2], rc_cap, sorted);
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)b), dim3(256), 0, s, x, y, z, rc, order, n, L[0],
+                     L[1], L[2], rc_cap, sorted, perm);
 }
 
 // ------------------------------------------------ periodic ghost images
@@ -497,12 +594,17 @@ __global__ __launch_bounds__(256) void k_ext_starts(const int32_t *__restrict__ 
                                                     const int32_t *__restrict__ row_start,
                                                     const int32_t *__restrict__ row_lo,
                                                     ExtGeom g, int64_t next, int64_t nrows,
-                                                    int32_t *__restrict__ ext_start) {
+                                                    int32_t *__restrict__ ext_start,
+                                                    const uint32_t *__restrict__ qword,
+                                                    int2 *__restrict__ ext_sq) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(
       (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6));
   const int nwaves = (int)(((int64_t)gridDim.x * blockDim.x) >> 6);
-  if (wave == 0 && lane == 0) ext_start[next] = row_start[nrows];
+  if (wave == 0 && lane == 0) {
+    ext_start[next] = row_start[nrows];
+    if (ext_sq) ext_sq[next] = make_int2(row_start[nrows], 0);
+  }
   const int nx = g.nc[0], hx = g.h[0], nex = g.ne[0];
   const bool near = hx <= nx;
   // next < 2^30 (checked at build), so 32-bit cell indices suffice
@@ -515,7 +617,10 @@ __global__ __launch_bounds__(256) void k_ext_starts(const int32_t *__restrict__ 
     for (int ex = lane; ex < nex; ex += 64) {
       const int u = ex - hx;
       const int p = near ? (u < 0 ? -1 : (u >= nx ? 1 : 0)) : floor_div(u, nx);
-      out[ex] = (int32_t)(base + p * T + (cell_start[r.r0 + (u - p * nx)] - c0));
+      const int rc = r.r0 + (u - p * nx);
+      const int32_t st = (int32_t)(base + p * T + (cell_start[rc] - c0));
+      out[ex] = st;
+      if (ext_sq) ext_sq[(int64_t)row * nex + ex] = make_int2(st, (int)qword[rc]);
     }
   }
 }
@@ -619,7 +724,7 @@ void launch_ext_refill(hipStream_t s, const int32_t *cell_start, const int32_t *
 void launch_ext_count(hipStream_t s, const int32_t *cell_start, const int32_t nc[3],
                       const int32_t h[3], const double L[3], int32_t *row_count,
                       int32_t *row_start, int32_t *row_lo, int32_t *ext_start,
-                      int32_t *scan_tmp) {
+                      int32_t *scan_tmp, const uint32_t *qword, int2 *ext_sq) {
   const ExtGeom g = ext_geom(nc, h, L);
   const int64_t next = (int64_t)g.ne[0] * g.ne[1] * g.ne[2];
   const int64_t nrows = (int64_t)g.ne[1] * g.ne[2];
@@ -632,7 +737,7 @@ void launch_ext_count(hipStream_t s, const int32_t *cell_start, const int32_t nc
   if (b < 1) b = 1;
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_ext_starts, dim3((unsigned)b), dim3(256), 0, s, cell_start, row_start,
-                     row_lo, g, next, nrows, ext_start);
+                     row_lo, g, next, nrows, ext_start, qword, ext_sq);
 }
 
 void launch_ext_images(hipStream_t s, const int32_t *cell_start, const int32_t *row_start,

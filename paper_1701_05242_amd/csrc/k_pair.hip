@@ -6,7 +6,11 @@
 // the neighbour list of Algorithm 2.2, each lane enumerates the cell rows
 // (fixed y and z cell; consecutive x cells are consecutive in memory) that can
 // hold a j within its search radius and trims each row to the chord of the
-// search sphere -- the small-cell traversal of Section 2.3.  The rows are
+// search sphere -- the small-cell traversal of Section 2.3.  Cells keep their
+// particles in x order with a table of where each quarter of the cell (along
+// x) starts, so a row's two end cells are trimmed to the quarters the chord
+// reaches: the walk sees about the candidates of cells a quarter as wide
+// while reading two table entries per row.  The rows are
 // walked in the ghost-extended cell grid, where periodic images sit in halo
 // cells with their coordinates already shifted, so every row is one
 // contiguous index range and a separation is a plain difference.  A lane
@@ -24,8 +28,9 @@
 // from the FP64 record.  FP32-mixed evaluates close pairs (r < 1.1 sigma)
 // in FP64 from the FP64 record: their forces are the largest and the
 // r^-14 dependence multiplies every relative rounding of r^2 and 1/r^2
-// by about 7, so in FP32 they alone would set the worst particle's error.  Also here: forces over a stored Verlet list, the
-// persistent batched form, and the fixed-order reduction of block partials.
+// by about 7, so in FP32 they alone would set the worst particle's error.
+// Also here: forces over a stored Verlet list, the persistent batched form,
+// and the fixed-order reduction of block partials.
 #include "dcm_device.hpp"
 #include "dcm_internal.hpp"
 
@@ -273,6 +278,11 @@ struct PairView {
   const float4 *ext_rel;         // its compact cell-relative copy (FP32-mixed builds)
   double rel_delta;              // bound on the per-coordinate error of ext_rel
   const int32_t *ext_start;      // this system's extended cells -> extended slots
+  // (first slot, quarter word) of every extended cell and (extended count,
+  // 0) past the last; the word's bytes o1, o2, o3, n count the cell's
+  // particles (in x order) below 1/4, 1/2, 3/4 of the cell and in all, and
+  // are 0 for a cell without quarters.  Null: rows take whole end cells.
+  const int2 *ext_sq;
   int64_t ext_cap;
   int nc[3], h[3], ne[3];
   double len[3], sc[3];
@@ -298,6 +308,10 @@ struct LaneGeo {
   // of its cell's positive (gp) and negative (gm) neighbours less one cell,
   // 0.5 len +- a0 + guard, and the lane's offset in cell units, a0/len + 1/2
   float gp[3], gm[3], ac[3];
+  // 4 invf[0] and 4 ac[0]: the quarter-cell offsets along x, and the
+  // extended grid's first and last quarter relative to the lane's cell
+  float qinv, qac;
+  int qmin, qmax;
   // compact records: FP32 r^2 below which a pair is evaluated in FP64, and
   // sigma^2 for that evaluation
   float near2f;
@@ -371,6 +385,7 @@ __device__ __forceinline__ void interact_rel(Acc<DCM_FP32_MIXED> &acc, float dx,
 // Compact records are read through a buffer resource: 32-bit offsets, and a
 // read past the resource's size returns zeros instead of touching memory.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit dword access (gfx9 family)
 
 __device__ __forceinline__ float4 load_rel(__amdgpu_buffer_rsrc_t rs, int j) {
@@ -495,6 +510,12 @@ __device__ __forceinline__ int cell_off(float p, const LaneGeo &g, int a) {
   return (int)floorf(fmaf(p, g.invf[a], g.ac[a]));
 }
 
+// The same along x in quarter cells: q >> 2 is cell_off(p, g, 0) (scaling by
+// 4 is exact in FP32), q & 3 the quarter of that cell holding a0 + p.
+__device__ __forceinline__ int quarter_off(float p, const LaneGeo &g) {
+  return (int)floorf(fmaf(p, g.qinv, g.qac));
+}
+
 // Walk this lane's rows (fill a list, scan it, repeat) for a lane with run
 // set.  REL: compact records (FP32-mixed, own-cutoff rule); else the FP64
 // records.  CAP: the row capacity of segs.
@@ -546,6 +567,11 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
   auto load_start = [&](int idx) -> int {
     return (int)__builtin_amdgcn_raw_buffer_load_b32(rs_start, (int)((uint32_t)idx << 2), 0, 0);
   };
+  // the trimming table, (next + 1) entries of 8 bytes (it exists for fewer
+  // than 2^28 extended cells, so its byte offsets fit in 32 bits)
+  const bool trim = v.ext_sq != nullptr;
+  const __amdgpu_buffer_rsrc_t rs_sq = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)v.ext_sq, (short)0, trim ? (int)(uint32_t)(2 * start_bytes) : 0, kBufferWord3);
   __amdgpu_buffer_rsrc_t rs;
   if constexpr (REL)
     rs = __builtin_amdgcn_make_buffer_rsrc((void *)v.ext_rel, (short)0,
@@ -559,7 +585,9 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     // a row adds at most one entry (compact records: two entries stay free
     // for the sentinel and the look-ahead)
     while (rows_left && nseg <= CAP - kFillRows - (REL ? 2 : 1)) {
-      int j0[kFillRows], j1[kFillRows], rz[kFillRows], ry[kFillRows];
+      int j0[kFillRows], j1[kFillRows], rz[kFillRows], ry[kFillRows], sl[kFillRows],
+          sh[kFillRows];
+      u32x2 tl[kFillRows], th[kFillRows];
       bool ok[kFillRows];
 #pragma unroll
       for (int k = 0; k < kFillRows; ++k) {
@@ -579,14 +607,30 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
         const float ey = face_gap(ycur - g.cy, g, 1);
         const float rem = fmaf(-ey, ey, remz);
         in = in && rem >= 0.0f;
-        // chord half-width, widened by the guard (it only selects cells)
+        // chord half-width, widened by the guard (it only selects cells and
+        // quarters of cells)
         const float w = in ? __builtin_amdgcn_sqrtf(rem) + g.fguard : 0.0f;
-        const int xlo = clampi(g.cx + cell_off(-w, g, 0), -hx, nx + hx - 1);
-        const int xhi = clampi(g.cx + cell_off(w, g, 0), -hx, nx + hx - 1);
+        // the chord's ends in quarter cells from the lane's cell, within the
+        // extended grid (-w <= 0 <= w: the lower end can only leave it below,
+        // the upper above)
+        const int qlo = max(quarter_off(-w, g), g.qmin);
+        const int qhi = min(quarter_off(w, g), g.qmax);
         // a row that is not taken still reads (its own cell row's) starts
         const int row = in ? rowbase + __mul24(ycur, nex) : own_row;
-        j0[k] = load_start(row + xlo);
-        j1[k] = load_start(row + xhi + 1);
+        const int e0 = row + g.cx + (qlo >> 2), e1 = row + g.cx + (qhi >> 2) + 1;
+        if (trim) {
+          // from the start of quarter qlo & 3 of cell e0 to the end of
+          // quarter qhi & 3 of cell e1 - 1 (the end cells' quarters beyond
+          // the chord are skipped): (start, word) of e0, and (word of e1 - 1,
+          // start of e1), 8 bytes each from one table
+          tl[k] = __builtin_amdgcn_raw_buffer_load_b64(rs_sq, (int)((uint32_t)e0 << 3), 0, 0);
+          th[k] = __builtin_amdgcn_raw_buffer_load_b64(rs_sq, (int)(((uint32_t)e1 << 3) - 4), 0, 0);
+          sl[k] = (qlo & 3) << 3;
+          sh[k] = (qhi & 3) << 3;
+        } else {
+          j0[k] = load_start(e0);
+          j1[k] = load_start(e1);
+        }
         rz[k] = zcur;
         ry[k] = ycur;
         ok[k] = in;
@@ -594,6 +638,12 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
 #pragma unroll
       for (int k = 0; k < kFillRows; ++k) {
         if (!ok[k]) continue;
+        if (trim) {
+          // start of quarter ql: the byte ql - 1 (0 for ql = 0); end of
+          // quarter qh: n less the byte qh (0 for qh = 3)
+          j0[k] = (int)(tl[k].x + (((tl[k].y << 8) >> sl[k]) & 0xffu));
+          j1[k] = (int)(th[k].y - ((th[k].x >> 24) - ((th[k].x >> sh[k]) & 0xffu)));
+        }
         const int a0 = j0[k];
         const int a1 = j1[k] > v.ext_cap ? (int)v.ext_cap : j1[k];  // overflow (flagged at build)
         if constexpr (REL) {
@@ -714,6 +764,8 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   g.lenf[0] = g.lenf[1] = g.lenf[2] = 0.0f;
   g.invf[0] = g.invf[1] = g.invf[2] = 0.0f;
   for (int k = 0; k < 3; ++k) g.gp[k] = g.gm[k] = g.ac[k] = 0.0f;
+  g.qinv = g.qac = 0.0f;
+  g.qmin = g.qmax = 0;
   g.cx = 0;
   g.zlo = 0;
   g.zhi = -1;
@@ -763,6 +815,10 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
       g.gm[k] = fmaf(0.5f, g.lenf[k], -a0[k]) + g.fguard;
       g.ac[k] = fmaf(a0[k], g.invf[k], 0.5f);
     }
+    g.qinv = 4.0f * g.invf[0];
+    g.qac = 4.0f * g.ac[0];
+    g.qmin = 4 * (-hx - cx);
+    g.qmax = 4 * (nx + hx - 1 - cx) + 3;
     const double Rf = Rg + (double)g.fguard;
     g.fR2 = (float)(Rf * Rf) * (1.0f + 0x1p-20f);
     if constexpr (REL) {
@@ -842,6 +898,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   v.ext_rel = a.ext_rel;
   v.rel_delta = a.rel_delta;
   v.ext_start = a.ext_start;
+  v.ext_sq = a.ext_sq;
   v.ext_cap = a.ext_cap;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -968,6 +1025,9 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
     v.ext_rel = a.ext_rel;
     v.rel_delta = g.rel_delta;
     v.ext_start = a.ext_start + g.ext_cell0;
+    v.ext_sq = a.ext_sq && (int64_t)g.ne[0] * g.ne[1] * g.ne[2] < kQStartMaxCells
+                   ? a.ext_sq + g.ext_cell0
+                   : nullptr;
     v.ext_cap = a.ext_cap;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {

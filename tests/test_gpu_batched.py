@@ -22,7 +22,7 @@ from gpu_util import DEV, F64, Ctx, dev, force_errors, gpu_forces, host, rel
 pytestmark = pytest.mark.gpu
 
 EV_ALL = dcm.DCM_EV_ENERGY | dcm.DCM_EV_VIRIAL | dcm.DCM_EV_COUNTS
-TUNE_EDGES = (1.0, 1.15, 1.3, 1.5)
+TUNE_EDGES = (1.0, 1.15, 1.3, 1.5, 1.75)
 
 
 @functools.lru_cache(maxsize=None)

@@ -333,8 +333,8 @@ def test_tuned_cell_edge(prec):
     s = workloads.make("slab_medium")
     rc = ref_detect("slab_medium")["rc"]
     r_ref = float(np.min(rc))
-    cands = sorted({min(f * r_ref, 2.0 if prec == dcm.DCM_FP32_MIXED else 1e9)
-                    for f in (1.0 / 3.0, 0.4, 0.5, 0.6)})
+    top = min(L / np.ceil(L / 2.0) for L in s.box) if prec == dcm.DCM_FP32_MIXED else 1e9
+    cands = sorted({min(f * r_ref, top) for f in (1.0 / 3.0, 0.4, 0.5, 0.6, 0.7, 0.8)})
     got = gpu_forces(s, rc, prec=prec, edge=-1.0, rc_bound=s.rule[1])
     again = gpu_forces(s, rc, prec=prec, edge=-1.0, rc_bound=s.rule[1])
     dims = got["dims"]
@@ -703,9 +703,12 @@ def test_step_without_energy_series_repeats_the_recorded_run(prec):
     np.testing.assert_array_equal(out[0], out[1])
 
 
-def step_forces(s, prec):
-    """dcm_step with nsteps = 0 (detection, distances, cutoffs, cells of
-    r_c^min/2, forces) from the generator's positions: forces and cutoffs."""
+def step_forces(s, prec, want_edge=False):
+    """dcm_step with nsteps = 0 (detection, distances, cutoffs, cells of its
+    tuned edge, forces) from the generator's positions: forces and cutoffs
+    (and the cell edge it used, one of its candidates f r_c^min,
+    f in 1/3, 0.4, 1/2, 0.6, 0.7, 0.8, identified by the cell counts; FP64
+    steps only, whose candidates are not capped)."""
     grid = dcm.make_grid(s.box, s.h)
     rule = dcm.make_rule(*s.rule)
     f = [torch.zeros(s.n, **F64) for _ in range(3)]
@@ -715,7 +718,15 @@ def step_forces(s, prec):
         dcm.dcm_step(ctx, dev(s.x), dev(s.y), dev(s.z), *v, *f, s.box, dcm.make_lj(), rule, grid,
                      dcm.dcm_rc_grid(rule, grid), dt=0.005, nsteps=0, prec=prec, rc=rc)
         assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK
-    return np.stack([host(t) for t in f], 1), host(rc)
+        nc, _ = dcm.dcm_cell_dims(ctx)
+    out = (np.stack([host(t) for t in f], 1), host(rc))
+    if not want_edge:
+        return out
+    assert prec == dcm.DCM_FP64
+    cands = [fr * s.rule[0] for fr in (1.0 / 3.0, 0.4, 0.5, 0.6, 0.7, 0.8)]
+    edge = [e for e in cands if all(int(np.floor(L / e)) == k for L, k in zip(s.box, nc))]
+    assert edge, (nc, cands)
+    return out + (edge[0],)
 
 
 def test_large_slab_parity_and_full_population_accuracy():
@@ -731,7 +742,7 @@ def test_large_slab_parity_and_full_population_accuracy():
     s = workloads.make(name)
     ref_d = ref_detect(name)
     F32, rc32 = step_forces(s, dcm.DCM_FP32_MIXED)
-    F64s, rc64 = step_forces(s, dcm.DCM_FP64)
+    F64s, rc64, edge64 = step_forces(s, dcm.DCM_FP64, want_edge=True)
     np.testing.assert_allclose(rc64, ref_d["rc"], rtol=1e-12, atol=0)
     np.testing.assert_array_equal(rc32, rc64)
     idx = workloads.sample_indices(s.n, 1536, seed=4242)
@@ -748,9 +759,10 @@ def test_large_slab_parity_and_full_population_accuracy():
     print(f"[gpu]   fp32_mixed vs fp64, all {s.n}: err_max={emax:.3e} err_rms={erms:.3e} "
           f"floored={efloor:.3e}", flush=True)
     assert emax <= 1e-5 and erms <= 1e-5 and efloor <= 1e-5
-    # neighbour counts: both precisions at the step's cells, every particle
-    c32 = gpu_forces(s, rc64, prec=dcm.DCM_FP32_MIXED, edge=1.25, rc_bound=s.rule[1])
-    c64 = gpu_forces(s, rc64, prec=dcm.DCM_FP64, edge=1.25, rc_bound=s.rule[1])
+    # neighbour counts: both precisions at the FP64 step's cells, every
+    # particle; dcm_forces there gives the step's FP64 forces bit for bit
+    c32 = gpu_forces(s, rc64, prec=dcm.DCM_FP32_MIXED, edge=edge64, rc_bound=s.rule[1])
+    c64 = gpu_forces(s, rc64, prec=dcm.DCM_FP64, edge=edge64, rc_bound=s.rule[1])
     np.testing.assert_array_equal(c64["nnbr"][idx], ref["nnbr"])
     np.testing.assert_array_equal(c32["nnbr"], c64["nnbr"])
     assert c32["npairs"] == c64["npairs"] == int(c64["nnbr"].astype(np.int64).sum())
