@@ -522,8 +522,10 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
     double *f = ptr<double>(ctx->tune_f);
     auto run = [&](double e) -> dcm_status {
       DCM_TRY(dcm_build_cells(ctx, x, y, z, rc, n, box, e, rc_bound, prec, nullptr, nullptr));
-      return dcm_forces(ctx, dcm_lj{1.0, 1.0}, DCM_PAIR_OWN, prec, DCM_EV_ENERGY, f, f + nn,
-                        f + 2 * nn, ptr<double>(ctx->scalars) + 14, nullptr, nullptr, nullptr);
+      // forces only: the trials run a kernel instance of their own, so a
+      // kernel trace keeps them apart from the caller's energy passes
+      return dcm_forces(ctx, dcm_lj{1.0, 1.0}, DCM_PAIR_OWN, prec, 0, f, f + nn, f + 2 * nn,
+                        nullptr, nullptr, nullptr, nullptr);
     };
     DCM_TRY(tune_edge(ctx, key, edge_candidates(r_ref, cap, box.L), run, &edge));
   }
@@ -1077,7 +1079,8 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
       auto run = [&](double e) -> dcm_status {
         DCM_TRY(dcm_build_cells(ctx, W[WX], W[WY], W[WZ], W[WRC], n, box, e, rule.rc_max, prec,
                                 nullptr, nullptr));
-        return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, W[WFX], W[WFY], W[WFZ], scal,
+        // forces only (a kernel instance apart from the steps' energy passes)
+        return dcm_forces(ctx, lj, pair_rule, prec, 0, W[WFX], W[WFY], W[WFZ], nullptr,
                           nullptr, nullptr, nullptr);
       };
       DCM_TRY(tune_edge(ctx, edge_key, edge_cands, run, &step_cell_edge));

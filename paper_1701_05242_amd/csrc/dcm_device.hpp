@@ -32,9 +32,11 @@ __device__ __forceinline__ int slab_index(double w, double scale, int n) {
 
 // x key of a particle in cell c of the slab grid (scale = n/L): its offset
 // into the cell, (w scale - c), in units of 2^-20 of the cell, clamped to
-// [0, 2^20).  Cells keep their particles in key order; quarter q of a cell
-// holds the keys [q 2^18, (q+1) 2^18).
+// [0, 2^20).  Cells keep their particles in key order; sub-cell q (of
+// kXSub along x) of a cell holds the keys [q, q + 1) 2^20 / kXSub.
 constexpr uint32_t kXKeyOne = 1u << 20;
+constexpr int kXSubLog = 3;
+constexpr int kXSub = 1 << kXSubLog;
 __device__ __forceinline__ uint32_t x_key(double w, double scale, int c) {
   const double f = (w * scale - (double)c) * (double)kXKeyOne;
   return f > 0.0 ? (f < (double)(kXKeyOne - 1) ? (uint32_t)f : kXKeyOne - 1) : 0u;

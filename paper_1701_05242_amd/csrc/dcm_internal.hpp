@@ -145,8 +145,8 @@ struct dcm_ctx {
   dcm::DevBuf tune_f;  // forces of the cell-edge tuner's trial passes (dcm_build_cells)
   // cells
   dcm::DevBuf cell_of, cell_count, cell_start, cell_fill, perm, sorted, scan_tmp, rcmax_part;
-  // x key of every particle (within-cell order), quarter word of every real
-  // cell and (start, quarter word) of every extended cell (the pair walk's
+  // x key of every particle (within-cell order), sub-cell word of every real
+  // cell and (start, sub-cell word) of every extended cell (the pair walk's
   // x trimming)
   dcm::DevBuf xkey, qword, ext_sq;
   dcm::DevBuf sort_tmp, sort_list;  // large-cell sort: scratch entries and the cells' list
@@ -288,9 +288,9 @@ void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
 // sorted_perm receives the entries of perm (particle ids in cell order, cell
 // c of particle id holding cell_of[id]) with each cell's sorted by (x key
 // xq[id], id); perm is left as scratch.  qword (null: none) receives the
-// cells' quarter words: bytes o1, o2, o3 (particles below 1/4, 1/2, 3/4 of
-// the cell along x) and the count, 0 for cells of more than 255.  big_list
-// holds cell_sort_list_elems(n) entries; big_count must be 0 on entry.
+// cells' sub-cell words (sub_word: prefix counts of each cell's eighths
+// along x, 0 for cells of more than 15).  big_list holds
+// cell_sort_list_elems(n) entries; big_count must be 0 on entry.
 void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell,
                       const int32_t *cell_of, int64_t n, int32_t *perm, const uint32_t *xq,
                       uint32_t *qword, int32_t *sorted_perm, int32_t *big_list,
@@ -306,7 +306,7 @@ int64_t ext_row_scratch_elems(const int32_t nc[3], const int32_t h[3]);
 // ghost-extended cells in two parts: the per-row tables and the extended
 // cell starts (ext_start[next] then holds the extended particle count), and
 // the images themselves into buffers of ext_cap slots.  ext_sq (null: none;
-// int2 [next + 1]) receives (ext_start, quarter word of the real cell) of
+// int2 [next + 1]) receives (ext_start, sub-cell word of the real cell) of
 // every extended cell and (extended count, 0) past the last.
 void launch_ext_count(hipStream_t s, const int32_t *cell_start, const int32_t nc[3],
                       const int32_t h[3], const double L[3], int32_t *row_count,
@@ -340,7 +340,7 @@ struct PairArgs {
   const float4 *ext_rel;     // compact cell-relative copy of ext_pos, or null
   double rel_delta;          // its per-coordinate error bound
   const int32_t *ext_start;  // extended cells [next + 1]
-  const int2 *ext_sq;        // (start, quarter word) of the extended cells [next + 1], or null
+  const int2 *ext_sq;        // (start, sub-cell word) of the extended cells [next + 1], or null
   int64_t n;
   int64_t ext_cap;           // capacity of ext_pos
   int32_t nc[3];
@@ -415,7 +415,7 @@ struct BatchPairArgs {
   const float4 *ext_rel;      // compact cell-relative copy of ext_pos, or null
   const double4 *ext_pos;
   const int32_t *ext_start;   // concatenated extended cells
-  const int2 *ext_sq;         // their (start, quarter word) [cells + 1], or null
+  const int2 *ext_sq;         // their (start, sub-cell word) [cells + 1], or null
   int64_t ext_cap;
   const unsigned long long *rc_max_bits;  // per system
   double eps, sigma;

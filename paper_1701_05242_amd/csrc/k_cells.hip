@@ -335,32 +335,22 @@ __device__ __forceinline__ uint64_t sort_key(const uint32_t *__restrict__ xq, in
   return ((uint64_t)xq[i] << 32) | (uint32_t)i;
 }
 
-// Quarter counts of a cell's particles along x: o1, o2, o3 = how many have x
-// keys below 1/4, 1/2, 3/4 of the cell (with the particles in key order, the
-// first slots of quarters 1, 2, 3 are a + o1, a + o2, a + o3).
-__device__ __forceinline__ void count_quarters(const uint32_t *__restrict__ xq,
-                                               const int32_t *__restrict__ perm, int p0, int p1,
-                                               int step, uint32_t &o1, uint32_t &o2,
-                                               uint32_t &o3) {
-  o1 = o2 = o3 = 0;
-  for (int p = p0; p < p1; p += step) {
-    const uint32_t q = xq[perm[p]];
-    o1 += q < kXKeyOne / 4 ? 1u : 0u;
-    o2 += q < kXKeyOne / 2 ? 1u : 0u;
-    o3 += q < 3 * (kXKeyOne / 4) ? 1u : 0u;
-  }
+// A cell's sub-cell word: nibble k (k = 0..6) counts its particles with x
+// keys below (k + 1)/8 of the cell -- with the particles in key order, the
+// first slot of sub-cell k + 1 is the cell's first plus that count -- and
+// nibble 7 counts them all; 0 (no sub-cells) for a cell of more than 15.
+// A nibble histogram of the sub-cells times 0x11111111 is its prefix sums.
+__device__ __forceinline__ uint32_t sub_word(const uint32_t *__restrict__ xq,
+                                             const int32_t *__restrict__ perm, int a, int b) {
+  if (b - a > 15) return 0u;
+  uint32_t hist = 0;
+  for (int p = a; p < b; ++p) hist += 1u << (4 * (xq[perm[p]] >> (20 - kXSubLog)));
+  return hist * 0x11111111u;
 }
 
-// A cell's quarter word: bytes o1, o2, o3 and the count n; 0 (no quarters)
-// for a cell of more than 255 particles.
-__device__ __forceinline__ uint32_t quarter_word(uint32_t o1, uint32_t o2, uint32_t o3,
-                                                 uint32_t n) {
-  return n > 255 ? 0u : (o1 | (o2 << 8) | (o3 << 16) | (n << 24));
-}
-
-// One thread per cell: a cell of more than kSmallCell particles goes to the
-// list that whole workgroups sort (k_cell_sort_big, which also writes its
-// quarter word); a smaller one gets its quarter word here.
+// One thread per cell: its sub-cell word, and a cell of more than
+// kSmallCell particles goes to the list that whole workgroups sort
+// (k_cell_sort_big).
 __global__ __launch_bounds__(256) void k_cell_small(const int32_t *__restrict__ cell_start,
                                                     int64_t ncell,
                                                     const int32_t *__restrict__ perm,
@@ -371,15 +361,8 @@ __global__ __launch_bounds__(256) void k_cell_small(const int32_t *__restrict__ 
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int a = cell_start[c], b = cell_start[c + 1];
-    if (b - a > kSmallCell) {
-      big_list[atomicAdd(big_count, 1u)] = (int32_t)c;
-      continue;
-    }
-    if (qword) {
-      uint32_t o1, o2, o3;
-      count_quarters(xq, perm, a, b, 1, o1, o2, o3);
-      qword[c] = quarter_word(o1, o2, o3, (uint32_t)(b - a));
-    }
+    if (qword) qword[c] = sub_word(xq, perm, a, b);
+    if (b - a > kSmallCell) big_list[atomicAdd(big_count, 1u)] = (int32_t)c;
   }
 }
 
@@ -420,28 +403,14 @@ __global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ c
 __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t *__restrict__ cell_start,
                                                        int32_t *perm, int32_t *tmp,
                                                        const uint32_t *__restrict__ xq,
-                                                       uint32_t *__restrict__ qword,
                                                        const int32_t *__restrict__ big_list,
                                                        const uint32_t *big_count) {
   __shared__ int32_t buf[kSortChunk];
-  __shared__ uint32_t qn[3];
   const int tid = threadIdx.x;
   const uint32_t nbig = *big_count;
   for (uint32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
     const int64_t c = big_list[q];
     const int a = cell_start[c], n = cell_start[c + 1] - a;
-    if (qword) {  // the counts do not depend on the order
-      if (tid < 3) qn[tid] = 0;
-      __syncthreads();
-      uint32_t o1, o2, o3;
-      count_quarters(xq, perm, a + tid, a + n, 256, o1, o2, o3);
-      atomicAdd(&qn[0], o1);
-      atomicAdd(&qn[1], o2);
-      atomicAdd(&qn[2], o3);
-      __syncthreads();
-      if (tid == 0) qword[c] = quarter_word(qn[0], qn[1], qn[2], (uint32_t)n);
-      __syncthreads();
-    }
     for (int c0 = 0; c0 < n; c0 += kSortChunk) {
       const int len = n - c0 < kSortChunk ? n - c0 : kSortChunk;
       int P = 1;
@@ -514,7 +483,7 @@ void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell,
   }
   // the large cells, in place in sorted_perm with perm as scratch
   hipLaunchKernelGGL(k_cell_sort_big, dim3(kBigSortBlocks), dim3(256), 0, s, cell_start,
-                     sorted_perm, perm, xq, qword, big_list, big_count);
+                     sorted_perm, perm, xq, big_list, big_count);
 }
 
 int64_t cell_sort_list_elems(int64_t n) { return n / (kSmallCell + 1) + 1; }

@@ -7,10 +7,10 @@
 // (fixed y and z cell; consecutive x cells are consecutive in memory) that can
 // hold a j within its search radius and trims each row to the chord of the
 // search sphere -- the small-cell traversal of Section 2.3.  Cells keep their
-// particles in x order with a table of where each quarter of the cell (along
-// x) starts, so a row's two end cells are trimmed to the quarters the chord
-// reaches: the walk sees about the candidates of cells a quarter as wide
-// while reading two table entries per row.  The rows are
+// particles in x order with a table of where each eighth of the cell (along
+// x) starts, so a row's two end cells are trimmed to the eighths the chord
+// reaches: the walk sees about the candidates of cells an eighth as wide
+// along x while reading two table entries per row.  The rows are
 // walked in the ghost-extended cell grid, where periodic images sit in halo
 // cells with their coordinates already shifted, so every row is one
 // contiguous index range and a separation is a plain difference.  A lane
@@ -278,10 +278,10 @@ struct PairView {
   const float4 *ext_rel;         // its compact cell-relative copy (FP32-mixed builds)
   double rel_delta;              // bound on the per-coordinate error of ext_rel
   const int32_t *ext_start;      // this system's extended cells -> extended slots
-  // (first slot, quarter word) of every extended cell and (extended count,
-  // 0) past the last; the word's bytes o1, o2, o3, n count the cell's
-  // particles (in x order) below 1/4, 1/2, 3/4 of the cell and in all, and
-  // are 0 for a cell without quarters.  Null: rows take whole end cells.
+  // (first slot, sub-cell word) of every extended cell and (extended count,
+  // 0) past the last; the word's nibbles k = 0..6 count the cell's particles
+  // (in x order) below (k + 1)/8 of the cell, nibble 7 all of them; 0 for a
+  // cell without sub-cells.  Null: rows take whole end cells.
   const int2 *ext_sq;
   int64_t ext_cap;
   int nc[3], h[3], ne[3];
@@ -308,8 +308,8 @@ struct LaneGeo {
   // of its cell's positive (gp) and negative (gm) neighbours less one cell,
   // 0.5 len +- a0 + guard, and the lane's offset in cell units, a0/len + 1/2
   float gp[3], gm[3], ac[3];
-  // 4 invf[0] and 4 ac[0]: the quarter-cell offsets along x, and the
-  // extended grid's first and last quarter relative to the lane's cell
+  // kXSub invf[0] and kXSub ac[0]: the sub-cell offsets along x, and the
+  // extended grid's first and last sub-cell relative to the lane's cell
   float qinv, qac;
   int qmin, qmax;
   // compact records: FP32 r^2 below which a pair is evaluated in FP64, and
@@ -510,9 +510,10 @@ __device__ __forceinline__ int cell_off(float p, const LaneGeo &g, int a) {
   return (int)floorf(fmaf(p, g.invf[a], g.ac[a]));
 }
 
-// The same along x in quarter cells: q >> 2 is cell_off(p, g, 0) (scaling by
-// 4 is exact in FP32), q & 3 the quarter of that cell holding a0 + p.
-__device__ __forceinline__ int quarter_off(float p, const LaneGeo &g) {
+// The same along x in sub-cells: q >> kXSubLog is cell_off(p, g, 0) (scaling
+// by a power of 2 is exact in FP32), q & (kXSub - 1) the sub-cell of that
+// cell holding a0 + p.
+__device__ __forceinline__ int sub_off(float p, const LaneGeo &g) {
   return (int)floorf(fmaf(p, g.qinv, g.qac));
 }
 
@@ -608,25 +609,25 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
         const float rem = fmaf(-ey, ey, remz);
         in = in && rem >= 0.0f;
         // chord half-width, widened by the guard (it only selects cells and
-        // quarters of cells)
+        // sub-cells)
         const float w = in ? __builtin_amdgcn_sqrtf(rem) + g.fguard : 0.0f;
-        // the chord's ends in quarter cells from the lane's cell, within the
+        // the chord's ends in sub-cells from the lane's cell, within the
         // extended grid (-w <= 0 <= w: the lower end can only leave it below,
         // the upper above)
-        const int qlo = max(quarter_off(-w, g), g.qmin);
-        const int qhi = min(quarter_off(w, g), g.qmax);
+        const int qlo = max(sub_off(-w, g), g.qmin);
+        const int qhi = min(sub_off(w, g), g.qmax);
         // a row that is not taken still reads (its own cell row's) starts
         const int row = in ? rowbase + __mul24(ycur, nex) : own_row;
-        const int e0 = row + g.cx + (qlo >> 2), e1 = row + g.cx + (qhi >> 2) + 1;
+        const int e0 = row + g.cx + (qlo >> kXSubLog), e1 = row + g.cx + (qhi >> kXSubLog) + 1;
         if (trim) {
-          // from the start of quarter qlo & 3 of cell e0 to the end of
-          // quarter qhi & 3 of cell e1 - 1 (the end cells' quarters beyond
+          // from the start of sub-cell qlo & 7 of cell e0 to the end of
+          // sub-cell qhi & 7 of cell e1 - 1 (the end cells' sub-cells beyond
           // the chord are skipped): (start, word) of e0, and (word of e1 - 1,
           // start of e1), 8 bytes each from one table
           tl[k] = __builtin_amdgcn_raw_buffer_load_b64(rs_sq, (int)((uint32_t)e0 << 3), 0, 0);
           th[k] = __builtin_amdgcn_raw_buffer_load_b64(rs_sq, (int)(((uint32_t)e1 << 3) - 4), 0, 0);
-          sl[k] = (qlo & 3) << 3;
-          sh[k] = (qhi & 3) << 3;
+          sl[k] = (qlo & (kXSub - 1)) << 2;
+          sh[k] = (qhi & (kXSub - 1)) << 2;
         } else {
           j0[k] = load_start(e0);
           j1[k] = load_start(e1);
@@ -639,10 +640,10 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
       for (int k = 0; k < kFillRows; ++k) {
         if (!ok[k]) continue;
         if (trim) {
-          // start of quarter ql: the byte ql - 1 (0 for ql = 0); end of
-          // quarter qh: n less the byte qh (0 for qh = 3)
-          j0[k] = (int)(tl[k].x + (((tl[k].y << 8) >> sl[k]) & 0xffu));
-          j1[k] = (int)(th[k].y - ((th[k].x >> 24) - ((th[k].x >> sh[k]) & 0xffu)));
+          // start of sub-cell ql: nibble ql - 1 (0 for ql = 0); end of
+          // sub-cell qh: n less nibble qh (0 for qh = 7)
+          j0[k] = (int)(tl[k].x + (((tl[k].y << 4) >> sl[k]) & 0xfu));
+          j1[k] = (int)(th[k].y - ((th[k].x >> 28) - ((th[k].x >> sh[k]) & 0xfu)));
         }
         const int a0 = j0[k];
         const int a1 = j1[k] > v.ext_cap ? (int)v.ext_cap : j1[k];  // overflow (flagged at build)
@@ -815,10 +816,10 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
       g.gm[k] = fmaf(0.5f, g.lenf[k], -a0[k]) + g.fguard;
       g.ac[k] = fmaf(a0[k], g.invf[k], 0.5f);
     }
-    g.qinv = 4.0f * g.invf[0];
-    g.qac = 4.0f * g.ac[0];
-    g.qmin = 4 * (-hx - cx);
-    g.qmax = 4 * (nx + hx - 1 - cx) + 3;
+    g.qinv = (float)kXSub * g.invf[0];
+    g.qac = (float)kXSub * g.ac[0];
+    g.qmin = kXSub * (-hx - cx);
+    g.qmax = kXSub * (nx + hx - 1 - cx) + (kXSub - 1);
     const double Rf = Rg + (double)g.fguard;
     g.fR2 = (float)(Rf * Rf) * (1.0f + 0x1p-20f);
     if constexpr (REL) {
