@@ -622,23 +622,24 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
     DCM_TRY(ensure(ctx, ctx->qword, std::max<int64_t>(ncell, 1) * sizeof(uint32_t)));
   }
   DCM_TRY(ensure(ctx, ctx->xkey, std::max<int64_t>(n, 1) * sizeof(uint32_t)));
+  DCM_TRY(ensure(ctx, ctx->skey, std::max<int64_t>(n, 1) * sizeof(uint32_t)));
   DCM_TRY(ensure(ctx, ctx->scan_tmp, scan_tmp_elems(std::max(ncell, nrow1)) * sizeof(int32_t)));
   // FP32-mixed builds also write the compact records the pair kernel reads
   const bool rel = prec == DCM_FP32_MIXED && halo[1] <= kRelMaxHalo && halo[2] <= kRelMaxHalo;
   hipStream_t s = ctx->stream;
   hipEvent_t ev;
   timer_begin(ctx, "cells", &ev);
-  launch_fill_i32(s, ptr<int32_t>(ctx->cell_count), 0, ncell);
+  launch_zero2_i32(s, ptr<int32_t>(ctx->cell_count), ptr<int32_t>(ctx->cell_fill), ncell);
   launch_cell_count(s, x, y, z, rc, n, box.L, nc, sc, rc_cap, cof, ptr<int32_t>(ctx->cell_count),
                     ptr<unsigned long long>(ctx->rcmax_part), ptr<uint32_t>(ctx->xkey), ctx->ctl,
                     ctx->d_status);
   launch_exclusive_scan(s, ptr<int32_t>(ctx->cell_count), ptr<int32_t>(ctx->cell_start), ncell,
                         ptr<int32_t>(ctx->scan_tmp));
-  launch_fill_i32(s, ptr<int32_t>(ctx->cell_fill), 0, ncell);
   launch_cell_scatter(s, cof, n, ptr<int32_t>(ctx->cell_start), ptr<int32_t>(ctx->cell_fill),
-                      ptr<int32_t>(ctx->perm));
+                      ptr<int32_t>(ctx->perm), ptr<uint32_t>(ctx->xkey), ptr<uint32_t>(ctx->skey));
   launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, cof, n, ptr<int32_t>(ctx->perm),
-                   ptr<uint32_t>(ctx->xkey), qtab ? ptr<uint32_t>(ctx->qword) : nullptr,
+                   ptr<uint32_t>(ctx->xkey), ptr<uint32_t>(ctx->skey),
+                   qtab ? ptr<uint32_t>(ctx->qword) : nullptr,
                    ptr<int32_t>(ctx->sort_tmp), ptr<int32_t>(ctx->sort_list), &ctx->ctl->big_cells);
   launch_gather(s, x, y, z, rc, ptr<int32_t>(ctx->sort_tmp), n, box.L, rc_cap,
                 ptr<double4>(ctx->sorted), ptr<int32_t>(ctx->perm));

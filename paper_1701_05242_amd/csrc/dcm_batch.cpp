@@ -47,7 +47,7 @@ struct BatchState {
   // device memory
   DevBuf tables, cell_of, cell_count, cell_fill, cell_start, perm, sorted, scan_tmp, row_count,
       row_start, row_lo, ext_start, ext_pos, ext_rel, partials, rcmax, rcmax_part, head,
-      sort_tmp, sort_list, xkey, qword, ext_sq;
+      sort_tmp, sort_list, xkey, skey, qword, ext_sq;
   // recorded graph
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -222,6 +222,8 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
     return st;
   if ((st = ensure(ctx, B.xkey, sizeof(uint32_t) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
     return st;
+  if ((st = ensure(ctx, B.skey, sizeof(uint32_t) * std::max<int64_t>(B.n_total, 1))) != DCM_OK)
+    return st;
   if ((st = ensure(ctx, B.qword, sizeof(uint32_t) * std::max<int64_t>(B.cells_total, 1))) !=
       DCM_OK)
     return st;
@@ -275,8 +277,7 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
                     : nullptr;
   hipEvent_t ev = nullptr;
   if (timed) timer_begin(ctx, "batch_cells", &ev);
-  launch_fill_i32(s, dptr<int32_t>(B.cell_count), 0, B.cells_total);
-  launch_fill_i32(s, dptr<int32_t>(B.cell_fill), 0, B.cells_total);
+  launch_zero2_i32(s, dptr<int32_t>(B.cell_count), dptr<int32_t>(B.cell_fill), B.cells_total);
   launch_fill_u32(s, dptr<uint32_t>(B.head), 0u, 2);
   launch_batch_cell_count(s, geo, nsys, items, nitems, dptr<int32_t>(B.cell_of),
                           dptr<int32_t>(B.cell_count), dptr<unsigned long long>(B.rcmax_part),
@@ -286,10 +287,10 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
                         B.cells_total, dptr<int32_t>(B.scan_tmp));
   launch_batch_cell_scatter(s, geo, items, nitems, dptr<int32_t>(B.cell_of),
                             dptr<int32_t>(B.cell_start), dptr<int32_t>(B.cell_fill),
-                            dptr<int32_t>(B.perm));
+                            dptr<int32_t>(B.perm), dptr<uint32_t>(B.xkey), dptr<uint32_t>(B.skey));
   launch_cell_sort(s, dptr<int32_t>(B.cell_start), B.cells_total, dptr<int32_t>(B.cell_of),
                    B.n_total, dptr<int32_t>(B.perm), dptr<uint32_t>(B.xkey),
-                   dptr<uint32_t>(B.qword), dptr<int32_t>(B.sort_tmp), dptr<int32_t>(B.sort_list),
+                   dptr<uint32_t>(B.skey), dptr<uint32_t>(B.qword), dptr<int32_t>(B.sort_tmp), dptr<int32_t>(B.sort_list),
                    dptr<uint32_t>(B.head) + 1);
   launch_batch_gather(s, geo, items, nitems, dptr<int32_t>(B.sort_tmp), dptr<double4>(B.sorted),
                       dptr<int32_t>(B.perm));

@@ -148,7 +148,7 @@ struct dcm_ctx {
   // x key of every particle (within-cell order), sub-cell word of every real
   // cell and (start, sub-cell word) of every extended cell (the pair walk's
   // x trimming)
-  dcm::DevBuf xkey, qword, ext_sq;
+  dcm::DevBuf xkey, skey, qword, ext_sq;
   dcm::DevBuf sort_tmp, sort_list;  // large-cell sort: scratch entries and the cells' list
   dcm::DevBuf ext_row_count, ext_row_start, ext_row_lo, ext_start, ext_pos;
   dcm::DevBuf ext_rel;  // FP32-mixed builds: compact cell-relative copy of ext_pos
@@ -226,6 +226,8 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // k_common.hip
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n);
 void launch_fill_i32(hipStream_t s, int32_t *p, int32_t v, int64_t n);
+// p[0..n) = q[0..n) = 0 in one launch
+void launch_zero2_i32(hipStream_t s, int32_t *p, int32_t *q, int64_t n);
 void launch_reset_ctl(hipStream_t s, Ctl *ctl);
 void launch_min_f64(hipStream_t s, const double *v, int64_t n, double *out);
 void launch_clear_status(hipStream_t s, uint32_t *st);
@@ -283,18 +285,20 @@ void launch_cell_count(hipStream_t s, const double *x, const double *y, const do
 void launch_exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64_t n,
                            int32_t *tmp);
 int64_t scan_tmp_elems(int64_t n);
+// perm[slot] = id and skey[slot] = xq[id] for every particle's slot in its cell
 void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
-                         const int32_t *cell_start, int32_t *cell_fill, int32_t *perm);
+                         const int32_t *cell_start, int32_t *cell_fill, int32_t *perm,
+                         const uint32_t *xq, uint32_t *skey);
 // sorted_perm receives the entries of perm (particle ids in cell order, cell
-// c of particle id holding cell_of[id]) with each cell's sorted by (x key
-// xq[id], id); perm is left as scratch.  qword (null: none) receives the
+// c of particle id holding cell_of[id], x keys xq by id and skey by slot)
+// with each cell's sorted by (x key, id); perm is left as scratch.  qword (null: none) receives the
 // cells' sub-cell words (sub_word: prefix counts of each cell's eighths
 // along x, 0 for cells of more than 15).  big_list holds
 // cell_sort_list_elems(n) entries; big_count must be 0 on entry.
 void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell,
                       const int32_t *cell_of, int64_t n, int32_t *perm, const uint32_t *xq,
-                      uint32_t *qword, int32_t *sorted_perm, int32_t *big_list,
-                      uint32_t *big_count);
+                      const uint32_t *skey, uint32_t *qword, int32_t *sorted_perm,
+                      int32_t *big_list, uint32_t *big_count);
 int64_t cell_sort_list_elems(int64_t n);
 // sorted copy (x, y, z, rc) in the order order[] of particle ids, which is
 // also copied to perm
@@ -434,7 +438,8 @@ void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, int32_t nsys, co
                              uint32_t *xq, uint32_t *status);
 void launch_batch_cell_scatter(hipStream_t s, const SysGeom *sys, const int2 *pblk,
                                int64_t npblk, const int32_t *cell_of, const int32_t *cell_start,
-                               int32_t *cell_fill, int32_t *perm);
+                               int32_t *cell_fill, int32_t *perm, const uint32_t *xq,
+                               uint32_t *skey);
 void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,
                          const int32_t *order, double4 *sorted, int32_t *perm);
 void launch_batch_ext(hipStream_t s, const SysGeom *sys, const int2 *eblk, int64_t neblk,

@@ -109,11 +109,12 @@ __global__ __launch_bounds__(256) void kb_reduce_rcmax(const SysGeom *__restrict
   }
 }
 
-// Slot of every particle inside its cell; perm[slot] = concatenated id.
+// Slot of every particle inside its cell; perm[slot] = concatenated id,
+// skey[slot] = its x key.
 __global__ __launch_bounds__(kBatchBlock) void kb_cell_scatter(
     const SysGeom *__restrict__ sys, const int2 *__restrict__ pblk,
     const int32_t *__restrict__ cell_of, const int32_t *__restrict__ cell_start, int32_t *fill,
-    int32_t *__restrict__ perm) {
+    int32_t *__restrict__ perm, const uint32_t *__restrict__ xq, uint32_t *__restrict__ skey) {
   int64_t first;
   const int b = block_system(pblk, first);
   const SysGeom &g = sys[b];
@@ -121,7 +122,11 @@ __global__ __launch_bounds__(kBatchBlock) void kb_cell_scatter(
   const bool valid = i < g.n;
   const int c = valid ? cell_of[g.p0 + i] : 0;
   const int slot = wave_run_slot(fill, (uint32_t)c, valid);
-  if (valid) perm[cell_start[c] + slot] = (int32_t)(g.p0 + i);
+  if (valid) {
+    const int64_t p = cell_start[c] + slot;
+    perm[p] = (int32_t)(g.p0 + i);
+    skey[p] = xq[g.p0 + i];
+  }
 }
 
 // Sorted copy (x, y, z, rc) in the order order[] (concatenated ids, copied
@@ -297,10 +302,11 @@ void launch_batch_cell_count(hipStream_t s, const SysGeom *sys, int32_t nsys, co
 
 void launch_batch_cell_scatter(hipStream_t s, const SysGeom *sys, const int2 *pblk,
                                int64_t npblk, const int32_t *cell_of, const int32_t *cell_start,
-                               int32_t *cell_fill, int32_t *perm) {
+                               int32_t *cell_fill, int32_t *perm, const uint32_t *xq,
+                               uint32_t *skey) {
   if (npblk <= 0) return;
   hipLaunchKernelGGL(kb_cell_scatter, dim3((unsigned)npblk), dim3(kBatchBlock), 0, s, sys, pblk,
-                     cell_of, cell_start, cell_fill, perm);
+                     cell_of, cell_start, cell_fill, perm, xq, skey);
 }
 
 void launch_batch_gather(hipStream_t s, const SysGeom *sys, const int2 *pblk, int64_t npblk,

@@ -167,6 +167,7 @@ constexpr int kScanThreads = 256;
 constexpr int kScanPer = 16;
 constexpr int kScanTile = kScanThreads * kScanPer;
 constexpr int kTotalsThreads = 1024;
+constexpr int64_t kScanSumTiles = 4096;  // up to this many tiles: no pass over the totals
 
 int64_t scan_tmp_elems(int64_t n) { return ceil_div(n, kScanTile) + 1; }
 
@@ -253,11 +254,23 @@ __global__ __launch_bounds__(kTotalsThreads) void k_scan_totals(int32_t *tile_su
   if (threadIdx.x == 0) *out_last = total;
 }
 
+// Each tile's local scan plus its offset: the scanned tile totals (SUM
+// false), or the sum of the raw totals of the tiles before it (SUM true: no
+// separate pass over the totals; the last tile also writes out[n]).
+template <bool SUM>
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *__restrict__ in,
                                                              int64_t n,
                                                              const int32_t *__restrict__ tile_off,
                                                              int32_t *__restrict__ out) {
   __shared__ int32_t lds[kScanThreads / 64];
+  int32_t off;
+  if constexpr (SUM) {
+    int32_t pre = 0;
+    for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += kScanThreads) pre += tile_off[t];
+    block_exclusive_scan<kScanThreads / 64>(pre, lds, &off);
+  } else {
+    off = tile_off[blockIdx.x];
+  }
   const int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * kScanPer;
   int32_t v[kScanPer];
   load_run(in, base, n, v);
@@ -265,7 +278,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *__re
 #pragma unroll
   for (int q = 0; q < kScanPer; ++q) s += v[q];
   int32_t total;
-  int32_t run = block_exclusive_scan<kScanThreads / 64>(s, lds, &total) + tile_off[blockIdx.x];
+  int32_t run = block_exclusive_scan<kScanThreads / 64>(s, lds, &total) + off;
+  if (SUM && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + total;
   int32_t o[kScanPer];
 #pragma unroll
   for (int q = 0; q < kScanPer; ++q) {
@@ -290,33 +304,49 @@ void launch_exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64
   int64_t ntiles = ceil_div(n, kScanTile);
   if (ntiles < 1) ntiles = 1;
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n, tmp);
+  if (ntiles <= kScanSumTiles) {
+    // each tile sums the totals before it (at most kScanSumTiles / 256 reads
+    // per thread): two launches
+    hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in,
+                       n, tmp, out);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kTotalsThreads), 0, s, tmp, ntiles, out + n);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n, tmp,
-                     out);
+  hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)ntiles), dim3(kScanThreads), 0, s, in, n,
+                     tmp, out);
 }
 
 // ------------------------------------------------ scatter + stable order
+// Slot of every particle inside its cell: perm[slot] = id, skey[slot] = its
+// x key.
 __global__ __launch_bounds__(256) void k_cell_scatter(const int32_t *__restrict__ cell_of,
                                                       int64_t n,
                                                       const int32_t *__restrict__ cell_start,
-                                                      int32_t *fill, int32_t *__restrict__ perm) {
+                                                      int32_t *fill, int32_t *__restrict__ perm,
+                                                      const uint32_t *__restrict__ xq,
+                                                      uint32_t *__restrict__ skey) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
     const int64_t i = base + threadIdx.x;
     const bool valid = i < n;
     const int c = valid ? cell_of[i] : 0;
     const int slot = wave_run_slot(fill, (uint32_t)c, valid);
-    if (valid) perm[cell_start[c] + slot] = (int32_t)i;
+    if (valid) {
+      const int64_t p = cell_start[c] + slot;
+      perm[p] = (int32_t)i;
+      skey[p] = xq[i];
+    }
   }
 }
 
 void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
-                         const int32_t *cell_start, int32_t *cell_fill, int32_t *perm) {
+                         const int32_t *cell_start, int32_t *cell_fill, int32_t *perm,
+                         const uint32_t *xq, uint32_t *skey) {
   if (n <= 0) return;
   int64_t b = ceil_div(n, 256);
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_cell_scatter, dim3((unsigned)b), dim3(256), 0, s, cell_of, n, cell_start,
-                     cell_fill, perm);
+                     cell_fill, perm, xq, skey);
 }
 
 // Atomic slots give an arbitrary order inside a cell; sort each cell's
@@ -335,16 +365,16 @@ __device__ __forceinline__ uint64_t sort_key(const uint32_t *__restrict__ xq, in
   return ((uint64_t)xq[i] << 32) | (uint32_t)i;
 }
 
-// A cell's sub-cell word: nibble k (k = 0..6) counts its particles with x
-// keys below (k + 1)/8 of the cell -- with the particles in key order, the
-// first slot of sub-cell k + 1 is the cell's first plus that count -- and
-// nibble 7 counts them all; 0 (no sub-cells) for a cell of more than 15.
-// A nibble histogram of the sub-cells times 0x11111111 is its prefix sums.
-__device__ __forceinline__ uint32_t sub_word(const uint32_t *__restrict__ xq,
-                                             const int32_t *__restrict__ perm, int a, int b) {
+// A cell's sub-cell word from the x keys of its slots [a, b): nibble k
+// (k = 0..6) counts its particles with x keys below (k + 1)/8 of the cell --
+// with the particles in key order, the first slot of sub-cell k + 1 is the
+// cell's first plus that count -- and nibble 7 counts them all; 0 (no
+// sub-cells) for a cell of more than 15.  A nibble histogram of the
+// sub-cells times 0x11111111 is its prefix sums.
+__device__ __forceinline__ uint32_t sub_word(const uint32_t *__restrict__ skey, int a, int b) {
   if (b - a > 15) return 0u;
   uint32_t hist = 0;
-  for (int p = a; p < b; ++p) hist += 1u << (4 * (xq[perm[p]] >> (20 - kXSubLog)));
+  for (int p = a; p < b; ++p) hist += 1u << (4 * (skey[p] >> (20 - kXSubLog)));
   return hist * 0x11111111u;
 }
 
@@ -353,27 +383,27 @@ __device__ __forceinline__ uint32_t sub_word(const uint32_t *__restrict__ xq,
 // (k_cell_sort_big).
 __global__ __launch_bounds__(256) void k_cell_small(const int32_t *__restrict__ cell_start,
                                                     int64_t ncell,
-                                                    const int32_t *__restrict__ perm,
-                                                    const uint32_t *__restrict__ xq,
+                                                    const uint32_t *__restrict__ skey,
                                                     uint32_t *__restrict__ qword,
                                                     int32_t *__restrict__ big_list,
                                                     uint32_t *big_count) {
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncell;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int a = cell_start[c], b = cell_start[c + 1];
-    if (qword) qword[c] = sub_word(xq, perm, a, b);
+    if (qword) qword[c] = sub_word(skey, a, b);
     if (b - a > kSmallCell) big_list[atomicAdd(big_count, 1u)] = (int32_t)c;
   }
 }
 
-// One thread per slot of the cell-scattered order perm: a particle of a
-// small cell moves to its cell's start plus its rank there (the count of the
-// cell's particles with smaller (x key, id)); a particle of a large cell
-// keeps its slot.  out receives the result; no thread waits on another.
+// One thread per slot of the cell-scattered order perm (x keys skey): a
+// particle of a small cell moves to its cell's start plus its rank there
+// (the count of the cell's particles with smaller (x key, id)); a particle
+// of a large cell keeps its slot.  out receives the result; no thread waits
+// on another.
 __global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ cell_start,
                                                    const int32_t *__restrict__ cell_of,
                                                    const int32_t *__restrict__ perm, int64_t n,
-                                                   const uint32_t *__restrict__ xq,
+                                                   const uint32_t *__restrict__ skey,
                                                    int32_t *__restrict__ out) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
@@ -384,12 +414,12 @@ __global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ c
       out[p] = i;
       continue;
     }
-    const uint32_t ki = xq[i];
+    const uint32_t ki = skey[p];
     int r = 0;
     for (int q = a; q < b; ++q) {
-      const int j = perm[q];
-      const uint32_t kj = xq[j];
-      r += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+      const uint32_t kj = skey[q];
+      r += kj < ki ? 1 : 0;
+      if (kj == ki) r += perm[q] < i ? 1 : 0;  // equal keys (rare): by id
     }
     out[a + r] = i;
   }
@@ -468,18 +498,18 @@ __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t *__restrict
 
 void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell,
                       const int32_t *cell_of, int64_t n, int32_t *perm, const uint32_t *xq,
-                      uint32_t *qword, int32_t *sorted_perm, int32_t *big_list,
-                      uint32_t *big_count) {
+                      const uint32_t *skey, uint32_t *qword, int32_t *sorted_perm,
+                      int32_t *big_list, uint32_t *big_count) {
   int64_t b = ceil_div(ncell, 256);
   if (b < 1) b = 1;
   if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_cell_small, dim3((unsigned)b), dim3(256), 0, s, cell_start, ncell, perm,
-                     xq, qword, big_list, big_count);
+  hipLaunchKernelGGL(k_cell_small, dim3((unsigned)b), dim3(256), 0, s, cell_start, ncell, skey,
+                     qword, big_list, big_count);
   if (n > 0) {
     int64_t bn = ceil_div(n, 256);
     if (bn > 16384) bn = 16384;
     hipLaunchKernelGGL(k_cell_rank, dim3((unsigned)bn), dim3(256), 0, s, cell_start, cell_of,
-                       perm, n, xq, sorted_perm);
+                       perm, n, skey, sorted_perm);
   }
   // the large cells, in place in sorted_perm with perm as scratch
   hipLaunchKernelGGL(k_cell_sort_big, dim3(kBigSortBlocks), dim3(256), 0, s, cell_start,

@@ -46,6 +46,19 @@ void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n) {
   hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
 }
 
+__global__ void k_zero2_i32(int32_t *p, int32_t *q, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    p[i] = 0;
+    q[i] = 0;
+  }
+}
+
+void launch_zero2_i32(hipStream_t s, int32_t *p, int32_t *q, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero2_i32, dim3(fill_grid(n)), dim3(256), 0, s, p, q, n);
+}
+
 void launch_fill_i32(hipStream_t s, int32_t *p, int32_t v, int64_t n) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
