@@ -111,6 +111,15 @@ def run_leg(s, prec, steps, warmup, dev, redetect=1):
         if status != dcm.DCM_OK:
             raise RuntimeError(f"device status {status}: {dcm.dcm_last_error(ctx)}")
         pairs_after = count_pairs()
+        # the cell walk's work at the step's cell edge (a pair-count pass)
+        npairs = torch.zeros(1, dtype=torch.uint64, device=dev)
+        dcm.dcm_build_cells(ctx, *pos, rc, s.box, min(cell_len) * (1.0 - 1e-12), prec,
+                            rc_bound=s.rule[1])
+        dcm.dcm_forces(ctx, lj, *frc, prec=prec, ev_flags=dcm.DCM_EV_COUNTS, npairs=npairs)
+        cand, rows = dcm.dcm_walk_stats(ctx)
+        walk_pairs = max(int(npairs.cpu().numpy()[0]), 1)
+        walk = {"candidates_per_pair": cand / walk_pairs, "rows_per_particle": rows / s.n,
+                "candidates": cand, "rows": rows, "pairs": walk_pairs}
     finally:
         dcm.dcm_destroy(ctx)
     wall = t1 - t0
@@ -123,7 +132,7 @@ def run_leg(s, prec, steps, warmup, dev, redetect=1):
                 pair_kernel_tflops=pairs * FLOP_PER_PAIR_FE / avg_pair_s / 1e12,
                 pair_launches=pair_launches,
                 stage_ms={k: v[0] / max(v[1], 1) for k, v in fam_ms.items()},
-                stage_launches={k: v[1] for k, v in fam_ms.items()})
+                stage_launches={k: v[1] for k, v in fam_ms.items()}, walk=walk)
 
 
 # (rc_min, rc_max) settings of the paper's Table 1 and the speedups it prints
@@ -618,6 +627,7 @@ def main():
                    "precision": args.prec, "tuned_cell_edge": main_leg["cell_len"]},
         "force_evals_per_s": main_leg["force_evals"],
         "stage_ms": main_leg["stage_ms"],
+        "walk": main_leg["walk"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(s.name, args.prec)},

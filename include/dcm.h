@@ -284,6 +284,16 @@ dcm_status dcm_forces(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_f
                       double *fx, double *fy, double *fz, double *energy, double *virial,
                       int32_t *nnbr, uint64_t *npairs);
 
+/* Work of the cell walk (the small-bin traversal of Section 2.3) in the last
+ * dcm_forces call on this context made with DCM_EV_COUNTS: stats[0] = the
+ * candidate pairs it tested (each particle's trimmed rows, its own slot
+ * excluded), stats[1] = the cell rows it visited, both summed over the
+ * particles (host uint64 [2]).  Candidates per interacting pair, stats[0] /
+ * npairs, is the overhead of the search over the pairs the rule accepts.
+ * Synchronises the context's stream.
+ * Errors: DCM_ERR_INVALID if the last dcm_forces call had no DCM_EV_COUNTS. */
+dcm_status dcm_walk_stats(dcm_ctx *ctx, uint64_t stats[2]);
+
 /* Verlet neighbour list with a skin (Section 2.3, Algorithm 2.2) on the cells
  * of the last dcm_build_cells: particle i's list holds every other particle or
  * periodic image j with r_ij^2 < R_i^2, R_i = min(r_c(i), rc_bound) + skin,

@@ -115,6 +115,7 @@ SIGNATURES = {
                  dcm_grid, _F64, _INT, _INT, _F64, _I32, _I32, _I64, _P, _P, _P],
     "dcm_forces_batched": [_P, _I32, _P, dcm_lj, _INT, _INT, _INT, _INT],
     "dcm_batched_edge": [_P, ctypes.POINTER(_F64)],
+    "dcm_walk_stats": [_P, ctypes.POINTER(ctypes.c_uint64)],
     "dcm_set_profiling": [_P, _INT],
     "dcm_kernel_time": [_P, ctypes.c_char_p, ctypes.POINTER(_F64), ctypes.POINTER(_I64)],
 }
@@ -291,6 +292,13 @@ def dcm_build_cells(ctx, x, y, z, rc, box, cell_edge: float = 0.0, prec: int = D
         _ptr(rc, f64, "rc", n), n, _box(box), float(cell_edge), float(rc_bound), int(prec),
         _ptr(cell_of, torch.int32, "cell_of", n), _ptr(cell_start, torch.int32, "cell_start"))
     _check(ctx, code)
+
+
+def dcm_walk_stats(ctx):
+    """(candidates tested, cell rows visited) of the last DCM_EV_COUNTS forces call."""
+    st = (ctypes.c_uint64 * 2)()
+    _check(ctx, load_library().dcm_walk_stats(ctx, st))
+    return int(st[0]), int(st[1])
 
 
 def dcm_cell_dims(ctx):

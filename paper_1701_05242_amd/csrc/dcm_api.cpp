@@ -697,6 +697,19 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   return check_launch(ctx, "dcm_build_cells");
 }
 
+dcm_status dcm_walk_stats(dcm_ctx *ctx, uint64_t stats[2]) {
+  if (!ctx || !stats) return DCM_ERR_INVALID;
+  if (!ctx->walk_valid)
+    return fail(ctx, DCM_ERR_INVALID, "dcm_walk_stats: no dcm_forces call with DCM_EV_COUNTS");
+  unsigned long long h[2] = {0, 0};
+  if (hipMemcpyAsync(h, ctx->walk.p, sizeof(h), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return fail(ctx, DCM_ERR_HIP, "dcm_walk_stats: read-back failed");
+  stats[0] = h[0];
+  stats[1] = h[1];
+  return DCM_OK;
+}
+
 dcm_status dcm_cell_dims(const dcm_ctx *ctx, int32_t n_cells[3], double cell_len[3]) {
   if (!ctx || !n_cells) return DCM_ERR_INVALID;
   if (ctx->cell_n < 0) return DCM_ERR_INVALID;
@@ -795,6 +808,15 @@ dcm_status forces_impl(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_
     // zero sums (fill kernels, not memsets, so the calls stay capturable)
     launch_fill_u32(ctx->stream, ptr<uint32_t>(ctx->n3_f), 0u, 8 * n);
     if (a.n3_cnt) launch_fill_i32(ctx->stream, a.n3_cnt, 0, n);
+  }
+  // a pair-count pass over the cells also counts the walk's candidates and rows
+  a.walk = nullptr;
+  ctx->walk_valid = false;
+  if ((ev_flags & DCM_EV_COUNTS) && !use_list) {
+    DCM_TRY(ensure(ctx, ctx->walk, 2 * sizeof(unsigned long long)));
+    a.walk = ptr<unsigned long long>(ctx->walk);
+    launch_fill_u64(ctx->stream, a.walk, 0ull, 2);
+    ctx->walk_valid = true;
   }
   hipEvent_t ev;
   timer_begin(ctx, "pair", &ev);

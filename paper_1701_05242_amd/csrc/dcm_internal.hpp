@@ -149,6 +149,9 @@ struct dcm_ctx {
   // cell and (start, sub-cell word) of every extended cell (the pair walk's
   // x trimming)
   dcm::DevBuf xkey, skey, qword, ext_sq;
+  // candidates tested and rows visited by the last DCM_EV_COUNTS cell walk
+  dcm::DevBuf walk;
+  bool walk_valid = false;
   dcm::DevBuf sort_tmp, sort_list;  // large-cell sort: scratch entries and the cells' list
   dcm::DevBuf ext_row_count, ext_row_start, ext_row_lo, ext_start, ext_pos;
   dcm::DevBuf ext_rel;  // FP32-mixed builds: compact cell-relative copy of ext_pos
@@ -345,6 +348,7 @@ struct PairArgs {
   double rel_delta;          // its per-coordinate error bound
   const int32_t *ext_start;  // extended cells [next + 1]
   const int2 *ext_sq;        // (start, sub-cell word) of the extended cells [next + 1], or null
+  unsigned long long *walk;  // DCM_EV_COUNTS cell walks: candidates, rows (zeroed), or null
   int64_t n;
   int64_t ext_cap;           // capacity of ext_pos
   int32_t nc[3];

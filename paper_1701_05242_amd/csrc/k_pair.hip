@@ -262,6 +262,14 @@ __device__ __forceinline__ void scan_ranges(const uint2 (*segs)[kPairBlock], int
   }
 }
 
+// Kernels that count the walk's candidates and rows (for dcm_walk_stats):
+// the compact-record ones in their pair-count instance, the others (which
+// always count pairs) whenever a counter buffer is passed.
+template <bool REL, int EVM>
+constexpr bool walk_counts() {
+  return !REL || (EVM & 4) != 0;
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) {
   return min(max(v, lo), hi);  // one v_med3_i32 (lo <= hi)
 }
@@ -284,6 +292,9 @@ struct PairView {
   // cell without sub-cells.  Null: rows take whole end cells.
   const int2 *ext_sq;
   int64_t ext_cap;
+  // pair-count passes: candidates tested and cell rows visited, summed over
+  // the particles (null: not collected)
+  unsigned long long *walk;
   int nc[3], h[3], ne[3];
   double len[3], sc[3];
   double rc_bound;
@@ -524,7 +535,7 @@ template <int RULE, int PREC, int EVM, bool REL, int CAP>
 __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const LaneGeo &g,
                                            double sig2, uint2 (*segs)[kPairBlock],
                                            int32_t (*nearq)[kPairBlock], Acc<PREC> &acc,
-                                           int &cnt, bool &redo) {
+                                           int &cnt, bool &redo, int &wcand, int &wrows) {
   const int lane_id = threadIdx.x;
   const int nx = v.nc[0], hx = v.h[0], hy = v.h[1], hz = v.h[2];
   const int nex = v.ne[0], ney = v.ne[1];
@@ -647,6 +658,10 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
         }
         const int a0 = j0[k];
         const int a1 = j1[k] > v.ext_cap ? (int)v.ext_cap : j1[k];  // overflow (flagged at build)
+        if constexpr (walk_counts<REL, EVM>()) {
+          ++wrows;
+          wcand += a1 > a0 ? a1 - a0 : 0;
+        }
         if constexpr (REL) {
           // the lane's own slot stays in its row: at separation 0 it is
           // queued like a close pair, and flush_near drops it
@@ -850,8 +865,9 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
     g.self = v.ext_start[ext_cell] + (int)(s - v.cell_start[real_cell]);
   }
   bool redo = false;
+  int wcand = 0, wrows = 0;
   sweep_rows<RULE, PREC, EVM, REL, seg_cap<REL>()>(v, active, g, sig2, segs, nearq, acc, cnt,
-                                                   redo);
+                                                   redo, wcand, wrows);
   if constexpr (REL) {
     // rare: lanes with a row longer than a list entry can describe, or with
     // more close pairs in one chunk than their queue holds, start over on
@@ -863,7 +879,17 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
       }
       bool unused = false;
       sweep_rows<RULE, PREC, EVM, false, seg_cap<REL>()>(v, active && redo, g, sig2, segs, nearq,
-                                                        acc, cnt, unused);
+                                                        acc, cnt, unused, wcand, wrows);
+    }
+  }
+  if constexpr (walk_counts<REL, EVM>()) {
+    if (v.walk) {  // the lane's own slot lies in its rows but is no candidate
+      const unsigned long long c = wave_sum_u64((unsigned long long)(wcand - (active ? 1 : 0)));
+      const unsigned long long r = wave_sum_u64((unsigned long long)wrows);
+      if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&v.walk[0], c);
+        atomicAdd(&v.walk[1], r);
+      }
     }
   }
   if constexpr (RULE == DCM_PAIR_MAX_N3) {
@@ -900,6 +926,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   v.rel_delta = a.rel_delta;
   v.ext_start = a.ext_start;
   v.ext_sq = a.ext_sq;
+  v.walk = a.walk;
   v.ext_cap = a.ext_cap;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -1029,6 +1056,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
     v.ext_sq = a.ext_sq && (int64_t)g.ne[0] * g.ne[1] * g.ne[2] < kQStartMaxCells
                    ? a.ext_sq + g.ext_cell0
                    : nullptr;
+    v.walk = nullptr;
     v.ext_cap = a.ext_cap;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {

@@ -78,9 +78,10 @@ def gpu_forces(s, rc, prec=dcm.DCM_FP64, rule=dcm.DCM_PAIR_OWN, edge=0.0, eps=1.
                        energy=e, virial=w, nnbr=nn, npairs=npairs)
         code = dcm.dcm_sync_status(ctx)
         dims = dcm.dcm_cell_dims(ctx)
+        walk = dcm.dcm_walk_stats(ctx)
     F = np.stack([host(fx), host(fy), host(fz)], 1)
     out = dict(F=F, E=float(host(e)[0]), W=host(w), nnbr=host(nn),
-               npairs=int(host(npairs)[0]), status=code, dims=dims)
+               npairs=int(host(npairs)[0]), status=code, dims=dims, walk=walk)
     if idx is not None:
         out["F"] = out["F"][idx]
         out["nnbr"] = out["nnbr"][idx]

@@ -83,6 +83,7 @@ def test_null_context_is_rejected_before_any_device_call(lib):
     assert lib.dcm_forces_batched(None, 0, None, dcm.make_lj(), 0, 0, 0,
                                   0) == dcm.DCM_ERR_INVALID
     assert lib.dcm_batched_edge(None, None) == dcm.DCM_ERR_INVALID
+    assert lib.dcm_walk_stats(None, None) == dcm.DCM_ERR_INVALID
 
 
 def test_system_descriptor_layout_matches_header():

@@ -324,6 +324,34 @@ def test_fp32_mixed_many_close_pairs(edge):
     assert rel(got["W"], ref["W"]) <= 1e-5
 
 
+@pytest.mark.parametrize("edge", [0.9, 1.3, 2.0])
+def test_walk_stats_bracket_the_candidates(edge):
+    """dcm_walk_stats after a pair-count pass: every interacting pair is among
+    the candidates the walk tested, and no candidate lies outside the particle's
+    box of half-width r_c + one cell edge (the rows reach one cell past the
+    search sphere at most; brute force over that box with a periodic KD-tree).
+    Both precisions walk the same rows and candidates: the compact records
+    change only the arithmetic.  Each particle visits at least one row."""
+    from scipy.spatial import cKDTree
+    print(f"[gpu] walk stats edge={edge}", flush=True)
+    s = workloads.make("slab_medium")
+    rc = ref_detect("slab_medium")["rc"]
+    g64 = gpu_forces(s, rc, prec=dcm.DCM_FP64, edge=edge, rc_bound=s.rule[1])
+    g32 = gpu_forces(s, rc, prec=dcm.DCM_FP32_MIXED, edge=edge, rc_bound=s.rule[1])
+    assert g64["status"] == dcm.DCM_OK and g32["status"] == dcm.DCM_OK
+    cand, rows = g64["walk"]
+    assert g32["walk"] == g64["walk"]
+    assert cand >= g64["npairs"] and rows >= s.n
+    length = max(g64["dims"][1])
+    pts = np.mod(np.stack([s.x, s.y, s.z], 1), np.array(s.box))
+    tree = cKDTree(pts, boxsize=np.array(s.box))
+    # (1e-3: above the walk's 4e-6 (R + len) row-selection guard)
+    box = tree.query_ball_point(pts, rc + length + 1e-3, p=np.inf, return_length=True)
+    assert cand <= int(np.sum(box)) - s.n
+    print(f"[gpu]   candidates/pair {cand / g64['npairs']:.3f}, rows/particle {rows / s.n:.1f}, "
+          f"box bound/pair {(np.sum(box) - s.n) / g64['npairs']:.3f}", flush=True)
+
+
 @pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
 def test_tuned_cell_edge(prec):
     """cell_edge < 0: the edge is one of the tuner's candidates (fractions of
