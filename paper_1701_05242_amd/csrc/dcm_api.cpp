@@ -109,8 +109,7 @@ dcm_status detect_enqueue(dcm_ctx *ctx, const double *x, const double *y, const 
   hipStream_t s = ctx->stream;
   hipEvent_t ev = nullptr;
   if (timed) timer_begin(ctx, "detect", &ev);
-  launch_fill_u32(s, sc.counts, 0u, nvox);
-  launch_fill_u32(s, sc.hist, 0u, (int64_t)kHistCopies * kHistBins);
+  launch_zero2_u32(s, sc.counts, nvox, sc.hist, (int64_t)kHistCopies * kHistBins);
   launch_bin_density(s, x, y, z, n, box.L, grid.n, sc3, sc.counts, ctx->d_status);
   launch_gray_hist(s, sc.counts, sc.gray, grid.n, sc.hist, ctx->d_status);
   if (opts.split <= 0.0) launch_otsu(s, sc.hist, nvox, ctx->ctl, threshold_out, ctx->d_status);
@@ -121,13 +120,15 @@ dcm_status detect_enqueue(dcm_ctx *ctx, const double *x, const double *y, const 
     else
       launch_potts_pass(s, sc.seg_a, sc.seg_b, sc.gray, grid.n, opts.nu, p, ctx->ctl);
   }
-  launch_interface(s, sc.seg_a, sc.seg_b, grid.n, ctx->ctl, seg, iface);
+  // seg null (dcm_step): the phase maps feed the distance sweep directly
+  if (seg) launch_interface(s, sc.seg_a, sc.seg_b, grid.n, ctx->ctl, seg, iface);
   if (opts.min_volume > 0)
     launch_bubble_filter(s, grid.n, opts.min_volume, seg, iface, sc.ccl_label, sc.ccl_size,
                          ctx->d_status);
   if (timed) timer_end(ctx, "detect", ev);
   return check_launch(ctx, "dcm_detect_interface");
 }
+
 
 }  // namespace dcm
 
@@ -249,6 +250,34 @@ dcm_status tune_edge(dcm_ctx *ctx, const std::vector<double> &key,
 }
 
 }  // namespace
+
+namespace dcm {
+dcm_status detect_scratch(dcm_ctx *ctx, const dcm_grid &grid, int64_t nvox,
+                          const dcm_detect_opts &o, uint32_t *counts, DetectScratch *out) {
+  const dcm_detect_opts *opts = &o;
+  DetectScratch &sc = *out;
+  DCM_TRY(ensure(ctx, ctx->gray, nvox * sizeof(uint32_t)));
+  DCM_TRY(ensure(ctx, ctx->hist, (size_t)kHistCopies * kHistBins * sizeof(uint32_t)));
+  DCM_TRY(ensure(ctx, ctx->seg_a, phase_bits_words(grid.n) * sizeof(uint32_t)));
+  DCM_TRY(ensure(ctx, ctx->seg_b, phase_bits_words(grid.n) * sizeof(uint32_t)));
+  if (opts->min_volume > 0) {
+    DCM_TRY(ensure(ctx, ctx->ccl_label, nvox * sizeof(int32_t)));
+    DCM_TRY(ensure(ctx, ctx->ccl_size, nvox * sizeof(int32_t)));
+    sc.ccl_label = ptr<int32_t>(ctx->ccl_label);
+    sc.ccl_size = ptr<int32_t>(ctx->ccl_size);
+  }
+  if (!counts) {
+    DCM_TRY(ensure(ctx, ctx->counts, nvox * sizeof(uint32_t)));
+    counts = ptr<uint32_t>(ctx->counts);
+  }
+  sc.counts = counts;
+  sc.gray = ptr<uint32_t>(ctx->gray);
+  sc.hist = ptr<uint32_t>(ctx->hist);
+  sc.seg_a = ptr<uint32_t>(ctx->seg_a);
+  sc.seg_b = ptr<uint32_t>(ctx->seg_b);
+  return DCM_OK;
+}
+}  // namespace dcm
 
 extern "C" {
 
@@ -408,27 +437,45 @@ dcm_status dcm_detect_interface_opts(dcm_ctx *ctx, const double *x, const double
   int64_t nvox = 0;
   DCM_TRY(detect_check(ctx, x, y, z, n, box, grid, opts, seg, iface, &nvox));
   DetectScratch sc;
-  DCM_TRY(ensure(ctx, ctx->gray, nvox * sizeof(uint32_t)));
-  DCM_TRY(ensure(ctx, ctx->hist, (size_t)kHistCopies * kHistBins * sizeof(uint32_t)));
-  DCM_TRY(ensure(ctx, ctx->seg_a, phase_bits_words(grid.n) * sizeof(uint32_t)));
-  DCM_TRY(ensure(ctx, ctx->seg_b, phase_bits_words(grid.n) * sizeof(uint32_t)));
-  if (opts->min_volume > 0) {
-    DCM_TRY(ensure(ctx, ctx->ccl_label, nvox * sizeof(int32_t)));
-    DCM_TRY(ensure(ctx, ctx->ccl_size, nvox * sizeof(int32_t)));
-    sc.ccl_label = ptr<int32_t>(ctx->ccl_label);
-    sc.ccl_size = ptr<int32_t>(ctx->ccl_size);
-  }
-  if (!counts) {
-    DCM_TRY(ensure(ctx, ctx->counts, nvox * sizeof(uint32_t)));
-    counts = ptr<uint32_t>(ctx->counts);
-  }
-  sc.counts = counts;
-  sc.gray = ptr<uint32_t>(ctx->gray);
-  sc.hist = ptr<uint32_t>(ctx->hist);
-  sc.seg_a = ptr<uint32_t>(ctx->seg_a);
-  sc.seg_b = ptr<uint32_t>(ctx->seg_b);
+  DCM_TRY(detect_scratch(ctx, grid, nvox, *opts, counts, &sc));
   return detect_enqueue(ctx, x, y, z, n, box, grid, *opts, sc, seg, iface, threshold_out, true);
 }
+
+
+namespace {
+// The sweep on the context's buffers; dist null: no final pass (the field
+// stays in dA / dB with the pass flags, as dcm_step reads it).
+// maps set: sources from the regularisation passes' bit-packed phase maps
+// (launch_fsm_init_bits) instead of the byte maps seg / iface.
+dcm_status sweep_enqueue(dcm_ctx *ctx, const uint8_t *seg, const uint8_t *iface,
+                         const dcm_grid &grid, int64_t nvox, double rc_grid, int32_t max_waves,
+                         double *dist, int32_t *waves_out, const uint32_t *const *maps = nullptr) {
+  DCM_TRY(ensure(ctx, ctx->dA, nvox * sizeof(double)));
+  DCM_TRY(ensure(ctx, ctx->dB, nvox * sizeof(double)));
+  const int64_t ntiles = fsm_tile_count(grid.n);
+  DCM_TRY(ensure(ctx, ctx->fsm_chg, 2 * ntiles));
+  uint8_t *chg0 = ptr<uint8_t>(ctx->fsm_chg), *chg1 = chg0 + ntiles;
+  DCM_TRY(ensure(ctx, ctx->fsm_flags, (size_t)(max_waves + 2) * sizeof(uint32_t)));
+  uint32_t *flags = ptr<uint32_t>(ctx->fsm_flags);
+  hipStream_t s = ctx->stream;
+  hipEvent_t ev;
+  timer_begin(ctx, "sweep", &ev);
+  if (maps)
+    launch_fsm_init_bits(s, maps, ctx->ctl, grid.n, ptr<double>(ctx->dA), ptr<double>(ctx->dB),
+                         chg0, flags, max_waves);
+  else
+    launch_fsm_init(s, seg, iface, grid.n, ptr<double>(ctx->dA), ptr<double>(ctx->dB), chg0,
+                    flags, max_waves);
+  for (int w = 1; w <= max_waves; ++w)
+    launch_fsm_step(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), chg0, chg1, grid.n, grid.h,
+                    rc_grid, w, flags);
+  if (dist)
+    launch_fsm_final(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), nvox, rc_grid, flags,
+                     max_waves, dist, waves_out, ctx->d_status);
+  timer_end(ctx, "sweep", ev);
+  return check_launch(ctx, "dcm_sweep_distance");
+}
+}  // namespace
 
 dcm_status dcm_sweep_distance(dcm_ctx *ctx, const uint8_t *seg, const uint8_t *iface,
                               dcm_grid grid, double rc_grid, int32_t max_waves, double *dist,
@@ -440,25 +487,8 @@ dcm_status dcm_sweep_distance(dcm_ctx *ctx, const uint8_t *seg, const uint8_t *i
   if (!finite_pos(rc_grid)) return fail(ctx, DCM_ERR_INVALID, "rc_grid must be > 0");
   if (max_waves < 1 || max_waves > 100000)
     return fail(ctx, DCM_ERR_INVALID, "max_waves must be in [1, 100000]");
-  DCM_TRY(ensure(ctx, ctx->dA, nvox * sizeof(double)));
-  DCM_TRY(ensure(ctx, ctx->dB, nvox * sizeof(double)));
-  const int64_t ntiles = fsm_tile_count(grid.n);
-  DCM_TRY(ensure(ctx, ctx->fsm_chg, 2 * ntiles));
-  uint8_t *chg0 = ptr<uint8_t>(ctx->fsm_chg), *chg1 = chg0 + ntiles;
-  DCM_TRY(ensure(ctx, ctx->fsm_flags, (size_t)(max_waves + 2) * sizeof(uint32_t)));
-  uint32_t *flags = ptr<uint32_t>(ctx->fsm_flags);
-  hipStream_t s = ctx->stream;
-  hipEvent_t ev;
-  timer_begin(ctx, "sweep", &ev);
-  launch_fsm_init(s, seg, iface, grid.n, ptr<double>(ctx->dA), ptr<double>(ctx->dB), chg0, flags,
-                  max_waves);
-  for (int w = 1; w <= max_waves; ++w)
-    launch_fsm_step(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), chg0, chg1, grid.n, grid.h,
-                    rc_grid, w, flags);
-  launch_fsm_final(s, ptr<double>(ctx->dA), ptr<double>(ctx->dB), nvox, rc_grid, flags,
-                   max_waves, dist, waves_out, ctx->d_status);
-  timer_end(ctx, "sweep", ev);
-  return check_launch(ctx, "dcm_sweep_distance");
+  ctx->have_field = false;  // dcm_step's field lives in the sweep buffers this call reuses
+  return sweep_enqueue(ctx, seg, iface, grid, nvox, rc_grid, max_waves, dist, waves_out);
 }
 
 dcm_status dcm_assign_cutoffs(dcm_ctx *ctx, const double *x, const double *y, const double *z,
@@ -987,9 +1017,6 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
   for (int a = 0; a < 3; ++a)
     if (!(rule.rc_max < 0.5 * box.L[a]))
       return fail(ctx, DCM_ERR_RANGE, "rc_max must be below half of every box length");
-  DCM_TRY(ensure(ctx, ctx->seg, nvox));
-  DCM_TRY(ensure(ctx, ctx->iface, nvox));
-  DCM_TRY(ensure(ctx, ctx->dist, nvox * sizeof(double)));
   DCM_TRY(ensure(ctx, ctx->scalars, 16 * sizeof(double)));
   DCM_TRY(ensure(ctx, ctx->ke, kinetic_blocks(n) * sizeof(double)));
   // working copies: fields x y z, vx vy vz, fx fy fz, delta, rc of every
@@ -1068,12 +1095,20 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
                           ? std::max<int32_t>(12, (int32_t)std::ceil(2.0 * rc_grid / (8.0 * hmin)) + 8)
                           : std::max<int32_t>(64, (int32_t)std::ceil(4.0 * rc_grid / hmin) + 8);
   double *scal = ptr<double>(ctx->scalars);
+  const dcm_detect_opts dopts = {0.0, -1.0, 0};
   auto detect = [&]() -> dcm_status {
-    DCM_TRY(dcm_detect_interface(ctx, W[WX], W[WY], W[WZ], n, box, grid, 0.0, nullptr,
-                                 ptr<uint8_t>(ctx->seg), ptr<uint8_t>(ctx->iface), nullptr));
-    DCM_TRY(dcm_sweep_distance(ctx, ptr<uint8_t>(ctx->seg), ptr<uint8_t>(ctx->iface), grid,
-                               rc_grid, max_waves, ptr<double>(ctx->dist), nullptr));
+    // detection (Section 2.1) without the byte maps: the sweep takes its
+    // sources from the phase maps, and the field stays in the sweep's
+    // buffers, where the cutoffs read it
+    DetectScratch sc;
+    DCM_TRY(detect_scratch(ctx, grid, nvox, dopts, nullptr, &sc));
+    DCM_TRY(detect_enqueue(ctx, W[WX], W[WY], W[WZ], n, box, grid, dopts, sc, nullptr, nullptr,
+                           nullptr, true));
+    const uint32_t *const maps[2] = {sc.seg_a, sc.seg_b};
+    DCM_TRY(sweep_enqueue(ctx, nullptr, nullptr, grid, nvox, rc_grid, max_waves, nullptr, nullptr,
+                          maps));
     ctx->have_field = true;
+    ctx->field_waves = max_waves;
     for (int a = 0; a < 3; ++a) {
       ctx->field_n[a] = grid.n[a];
       ctx->field_h[a] = grid.h[a];
@@ -1095,9 +1130,19 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
       rule.rc_min, prec == DCM_FP32_MIXED ? kRelMaxEdgeSigma * lj.sigma : INFINITY, box.L);
   // cutoffs, cells and forces of the working copies; the forces land in the
   // working order (the cells map sorted slots back to it)
+  const double vsc[3] = {(double)grid.n[0] / box.L[0], (double)grid.n[1] / box.L[1],
+                         (double)grid.n[2] / box.L[2]};
   auto forces = [&](double *e_out) -> dcm_status {
-    DCM_TRY(dcm_assign_cutoffs(ctx, W[WX], W[WY], W[WZ], n, box, grid, ptr<double>(ctx->dist),
-                               rule, W[WDELTA], W[WRC]));
+    {  // cutoffs (Section 2.2) from the field in the sweep's buffers
+      hipEvent_t cev;
+      timer_begin(ctx, "cutoffs", &cev);
+      launch_assign_cutoffs_sweep(s, W[WX], W[WY], W[WZ], n, box.L, grid.n, vsc,
+                                  ptr<double>(ctx->dA), ptr<double>(ctx->dB),
+                                  ptr<uint32_t>(ctx->fsm_flags), ctx->field_waves,
+                                  ctx->field_rc_grid, rule, W[WDELTA], W[WRC], ctx->d_status);
+      timer_end(ctx, "cutoffs", cev);
+      DCM_TRY(check_launch(ctx, "dcm_step cutoffs"));
+    }
     if (step_cell_edge <= 0.0) {
       auto run = [&](double e) -> dcm_status {
         DCM_TRY(dcm_build_cells(ctx, W[WX], W[WY], W[WZ], W[WRC], n, box, e, rule.rc_max, prec,

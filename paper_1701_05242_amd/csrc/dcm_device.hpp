@@ -42,6 +42,30 @@ __device__ __forceinline__ uint32_t x_key(double w, double scale, int c) {
   return f > 0.0 ? (f < (double)(kXKeyOne - 1) ? (uint32_t)f : kXKeyOne - 1) : 0u;
 }
 
+// The regularisation passes of the phase map (majority vote or length term):
+// pass q ended the iteration if it changed nothing (chg1[q] = 0: fixed point)
+// or, from the second pass on, reproduced state q-2 (chg2[q] = 0: 2-cycle).
+// A pass that did not run left both at 0, so the test holds after the end.
+__device__ __forceinline__ bool phase_pass_stopped(const uint32_t *chg1, const uint32_t *chg2,
+                                                   int q) {
+  return chg1[q] == 0u || (q >= 2 && chg2[q] == 0u);
+}
+
+// The map holding the final phase: state p lives in b[p & 1]; the last pass
+// is the first that stopped (max_passes if none did).
+__device__ __forceinline__ const uint32_t *final_phase_map(const uint32_t *chg1,
+                                                           const uint32_t *chg2, int max_passes,
+                                                           const uint32_t *b0,
+                                                           const uint32_t *b1) {
+  int last = max_passes;
+  for (int p = 1; p <= max_passes; ++p)
+    if (phase_pass_stopped(chg1, chg2, p)) {
+      last = p;
+      break;
+    }
+  return (last & 1) ? b1 : b0;
+}
+
 __device__ __forceinline__ int wrap_index(int i, int n) {
   int r = i % n;
   return r < 0 ? r + n : r;

@@ -130,7 +130,8 @@ struct dcm_ctx {
   uint32_t *h_status = nullptr;  // pinned
   dcm::Ctl *ctl = nullptr;       // device control block
   // grid scratch
-  dcm::DevBuf counts, gray, hist, seg_a, seg_b, seg, iface, dA, dB, dist, fsm_chg, fsm_flags;
+  dcm::DevBuf counts, gray, hist, seg_a, seg_b, dA, dB, fsm_chg,
+      fsm_flags;
   dcm::DevBuf ccl_label, ccl_size;  // bubble filter
   // Verlet list of the last cell build
   dcm::DevBuf list_count, list_wave_len, list_wave_start, list;
@@ -185,6 +186,7 @@ struct dcm_ctx {
   double field_h[3] = {0, 0, 0}, field_L[3] = {0, 0, 0};
   double field_rc_grid = 0.0;
   int64_t field_particles = -1;
+  int32_t field_waves = 0;  // pass limit of the sweep whose buffers hold the field
   // batched form: plan, buffers and recorded graph
   dcm::BatchState *batch = nullptr;
   // profiling
@@ -203,6 +205,10 @@ struct DetectScratch {
            *seg_b = nullptr;
   int32_t *ccl_label = nullptr, *ccl_size = nullptr;
 };
+// the context's detection scratch for a grid of nvox voxels (counts: the
+// caller's, or null for the context's own)
+dcm_status detect_scratch(dcm_ctx *ctx, const dcm_grid &grid, int64_t nvox,
+                          const dcm_detect_opts &opts, uint32_t *counts, DetectScratch *out);
 dcm_status detect_check(dcm_ctx *ctx, const double *x, const double *y, const double *z,
                         int64_t n, const dcm_box &box, const dcm_grid &grid,
                         const dcm_detect_opts *opts, const uint8_t *seg, const uint8_t *iface,
@@ -231,6 +237,8 @@ void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n);
 void launch_fill_i32(hipStream_t s, int32_t *p, int32_t v, int64_t n);
 // p[0..n) = q[0..n) = 0 in one launch
 void launch_zero2_i32(hipStream_t s, int32_t *p, int32_t *q, int64_t n);
+// p[0..np) = 0 and q[0..nq) = 0 in one launch
+void launch_zero2_u32(hipStream_t s, uint32_t *p, int64_t np, uint32_t *q, int64_t nq);
 void launch_reset_ctl(hipStream_t s, Ctl *ctl);
 void launch_min_f64(hipStream_t s, const double *v, int64_t n, double *out);
 void launch_clear_status(hipStream_t s, uint32_t *st);
@@ -256,11 +264,17 @@ void launch_threshold(hipStream_t s, const uint32_t *gray, const int32_t nv[3], 
                       const Ctl *ctl, uint32_t *bits0, int32_t *t_out);
 void launch_majority_pass(hipStream_t s, uint32_t *buf0, uint32_t *buf1, const int32_t nv[3],
                           int pass, int max_passes, Ctl *ctl);
+// byte maps of the final phase and the interface
 void launch_interface(hipStream_t s, const uint32_t *buf0, const uint32_t *buf1,
                       const int32_t nv[3], const Ctl *ctl, uint8_t *seg, uint8_t *iface);
 
 // k_fsm.hip
 // initial distances; with tiles also the first pass's tile flags in chg0
+// the same from the regularisation passes' two bit-packed phase maps (the
+// final one chosen from the pass flags, as launch_interface does)
+void launch_fsm_init_bits(hipStream_t s, const uint32_t *const maps[2], const Ctl *ctl,
+                          const int32_t nv[3], double *dA, double *dB, uint8_t *chg0,
+                          uint32_t *flags, int max_steps);
 void launch_fsm_init(hipStream_t s, const uint8_t *seg, const uint8_t *iface, const int32_t nv[3],
                      double *dA, double *dB, uint8_t *chg0, uint32_t *flags, int max_steps);
 // one launch of the sweep: a temporally blocked tile pass when fsm_tiled(nv),
@@ -275,6 +289,14 @@ void launch_fsm_final(hipStream_t s, const double *dA, const double *dB, int64_t
                       int32_t *waves_out, uint32_t *status);
 
 // k_cells.hip
+// the same from the distance sweep's buffers (dA, dB) and pass flags, as
+// its final pass would have written the field (see launch_fsm_final)
+void launch_assign_cutoffs_sweep(hipStream_t s, const double *x, const double *y,
+                                 const double *z, int64_t n, const double L[3],
+                                 const int32_t nv[3], const double sc[3], const double *dA,
+                                 const double *dB, const uint32_t *flags, int max_steps,
+                                 double rc_grid, dcm_rule rule, double *delta, double *rc,
+                                 uint32_t *status);
 void launch_assign_cutoffs(hipStream_t s, const double *x, const double *y, const double *z,
                            int64_t n, const double L[3], const int32_t nv[3],
                            const double sc[3], const double *dist, dcm_rule rule,

@@ -7,11 +7,28 @@ namespace dcm {
 // ----------------------------------------------------- cutoff assignment
 // delta_i: periodic trilinear interpolation of the voxel-centred distances at
 // the particle; rc_i = rc_max - (rc_max - rc_min) * min(delta_i/ramp, 1).
+// SWEEP: D is the sweep's own pair of buffers (D, D2) and its pass flags,
+// read as the sweep's final pass would write the field: the buffer of the
+// first pass that changed nothing, each value capped at `cap`; a sweep that
+// ran out of passes is flagged here.
+template <bool SWEEP>
 __global__ __launch_bounds__(256) void k_assign_cutoffs(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     int64_t n, double Lx, double Ly, double Lz, int nx, int ny, int nz, double sx, double sy,
     double sz, const double *__restrict__ D, double rc_min, double rc_max, double ramp,
-    double *__restrict__ delta, double *__restrict__ rc) {
+    double *__restrict__ delta, double *__restrict__ rc, const double *__restrict__ D2,
+    const uint32_t *__restrict__ flags, int max_steps, double cap, uint32_t *status) {
+  if constexpr (SWEEP) {
+    int last = max_steps;
+    for (int q = 1; q <= max_steps; ++q)
+      if (flags[q] == 0u) {
+        last = q;
+        break;
+      }
+    if (last & 1) D = D2;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && flags[max_steps] != 0u)
+      atomicOr(status, ST_NOT_CONVERGED);
+  }
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
     double px = x[p], py = y[p], pz = z[p];
@@ -34,7 +51,11 @@ __global__ __launch_bounds__(256) void k_assign_cutoffs(
       i0[a] = wrap_index(ia, nn[a]);
       i1[a] = wrap_index(ia + 1, nn[a]);
     }
-    auto DV = [&](int i, int j, int k) { return D[((int64_t)k * ny + j) * nx + i]; };
+    auto DV = [&](int i, int j, int k) {
+      const double v = D[((int64_t)k * ny + j) * nx + i];
+      if constexpr (SWEEP) return v > cap ? cap : v;
+      else return v;
+    };
     double wx0 = 1.0 - t[0], wx1 = t[0];
     double wy0 = 1.0 - t[1], wy1 = t[1];
     double wz0 = 1.0 - t[2], wz1 = t[2];
@@ -59,9 +80,23 @@ void launch_assign_cutoffs(hipStream_t s, const double *x, const double *y, cons
   if (n <= 0) return;
   int64_t b = ceil_div(n, 256);
   if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_assign_cutoffs, dim3((unsigned)b), dim3(256), 0, s, x, y, z, n, L[0],
-                     L[1], L[2], nv[0], nv[1], nv[2], sc[0], sc[1], sc[2], dist, rule.rc_min,
-                     rule.rc_max, rule.ramp, delta, rc);
+  hipLaunchKernelGGL(k_assign_cutoffs<false>, dim3((unsigned)b), dim3(256), 0, s, x, y, z, n,
+                     L[0], L[1], L[2], nv[0], nv[1], nv[2], sc[0], sc[1], sc[2], dist, rule.rc_min,
+                     rule.rc_max, rule.ramp, delta, rc, nullptr, nullptr, 0, 0.0, nullptr);
+}
+
+void launch_assign_cutoffs_sweep(hipStream_t s, const double *x, const double *y,
+                                 const double *z, int64_t n, const double L[3],
+                                 const int32_t nv[3], const double sc[3], const double *dA,
+                                 const double *dB, const uint32_t *flags, int max_steps,
+                                 double rc_grid, dcm_rule rule, double *delta, double *rc,
+                                 uint32_t *status) {
+  if (n <= 0) return;
+  int64_t b = ceil_div(n, 256);
+  if (b > 16384) b = 16384;
+  hipLaunchKernelGGL(k_assign_cutoffs<true>, dim3((unsigned)b), dim3(256), 0, s, x, y, z, n,
+                     L[0], L[1], L[2], nv[0], nv[1], nv[2], sc[0], sc[1], sc[2], dA, rule.rc_min,
+                     rule.rc_max, rule.ramp, delta, rc, dB, flags, max_steps, rc_grid, status);
 }
 
 // ------------------------------------------------------------ cell count

@@ -54,6 +54,21 @@ __global__ void k_zero2_i32(int32_t *p, int32_t *q, int64_t n) {
   }
 }
 
+__global__ void k_zero2_u32(uint32_t *p, int64_t np, uint32_t *q, int64_t nq) {
+  const int64_t n = np > nq ? np : nq;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < np) p[i] = 0u;
+    if (i < nq) q[i] = 0u;
+  }
+}
+
+void launch_zero2_u32(hipStream_t s, uint32_t *p, int64_t np, uint32_t *q, int64_t nq) {
+  const int64_t n = np > nq ? np : nq;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero2_u32, dim3(fill_grid(n)), dim3(256), 0, s, p, np, q, nq);
+}
+
 void launch_zero2_i32(hipStream_t s, int32_t *p, int32_t *q, int64_t n) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_zero2_i32, dim3(fill_grid(n)), dim3(256), 0, s, p, q, n);

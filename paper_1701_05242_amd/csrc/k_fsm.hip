@@ -61,6 +61,41 @@ __global__ __launch_bounds__(256) void k_fsm_init(const uint8_t *__restrict__ se
   }
 }
 
+// The same from the bit-packed phase maps of the regularisation passes
+// (final_phase_map), without the byte maps: a voxel starts at +inf iff it
+// and its six face neighbours (periodic) are all high density -- otherwise
+// it is low density or an interface voxel, a source.
+__global__ __launch_bounds__(256) void k_fsm_init_bits(const uint32_t *b0, const uint32_t *b1,
+                                                       const Ctl *ctl, int nx, int ny, int nz,
+                                                       double *dA, double *dB, uint8_t *chg0,
+                                                       int ntx, int nty) {
+  const uint32_t *__restrict__ s =
+      final_phase_map(ctl->maj_chg1, ctl->maj_chg2, kMajorityMaxPasses, b0, b1);
+  const int W = (nx + 31) >> 5;
+  const int64_t nvox = (int64_t)nx * ny * nz;
+  auto bit = [&](int x, int y, int z) -> uint32_t {
+    return (s[((int64_t)z * ny + y) * W + (x >> 5)] >> (x & 31)) & 1u;
+  };
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < nvox;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = v / nx;
+    const int x = (int)(v - row * nx), y = (int)(row % ny), z = (int)(row / ny);
+    const uint32_t sv = bit(x, y, z);
+    bool fc = false;
+    if (sv) {
+      const int xm = x == 0 ? nx - 1 : x - 1, xp = x + 1 == nx ? 0 : x + 1;
+      const int ym = y == 0 ? ny - 1 : y - 1, yp = y + 1 == ny ? 0 : y + 1;
+      const int zm = z == 0 ? nz - 1 : z - 1, zp = z + 1 == nz ? 0 : z + 1;
+      fc = (bit(xm, y, z) & bit(xp, y, z) & bit(x, ym, z) & bit(x, yp, z) & bit(x, y, zm) &
+            bit(x, y, zp)) == 0u;
+    }
+    const double d = (sv == 0u || fc) ? 0.0 : __builtin_huge_val();
+    dA[v] = d;
+    dB[v] = d;
+    if (fc && chg0) chg0[((z / TZ) * nty + y / TY) * ntx + x / TX] = 1;
+  }
+}
+
 // Godunov solve: with the smaller face neighbour a_k and spacing h_k per axis
 // (w_k = 1/h_k^2), d solves sum over the m smallest a_k of w_k (d - a_k)^2 = 1
 // for the largest m whose root does not pass the next a_k; written relative
@@ -307,6 +342,18 @@ void launch_fsm_init(hipStream_t s, const uint8_t *seg, const uint8_t *iface, co
   hipLaunchKernelGGL(k_fsm_clear, dim3(1), dim3(1024), 0, s, chg0, ntiles, flags, max_steps + 2);
   hipLaunchKernelGGL(k_fsm_init, dim3(flat_grid(nvox)), dim3(256), 0, s, seg, iface, nvox, nv[0],
                      nv[1], dA, dB, tiled ? chg0 : nullptr, ntx, nty);
+}
+
+void launch_fsm_init_bits(hipStream_t s, const uint32_t *const maps[2], const Ctl *ctl,
+                          const int32_t nv[3], double *dA, double *dB, uint8_t *chg0,
+                          uint32_t *flags, int max_steps) {
+  const int64_t nvox = (int64_t)nv[0] * nv[1] * nv[2];
+  const bool tiled = fsm_tiled(nv);
+  const int ntx = (int)ceil_div(nv[0], TX), nty = (int)ceil_div(nv[1], TY);
+  const int ntiles = tiled ? (int)fsm_tile_count(nv) : 0;
+  hipLaunchKernelGGL(k_fsm_clear, dim3(1), dim3(1024), 0, s, chg0, ntiles, flags, max_steps + 2);
+  hipLaunchKernelGGL(k_fsm_init_bits, dim3(flat_grid(nvox)), dim3(256), 0, s, maps[0], maps[1],
+                     ctl, nv[0], nv[1], nv[2], dA, dB, tiled ? chg0 : nullptr, ntx, nty);
 }
 
 void launch_fsm_step(hipStream_t s, double *dA, double *dB, uint8_t *chg0, uint8_t *chg1,

@@ -364,7 +364,7 @@ void launch_threshold(hipStream_t s, const uint32_t *gray, const int32_t nv[3], 
 // second pass on, reproduced state q-2 (2-cycle).  A pass that did not run
 // left both flags at 0, so the test also holds for every pass after the end.
 __device__ __forceinline__ bool majority_stopped(const Ctl *ctl, int q) {
-  return ctl->maj_chg1[q] == 0u || (q >= 2 && ctl->maj_chg2[q] == 0u);
+  return phase_pass_stopped(ctl->maj_chg1, ctl->maj_chg2, q);
 }
 
 // Word k of a row with its periodic x-neighbours: a holds bit x-1 and c bit
@@ -570,14 +570,8 @@ __global__ __launch_bounds__(256) void k_interface(const uint32_t *buf0, const u
                                                    int nx, int ny, int nz, const Ctl *ctl,
                                                    uint8_t *__restrict__ seg,
                                                    uint8_t *__restrict__ iface) {
-  // state p lives in buf[p & 1]; the last pass is the first that stopped
-  int last = kMajorityMaxPasses;
-  for (int p = 1; p <= kMajorityMaxPasses; ++p)
-    if (majority_stopped(ctl, p)) {
-      last = p;
-      break;
-    }
-  const uint32_t *__restrict__ s = (last & 1) ? buf1 : buf0;
+  const uint32_t *__restrict__ s =
+      final_phase_map(ctl->maj_chg1, ctl->maj_chg2, kMajorityMaxPasses, buf0, buf1);
   const int W = row_words(nx);
   const int i = blockIdx.x * SX + threadIdx.x;
   const int j = blockIdx.y * SY + threadIdx.y;
