@@ -283,6 +283,14 @@ def batched_leg(steps, dev):
         graph_s = timed(batched(dcm.DCM_FP32_MIXED, True), steps)
         pairs = check()
         edge = dcm.dcm_batched_edge(ctx)
+        queues = dcm.dcm_batched_queues(ctx)
+        # each work-queue layout forced (the edge re-tuned under it)
+        layout_s = {}
+        for q in (1, 8):
+            dcm.dcm_set_batched_queues(ctx, q)
+            layout_s[q] = timed(batched(dcm.DCM_FP32_MIXED, True), steps)
+            check()
+        dcm.dcm_set_batched_queues(ctx, 0)
         # the same batch without the recorded graph, and in FP64 with it
         eager_s = timed(batched(dcm.DCM_FP32_MIXED, False), steps)
         check()
@@ -309,7 +317,10 @@ def batched_leg(steps, dev):
     return {"workload": f"{len(systems)} slabs, N 2e3-2e5 log-uniform (total {n_total}), "
                         "rc_max U[4,8], cells + forces per evaluation",
             "n_particles": n_total, "pairs": pairs, "tuned_cell_edge": edge,
+            "tuned_queues": queues,
             "graph_fp32_mixed": leg(graph_s, pairs),
+            "graph_fp32_mixed_one_queue": leg(layout_s[1], pairs),
+            "graph_fp32_mixed_queue_per_xcd": leg(layout_s[8], pairs),
             "eager_batched_fp32_mixed": leg(eager_s, pairs),
             "graph_fp64": leg(graph64_s, pairs),
             "sequential_fp32_mixed": leg(seq32_s, pairs),

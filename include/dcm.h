@@ -383,13 +383,14 @@ typedef struct {
  * by dcm_forces(lj, pair_rule, prec, ev_flags) -- bit for bit when the cell
  * edge is the same -- but all systems share one launch of each build kernel
  * and one persistent pair kernel that takes blocks of 256 particles from a
- * work queue ordered by estimated cost (largest first), so systems of very
- * different size and cutoff balance across the GPU (the dynamic scheduling
- * of Section 2.4).
+ * work queue ordered by estimated cost (largest first), or from one such
+ * queue per XCD (dcm_set_batched_queues), so systems of very different size
+ * and cutoff balance across the GPU (the dynamic scheduling of Section 2.4).
  * sys: host array of nsys descriptors (nsys = 0 is a no-op).  Systems whose
- * cell_edge is <= 0 share one edge chosen by timing a few candidates the
- * first time a batch is seen (this call synchronises the stream); the choice
- * is kept for later calls with the same descriptors.
+ * cell_edge is <= 0 share one edge chosen, together with the work-queue
+ * layout, by timing a few candidates the first time a batch is seen (this
+ * call synchronises the stream); the choice is kept for later calls with the
+ * same descriptors.
  * use_graph != 0: the first call for a given set of descriptors and
  * parameters records the launches in a HIP graph; later identical calls
  * replay it (the arrays' contents may change between calls, their addresses
@@ -401,8 +402,22 @@ typedef struct {
 dcm_status dcm_forces_batched(dcm_ctx *ctx, int32_t nsys, const dcm_system *sys, dcm_lj lj,
                               int pair_rule, int prec, int ev_flags, int use_graph);
 
+
 /* Cell edge the tuner chose for the last batch (0 if none was needed). */
 dcm_status dcm_batched_edge(const dcm_ctx *ctx, double *edge);
+
+/* Work-queue layout of the batched pair kernel for later dcm_forces_batched
+ * calls on this context: queues = 1, one queue with the costliest work first;
+ * 8, one queue per XCD of the MI355X, each holding whole systems (balanced by
+ * estimated cost, so a system's records are read through one L2), drained by
+ * that XCD's workgroups before they help the others; 0 (the default), timed
+ * together with the cell edge when a batch needs tuning, else 1.  The
+ * results do not depend on the layout.  A change re-plans (and re-tunes) the
+ * next batch.  Errors: DCM_ERR_INVALID for other values. */
+dcm_status dcm_set_batched_queues(dcm_ctx *ctx, int32_t queues);
+
+/* The work-queue layout (1 or 8) of the last batch, 0 before any. */
+dcm_status dcm_batched_queues(const dcm_ctx *ctx, int32_t *queues);
 
 /* ------------------------------------------------------------ profiling */
 

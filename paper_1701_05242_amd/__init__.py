@@ -115,6 +115,8 @@ SIGNATURES = {
                  dcm_grid, _F64, _INT, _INT, _F64, _I32, _I32, _I64, _P, _P, _P],
     "dcm_forces_batched": [_P, _I32, _P, dcm_lj, _INT, _INT, _INT, _INT],
     "dcm_batched_edge": [_P, ctypes.POINTER(_F64)],
+    "dcm_batched_queues": [_P, ctypes.POINTER(ctypes.c_int32)],
+    "dcm_set_batched_queues": [_P, ctypes.c_int32],
     "dcm_walk_stats": [_P, ctypes.POINTER(ctypes.c_uint64)],
     "dcm_set_profiling": [_P, _INT],
     "dcm_kernel_time": [_P, ctypes.c_char_p, ctypes.POINTER(_F64), ctypes.POINTER(_I64)],
@@ -404,6 +406,18 @@ def dcm_forces_batched(ctx, systems, lj: dcm_lj, pair_rule: int = DCM_PAIR_OWN,
         int(ev_flags), 1 if use_graph else 0)
     _check(ctx, code)
     return arr
+
+
+def dcm_batched_queues(ctx) -> int:
+    """Work-queue layout (1 or 8) of the last batch, 0 before any."""
+    q = ctypes.c_int32(0)
+    _check(ctx, load_library().dcm_batched_queues(ctx, ctypes.byref(q)))
+    return int(q.value)
+
+
+def dcm_set_batched_queues(ctx, queues: int) -> None:
+    """Work-queue layout of later batches: 0 (tuned), 1 or 8."""
+    _check(ctx, load_library().dcm_set_batched_queues(ctx, int(queues)))
 
 
 def dcm_batched_edge(ctx) -> float:

@@ -32,17 +32,21 @@ struct BatchState {
   double plan_edge = 0.0;  // edge used for systems with cell_edge <= 0
   bool tuned = false;
   double tuned_edge = 0.0;
+  int tuned_queues = 1;
   bool needs_tuning = false;
+  int plan_queues = 1;  // work-queue segments of the plan: 1 or kXcds
   // plan
   std::vector<SysGeom> geo;
   std::vector<int2> items;  // natural order: system-major, also the particle block table
   std::vector<int2> eblk;
   std::vector<int2> rblk;  // (system, first extended row) per group of 256 rows
   std::vector<int32_t> queue;
+  std::vector<int32_t> qseg;  // segment starts in queue [plan_queues + 1]
   int64_t n_total = 0, cells_total = 0, ext_cells_total = 0, ext_rows_total = 0, ext_cap = 0;
   bool rel_ok = true;  // every system's halos fit the compact records
   double max_len = 0.0;  // widest cell edge of any system
-  size_t off_geo = 0, off_items = 0, off_eblk = 0, off_rblk = 0, off_queue = 0, table_bytes = 0;
+  size_t off_geo = 0, off_items = 0, off_eblk = 0, off_rblk = 0, off_queue = 0, off_qseg = 0,
+         table_bytes = 0;
   std::vector<unsigned char> table_host;
   // device memory
   DevBuf tables, cell_of, cell_count, cell_fill, cell_start, perm, sorted, scan_tmp, row_count,
@@ -88,8 +92,9 @@ dcm_status check_system(dcm_ctx *ctx, const dcm_system &s, int32_t b, int ev_fla
 }
 
 // Cell geometry, concatenated layout, block tables and work queue for the
-// batch, with `edge` for the systems that leave the cell edge to the tuner.
-dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
+// batch, with `edge` for the systems that leave the cell edge to the tuner,
+// and `queues` work-queue segments (1 or kBatchQueues).
+dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge, int queues) {
   const int32_t nsys = (int32_t)B.desc.size();
   B.geo.assign(nsys, SysGeom{});
   B.items.clear();
@@ -184,22 +189,52 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
     const int64_t cnt = std::min<int64_t>(kItem, B.desc[b].n - B.items[k].y);
     cost[k] = cost_pp[b] * (double)cnt;
   }
+  B.plan_queues = queues;
   B.queue.resize(nitems);
-  std::iota(B.queue.begin(), B.queue.end(), 0);
-  std::stable_sort(B.queue.begin(), B.queue.end(),
-                   [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  B.qseg.assign(queues + 1, 0);
+  if (queues == 1) {
+    std::iota(B.queue.begin(), B.queue.end(), 0);
+    std::stable_sort(B.queue.begin(), B.queue.end(),
+                     [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    B.qseg[1] = (int32_t)nitems;
+  } else {
+    // whole systems to segments, the costliest first onto the least loaded
+    // one; a segment lists its systems' items in natural order
+    std::vector<double> scost(nsys, 0.0);
+    for (int64_t k = 0; k < nitems; ++k) scost[B.items[k].x] += cost[k];
+    std::vector<int32_t> order(nsys);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return scost[a] > scost[b]; });
+    std::vector<double> load(queues, 0.0);
+    std::vector<int32_t> seg_of(nsys, 0);
+    for (int32_t b : order) {
+      const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      seg_of[b] = q;
+      load[q] += scost[b];
+    }
+    int64_t pos = 0;
+    for (int q = 0; q < queues; ++q) {
+      B.qseg[q] = (int32_t)pos;
+      for (int64_t k = 0; k < nitems; ++k)
+        if (seg_of[B.items[k].x] == q) B.queue[pos++] = (int32_t)k;
+    }
+    B.qseg[queues] = (int32_t)pos;
+  }
   // device tables, uploaded once per plan
   B.off_geo = 0;
   B.off_items = align256(sizeof(SysGeom) * nsys);
   B.off_eblk = B.off_items + align256(sizeof(int2) * std::max<int64_t>(nitems, 1));
   B.off_rblk = B.off_eblk + align256(sizeof(int2) * std::max<size_t>(B.eblk.size(), 1));
   B.off_queue = B.off_rblk + align256(sizeof(int2) * std::max<size_t>(B.rblk.size(), 1));
-  B.table_bytes = B.off_queue + align256(sizeof(int32_t) * std::max<int64_t>(nitems, 1));
+  B.off_qseg = B.off_queue + align256(sizeof(int32_t) * std::max<int64_t>(nitems, 1));
+  B.table_bytes = B.off_qseg + align256(sizeof(int32_t) * (queues + 1));
   B.table_host.assign(B.table_bytes, 0);
   std::memcpy(B.table_host.data() + B.off_geo, B.geo.data(), sizeof(SysGeom) * nsys);
   if (nitems) {
     std::memcpy(B.table_host.data() + B.off_items, B.items.data(), sizeof(int2) * nitems);
     std::memcpy(B.table_host.data() + B.off_queue, B.queue.data(), sizeof(int32_t) * nitems);
+  std::memcpy(B.table_host.data() + B.off_qseg, B.qseg.data(), sizeof(int32_t) * (queues + 1));
   }
   if (!B.eblk.empty())
     std::memcpy(B.table_host.data() + B.off_eblk, B.eblk.data(), sizeof(int2) * B.eblk.size());
@@ -248,8 +283,8 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge) {
   if ((st = ensure(ctx, B.rcmax_part, sizeof(unsigned long long) * std::max<int64_t>(nitems, 1))) !=
       DCM_OK)
     return st;
-  // work-queue head and the cell sort's count of large cells
-  if ((st = ensure(ctx, B.head, 2 * sizeof(uint32_t))) != DCM_OK) return st;
+  // work-queue positions and the cell sort's count of large cells
+  if ((st = ensure(ctx, B.head, (kBatchQueues + 1) * sizeof(uint32_t))) != DCM_OK) return st;
   // plans change rarely: a synchronous upload keeps the host copy free to
   // change as soon as this returns
   if (hipMemcpyAsync(B.tables.p, B.table_host.data(), B.table_bytes, hipMemcpyHostToDevice,
@@ -278,7 +313,7 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   hipEvent_t ev = nullptr;
   if (timed) timer_begin(ctx, "batch_cells", &ev);
   launch_zero2_i32(s, dptr<int32_t>(B.cell_count), dptr<int32_t>(B.cell_fill), B.cells_total);
-  launch_fill_u32(s, dptr<uint32_t>(B.head), 0u, 2);
+  launch_fill_u32(s, dptr<uint32_t>(B.head), 0u, kBatchQueues + 1);
   launch_batch_cell_count(s, geo, nsys, items, nitems, dptr<int32_t>(B.cell_of),
                           dptr<int32_t>(B.cell_count), dptr<unsigned long long>(B.rcmax_part),
                           dptr<unsigned long long>(B.rcmax), dptr<uint32_t>(B.xkey),
@@ -290,8 +325,8 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
                             dptr<int32_t>(B.perm), dptr<uint32_t>(B.xkey), dptr<uint32_t>(B.skey));
   launch_cell_sort(s, dptr<int32_t>(B.cell_start), B.cells_total, dptr<int32_t>(B.cell_of),
                    B.n_total, dptr<int32_t>(B.perm), dptr<uint32_t>(B.xkey),
-                   dptr<uint32_t>(B.skey), dptr<uint32_t>(B.qword), dptr<int32_t>(B.sort_tmp), dptr<int32_t>(B.sort_list),
-                   dptr<uint32_t>(B.head) + 1);
+                   dptr<uint32_t>(B.skey), dptr<uint32_t>(B.qword), dptr<int32_t>(B.sort_tmp),
+                   dptr<int32_t>(B.sort_list), dptr<uint32_t>(B.head) + kBatchQueues);
   launch_batch_gather(s, geo, items, nitems, dptr<int32_t>(B.sort_tmp), dptr<double4>(B.sorted),
                       dptr<int32_t>(B.perm));
   launch_batch_ext(s, geo, eblk, (int64_t)B.eblk.size(), dptr<int2>(B.tables, B.off_rblk),
@@ -305,6 +340,8 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   a.sys = geo;
   a.items = items;
   a.queue = queue;
+  a.qseg = dptr<int32_t>(B.tables, B.off_qseg);
+  a.nqueues = B.plan_queues;
   a.nitems = (int32_t)nitems;
   a.head = dptr<uint32_t>(B.head);
   a.pos = dptr<double4>(B.sorted);
@@ -327,10 +364,12 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   if (timed) timer_end(ctx, "batch_pair", ev);
 }
 
-// Time the batch at each candidate edge (second of two runs) and keep the
-// fastest.  Synchronises the stream.
+// Time the batch at each candidate edge and work-queue layout (one queue in
+// cost order, or one per XCD; second of two runs) and keep the fastest.
+// Synchronises the stream.
 dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int ev_flags) {
   double best_ms = 0.0, best_edge = kTuneEdges[0];
+  int best_queues = 1;
   bool first = true;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(ctx, DCM_ERR_HIP, "event create failed");
@@ -339,8 +378,11 @@ dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int 
     return fail(ctx, DCM_ERR_HIP, "event create failed");
   }
   dcm_status st = DCM_OK;
-  for (double edge : kTuneEdges) {
-    if ((st = make_plan(ctx, B, edge)) != DCM_OK) break;
+  for (int trial = 0; trial < 2 * (int)(sizeof(kTuneEdges) / sizeof(kTuneEdges[0])); ++trial) {
+    const double edge = kTuneEdges[trial / 2];
+    const int queues = ctx->batch_queues ? ctx->batch_queues : ((trial & 1) ? kBatchQueues : 1);
+    if (ctx->batch_queues && (trial & 1)) continue;  // a fixed layout: edges only
+    if ((st = make_plan(ctx, B, edge, queues)) != DCM_OK) break;
     enqueue(ctx, B, ctx->stream, lj, rule, prec, ev_flags, false);
     hipEventRecord(e0, ctx->stream);
     enqueue(ctx, B, ctx->stream, lj, rule, prec, ev_flags, false);
@@ -355,6 +397,7 @@ dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int 
     if (first || ms < best_ms) {
       best_ms = ms;
       best_edge = edge;
+      best_queues = queues;
       first = false;
     }
   }
@@ -363,6 +406,7 @@ dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int 
   if (st != DCM_OK) return st;
   B.tuned = true;
   B.tuned_edge = best_edge;
+  B.tuned_queues = best_queues;
   return DCM_OK;
 }
 
@@ -376,6 +420,7 @@ std::vector<unsigned char> graph_key(const BatchState &B, dcm_lj lj, int rule, i
   std::memcpy(t + 20, &prec, sizeof(int));
   std::memcpy(t + 24, &ev_flags, sizeof(int));
   std::memcpy(t + 28, &B.plan_edge, sizeof(double));
+  std::memcpy(t + 36, &B.plan_queues, sizeof(int));
   return k;
 }
 
@@ -435,8 +480,10 @@ dcm_status dcm_forces_batched(dcm_ctx *ctx, int32_t nsys, const dcm_system *sys,
     }
   }
   const double edge = B.needs_tuning ? B.tuned_edge : 0.0;
-  if (!B.have_plan || B.plan_edge != edge) {
-    if ((st = make_plan(ctx, B, edge)) != DCM_OK) {
+  const int queues =
+      ctx->batch_queues ? ctx->batch_queues : (B.needs_tuning ? B.tuned_queues : 1);
+  if (!B.have_plan || B.plan_edge != edge || B.plan_queues != queues) {
+    if ((st = make_plan(ctx, B, edge, queues)) != DCM_OK) {
       B.have_plan = false;
       return st;
     }
@@ -483,6 +530,24 @@ dcm_status dcm_forces_batched(dcm_ctx *ctx, int32_t nsys, const dcm_system *sys,
 dcm_status dcm_batched_edge(const dcm_ctx *ctx, double *edge) {
   if (!ctx || !edge) return DCM_ERR_INVALID;
   *edge = (ctx->batch && ctx->batch->needs_tuning) ? ctx->batch->tuned_edge : 0.0;
+  return DCM_OK;
+}
+
+dcm_status dcm_batched_queues(const dcm_ctx *ctx, int32_t *queues) {
+  if (!ctx || !queues) return DCM_ERR_INVALID;
+  *queues = ctx->batch && ctx->batch->have_plan ? ctx->batch->plan_queues : 0;
+  return DCM_OK;
+}
+
+dcm_status dcm_set_batched_queues(dcm_ctx *ctx, int32_t queues) {
+  if (!ctx) return DCM_ERR_INVALID;
+  if (queues != 0 && queues != 1 && queues != kBatchQueues)
+    return fail(ctx, DCM_ERR_INVALID, "dcm_set_batched_queues: queues must be 0, 1 or 8");
+  if (queues != ctx->batch_queues && ctx->batch) {
+    ctx->batch->tuned = false;  // tune again (and re-plan) under the new layout
+    ctx->batch->have_plan = false;
+  }
+  ctx->batch_queues = queues;
   return DCM_OK;
 }
 

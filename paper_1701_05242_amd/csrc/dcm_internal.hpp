@@ -30,6 +30,7 @@ enum : uint32_t {
 constexpr int kHistBins = 4096;       // gray values (27-window counts) must stay below this
 constexpr int kHistCopies = 32;      // histogram copies the gray-value workgroups add into
 constexpr int kMajorityMaxPasses = 16;
+constexpr int kBatchQueues = 8;  // work-queue segments of the XCD-affine batched plan (one per XCD)
 constexpr int kPartialSlots = 8;      // per-block partial sums: E, W[6], pair count
 constexpr int kReduceThreads = 1024;  // workgroup that sums the block partials
 constexpr int kReorderEvery = 8;      // dcm_step re-sorts its working copies this often
@@ -189,6 +190,7 @@ struct dcm_ctx {
   int32_t field_waves = 0;  // pass limit of the sweep whose buffers hold the field
   // batched form: plan, buffers and recorded graph
   dcm::BatchState *batch = nullptr;
+  int batch_queues = 0;  // work-queue layout asked for (0: tuned)
   // profiling
   bool profile = false;
   std::map<std::string, dcm::Timer> timers;
@@ -436,9 +438,11 @@ void launch_list_fill(hipStream_t s, const ListArgs &a);
 struct BatchPairArgs {
   const SysGeom *sys;
   const int2 *items;          // work item -> (system, first local particle)
-  const int32_t *queue;       // items in the order they are handed out
+  const int32_t *queue;       // items in the order they are handed out, in nqueues segments
+  const int32_t *qseg;        // [nqueues + 1] segment starts in queue
+  int32_t nqueues;            // 1, or kXcds: segment x first serves workgroups on XCD x
   int32_t nitems;
-  uint32_t *head;             // queue position, zero before the launch
+  uint32_t *head;             // [nqueues] positions in the segments, zero before the launch
   const double4 *pos;         // sorted particles, concatenated
   const int32_t *cell_start;  // concatenated real cells
   const int32_t *perm;        // sorted slot -> concatenated particle id

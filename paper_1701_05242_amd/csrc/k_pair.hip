@@ -1024,8 +1024,11 @@ void launch_pair_list(hipStream_t s, const PairArgs &a, int prec, const int32_t 
 }
 
 // Batched form: a persistent grid takes work items (blocks of kPairBlock
-// particles of one system) from a queue ordered by estimated cost.  Every
-// workgroup leaves the loop once the queue head passes the item count.
+// particles of one system) from a queue in segments: one, ordered by
+// estimated cost, or one per XCD holding whole systems, so that a system's
+// records are read through one L2.  A workgroup drains its home segment
+// (workgroup b runs on XCD b mod kXcds) and then the others in turn; it
+// leaves the loop once every segment's position has passed its end.
 template <int RULE, int PREC, int EVM, bool REL>
 __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
   __shared__ uint2 segs[seg_cap<REL>()][kPairBlock];
@@ -1033,12 +1036,26 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
   __shared__ double red[kPairBlock / 64][kPartialSlots];
   __shared__ int32_t next_item;
   const double sig2 = a.sigma * a.sigma;
+  const int home = a.nqueues > 1 ? (int)(blockIdx.x % (unsigned)a.nqueues) : 0;
+  int tried = 0;  // segments found empty
   while (true) {
-    if (threadIdx.x == 0) next_item = (int32_t)atomicAdd(a.head, 1u);
+    if (threadIdx.x == 0) {
+      int32_t got = -1;
+      while (tried < a.nqueues) {
+        const int q = (home + tried) % a.nqueues;
+        const int32_t pos = a.qseg[q] + (int32_t)atomicAdd(&a.head[q], 1u);
+        if (pos < a.qseg[q + 1]) {
+          got = pos;
+          break;
+        }
+        ++tried;
+      }
+      next_item = got;
+    }
     __syncthreads();
     const int32_t qi = next_item;
     __syncthreads();
-    if (qi >= a.nitems) break;
+    if (qi < 0) break;
     const int32_t item = __builtin_amdgcn_readfirstlane(a.queue[qi]);
     const int2 w = a.items[item];
     const int b = __builtin_amdgcn_readfirstlane(w.x);

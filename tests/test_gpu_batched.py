@@ -102,20 +102,24 @@ def test_batched_matches_oracle(rule, prec):
         assert rel(got["W"], ref["W"]) <= tol
 
 
+@pytest.mark.parametrize("queues", [1, 8])
 @pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
 @pytest.mark.parametrize("rule", [dcm.DCM_PAIR_OWN, dcm.DCM_PAIR_MAX])
-def test_batched_bitwise_equals_single_system(rule, prec):
+def test_batched_bitwise_equals_single_system(rule, prec, queues):
     """Same cell edge => the batch reproduces every single-system result
-    exactly (forces, counts, energy and virial sums)."""
-    print(f"[gpu] batched vs single rule={rule} prec={prec}", flush=True)
+    exactly (forces, counts, energy and virial sums), whichever work-queue
+    layout drains it."""
+    print(f"[gpu] batched vs single rule={rule} prec={prec} queues={queues}", flush=True)
     systems = small_batch()
     rcs = [workloads.uniform_cutoffs(s.n, s.rule[0], s.rule[1], seed=900 + b)
            for b, s in enumerate(systems)]
     batch = device_batch(systems, rcs, edge=1.1)
     with Ctx() as ctx:
+        dcm.dcm_set_batched_queues(ctx, queues)
         dcm.dcm_forces_batched(ctx, batch, dcm.make_lj(), pair_rule=rule, prec=prec,
                                ev_flags=EV_ALL)
         assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
+        assert dcm.dcm_batched_queues(ctx) == queues
     for b, (s, rc, d) in enumerate(zip(systems, rcs, batch)):
         got = results(d)
         one = gpu_forces(s, rc, prec=prec, rule=rule, edge=1.1, rc_bound=s.rule[1])
@@ -143,6 +147,8 @@ def test_batched_tuner_and_graph_replays():
         assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
         edge = dcm.dcm_batched_edge(ctx)
         assert edge in TUNE_EDGES
+        queues = dcm.dcm_batched_queues(ctx)
+        assert queues in (1, 8)
         first = [results(d) for d in batch]
         for b, got in enumerate(first):
             ref = oracle_forces("small", b, dcm.DCM_PAIR_OWN)
@@ -165,6 +171,7 @@ def test_batched_tuner_and_graph_replays():
             assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
             eager = [results(d) for d in batch]
             assert dcm.dcm_batched_edge(ctx) == edge
+            assert dcm.dcm_batched_queues(ctx) == queues
             for b, (g, e) in enumerate(zip(replay, eager)):
                 np.testing.assert_array_equal(g["F"], e["F"])
                 np.testing.assert_array_equal(g["nnbr"], e["nnbr"])
