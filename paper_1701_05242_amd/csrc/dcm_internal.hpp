@@ -87,7 +87,7 @@ struct DevBuf {
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);  // nothing to report from a destructor
   }
 };
 

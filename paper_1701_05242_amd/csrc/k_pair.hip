@@ -399,30 +399,26 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit dword access (gfx9 family)
 
-__device__ __forceinline__ float4 load_rel(__amdgpu_buffer_rsrc_t rs, int j) {
-  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, j << 4, 0, 0);
-  return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
-                     __uint_as_float(v.w));
-}
-
 // Flat loop over the compact-record candidates of this lane's first nseg
-// listed rows, total candidates in all (FP32-mixed, own-cutoff rule).  A list
-// entry is (first slot, length | (row y - cy) << 16 | (row z - cz) << 24),
-// the offsets as signed bytes, the length at least 1; the lane's own slot is
+// listed rows, two candidates of one row per step (steps in all: the sum of
+// the rows' halved lengths, rounded up; the second candidate of a row's last
+// step is masked when the row's length is odd).  The order of evaluation,
+// and so every sum, is that of one candidate at a time.  A list entry is
+// (first slot, length | (row y - cy) << 16 | (row z - cz) << 24), the
+// offsets as signed bytes, the length at least 1; the lane's own slot is
 // never listed.  Entry nseg is a sentinel (slot 0, length 65535) and entry
 // nseg + 1 exists, so the stream needs no bounds: it moves at most one entry
-// past the last row (into the sentinel) before the candidate count ends it.
+// past the last row (into the sentinel) before the step count ends it.
 // Separations are formed in FP32 between the two cell-centre-relative
 // positions, the candidate's cell k cells away: d = (a0 - k len) - rel.  A
 // close pair, and a pair whose FP32 r^2 lies within the lane's proven error
 // band around rc^2, is queued in nearq (nq entries; row kNearCap takes the
 // overflow) for flush_near, which decides and evaluates it in FP64.  The
 // stream advances with selects, and two register sets take turns so that
-// every record is loaded a full candidate before its use.
+// every pair of records is loaded a full step before its use.
 template <int EVM>
-__device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int total,
-                                         __amdgpu_buffer_rsrc_t rs,
-                                         const double4 *__restrict__ ext_pos, const LaneGeo &g,
+__device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int steps,
+                                         __amdgpu_buffer_rsrc_t rs, const LaneGeo &g,
                                          float sig2, Acc<DCM_FP32_MIXED> &acc, int &cnt,
                                          int32_t (*nearq)[kPairBlock], int &nq) {
   const int lane_id = threadIdx.x;
@@ -430,10 +426,10 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int to
   int j = (int)s0.x, jend = (int)s0.x + (int)(s0.y & 0xffffu), sidx = 1;
   uint32_t tag = s0.y;
   uint2 nx = segs[1][lane_id];
-  // move to the next candidate of the stream (past the last row: slots of the
+  // move to the next step of the stream (past the last row: slots of the
   // sentinel, never evaluated)
   auto advance = [&]() {
-    const int jn = j + 1;
+    const int jn = j + 2;
     const bool sw = jn >= jend;
     j = sw ? (int)nx.x : jn;
     jend = sw ? (int)nx.x + (int)(nx.y & 0xffffu) : jend;
@@ -441,41 +437,60 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int to
     sidx += sw ? 1 : 0;
     nx = segs[sidx][lane_id];
   };
-  auto eval = [&](const float4 &r, uint32_t t, int jr) {
-    const int dyc = (int)(t << 8) >> 24, dzc = (int)t >> 24;
-    const float ay = fmaf(-(float)dyc, g.lenf[1], g.a0y);
-    const float az = fmaf(-(float)dzc, g.lenf[2], g.a0z);
-    float dx = fmaf(-(r.w - g.wc), g.lenf[0], g.a0x) - r.x;
-    float dy = ay - r.y, dz = az - r.z;
-    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  auto one = [&](const float4 &r, float ay, float az, int jr, bool valid) {
+    const float dx = fmaf(-(r.w - g.wc), g.lenf[0], g.a0x) - r.x;
+    const float dy = ay - r.y, dz = az - r.z;
+    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    // a masked slot (past the row's end) takes part in nothing
+    r2 = valid ? r2 : 3.0e38f;
     // a close pair, or one too near rc^2 for the FP32 test (rare: the band
-    // is 3e-5 to 2e-4 sigma^2 wide), waits for flush_near
+    // is 3e-5 to 2e-4 sigma^2 wide), waits for flush_near; the queue's next
+    // entry is written whatever the test says and kept only if it holds
     const bool exact = r2 < g.near2f || fabsf(r2 - g.rc2f) <= g.margin;
     const bool inc = r2 < g.rc2f && !exact;
-    if (exact) {
-      nearq[nq < kNearCap ? nq : kNearCap][lane_id] = jr;
-      ++nq;
-    }
+    nearq[nq < kNearCap ? nq : kNearCap][lane_id] = jr;
+    nq += exact ? 1 : 0;
     interact_rel<EVM>(acc, dx, dy, dz, r2, sig2, inc);
     if constexpr ((EVM & 4) != 0) cnt += inc ? 1 : 0;
   };
-  int left = total;
+  auto eval = [&](const float4 &r0, const float4 &r1, uint32_t t, int jr, bool v2) {
+    const int dyc = (int)(t << 8) >> 24, dzc = (int)t >> 24;
+    const float ay = fmaf(-(float)dyc, g.lenf[1], g.a0y);
+    const float az = fmaf(-(float)dzc, g.lenf[2], g.a0z);
+    one(r0, ay, az, jr, true);
+    one(r1, ay, az, jr + 1, v2);
+  };
+  // records jr and jr + 1 (one address, the second at an immediate offset;
+  // a slot past the records reads zeros)
+  auto load2 = [&](int jr, float4 &r0, float4 &r1) {
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rs, jr << 4, 0, 0);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rs, jr << 4, 16, 0);
+    r0 = make_float4(__uint_as_float(a.x), __uint_as_float(a.y), __uint_as_float(a.z),
+                     __uint_as_float(a.w));
+    r1 = make_float4(__uint_as_float(b.x), __uint_as_float(b.y), __uint_as_float(b.z),
+                     __uint_as_float(b.w));
+  };
+  int left = steps;
   int ja = j;
   uint32_t ta = tag;
-  float4 A = load_rel(rs, ja);
+  bool va = j + 1 < jend;
+  float4 A0, A1, B0, B1;
+  load2(ja, A0, A1);
   advance();
   while (true) {
     const int jb = j;
     const uint32_t tb = tag;
-    const float4 B = load_rel(rs, jb);
+    const bool vb = j + 1 < jend;
+    load2(jb, B0, B1);
     advance();
-    eval(A, ta, ja);
+    eval(A0, A1, ta, ja, va);
     if (--left == 0) break;
     ja = j;
     ta = tag;
-    A = load_rel(rs, ja);
+    va = j + 1 < jend;
+    load2(ja, A0, A1);
     advance();
-    eval(B, tb, jb);
+    eval(B0, B1, tb, jb, vb);
     if (--left == 0) break;
   }
 }
@@ -537,7 +552,7 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
                                            int32_t (*nearq)[kPairBlock], Acc<PREC> &acc,
                                            int &cnt, bool &redo, int &wcand, int &wrows) {
   const int lane_id = threadIdx.x;
-  const int nx = v.nc[0], hx = v.h[0], hy = v.h[1], hz = v.h[2];
+  const int hx = v.h[0], hy = v.h[1], hz = v.h[2];
   const int nex = v.ne[0], ney = v.ne[1];
   const int ny = v.nc[1];
   // rows are walked plane by plane (z), each plane's rows limited to the
@@ -593,7 +608,7 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     // ---- fill: append the ranges of the next rows to this lane's list,
     // kFillRows rows at a time: the two ext_start reads of all of them are
     // issued before the first is used, so their latencies overlap
-    int nseg = 0, total = 0;
+    int nseg = 0, steps = 0;
     // a row adds at most one entry (compact records: two entries stay free
     // for the sentinel and the look-ahead)
     while (rows_left && nseg <= CAP - kFillRows - (REL ? 2 : 1)) {
@@ -676,7 +691,7 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
           if (len > 0) {
             segs[nseg][lane_id] = make_uint2((uint32_t)a0, (uint32_t)len | rowtag);
             ++nseg;
-            total += len;
+            steps += (len + 1) >> 1;
           }
         } else {
           if (a1 > a0) {
@@ -690,7 +705,7 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
       if constexpr (REL) {
         segs[nseg][lane_id] = make_uint2(0u, 0xffffu);
         int nq = 0;
-        scan_rel<EVM>(segs, total, rs, v.ext_pos, g, (float)sig2, acc, cnt, nearq, nq);
+        scan_rel<EVM>(segs, steps, rs, g, (float)sig2, acc, cnt, nearq, nq);
         if (nq > kNearCap) redo = true;  // more close pairs than the queue holds
         flush_near<EVM>(nearq, nq, v.ext_pos, g, acc, cnt);
         acc.fx += (double)acc.px;
