@@ -314,7 +314,8 @@ struct LaneGeo {
   // with the row-selection guard fguard added (fR2); for compact records also
   // the cell's x index + 1/2 (wc), rc^2 and the band around it within which
   // an FP32 r^2 cannot decide a pair
-  float a0x, a0y, a0z, lenf[3], invf[3], fR2, fguard, wc, rc2f, margin;
+  float a0x, a0y, a0z, lenf[3], invf[3], fR2, fguard, wc, rc2f, margin, hi2f;
+  uint32_t incw;  // FP32 bits of the inside range's width (compact records)
   // per axis: the distances (plus the guard) from the lane to the far faces
   // of its cell's positive (gp) and negative (gm) neighbours less one cell,
   // 0.5 len +- a0 + guard, and the lane's offset in cell units, a0/len + 1/2
@@ -443,11 +444,15 @@ __device__ __forceinline__ void scan_rel(const uint2 (*segs)[kPairBlock], int st
     float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     // a masked slot (past the row's end) takes part in nothing
     r2 = valid ? r2 : 3.0e38f;
-    // a close pair, or one too near rc^2 for the FP32 test (rare: the band
-    // is 3e-5 to 2e-4 sigma^2 wide), waits for flush_near; the queue's next
-    // entry is written whatever the test says and kept only if it holds
-    const bool exact = r2 < g.near2f || fabsf(r2 - g.rc2f) <= g.margin;
-    const bool inc = r2 < g.rc2f && !exact;
+    // inside: near^2 <= r^2 < rc^2 - margin, one unsigned comparison of the
+    // bits of r^2 - near^2 (a negative difference has its sign bit set, so
+    // it compares above every positive width).  A close pair, or one too
+    // near rc^2 for the FP32 test (rare: the band is 3e-5 to 2e-4 sigma^2
+    // wide), is neither inside nor beyond rc^2 + margin and waits for
+    // flush_near; the queue's next entry is written whatever the test says
+    // and kept only if it holds
+    const bool inc = __float_as_uint(r2 - g.near2f) < g.incw;
+    const bool exact = !inc && r2 <= g.hi2f;
     nearq[nq < kNearCap ? nq : kNearCap][lane_id] = jr;
     nq += exact ? 1 : 0;
     interact_rel<EVM>(acc, dx, dy, dz, r2, sig2, inc);
@@ -787,7 +792,8 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   const int nex = v.ne[0], ney = v.ne[1];
   LaneGeo g;
   g.xi = g.yi = g.zi = g.rci = g.rci2 = 0.0;
-  g.a0x = g.a0y = g.a0z = g.wc = g.rc2f = g.margin = g.fR2 = g.fguard = 0.0f;
+  g.a0x = g.a0y = g.a0z = g.wc = g.rc2f = g.margin = g.fR2 = g.fguard = g.hi2f = 0.0f;
+  g.incw = 0u;
   // the FP32 r^2 of a pair at most a few ulps off: evaluating a pair just
   // past the threshold in FP64 as well costs nothing in accuracy
   g.near2f = (float)(kNear2 * sig2);
@@ -870,6 +876,13 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
       const double E = 3.4641016151377548 * rr * del + 3.0 * del * del + 3.01 * u * rr * rr +
                        1e-12 * rr * rr;
       g.margin = (float)(2.0 * (E + u * g.rci2)) * (1.0f + 0x1p-20f);
+      // the band's two edges as the FP32 tests use them, each moved outward
+      // past the roundings of forming it and of r^2 - near^2 (relative
+      // 2^-24 each): a pair these move only changes from the FP32 decision
+      // to the FP64 one
+      g.hi2f = (float)(((double)g.rc2f + (double)g.margin) * (1.0 + 0x1p-22));
+      const double lo = ((double)g.rc2f - (double)g.margin - (double)g.near2f) * (1.0 - 0x1p-20);
+      g.incw = lo > 0.0 ? __float_as_uint((float)lo) : 0u;
     }
     // the halo holds ceil(rc_bound/len) + 1 cells, so these stay inside it
     g.zlo = clampi((int)floor((g.zi - Rg) * v.sc[2]), -hz, nz + hz - 1);
