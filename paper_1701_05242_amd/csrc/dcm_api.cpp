@@ -665,14 +665,17 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
                     ctx->d_status);
   launch_exclusive_scan(s, ptr<int32_t>(ctx->cell_count), ptr<int32_t>(ctx->cell_start), ncell,
                         ptr<int32_t>(ctx->scan_tmp));
+  // the scatter's order (arbitrary within a cell) goes to sort_tmp; the sort
+  // writes the final order into perm and the sorted copy beside it
   launch_cell_scatter(s, cof, n, ptr<int32_t>(ctx->cell_start), ptr<int32_t>(ctx->cell_fill),
-                      ptr<int32_t>(ctx->perm), ptr<uint32_t>(ctx->xkey), ptr<uint32_t>(ctx->skey));
-  launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, cof, n, ptr<int32_t>(ctx->perm),
+                      ptr<int32_t>(ctx->sort_tmp), ptr<uint32_t>(ctx->xkey),
+                      ptr<uint32_t>(ctx->skey));
+  const GatherOut go = {x, y, z, rc, {box.L[0], box.L[1], box.L[2]}, rc_cap,
+                        ptr<double4>(ctx->sorted)};
+  launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, cof, n, ptr<int32_t>(ctx->sort_tmp),
                    ptr<uint32_t>(ctx->xkey), ptr<uint32_t>(ctx->skey),
-                   qtab ? ptr<uint32_t>(ctx->qword) : nullptr,
-                   ptr<int32_t>(ctx->sort_tmp), ptr<int32_t>(ctx->sort_list), &ctx->ctl->big_cells);
-  launch_gather(s, x, y, z, rc, ptr<int32_t>(ctx->sort_tmp), n, box.L, rc_cap,
-                ptr<double4>(ctx->sorted), ptr<int32_t>(ctx->perm));
+                   qtab ? ptr<uint32_t>(ctx->qword) : nullptr, ptr<int32_t>(ctx->perm),
+                   ptr<int32_t>(ctx->sort_list), &ctx->ctl->big_cells, &go);
   launch_ext_count(s, ptr<int32_t>(ctx->cell_start), nc, halo, box.L,
                    ptr<int32_t>(ctx->ext_row_count), ptr<int32_t>(ctx->ext_row_start),
                    ptr<int32_t>(ctx->ext_row_lo), ptr<int32_t>(ctx->ext_start),

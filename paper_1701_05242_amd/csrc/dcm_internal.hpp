@@ -316,6 +316,16 @@ int64_t scan_tmp_elems(int64_t n);
 void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
                          const int32_t *cell_start, int32_t *cell_fill, int32_t *perm,
                          const uint32_t *xq, uint32_t *skey);
+// The sorted copy written by the cell sort itself (launch_cell_sort with go
+// not null): sorted[slot] = (x, y, z, rc) of the particle sorted_perm[slot],
+// positions wrapped into the box (0 when not finite), rc clamped to
+// [0, rc_cap] (NaN -> 0).
+struct GatherOut {
+  const double *x, *y, *z, *rc;
+  double L[3];
+  double rc_cap;
+  double4 *sorted;
+};
 // sorted_perm receives the entries of perm (particle ids in cell order, cell
 // c of particle id holding cell_of[id], x keys xq by id and skey by slot)
 // with each cell's sorted by (x key, id); perm is left as scratch.  qword (null: none) receives the
@@ -325,13 +335,8 @@ void launch_cell_scatter(hipStream_t s, const int32_t *cell_of, int64_t n,
 void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell,
                       const int32_t *cell_of, int64_t n, int32_t *perm, const uint32_t *xq,
                       const uint32_t *skey, uint32_t *qword, int32_t *sorted_perm,
-                      int32_t *big_list, uint32_t *big_count);
+                      int32_t *big_list, uint32_t *big_count, const GatherOut *go = nullptr);
 int64_t cell_sort_list_elems(int64_t n);
-// sorted copy (x, y, z, rc) in the order order[] of particle ids, which is
-// also copied to perm
-void launch_gather(hipStream_t s, const double *x, const double *y, const double *z,
-                   const double *rc, const int32_t *order, int64_t n, const double L[3],
-                   double rc_cap, double4 *sorted, int32_t *perm);
 // rows of the extended grid + 1: the size of each per-row scratch array
 int64_t ext_row_scratch_elems(const int32_t nc[3], const int32_t h[3]);
 // ghost-extended cells in two parts: the per-row tables and the extended

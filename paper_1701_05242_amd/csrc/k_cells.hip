@@ -435,11 +435,32 @@ __global__ __launch_bounds__(256) void k_cell_small(const int32_t *__restrict__ 
 // (the count of the cell's particles with smaller (x key, id)); a particle
 // of a large cell keeps its slot.  out receives the result; no thread waits
 // on another.
+// The sorted record of particle i: (x, y, z) wrapped into the box (0 when
+// not finite) and rc clamped to [0, rc_cap] (NaN -> 0).
+__device__ __forceinline__ double4 gather_record(const GatherOut &go, int i) {
+  const double px = go.x[i], py = go.y[i], pz = go.z[i];
+  double4 o;
+  if (finite3(px, py, pz)) {
+    o.x = wrap_coord(px, go.L[0]);
+    o.y = wrap_coord(py, go.L[1]);
+    o.z = wrap_coord(pz, go.L[2]);
+  } else {
+    o.x = o.y = o.z = 0.0;
+  }
+  const double r = go.rc[i];
+  o.w = (r >= 0.0) ? (r < go.rc_cap ? r : go.rc_cap) : 0.0;
+  return o;
+}
+
+// GATHER: a particle of a small cell also writes its sorted record at its
+// final slot (the gather of the sorted copy done here, not in a pass of its
+// own); out is then the final order.
+template <bool GATHER>
 __global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ cell_start,
                                                    const int32_t *__restrict__ cell_of,
                                                    const int32_t *__restrict__ perm, int64_t n,
                                                    const uint32_t *__restrict__ skey,
-                                                   int32_t *__restrict__ out) {
+                                                   int32_t *__restrict__ out, GatherOut go) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
     const int i = perm[p];
@@ -457,6 +478,7 @@ __global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ c
       if (kj == ki) r += perm[q] < i ? 1 : 0;  // equal keys (rare): by id
     }
     out[a + r] = i;
+    if constexpr (GATHER) go.sorted[a + r] = gather_record(go, i);
   }
 }
 
@@ -465,11 +487,12 @@ __global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ c
 // offset in its run plus the count of smaller keys in the partner run (keys
 // are distinct: they end in the caller index), ping-ponging between perm and
 // tmp.  Entries are caller indices; their keys are looked up (sort_key).
+template <bool GATHER>
 __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t *__restrict__ cell_start,
                                                        int32_t *perm, int32_t *tmp,
                                                        const uint32_t *__restrict__ xq,
                                                        const int32_t *__restrict__ big_list,
-                                                       const uint32_t *big_count) {
+                                                       const uint32_t *big_count, GatherOut go) {
   __shared__ int32_t buf[kSortChunk];
   const int tid = threadIdx.x;
   const uint32_t nbig = *big_count;
@@ -528,68 +551,41 @@ __global__ __launch_bounds__(256) void k_cell_sort_big(const int32_t *__restrict
       for (int p = tid; p < n; p += 256) perm[a + p] = src[p];
       __syncthreads();
     }
+    if constexpr (GATHER)
+      for (int p = tid; p < n; p += 256) go.sorted[a + p] = gather_record(go, perm[a + p]);
   }
 }
 
 void launch_cell_sort(hipStream_t s, const int32_t *cell_start, int64_t ncell,
                       const int32_t *cell_of, int64_t n, int32_t *perm, const uint32_t *xq,
                       const uint32_t *skey, uint32_t *qword, int32_t *sorted_perm,
-                      int32_t *big_list, uint32_t *big_count) {
+                      int32_t *big_list, uint32_t *big_count, const GatherOut *go) {
   int64_t b = ceil_div(ncell, 256);
   if (b < 1) b = 1;
   if (b > 16384) b = 16384;
   hipLaunchKernelGGL(k_cell_small, dim3((unsigned)b), dim3(256), 0, s, cell_start, ncell, skey,
                      qword, big_list, big_count);
+  const GatherOut g = go ? *go : GatherOut{};
   if (n > 0) {
     int64_t bn = ceil_div(n, 256);
     if (bn > 16384) bn = 16384;
-    hipLaunchKernelGGL(k_cell_rank, dim3((unsigned)bn), dim3(256), 0, s, cell_start, cell_of,
-                       perm, n, skey, sorted_perm);
+    if (go)
+      hipLaunchKernelGGL(k_cell_rank<true>, dim3((unsigned)bn), dim3(256), 0, s, cell_start,
+                         cell_of, perm, n, skey, sorted_perm, g);
+    else
+      hipLaunchKernelGGL(k_cell_rank<false>, dim3((unsigned)bn), dim3(256), 0, s, cell_start,
+                         cell_of, perm, n, skey, sorted_perm, g);
   }
   // the large cells, in place in sorted_perm with perm as scratch
-  hipLaunchKernelGGL(k_cell_sort_big, dim3(kBigSortBlocks), dim3(256), 0, s, cell_start,
-                     sorted_perm, perm, xq, big_list, big_count);
+  if (go)
+    hipLaunchKernelGGL(k_cell_sort_big<true>, dim3(kBigSortBlocks), dim3(256), 0, s, cell_start,
+                       sorted_perm, perm, xq, big_list, big_count, g);
+  else
+    hipLaunchKernelGGL(k_cell_sort_big<false>, dim3(kBigSortBlocks), dim3(256), 0, s, cell_start,
+                       sorted_perm, perm, xq, big_list, big_count, g);
 }
 
 int64_t cell_sort_list_elems(int64_t n) { return n / (kSmallCell + 1) + 1; }
-
-// Sorted copy (x, y, z, rc) with positions wrapped into the box.
-__global__ __launch_bounds__(256) void k_gather(const double *__restrict__ x,
-                                                const double *__restrict__ y,
-                                                const double *__restrict__ z,
-                                                const double *__restrict__ rc,
-                                                const int32_t *__restrict__ order, int64_t n,
-                                                double Lx, double Ly, double Lz, double rc_cap,
-                                                double4 *__restrict__ sorted,
-                                                int32_t *__restrict__ perm) {
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n;
-       s += (int64_t)gridDim.x * blockDim.x) {
-    int i = order[s];
-    perm[s] = i;
-    double px = x[i], py = y[i], pz = z[i];
-    double4 o;
-    if (finite3(px, py, pz)) {
-      o.x = wrap_coord(px, Lx);
-      o.y = wrap_coord(py, Ly);
-      o.z = wrap_coord(pz, Lz);
-    } else {
-      o.x = o.y = o.z = 0.0;
-    }
-    double r = rc[i];
-    o.w = (r >= 0.0) ? (r < rc_cap ? r : rc_cap) : 0.0;  // NaN -> 0
-    sorted[s] = o;
-  }
-}
-
-void launch_gather(hipStream_t s, const double *x, const double *y, const double *z,
-                   const double *rc, const int32_t *order, int64_t n, const double L[3],
-                   double rc_cap, double4 *sorted, int32_t *perm) {
-  if (n <= 0) return;
-  int64_t b = ceil_div(n, 256);
-  if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)b), dim3(256), 0, s, x, y, z, rc, order, n, L[0],
-                     L[1], L[2], rc_cap, sorted, perm);
-}
 
 // ------------------------------------------------ periodic ghost images
 // The extended grid (ExtGeom) lets a lane walk any row of cells around its
