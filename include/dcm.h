@@ -427,6 +427,12 @@ dcm_status dcm_batched_queues(const dcm_ctx *ctx, int32_t *queues);
  * when enabled. */
 dcm_status dcm_set_profiling(dcm_ctx *ctx, int enable);
 
+/* While profiling, record events only around the launches of one kernel
+ * family (family NULL or "": every family, the default), so that timing one
+ * kernel adds two events per launch of it and none elsewhere.  The name is
+ * copied.  Errors: DCM_ERR_INVALID for a null context. */
+dcm_status dcm_set_profiling_only(dcm_ctx *ctx, const char *family);
+
 /* Synchronise, then return the summed event time (ms) and launch count of a
  * kernel family since profiling was enabled, and reset them. */
 dcm_status dcm_kernel_time(dcm_ctx *ctx, const char *family, double *total_ms,

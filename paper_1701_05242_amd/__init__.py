@@ -119,6 +119,7 @@ SIGNATURES = {
     "dcm_set_batched_queues": [_P, ctypes.c_int32],
     "dcm_walk_stats": [_P, ctypes.POINTER(ctypes.c_uint64)],
     "dcm_set_profiling": [_P, _INT],
+    "dcm_set_profiling_only": [_P, ctypes.c_char_p],
     "dcm_kernel_time": [_P, ctypes.c_char_p, ctypes.POINTER(_F64), ctypes.POINTER(_I64)],
 }
 
@@ -428,6 +429,11 @@ def dcm_batched_edge(ctx) -> float:
 
 def dcm_set_profiling(ctx, enable: bool) -> None:
     _check(ctx, load_library().dcm_set_profiling(ctx, 1 if enable else 0))
+
+
+def dcm_set_profiling_only(ctx, family=None) -> None:
+    """Time only this kernel family while profiling (None: every family)."""
+    _check(ctx, load_library().dcm_set_profiling_only(ctx, family.encode() if family else None))
 
 
 def dcm_kernel_time(ctx, family: str):

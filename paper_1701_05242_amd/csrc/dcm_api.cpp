@@ -50,9 +50,9 @@ dcm_status check_launch(dcm_ctx *ctx, const char *what) {
 }
 
 void timer_begin(dcm_ctx *ctx, const char *family, hipEvent_t *ev) {
-  (void)family;
   *ev = nullptr;
   if (!ctx->profile) return;
+  if (!ctx->profile_only.empty() && ctx->profile_only != family) return;
   if (hipEventCreate(ev) != hipSuccess) {
     *ev = nullptr;
     return;
@@ -1206,6 +1206,12 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
 dcm_status dcm_set_profiling(dcm_ctx *ctx, int enable) {
   if (!ctx) return DCM_ERR_INVALID;
   ctx->profile = enable != 0;
+  return DCM_OK;
+}
+
+dcm_status dcm_set_profiling_only(dcm_ctx *ctx, const char *family) {
+  if (!ctx) return DCM_ERR_INVALID;
+  ctx->profile_only = family ? family : "";
   return DCM_OK;
 }
 

@@ -193,6 +193,7 @@ struct dcm_ctx {
   int batch_queues = 0;  // work-queue layout asked for (0: tuned)
   // profiling
   bool profile = false;
+  std::string profile_only;  // record only this family ("" = every family)
   std::map<std::string, dcm::Timer> timers;
 };
 
