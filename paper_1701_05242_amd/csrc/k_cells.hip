@@ -437,8 +437,8 @@ __global__ __launch_bounds__(256) void k_cell_small(const int32_t *__restrict__ 
 // on another.
 // The sorted record of particle i: (x, y, z) wrapped into the box (0 when
 // not finite) and rc clamped to [0, rc_cap] (NaN -> 0).
-__device__ __forceinline__ double4 gather_record(const GatherOut &go, int i) {
-  const double px = go.x[i], py = go.y[i], pz = go.z[i];
+__device__ __forceinline__ double4 gather_record(const GatherOut &go, double px, double py,
+                                                 double pz, double r) {
   double4 o;
   if (finite3(px, py, pz)) {
     o.x = wrap_coord(px, go.L[0]);
@@ -447,9 +447,12 @@ __device__ __forceinline__ double4 gather_record(const GatherOut &go, int i) {
   } else {
     o.x = o.y = o.z = 0.0;
   }
-  const double r = go.rc[i];
   o.w = (r >= 0.0) ? (r < go.rc_cap ? r : go.rc_cap) : 0.0;
   return o;
+}
+
+__device__ __forceinline__ double4 gather_record(const GatherOut &go, int i) {
+  return gather_record(go, go.x[i], go.y[i], go.z[i], go.rc[i]);
 }
 
 // GATHER: a particle of a small cell also writes its sorted record at its
@@ -464,6 +467,14 @@ __global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ c
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
     const int i = perm[p];
+    // the record's inputs are read while the cell's keys are counted
+    double px = 0.0, py = 0.0, pz = 0.0, pr = 0.0;
+    if constexpr (GATHER) {
+      px = go.x[i];
+      py = go.y[i];
+      pz = go.z[i];
+      pr = go.rc[i];
+    }
     const int c = cell_of[i];
     const int a = cell_start[c], b = cell_start[c + 1];
     if (b - a > kSmallCell) {
@@ -472,13 +483,20 @@ __global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ c
     }
     const uint32_t ki = skey[p];
     int r = 0;
-    for (int q = a; q < b; ++q) {
-      const uint32_t kj = skey[q];
-      r += kj < ki ? 1 : 0;
-      if (kj == ki) r += perm[q] < i ? 1 : 0;  // equal keys (rare): by id
+    // four keys per round, all read before they are compared
+    for (int q0 = a; q0 < b; q0 += 4) {
+      uint32_t kj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) kj[u] = q0 + u < b ? skey[q0 + u] : 0xffffffffu;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (q0 + u >= b) continue;
+        r += kj[u] < ki ? 1 : 0;
+        if (kj[u] == ki) r += perm[q0 + u] < i ? 1 : 0;  // equal keys (rare): by id
+      }
     }
     out[a + r] = i;
-    if constexpr (GATHER) go.sorted[a + r] = gather_record(go, i);
+    if constexpr (GATHER) go.sorted[a + r] = gather_record(go, px, py, pz, pr);
   }
 }
 
@@ -686,25 +704,44 @@ __global__ __launch_bounds__(256) void k_ext_fill(const int32_t *__restrict__ ce
     const int lo = row_lo[row];
     const double sy = (double)r.py * g.L[1], sz = (double)r.pz * g.L[2];
     bool over = false;
-    for (int k = lane; k < cnt; k += 64) {
-      const int P = lo + k;
-      // cnt > 0 implies T > 0
-      const int p = near ? (P < 0 ? -1 : (P >= T ? 1 : 0)) : floor_div(P, T);
-      const int64_t o = o0 + k;
-      if (o >= cap) {
-        over = true;
-        continue;
+    // kFillUnroll slots per lane at a time: their source reads are all
+    // issued before the first is used
+    constexpr int kFillUnroll = 4;
+    for (int k0 = lane; k0 < cnt; k0 += 64 * kFillUnroll) {
+      double4 q[kFillUnroll];
+      int pk[kFillUnroll];
+      bool ok[kFillUnroll];
+#pragma unroll
+      for (int u = 0; u < kFillUnroll; ++u) {
+        const int k = k0 + 64 * u;
+        const int P = lo + k;
+        // cnt > 0 implies T > 0
+        const int p = near ? (P < 0 ? -1 : (P >= T ? 1 : 0)) : floor_div(P, T);
+        const int64_t o = o0 + k;
+        pk[u] = p;
+        ok[u] = k < cnt;
+        if (ok[u] && o >= cap) {
+          over = true;
+          ok[u] = false;
+        }
+        const int src = first + (P - p * T);
+        if (ok[u] && ext_src) ext_src[o] = src;
+        if (ok[u] && ext_pos) q[u] = sorted[src];
       }
-      const int src = first + (P - p * T);
-      if (ext_src) ext_src[o] = src;
       if (!ext_pos) continue;
-      double4 q = sorted[src];
-      const int ex = slab_index(q.x, sc0, g.nc[0]) + p * g.nc[0];
-      q.x = q.x + (double)p * g.L[0];
-      q.y = q.y + sy;
-      q.z = q.z + sz;
-      ext_pos[o] = q;
-      if (ext_rel) ext_rel[o] = rel_record(q, ex, r.ey, r.ez, len);
+#pragma unroll
+      for (int u = 0; u < kFillUnroll; ++u) {
+        if (!ok[u]) continue;
+        const int64_t o = o0 + k0 + 64 * u;
+        const int p = pk[u];
+        double4 w = q[u];
+        const int ex = slab_index(w.x, sc0, g.nc[0]) + p * g.nc[0];
+        w.x = w.x + (double)p * g.L[0];
+        w.y = w.y + sy;
+        w.z = w.z + sz;
+        ext_pos[o] = w;
+        if (ext_rel) ext_rel[o] = rel_record(w, ex, r.ey, r.ez, len);
+      }
     }
     if (over) atomicOr(status, ST_GHOST_OVERFLOW);
   }
