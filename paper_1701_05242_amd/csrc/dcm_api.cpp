@@ -25,15 +25,17 @@ dcm_status ensure(dcm_ctx *ctx, DevBuf &b, size_t bytes) {
   if (bytes < 256) bytes = 256;
   if (b.cap >= bytes) return DCM_OK;
   if (b.p) {
-    hipStreamSynchronize(ctx->stream);
-    hipFree(b.p);
+    // work queued on the stream may still use the old buffer
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "buffer growth: stream synchronisation failed");
+    (void)hipFree(b.p);
     b.p = nullptr;
     b.cap = 0;
   }
   size_t sz = (bytes + 4095) & ~size_t(4095);
   hipError_t e = hipMalloc(&b.p, sz);
   if (e != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     b.p = nullptr;
     return fail(ctx, DCM_ERR_NOMEM,
                 std::string("device allocation of ") + std::to_string(sz) + " bytes failed");
@@ -57,14 +59,14 @@ void timer_begin(dcm_ctx *ctx, const char *family, hipEvent_t *ev) {
     *ev = nullptr;
     return;
   }
-  hipEventRecord(*ev, ctx->stream);
+  (void)hipEventRecord(*ev, ctx->stream);  // a failed record only loses this timing
 }
 
 void timer_end(dcm_ctx *ctx, const char *family, hipEvent_t ev) {
   if (!ev) return;
   hipEvent_t e2;
   if (hipEventCreate(&e2) != hipSuccess) return;
-  hipEventRecord(e2, ctx->stream);
+  (void)hipEventRecord(e2, ctx->stream);
   ctx->timers[family].pending.push_back({ev, e2});
 }
 
@@ -216,8 +218,8 @@ dcm_status tune_edge(dcm_ctx *ctx, const std::vector<double> &key,
     ctx->profile = false;  // the trials are not part of any kernel family's time
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-      hipGetLastError();
-      if (e0) hipEventDestroy(e0);
+      (void)hipGetLastError();
+      if (e0) (void)hipEventDestroy(e0);
       ctx->profile = prof;
       return fail(ctx, DCM_ERR_HIP, "cell-edge tuner: event creation failed");
     }
@@ -225,11 +227,12 @@ dcm_status tune_edge(dcm_ctx *ctx, const std::vector<double> &key,
     dcm_status st = DCM_OK;
     for (double e : cands) {
       if ((st = run(e)) != DCM_OK) break;  // first run: buffers grow, caches warm
-      hipEventRecord(e0, ctx->stream);
+      const hipError_t r0 = hipEventRecord(e0, ctx->stream);
       if ((st = run(e)) != DCM_OK || (st = run(e)) != DCM_OK) break;
-      hipEventRecord(e1, ctx->stream);
+      const hipError_t r1 = hipEventRecord(e1, ctx->stream);
       float ms = 0.0f;
-      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      if (r0 != hipSuccess || r1 != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
         st = fail(ctx, DCM_ERR_HIP, "cell-edge tuner: timing failed");
         break;
       }
@@ -238,8 +241,8 @@ dcm_status tune_edge(dcm_ctx *ctx, const std::vector<double> &key,
         pick = e;
       }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     ctx->profile = prof;
     if (st != DCM_OK) return st;
   }
@@ -288,37 +291,37 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
   if (!ctx) return DCM_ERR_NOMEM;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   if (hipGetDevice(&ctx->device) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     delete ctx;
     return DCM_ERR_HIP;
   }
   void *p = nullptr;
   if (hipMalloc(&p, 256) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     delete ctx;
     return DCM_ERR_NOMEM;
   }
   ctx->d_status = static_cast<uint32_t *>(p);
   if (hipMalloc(&p, sizeof(Ctl)) != hipSuccess) {
-    hipGetLastError();
-    hipFree(ctx->d_status);
+    (void)hipGetLastError();
+    (void)hipFree(ctx->d_status);
     delete ctx;
     return DCM_ERR_NOMEM;
   }
   ctx->ctl = static_cast<Ctl *>(p);
   if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) {
-    hipGetLastError();
-    hipFree(ctx->d_status);
-    hipFree(ctx->ctl);
+    (void)hipGetLastError();
+    (void)hipFree(ctx->d_status);
+    (void)hipFree(ctx->ctl);
     delete ctx;
     return DCM_ERR_NOMEM;
   }
   ctx->h_status = static_cast<uint32_t *>(p);
   if (hipEventCreateWithFlags(&ctx->ext_event, hipEventDisableTiming) != hipSuccess) {
-    hipGetLastError();
-    hipFree(ctx->d_status);
-    hipFree(ctx->ctl);
-    hipHostFree(ctx->h_status);
+    (void)hipGetLastError();
+    (void)hipFree(ctx->d_status);
+    (void)hipFree(ctx->ctl);
+    (void)hipHostFree(ctx->h_status);
     delete ctx;
     return DCM_ERR_HIP;
   }
@@ -334,10 +337,10 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
   if (st == DCM_OK) st = noalloc_scratch_setup(ctx->device, &ctx->err);
   if (st == DCM_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = DCM_ERR_HIP;
   if (st != DCM_OK) {
-    hipEventDestroy(ctx->ext_event);
-    hipFree(ctx->d_status);
-    hipFree(ctx->ctl);
-    hipHostFree(ctx->h_status);
+    (void)hipEventDestroy(ctx->ext_event);
+    (void)hipFree(ctx->d_status);
+    (void)hipFree(ctx->ctl);
+    (void)hipHostFree(ctx->h_status);
     delete ctx;
     return st;
   }
@@ -347,18 +350,18 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
 
 dcm_status dcm_destroy(dcm_ctx *ctx) {
   if (!ctx) return DCM_ERR_INVALID;
-  hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);  // freed below whatever its status
   // the context's device buffers go with it
   batch_free(ctx);
   for (auto &kv : ctx->timers)
     for (auto &pr : kv.second.pending) {
-      hipEventDestroy(pr.first);
-      hipEventDestroy(pr.second);
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
     }
-  hipEventDestroy(ctx->ext_event);
-  hipFree(ctx->d_status);
-  hipFree(ctx->ctl);
-  hipHostFree(ctx->h_status);
+  (void)hipEventDestroy(ctx->ext_event);
+  (void)hipFree(ctx->d_status);
+  (void)hipFree(ctx->ctl);
+  (void)hipHostFree(ctx->h_status);
   delete ctx;
   return DCM_OK;
 }
@@ -613,7 +616,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   // it keeps the uniform-density estimate, the overflow is flagged.
   hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(ctx->stream, &capture) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     capture = hipStreamCaptureStatusNone;
   }
   const bool capturing = capture != hipStreamCaptureStatusNone;
@@ -703,14 +706,15 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   // exact ghost-extended count, read by the next build of this geometry
   std::copy(key, key + 7, ctx->ext_key);
   if (!capturing) {
-    hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
-                   hipMemcpyDeviceToHost, s);
-    hipEventRecord(ctx->ext_event, s);
+    if (hipMemcpyAsync(ctx->h_ext_total, ptr<int32_t>(ctx->ext_start) + next, sizeof(int32_t),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(ctx->ext_event, s) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_build_cells: ghost count read-back failed");
     ctx->ext_copy_pending = true;
   }
-  if (cell_start)
-    hipMemcpyAsync(cell_start, ctx->cell_start.p, (ncell + 1) * sizeof(int32_t),
-                   hipMemcpyDeviceToDevice, s);
+  if (cell_start && hipMemcpyAsync(cell_start, ctx->cell_start.p, (ncell + 1) * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(ctx, DCM_ERR_HIP, "dcm_build_cells: cell_start copy failed");
   timer_end(ctx, "cells", ev);
   for (int a = 0; a < 3; ++a) {
     ctx->halo[a] = halo[a];
@@ -1046,8 +1050,10 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     double *src[] = {x, y, z, vx, vy, vz, fx, fy, fz};
     const int nload = nsteps > 0 ? 9 : 3;
     for (int k = 0; k < nload; ++k)
-      if (n > 0 && src[k])
-        hipMemcpyAsync(field(0, k), src[k], n * sizeof(double), hipMemcpyDeviceToDevice, s);
+      if (n > 0 && src[k] &&
+          hipMemcpyAsync(field(0, k), src[k], n * sizeof(double), hipMemcpyDeviceToDevice,
+                         s) != hipSuccess)
+        return fail(ctx, DCM_ERR_HIP, "dcm_step: copy into the working arrays failed");
     launch_iota(s, owner(0), n);
   }
   double *W[WFIELDS];
@@ -1226,8 +1232,8 @@ dcm_status dcm_kernel_time(dcm_ctx *ctx, const char *family, double *total_ms,
       t.ms += ms;
       t.launches += 1;
     }
-    hipEventDestroy(pr.first);
-    hipEventDestroy(pr.second);
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
   }
   t.pending.clear();
   if (total_ms) *total_ms = t.ms;

@@ -59,8 +59,8 @@ struct BatchState {
   std::vector<unsigned char> graph_key;
 
   void drop_graph() {
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     exec = nullptr;
     graph = nullptr;
     graph_key.clear();
@@ -374,7 +374,7 @@ dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int 
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(ctx, DCM_ERR_HIP, "event create failed");
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return fail(ctx, DCM_ERR_HIP, "event create failed");
   }
   dcm_status st = DCM_OK;
@@ -384,16 +384,16 @@ dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int 
     if (ctx->batch_queues && (trial & 1)) continue;  // a fixed layout: edges only
     if ((st = make_plan(ctx, B, edge, queues)) != DCM_OK) break;
     enqueue(ctx, B, ctx->stream, lj, rule, prec, ev_flags, false);
-    hipEventRecord(e0, ctx->stream);
+    const hipError_t r0 = hipEventRecord(e0, ctx->stream);
     enqueue(ctx, B, ctx->stream, lj, rule, prec, ev_flags, false);
-    hipEventRecord(e1, ctx->stream);
+    const hipError_t r1 = hipEventRecord(e1, ctx->stream);
     if ((st = check_launch(ctx, "dcm_forces_batched (tuning)")) != DCM_OK) break;
-    if (hipEventSynchronize(e1) != hipSuccess) {
+    float ms = 0.0f;
+    if (r0 != hipSuccess || r1 != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
       st = fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: tuning run failed");
       break;
     }
-    float ms = 0.0f;
-    hipEventElapsedTime(&ms, e0, e1);
     if (first || ms < best_ms) {
       best_ms = ms;
       best_edge = edge;
@@ -401,8 +401,8 @@ dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int 
       first = false;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != DCM_OK) return st;
   B.tuned = true;
   B.tuned_edge = best_edge;
@@ -430,7 +430,7 @@ void batch_free(dcm_ctx *ctx) {
   BatchState *B = ctx->batch;
   if (!B) return;
   B->drop_graph();
-  if (B->cap) hipStreamDestroy(B->cap);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
   delete B;
   ctx->batch = nullptr;
 }
@@ -506,12 +506,12 @@ dcm_status dcm_forces_batched(dcm_ctx *ctx, int32_t nsys, const dcm_system *sys,
     enqueue(ctx, B, B.cap, lj, pair_rule, prec, ev_flags, false);
     hipError_t ce = hipStreamEndCapture(B.cap, &B.graph);
     if (ce != hipSuccess || !B.graph) {
-      hipGetLastError();
+      (void)hipGetLastError();
       B.graph = nullptr;
       return fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: capture failed");
     }
     if (hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0) != hipSuccess) {
-      hipGetLastError();
+      (void)hipGetLastError();
       B.drop_graph();
       return fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: graph instantiation failed");
     }
@@ -520,7 +520,7 @@ dcm_status dcm_forces_batched(dcm_ctx *ctx, int32_t nsys, const dcm_system *sys,
   hipEvent_t ev = nullptr;
   timer_begin(ctx, "batch_graph", &ev);
   if (hipGraphLaunch(B.exec, ctx->stream) != hipSuccess) {
-    hipGetLastError();
+    (void)hipGetLastError();
     return fail(ctx, DCM_ERR_HIP, "dcm_forces_batched: graph launch failed");
   }
   timer_end(ctx, "batch_graph", ev);

@@ -40,14 +40,14 @@ dcm_status noalloc_scratch_setup(int device, std::string *err) {
   if (g_scratch[device]) return DCM_OK;
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != device) {
-    hipGetLastError();
+    (void)hipGetLastError();  // clear the sticky error
     if (err) *err = "no-allocation scratch: the context's device is not current";
     return DCM_ERR_HIP;
   }
   void *p = nullptr;
   const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
   if (e != hipSuccess || !p) {
-    hipGetLastError();
+    (void)hipGetLastError();  // clear the sticky error
     if (err) *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
     return DCM_ERR_HIP;
   }
