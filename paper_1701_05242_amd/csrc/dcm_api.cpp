@@ -794,8 +794,9 @@ dcm_status forces_impl(dcm_ctx *ctx, dcm_lj lj, int pair_rule, int prec, int ev_
   // records, if the cells are narrow enough for their precision
   const double max_len =
       std::max(ctx->cell_len[0], std::max(ctx->cell_len[1], ctx->cell_len[2]));
-  const bool rel = ctx->cell_rel && prec == DCM_FP32_MIXED && pair_rule == DCM_PAIR_OWN &&
-                   max_len <= kRelMaxEdgeSigma * lj.sigma;
+  // (the compact-record walk always trims rows with the sub-cell table)
+  const bool rel = ctx->cell_rel && ctx->cell_qtab && prec == DCM_FP32_MIXED &&
+                   pair_rule == DCM_PAIR_OWN && max_len <= kRelMaxEdgeSigma * lj.sigma;
   a.ext_rel = rel ? ptr<float4>(ctx->ext_rel) : nullptr;
   double span = 0.0;  // largest coordinate magnitude in the extended grid
   for (int k = 0; k < 3; ++k)

@@ -600,8 +600,11 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
     return (int)__builtin_amdgcn_raw_buffer_load_b32(rs_start, (int)((uint32_t)idx << 2), 0, 0);
   };
   // the trimming table, (next + 1) entries of 8 bytes (it exists for fewer
-  // than 2^28 extended cells, so its byte offsets fit in 32 bits)
-  const bool trim = v.ext_sq != nullptr;
+  // than 2^28 extended cells, so its byte offsets fit in 32 bits); the
+  // compact-record walk is only chosen with it
+  const bool trim = REL || v.ext_sq != nullptr;
+  // the extended records' capacity, as a 32-bit clamp of the row ends
+  const int cap32 = v.ext_cap < 0x7fffffff ? (int)v.ext_cap : 0x7fffffff;
   const __amdgpu_buffer_rsrc_t rs_sq = __builtin_amdgcn_make_buffer_rsrc(
       (void *)v.ext_sq, (short)0, trim ? (int)(uint32_t)(2 * start_bytes) : 0, kBufferWord3);
   __amdgpu_buffer_rsrc_t rs;
@@ -677,7 +680,7 @@ __device__ __forceinline__ void sweep_rows(const PairView &v, bool run, const La
           j1[k] = (int)(th[k].y - ((th[k].x >> 28) - ((th[k].x >> sh[k]) & 0xfu)));
         }
         const int a0 = j0[k];
-        const int a1 = j1[k] > v.ext_cap ? (int)v.ext_cap : j1[k];  // overflow (flagged at build)
+        const int a1 = j1[k] > cap32 ? cap32 : j1[k];  // overflow (flagged at build)
         if constexpr (walk_counts<REL, EVM>()) {
           ++wrows;
           wcand += a1 > a0 ? a1 - a0 : 0;
