@@ -234,8 +234,8 @@ dcm_status make_plan(dcm_ctx *ctx, BatchState &B, double edge, int queues) {
   if (nitems) {
     std::memcpy(B.table_host.data() + B.off_items, B.items.data(), sizeof(int2) * nitems);
     std::memcpy(B.table_host.data() + B.off_queue, B.queue.data(), sizeof(int32_t) * nitems);
-  std::memcpy(B.table_host.data() + B.off_qseg, B.qseg.data(), sizeof(int32_t) * (queues + 1));
   }
+  std::memcpy(B.table_host.data() + B.off_qseg, B.qseg.data(), sizeof(int32_t) * (queues + 1));
   if (!B.eblk.empty())
     std::memcpy(B.table_host.data() + B.off_eblk, B.eblk.data(), sizeof(int2) * B.eblk.size());
   if (!B.rblk.empty())
