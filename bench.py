@@ -295,6 +295,7 @@ def batched_leg(steps, dev):
         pairs = check()
         edge = dcm.dcm_batched_edge(ctx)
         queues = dcm.dcm_batched_queues(ctx)
+        lists = dcm.dcm_batched_row_lists(ctx)
         # each work-queue layout forced (the edge re-tuned under it)
         layout_s = {}
         for q in (1, 8):
@@ -329,6 +330,7 @@ def batched_leg(steps, dev):
                         "rc_max U[4,8], cells + forces per evaluation",
             "n_particles": n_total, "pairs": pairs, "tuned_cell_edge": edge,
             "tuned_queues": queues,
+            "tuned_row_lists": lists,
             "graph_fp32_mixed": leg(graph_s, pairs),
             "graph_fp32_mixed_one_queue": leg(layout_s[1], pairs),
             "graph_fp32_mixed_queue_per_xcd": leg(layout_s[8], pairs),

@@ -388,9 +388,9 @@ typedef struct {
  * and cutoff balance across the GPU (the dynamic scheduling of Section 2.4).
  * sys: host array of nsys descriptors (nsys = 0 is a no-op).  Systems whose
  * cell_edge is <= 0 share one edge chosen, together with the work-queue
- * layout, by timing a few candidates the first time a batch is seen (this
- * call synchronises the stream); the choice is kept for later calls with the
- * same descriptors.
+ * layout and the pair kernel's row-list size, by timing a few candidates the
+ * first time a batch is seen (this call synchronises the stream); the choice
+ * is kept for later calls with the same descriptors.
  * use_graph != 0: the first call for a given set of descriptors and
  * parameters records the launches in a HIP graph; later identical calls
  * replay it (the arrays' contents may change between calls, their addresses
@@ -418,6 +418,20 @@ dcm_status dcm_set_batched_queues(dcm_ctx *ctx, int32_t queues);
 
 /* The work-queue layout (1 or 8) of the last batch, 0 before any. */
 dcm_status dcm_batched_queues(const dcm_ctx *ctx, int32_t *queues);
+
+/* Row-list entries per lane (14 or 16) of the FP32-mixed own-cutoff batched
+ * pair kernel for the last batch, 0 before any: a batch whose cell edge is
+ * tuned also times both and keeps the faster (more entries: fewer chunks per
+ * particle, fewer resident workgroups); otherwise 14.  Other kernels have one
+ * list size. */
+dcm_status dcm_batched_row_lists(const dcm_ctx *ctx, int32_t *entries);
+
+/* Row-list entries for later dcm_forces_batched calls on this context: 14 or
+ * 16, or 0 (the default) for the tuner's choice.  A change re-tunes the next
+ * batch that tunes.  Results differ between the two in the last bits of the
+ * forces (the FP32 chunk sums end at other rows), not in the pair counts.
+ * Errors: DCM_ERR_INVALID for other values. */
+dcm_status dcm_set_batched_row_lists(dcm_ctx *ctx, int32_t entries);
 
 /* ------------------------------------------------------------ profiling */
 

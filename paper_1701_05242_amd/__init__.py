@@ -116,6 +116,8 @@ SIGNATURES = {
     "dcm_forces_batched": [_P, _I32, _P, dcm_lj, _INT, _INT, _INT, _INT],
     "dcm_batched_edge": [_P, ctypes.POINTER(_F64)],
     "dcm_batched_queues": [_P, ctypes.POINTER(ctypes.c_int32)],
+    "dcm_batched_row_lists": [_P, ctypes.POINTER(ctypes.c_int32)],
+    "dcm_set_batched_row_lists": [_P, ctypes.c_int32],
     "dcm_set_batched_queues": [_P, ctypes.c_int32],
     "dcm_walk_stats": [_P, ctypes.POINTER(ctypes.c_uint64)],
     "dcm_set_profiling": [_P, _INT],
@@ -414,6 +416,18 @@ def dcm_batched_queues(ctx) -> int:
     q = ctypes.c_int32(0)
     _check(ctx, load_library().dcm_batched_queues(ctx, ctypes.byref(q)))
     return int(q.value)
+
+
+def dcm_batched_row_lists(ctx) -> int:
+    """Row-list entries per lane (14 or 16) of the last batch's pair kernel, 0 before any."""
+    q = ctypes.c_int32(0)
+    _check(ctx, load_library().dcm_batched_row_lists(ctx, ctypes.byref(q)))
+    return int(q.value)
+
+
+def dcm_set_batched_row_lists(ctx, entries: int) -> None:
+    """Row-list entries of later batches: 0 (tuned), 14 or 16."""
+    _check(ctx, load_library().dcm_set_batched_row_lists(ctx, int(entries)))
 
 
 def dcm_set_batched_queues(ctx, queues: int) -> None:

@@ -33,6 +33,8 @@ struct BatchState {
   bool tuned = false;
   double tuned_edge = 0.0;
   int tuned_queues = 1;
+  int tuned_lists = 0;  // row-list variant of the compact-record pair kernel
+  int row_lists = 0;    // the variant the next launches use
   bool needs_tuning = false;
   int plan_queues = 1;  // work-queue segments of the plan: 1 or kXcds
   // plan
@@ -359,17 +361,18 @@ void enqueue(dcm_ctx *ctx, BatchState &B, hipStream_t s, dcm_lj lj, int rule, in
   a.partials = dptr<double>(B.partials);
   a.status = ctx->d_status;
   if (timed) timer_begin(ctx, "batch_pair", &ev);
-  launch_pair_batched(s, a, rule, prec);
+  launch_pair_batched(s, a, rule, prec, B.row_lists);
   launch_batch_reduce(s, geo, nsys, dptr<double>(B.partials), ev_flags);
   if (timed) timer_end(ctx, "batch_pair", ev);
 }
 
-// Time the batch at each candidate edge and work-queue layout (one queue in
-// cost order, or one per XCD; second of two runs) and keep the fastest.
-// Synchronises the stream.
+// Time the batch at each candidate edge, work-queue layout (one queue in
+// cost order, or one per XCD) and, for the compact-record kernel, row-list
+// variant (second of two runs each) and keep the fastest.  Synchronises the
+// stream.
 dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int ev_flags) {
   double best_ms = 0.0, best_edge = kTuneEdges[0];
-  int best_queues = 1;
+  int best_queues = 1, best_lists = 0;
   bool first = true;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(ctx, DCM_ERR_HIP, "event create failed");
@@ -378,11 +381,16 @@ dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int 
     return fail(ctx, DCM_ERR_HIP, "event create failed");
   }
   dcm_status st = DCM_OK;
-  for (int trial = 0; trial < 2 * (int)(sizeof(kTuneEdges) / sizeof(kTuneEdges[0])); ++trial) {
-    const double edge = kTuneEdges[trial / 2];
-    const int queues = ctx->batch_queues ? ctx->batch_queues : ((trial & 1) ? kBatchQueues : 1);
-    if (ctx->batch_queues && (trial & 1)) continue;  // a fixed layout: edges only
-    if ((st = make_plan(ctx, B, edge, queues)) != DCM_OK) break;
+  const int nedges = (int)(sizeof(kTuneEdges) / sizeof(kTuneEdges[0]));
+  const int nlayouts = ctx->batch_queues ? 1 : 2;  // a fixed layout: edges only
+  const int nlists =
+      (prec == DCM_FP32_MIXED && rule == DCM_PAIR_OWN && ctx->batch_lists == 0) ? 2 : 1;
+  for (int trial = 0; trial < nedges * nlayouts * nlists && st == DCM_OK; ++trial) {
+    const int il = trial % nlists, iq = (trial / nlists) % nlayouts;
+    const double edge = kTuneEdges[trial / (nlists * nlayouts)];
+    const int queues = ctx->batch_queues ? ctx->batch_queues : (iq ? kBatchQueues : 1);
+    if (il == 0 && (st = make_plan(ctx, B, edge, queues)) != DCM_OK) break;
+    B.row_lists = ctx->batch_lists ? ctx->batch_lists - 1 : il;
     enqueue(ctx, B, ctx->stream, lj, rule, prec, ev_flags, false);
     const hipError_t r0 = hipEventRecord(e0, ctx->stream);
     enqueue(ctx, B, ctx->stream, lj, rule, prec, ev_flags, false);
@@ -398,6 +406,7 @@ dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int 
       best_ms = ms;
       best_edge = edge;
       best_queues = queues;
+      best_lists = B.row_lists;
       first = false;
     }
   }
@@ -407,6 +416,7 @@ dcm_status tune(dcm_ctx *ctx, BatchState &B, dcm_lj lj, int rule, int prec, int 
   B.tuned = true;
   B.tuned_edge = best_edge;
   B.tuned_queues = best_queues;
+  B.tuned_lists = best_lists;
   return DCM_OK;
 }
 
@@ -421,6 +431,7 @@ std::vector<unsigned char> graph_key(const BatchState &B, dcm_lj lj, int rule, i
   std::memcpy(t + 24, &ev_flags, sizeof(int));
   std::memcpy(t + 28, &B.plan_edge, sizeof(double));
   std::memcpy(t + 36, &B.plan_queues, sizeof(int));
+  std::memcpy(t + 40, &B.row_lists, sizeof(int));
   return k;
 }
 
@@ -482,6 +493,7 @@ dcm_status dcm_forces_batched(dcm_ctx *ctx, int32_t nsys, const dcm_system *sys,
   const double edge = B.needs_tuning ? B.tuned_edge : 0.0;
   const int queues =
       ctx->batch_queues ? ctx->batch_queues : (B.needs_tuning ? B.tuned_queues : 1);
+  B.row_lists = ctx->batch_lists ? ctx->batch_lists - 1 : (B.needs_tuning ? B.tuned_lists : 0);
   if (!B.have_plan || B.plan_edge != edge || B.plan_queues != queues) {
     if ((st = make_plan(ctx, B, edge, queues)) != DCM_OK) {
       B.have_plan = false;
@@ -536,6 +548,25 @@ dcm_status dcm_batched_edge(const dcm_ctx *ctx, double *edge) {
 dcm_status dcm_batched_queues(const dcm_ctx *ctx, int32_t *queues) {
   if (!ctx || !queues) return DCM_ERR_INVALID;
   *queues = ctx->batch && ctx->batch->have_plan ? ctx->batch->plan_queues : 0;
+  return DCM_OK;
+}
+
+dcm_status dcm_batched_row_lists(const dcm_ctx *ctx, int32_t *entries) {
+  if (!ctx || !entries) return DCM_ERR_INVALID;
+  *entries = ctx->batch && ctx->batch->have_plan ? batched_row_lists(ctx->batch->row_lists) : 0;
+  return DCM_OK;
+}
+
+dcm_status dcm_set_batched_row_lists(dcm_ctx *ctx, int32_t entries) {
+  if (!ctx) return DCM_ERR_INVALID;
+  int v = -1;
+  for (int k = 0; k < 2; ++k)
+    if (entries == batched_row_lists(k)) v = k + 1;
+  if (entries == 0) v = 0;
+  if (v < 0)
+    return fail(ctx, DCM_ERR_INVALID, "dcm_set_batched_row_lists: entries must be 0, 14 or 16");
+  if (v != ctx->batch_lists && ctx->batch) ctx->batch->tuned = false;  // tune again
+  ctx->batch_lists = v;
   return DCM_OK;
 }
 

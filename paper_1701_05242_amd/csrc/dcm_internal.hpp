@@ -191,6 +191,7 @@ struct dcm_ctx {
   // batched form: plan, buffers and recorded graph
   dcm::BatchState *batch = nullptr;
   int batch_queues = 0;  // work-queue layout asked for (0: tuned)
+  int batch_lists = 0;   // row-list variant asked for (0: tuned, 1: 14 entries, 2: 16)
   // profiling
   bool profile = false;
   std::string profile_only;  // record only this family ("" = every family)
@@ -463,7 +464,11 @@ struct BatchPairArgs {
   double *partials;           // [nitems * kPartialSlots], by item
   uint32_t *status;
 };
-void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int prec);
+// row_lists: 0 or 1, the compact-record kernel's row-list variant (entries
+// per lane: batched_row_lists(row_lists)); other kernels have one
+void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int prec,
+                         int row_lists);
+int batched_row_lists(int k);
 
 // k_batch.hip: build kernels of the batched form.  pblk holds one (system,
 // first local particle) entry per block of 256 particles, eblk one (system,

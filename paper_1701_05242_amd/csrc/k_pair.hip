@@ -52,6 +52,10 @@ constexpr int kPairBlock = 256;
 #endif
 constexpr int kSegCap = DCM_PAIR_SEGCAP;
 constexpr int kSegCapRel = DCM_PAIR_SEGCAP_REL;
+// The batched compact-record kernel also exists with a wider list (fewer
+// chunks per particle, one workgroup fewer per compute unit); its tuner
+// times both (16 entries won on a 64-system batch, 14 on the large slab).
+constexpr int kSegCapRelWide = 16;
 template <bool REL>
 constexpr int seg_cap() {
   return REL ? kSegCapRel : kSegCap;
@@ -782,7 +786,7 @@ __device__ __forceinline__ void finish_block(const int32_t *perm, int64_t id0, d
 // own-cutoff evaluation on compact records, then the lanes that met an
 // undecidable pair are recomputed from the FP64 records.  segs holds
 // seg_cap<REL>() rows.
-template <int RULE, int PREC, int EVM, bool REL>
+template <int RULE, int PREC, int EVM, bool REL, int CAP = seg_cap<REL>()>
 __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool active, double eps,
                                            double sig2, uint2 (*segs)[kPairBlock],
                                            int32_t (*nearq)[kPairBlock],
@@ -897,8 +901,8 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
   }
   bool redo = false;
   int wcand = 0, wrows = 0;
-  sweep_rows<RULE, PREC, EVM, REL, seg_cap<REL>()>(v, active, g, sig2, segs, nearq, acc, cnt,
-                                                   redo, wcand, wrows);
+  sweep_rows<RULE, PREC, EVM, REL, CAP>(v, active, g, sig2, segs, nearq, acc, cnt, redo, wcand,
+                                        wrows);
   if constexpr (REL) {
     // rare: lanes with a row longer than a list entry can describe, or with
     // more close pairs in one chunk than their queue holds, start over on
@@ -909,8 +913,8 @@ __device__ __forceinline__ void pair_block(const PairView &v, int64_t s, bool ac
         cnt = 0;
       }
       bool unused = false;
-      sweep_rows<RULE, PREC, EVM, false, seg_cap<REL>()>(v, active && redo, g, sig2, segs, nearq,
-                                                        acc, cnt, unused, wcand, wrows);
+      sweep_rows<RULE, PREC, EVM, false, CAP>(v, active && redo, g, sig2, segs, nearq, acc, cnt,
+                                              unused, wcand, wrows);
     }
   }
   if constexpr (walk_counts<REL, EVM>()) {
@@ -1060,9 +1064,10 @@ void launch_pair_list(hipStream_t s, const PairArgs &a, int prec, const int32_t 
 // records are read through one L2.  A workgroup drains its home segment
 // (workgroup b runs on XCD b mod kXcds) and then the others in turn; it
 // leaves the loop once every segment's position has passed its end.
-template <int RULE, int PREC, int EVM, bool REL>
+template <int RULE, int PREC, int EVM, bool REL, int CAP = seg_cap<REL>()>
 __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
-  __shared__ uint2 segs[seg_cap<REL>()][kPairBlock];
+  static_assert(CAP >= kFillRows + 4, "a chunk holds a batch of rows, a sentinel and a look-ahead");
+  __shared__ uint2 segs[CAP][kPairBlock];
   __shared__ int32_t nearq[REL ? kNearCap + 1 : 1][kPairBlock];
   __shared__ double red[kPairBlock / 64][kPartialSlots];
   __shared__ int32_t next_item;
@@ -1124,7 +1129,8 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
     v.n3_f = nullptr;
     v.n3_cnt = nullptr;
     const int64_t local = first + threadIdx.x;
-    pair_block<RULE, PREC, EVM, REL>(v, g.p0 + local, local < g.n, a.eps, sig2, segs, nearq, red,
+    pair_block<RULE, PREC, EVM, REL, CAP>(v, g.p0 + local, local < g.n, a.eps, sig2, segs, nearq,
+                                          red,
                                      a.status,
                                 a.partials + (int64_t)item * kPartialSlots);
   }
@@ -1195,25 +1201,30 @@ void launch_n3_out(hipStream_t s, const double4 *f, const int32_t *cnt, const in
                      fx, fy, fz, nnbr, status);
 }
 
-template <int RULE, int PREC, bool REL, int E = 0>
+template <int RULE, int PREC, bool REL, int CAP, int E = 0>
 static void launch_pair_batched_ev(hipStream_t s, const BatchPairArgs &a, dim3 g, dim3 b,
                                    int evm) {
   if constexpr (E < (REL ? 8 : 4)) {
-    if (evm == E) hipLaunchKernelGGL((k_pair_batched<RULE, PREC, E, REL>), g, b, 0, s, a);
-    else launch_pair_batched_ev<RULE, PREC, REL, E + 1>(s, a, g, b, evm);
+    if (evm == E) hipLaunchKernelGGL((k_pair_batched<RULE, PREC, E, REL, CAP>), g, b, 0, s, a);
+    else launch_pair_batched_ev<RULE, PREC, REL, CAP, E + 1>(s, a, g, b, evm);
   }
 }
 
+int batched_row_lists(int k) { return k == 1 ? kSegCapRelWide : kSegCapRel; }
+
 // Resident workgroups of the persistent kernel: what the occupancy allows on
 // every compute unit, never more than the number of items.
-static int64_t persistent_grid(int rule, int prec, int64_t nitems) {
-  static int cached[2][2] = {{0, 0}, {0, 0}};
-  int &per_cu = cached[rule][prec];
+static int64_t persistent_grid(int rule, int prec, bool wide, int64_t nitems) {
+  static int cached[2][2][2] = {{{0, 0}, {0, 0}}, {{0, 0}, {0, 0}}};
+  int &per_cu = cached[rule][prec][wide ? 1 : 0];
   if (per_cu == 0) {
     const void *fn;
     if (rule == DCM_PAIR_OWN)
-      fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP64, 3, false>
-                            : (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP32_MIXED, 7, true>;
+      fn = prec == DCM_FP64
+               ? (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP64, 3, false>
+               : (wide ? (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP32_MIXED, 7, true,
+                                                     kSegCapRelWide>
+                       : (const void *)k_pair_batched<DCM_PAIR_OWN, DCM_FP32_MIXED, 7, true>);
     else
       fn = prec == DCM_FP64 ? (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP64, 3, false>
                             : (const void *)k_pair_batched<DCM_PAIR_MAX, DCM_FP32_MIXED, 3, false>;
@@ -1232,19 +1243,30 @@ static int64_t persistent_grid(int rule, int prec, int64_t nitems) {
   return g < nitems ? g : (nitems > 0 ? nitems : 1);
 }
 
-void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int prec) {
+void launch_pair_batched(hipStream_t s, const BatchPairArgs &a, int rule, int prec,
+                         int row_lists) {
   if (a.nitems <= 0) return;
-  dim3 g((unsigned)persistent_grid(rule, prec, a.nitems)), b(kPairBlock);
+  constexpr int kF = seg_cap<false>(), kR = kSegCapRel, kW = kSegCapRelWide;
+  // the row-list capacity is a choice of the compact-record kernel only
+  const bool wide = rule == DCM_PAIR_OWN && prec != DCM_FP64 && a.ext_rel && row_lists == 1;
+  dim3 g((unsigned)persistent_grid(rule, prec, wide, a.nitems)), b(kPairBlock);
   const int evm = ev_mode(a.ev_flags, false);
   if (rule == DCM_PAIR_OWN) {
-    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP64, false>(s, a, g, b, evm);
+    if (prec == DCM_FP64)
+      launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP64, false, kF>(s, a, g, b, evm);
+    else if (a.ext_rel && wide)
+      launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true, kW>(s, a, g, b,
+                                                                     ev_mode(a.ev_flags, true));
     else if (a.ext_rel)
-      launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true>(s, a, g, b,
-                                                                 ev_mode(a.ev_flags, true));
-    else launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, false>(s, a, g, b, evm);
+      launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, true, kR>(s, a, g, b,
+                                                                     ev_mode(a.ev_flags, true));
+    else
+      launch_pair_batched_ev<DCM_PAIR_OWN, DCM_FP32_MIXED, false, kF>(s, a, g, b, evm);
   } else {
-    if (prec == DCM_FP64) launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP64, false>(s, a, g, b, evm);
-    else launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP32_MIXED, false>(s, a, g, b, evm);
+    if (prec == DCM_FP64)
+      launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP64, false, kF>(s, a, g, b, evm);
+    else
+      launch_pair_batched_ev<DCM_PAIR_MAX, DCM_FP32_MIXED, false, kF>(s, a, g, b, evm);
   }
 }
 

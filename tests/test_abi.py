@@ -85,6 +85,8 @@ def test_null_context_is_rejected_before_any_device_call(lib):
     assert lib.dcm_batched_edge(None, None) == dcm.DCM_ERR_INVALID
     assert lib.dcm_walk_stats(None, None) == dcm.DCM_ERR_INVALID
     assert lib.dcm_batched_queues(None, None) == dcm.DCM_ERR_INVALID
+    assert lib.dcm_batched_row_lists(None, None) == dcm.DCM_ERR_INVALID
+    assert lib.dcm_set_batched_row_lists(None, 16) == dcm.DCM_ERR_INVALID
     assert lib.dcm_set_profiling_only(None, b"pair") == dcm.DCM_ERR_INVALID
     assert lib.dcm_set_batched_queues(None, 8) == dcm.DCM_ERR_INVALID
 

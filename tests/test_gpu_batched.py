@@ -102,6 +102,31 @@ def test_batched_matches_oracle(rule, prec):
         assert rel(got["W"], ref["W"]) <= tol
 
 
+@pytest.mark.parametrize("lists", [14, 16])
+def test_batched_row_lists_match_oracle(lists):
+    """The compact-record batched kernel with each row-list size forced: the
+    oracle's counts bit for bit, forces, energy and virial within 1e-5."""
+    print(f"[gpu] batched row lists {lists}", flush=True)
+    systems = small_batch()
+    rcs = [oracle_rc("small", b) for b in range(len(systems))]
+    batch = device_batch(systems, rcs, edge=1.25)
+    with Ctx() as ctx:
+        dcm.dcm_set_batched_row_lists(ctx, lists)
+        dcm.dcm_forces_batched(ctx, batch, dcm.make_lj(), prec=dcm.DCM_FP32_MIXED,
+                               ev_flags=EV_ALL)
+        assert dcm.dcm_sync_status(ctx) == dcm.DCM_OK, dcm.dcm_last_error(ctx)
+        assert dcm.dcm_batched_row_lists(ctx) == lists
+    for b, d in enumerate(batch):
+        got = results(d)
+        ref = oracle_forces("small", b, dcm.DCM_PAIR_OWN)
+        R = np.stack([ref["fx"], ref["fy"], ref["fz"]], 1)
+        np.testing.assert_array_equal(got["nnbr"], ref["nnbr"])
+        emax, erms = force_errors(got["F"], R)
+        assert emax <= 1e-5 and erms <= 1e-5, (b, emax, erms)
+        assert abs(got["E"] - ref["E"]) <= 1e-5 * abs(ref["E"])
+        assert rel(got["W"], ref["W"]) <= 1e-5
+
+
 @pytest.mark.parametrize("queues", [1, 8])
 @pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
 @pytest.mark.parametrize("rule", [dcm.DCM_PAIR_OWN, dcm.DCM_PAIR_MAX])
@@ -149,6 +174,8 @@ def test_batched_tuner_and_graph_replays():
         assert edge in TUNE_EDGES
         queues = dcm.dcm_batched_queues(ctx)
         assert queues in (1, 8)
+        lists = dcm.dcm_batched_row_lists(ctx)
+        assert lists in (14, 16)
         first = [results(d) for d in batch]
         for b, got in enumerate(first):
             ref = oracle_forces("small", b, dcm.DCM_PAIR_OWN)
@@ -172,6 +199,7 @@ def test_batched_tuner_and_graph_replays():
             eager = [results(d) for d in batch]
             assert dcm.dcm_batched_edge(ctx) == edge
             assert dcm.dcm_batched_queues(ctx) == queues
+            assert dcm.dcm_batched_row_lists(ctx) == lists
             for b, (g, e) in enumerate(zip(replay, eager)):
                 np.testing.assert_array_equal(g["F"], e["F"])
                 np.testing.assert_array_equal(g["nnbr"], e["nnbr"])
