@@ -25,8 +25,10 @@ dcm_status ensure(dcm_ctx *ctx, DevBuf &b, size_t bytes) {
   if (bytes < 256) bytes = 256;
   if (b.cap >= bytes) return DCM_OK;
   if (b.p) {
-    // work queued on the stream may still use the old buffer
-    if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+    // work queued on the stream may still use the old buffer (with dcm_step's
+    // second stream in use, work on either stream: the whole device waits)
+    const hipError_t e = ctx->side ? hipDeviceSynchronize() : hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
       return fail(ctx, DCM_ERR_HIP, "buffer growth: stream synchronisation failed");
     (void)hipFree(b.p);
     b.p = nullptr;
@@ -351,6 +353,12 @@ dcm_status dcm_create(dcm_ctx **out, void *hip_stream) {
 dcm_status dcm_destroy(dcm_ctx *ctx) {
   if (!ctx) return DCM_ERR_INVALID;
   (void)hipStreamSynchronize(ctx->stream);  // freed below whatever its status
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   // the context's device buffers go with it
   batch_free(ctx);
   for (auto &kv : ctx->timers)
@@ -520,6 +528,10 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
                            const double *rc, int64_t n, dcm_box box, double cell_edge,
                            double rc_bound, int prec, int32_t *cell_of, int32_t *cell_start) {
   if (!ctx) return DCM_ERR_INVALID;
+  // dcm_step's build beside the sweep: rc is not read (the
+  // sorted records' cutoffs are written by the cutoff assignment)
+  const bool no_rc = ctx->build_no_rc;
+  ctx->build_no_rc = false;
   ctx->list_n = -1;
   ctx->ext_src_ok = false;
   DCM_TRY(check_n(ctx, n));
@@ -663,7 +675,8 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   hipEvent_t ev;
   timer_begin(ctx, "cells", &ev);
   launch_zero2_i32(s, ptr<int32_t>(ctx->cell_count), ptr<int32_t>(ctx->cell_fill), ncell);
-  launch_cell_count(s, x, y, z, rc, n, box.L, nc, sc, rc_cap, cof, ptr<int32_t>(ctx->cell_count),
+  const double *rc_in = no_rc ? nullptr : rc;
+  launch_cell_count(s, x, y, z, rc_in, n, box.L, nc, sc, rc_cap, cof, ptr<int32_t>(ctx->cell_count),
                     ptr<unsigned long long>(ctx->rcmax_part), ptr<uint32_t>(ctx->xkey), ctx->ctl,
                     ctx->d_status);
   launch_exclusive_scan(s, ptr<int32_t>(ctx->cell_count), ptr<int32_t>(ctx->cell_start), ncell,
@@ -673,7 +686,7 @@ dcm_status dcm_build_cells(dcm_ctx *ctx, const double *x, const double *y, const
   launch_cell_scatter(s, cof, n, ptr<int32_t>(ctx->cell_start), ptr<int32_t>(ctx->cell_fill),
                       ptr<int32_t>(ctx->sort_tmp), ptr<uint32_t>(ctx->xkey),
                       ptr<uint32_t>(ctx->skey));
-  const GatherOut go = {x, y, z, rc, {box.L[0], box.L[1], box.L[2]}, rc_cap,
+  const GatherOut go = {x, y, z, rc_in, {box.L[0], box.L[1], box.L[2]}, rc_cap,
                         ptr<double4>(ctx->sorted)};
   launch_cell_sort(s, ptr<int32_t>(ctx->cell_start), ncell, cof, n, ptr<int32_t>(ctx->sort_tmp),
                    ptr<uint32_t>(ctx->xkey), ptr<uint32_t>(ctx->skey),
@@ -1106,6 +1119,8 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
                           : std::max<int32_t>(64, (int32_t)std::ceil(4.0 * rc_grid / hmin) + 8);
   double *scal = ptr<double>(ctx->scalars);
   const dcm_detect_opts dopts = {0.0, -1.0, 0};
+  // the cell build beside the sweep (set below; a no-op where it does not apply)
+  std::function<dcm_status()> build_beside;
   auto detect = [&]() -> dcm_status {
     // detection (Section 2.1) without the byte maps: the sweep takes its
     // sources from the phase maps, and the field stays in the sweep's
@@ -1115,6 +1130,7 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     DCM_TRY(detect_enqueue(ctx, W[WX], W[WY], W[WZ], n, box, grid, dopts, sc, nullptr, nullptr,
                            nullptr, true));
     const uint32_t *const maps[2] = {sc.seg_a, sc.seg_b};
+    if (build_beside) DCM_TRY(build_beside());
     DCM_TRY(sweep_enqueue(ctx, nullptr, nullptr, grid, nvox, rc_grid, max_waves, nullptr, nullptr,
                           maps));
     ctx->have_field = true;
@@ -1138,20 +1154,36 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
       rule.rc_min,         rule.rc_max, (double)prec,   (double)pair_rule, lj.sigma};
   const std::vector<double> edge_cands = edge_candidates(
       rule.rc_min, prec == DCM_FP32_MIXED ? kRelMaxEdgeSigma * lj.sigma : INFINITY, box.L);
+  // an edge tuned by an earlier call serves from the first step on
+  (void)edge_cached(edge_key, &step_cell_edge);
   // cutoffs, cells and forces of the working copies; the forces land in the
   // working order (the cells map sorted slots back to it)
   const double vsc[3] = {(double)grid.n[0] / box.L[0], (double)grid.n[1] / box.L[1],
                          (double)grid.n[2] / box.L[2]};
+  // the cells of this step were built beside the sweep (prebuild), and only
+  // their records' cutoffs are missing
+  bool prebuilt = false;
   auto forces = [&](double *e_out) -> dcm_status {
+    // cells built on the second stream: complete before their records
+    // take the cutoffs
+    if (prebuilt && hipStreamWaitEvent(s, ctx->join_ev, 0) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_step: stream join failed");
     {  // cutoffs (Section 2.2) from the field in the sweep's buffers
       hipEvent_t cev;
       timer_begin(ctx, "cutoffs", &cev);
       launch_assign_cutoffs_sweep(s, W[WX], W[WY], W[WZ], n, box.L, grid.n, vsc,
                                   ptr<double>(ctx->dA), ptr<double>(ctx->dB),
                                   ptr<uint32_t>(ctx->fsm_flags), ctx->field_waves,
-                                  ctx->field_rc_grid, rule, W[WDELTA], W[WRC], ctx->d_status);
+                                  ctx->field_rc_grid, rule, W[WDELTA], W[WRC], ctx->d_status,
+                                  prebuilt ? ptr<int32_t>(ctx->perm) : nullptr,
+                                  ptr<double4>(ctx->sorted), ctx->rc_bound);
       timer_end(ctx, "cutoffs", cev);
       DCM_TRY(check_launch(ctx, "dcm_step cutoffs"));
+    }
+    if (prebuilt) {
+      prebuilt = false;
+      return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, W[WFX], W[WFY], W[WFZ],
+                        e_out ? e_out : scal, nullptr, nullptr, nullptr);
     }
     if (step_cell_edge <= 0.0) {
       auto run = [&](double e) -> dcm_status {
@@ -1168,6 +1200,44 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     return dcm_forces(ctx, lj, pair_rule, prec, DCM_EV_ENERGY, W[WFX], W[WFY], W[WFZ],
                       e_out ? e_out : scal, nullptr, nullptr, nullptr);
   };
+  // Build the cells of a step on a second stream while the sweep runs on the
+  // context's stream: the build reads only the positions, and the
+  // own-cutoff walk reads only each particle's own cutoff, which the cutoff
+  // assignment writes into its sorted record once the cells are complete.
+  // The sweep's passes are bound by latency and leave the memory system to
+  // the build (the detection before it is bound by HBM bandwidth, as the
+  // build is).  Taken once the cell edge is tuned, for the own-cutoff rule,
+  // outside stream capture.
+  auto prebuild = [&]() -> dcm_status {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (pair_rule != DCM_PAIR_OWN || step_cell_edge <= 0.0 ||
+        hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+      return DCM_OK;
+    if (!ctx->side) {
+      if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) {
+        ctx->side = nullptr;
+        return fail(ctx, DCM_ERR_HIP, "dcm_step: stream creation failed");
+      }
+      if (hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess)
+        return fail(ctx, DCM_ERR_HIP, "dcm_step: event creation failed");
+    }
+    if (hipEventRecord(ctx->fork_ev, s) != hipSuccess ||
+        hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_step: stream fork failed");
+    ctx->stream = ctx->side;
+    ctx->build_no_rc = true;
+    const dcm_status st = dcm_build_cells(ctx, W[WX], W[WY], W[WZ], W[WRC], n, box,
+                                          step_cell_edge, rule.rc_max, prec, nullptr, nullptr);
+    ctx->stream = s;
+    ctx->build_no_rc = false;
+    if (st != DCM_OK) return st;
+    if (hipEventRecord(ctx->join_ev, ctx->side) != hipSuccess)
+      return fail(ctx, DCM_ERR_HIP, "dcm_step: stream join failed");
+    prebuilt = true;
+    return DCM_OK;
+  };
+  build_beside = prebuild;
   if (nsteps == 0) {
     DCM_TRY(detect());
     DCM_TRY(forces(nullptr));
@@ -1183,7 +1253,10 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
                         n, c, dt, box.L);
       timer_end(ctx, "verlet", ev);
     }
-    if (!ctx->have_field || (step0 + st + 1) % redetect_every == 0) DCM_TRY(detect());
+    if (!ctx->have_field || (step0 + st + 1) % redetect_every == 0)
+      DCM_TRY(detect());
+    else
+      DCM_TRY(prebuild());
     DCM_TRY(forces(energy_series ? energy_series + 2 * (int64_t)st : nullptr));
     timer_begin(ctx, "verlet", &ev);
     // without an energy series to record in between, the closing kick and

@@ -191,6 +191,13 @@ struct dcm_ctx {
   // batched form: plan, buffers and recorded graph
   dcm::BatchState *batch = nullptr;
   int batch_queues = 0;  // work-queue layout asked for (0: tuned)
+  // dcm_step: a second stream on which the cell build of a step runs beside
+  // detection, sweep and cutoffs, with its fork and join events
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // set for the next cell build: build without the cutoffs (the sorted
+  // records' rc comes later, from the cutoff assignment); consumed by that build
+  bool build_no_rc = false;
   int batch_lists = 0;   // row-list variant asked for (0: tuned, 1: 14 entries, 2: 16)
   // profiling
   bool profile = false;
@@ -294,13 +301,17 @@ void launch_fsm_final(hipStream_t s, const double *dA, const double *dB, int64_t
 
 // k_cells.hip
 // the same from the distance sweep's buffers (dA, dB) and pass flags, as
-// its final pass would have written the field (see launch_fsm_final)
+// its final pass would have written the field (see launch_fsm_final); with
+// perm, for cells built without the cutoffs: the threads walk the sorted
+// slots and sorted[slot].w takes rc[perm[slot]] clamped to [0, rc_cap]
+// (out of range flagged)
 void launch_assign_cutoffs_sweep(hipStream_t s, const double *x, const double *y,
                                  const double *z, int64_t n, const double L[3],
                                  const int32_t nv[3], const double sc[3], const double *dA,
                                  const double *dB, const uint32_t *flags, int max_steps,
                                  double rc_grid, dcm_rule rule, double *delta, double *rc,
-                                 uint32_t *status);
+                                 uint32_t *status, const int32_t *perm = nullptr,
+                                 double4 *sorted = nullptr, double rc_cap = 0.0);
 void launch_assign_cutoffs(hipStream_t s, const double *x, const double *y, const double *z,
                            int64_t n, const double L[3], const int32_t nv[3],
                            const double sc[3], const double *dist, dcm_rule rule,

@@ -11,13 +11,18 @@ namespace dcm {
 // read as the sweep's final pass would write the field: the buffer of the
 // first pass that changed nothing, each value capped at `cap`; a sweep that
 // ran out of passes is flagged here.
-template <bool SWEEP>
+// SLOTS: cells built before the cutoffs were known (their records carry no
+// cutoff): the threads walk the sorted slots, particle p = perm[slot], and
+// each record takes its particle's cutoff, clamped to [0, rc_cap] as the
+// cell build's gather clamps it (a value outside is flagged).
+template <bool SWEEP, bool SLOTS>
 __global__ __launch_bounds__(256) void k_assign_cutoffs(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     int64_t n, double Lx, double Ly, double Lz, int nx, int ny, int nz, double sx, double sy,
     double sz, const double *__restrict__ D, double rc_min, double rc_max, double ramp,
     double *__restrict__ delta, double *__restrict__ rc, const double *__restrict__ D2,
-    const uint32_t *__restrict__ flags, int max_steps, double cap, uint32_t *status) {
+    const uint32_t *__restrict__ flags, int max_steps, double cap, uint32_t *status,
+    const int32_t *__restrict__ perm, double4 *__restrict__ sorted, double rc_cap) {
   if constexpr (SWEEP) {
     int last = max_steps;
     for (int q = 1; q <= max_steps; ++q)
@@ -29,12 +34,22 @@ __global__ __launch_bounds__(256) void k_assign_cutoffs(
     if (blockIdx.x == 0 && threadIdx.x == 0 && flags[max_steps] != 0u)
       atomicOr(status, ST_NOT_CONVERGED);
   }
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-       p += (int64_t)gridDim.x * blockDim.x) {
+  // the record's cutoff as the gather writes it
+  auto record = [&](int64_t slot, double r) {
+    if constexpr (SLOTS) {
+      if (!(r >= 0.0) || r > rc_cap) atomicOr(status, ST_RC_RANGE);
+      sorted[slot].w = (r >= 0.0) ? (r < rc_cap ? r : rc_cap) : 0.0;  // NaN -> 0
+    }
+  };
+  for (int64_t it = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; it < n;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    int64_t p = it;
+    if constexpr (SLOTS) p = perm[it];
     double px = x[p], py = y[p], pz = z[p];
     if (!finite3(px, py, pz)) {
       if (delta) delta[p] = __builtin_nan("");
       rc[p] = rc_max;
+      record(it, rc_max);
       continue;
     }
     const double pos[3] = {wrap_coord(px, Lx), wrap_coord(py, Ly), wrap_coord(pz, Lz)};
@@ -69,7 +84,9 @@ __global__ __launch_bounds__(256) void k_assign_cutoffs(
     if (delta) delta[p] = d;
     double q = d / ramp;
     if (q > 1.0) q = 1.0;
-    rc[p] = rc_max - (rc_max - rc_min) * q;
+    const double r = rc_max - (rc_max - rc_min) * q;
+    rc[p] = r;
+    record(it, r);
   }
 }
 
@@ -80,9 +97,10 @@ void launch_assign_cutoffs(hipStream_t s, const double *x, const double *y, cons
   if (n <= 0) return;
   int64_t b = ceil_div(n, 256);
   if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_assign_cutoffs<false>, dim3((unsigned)b), dim3(256), 0, s, x, y, z, n,
-                     L[0], L[1], L[2], nv[0], nv[1], nv[2], sc[0], sc[1], sc[2], dist, rule.rc_min,
-                     rule.rc_max, rule.ramp, delta, rc, nullptr, nullptr, 0, 0.0, nullptr);
+  hipLaunchKernelGGL((k_assign_cutoffs<false, false>), dim3((unsigned)b), dim3(256), 0, s, x, y,
+                     z, n, L[0], L[1], L[2], nv[0], nv[1], nv[2], sc[0], sc[1], sc[2], dist,
+                     rule.rc_min, rule.rc_max, rule.ramp, delta, rc, nullptr, nullptr, 0, 0.0,
+                     nullptr, nullptr, nullptr, 0.0);
 }
 
 void launch_assign_cutoffs_sweep(hipStream_t s, const double *x, const double *y,
@@ -90,13 +108,21 @@ void launch_assign_cutoffs_sweep(hipStream_t s, const double *x, const double *y
                                  const int32_t nv[3], const double sc[3], const double *dA,
                                  const double *dB, const uint32_t *flags, int max_steps,
                                  double rc_grid, dcm_rule rule, double *delta, double *rc,
-                                 uint32_t *status) {
+                                 uint32_t *status, const int32_t *perm, double4 *sorted,
+                                 double rc_cap) {
   if (n <= 0) return;
   int64_t b = ceil_div(n, 256);
   if (b > 16384) b = 16384;
-  hipLaunchKernelGGL(k_assign_cutoffs<true>, dim3((unsigned)b), dim3(256), 0, s, x, y, z, n,
-                     L[0], L[1], L[2], nv[0], nv[1], nv[2], sc[0], sc[1], sc[2], dA, rule.rc_min,
-                     rule.rc_max, rule.ramp, delta, rc, dB, flags, max_steps, rc_grid, status);
+  if (perm)
+    hipLaunchKernelGGL((k_assign_cutoffs<true, true>), dim3((unsigned)b), dim3(256), 0, s, x, y,
+                       z, n, L[0], L[1], L[2], nv[0], nv[1], nv[2], sc[0], sc[1], sc[2], dA,
+                       rule.rc_min, rule.rc_max, rule.ramp, delta, rc, dB, flags, max_steps,
+                       rc_grid, status, perm, sorted, rc_cap);
+  else
+    hipLaunchKernelGGL((k_assign_cutoffs<true, false>), dim3((unsigned)b), dim3(256), 0, s, x, y,
+                       z, n, L[0], L[1], L[2], nv[0], nv[1], nv[2], sc[0], sc[1], sc[2], dA,
+                       rule.rc_min, rule.rc_max, rule.ramp, delta, rc, dB, flags, max_steps,
+                       rc_grid, status, nullptr, nullptr, 0.0);
 }
 
 // ------------------------------------------------------------ cell count
@@ -114,7 +140,8 @@ __global__ __launch_bounds__(256) void k_cell_count(
     const bool valid = i < n;
     int c = 0;
     if (valid) {
-      double px = x[i], py = y[i], pz = z[i], r = rc[i];
+      // rc null: the cutoffs are not known yet (the cutoff assignment adds them)
+      double px = x[i], py = y[i], pz = z[i], r = rc ? rc[i] : 0.0;
       uint32_t q = 0;
       if (finite3(px, py, pz)) {
         const double wx = wrap_coord(px, Lx);
@@ -452,7 +479,7 @@ __device__ __forceinline__ double4 gather_record(const GatherOut &go, double px,
 }
 
 __device__ __forceinline__ double4 gather_record(const GatherOut &go, int i) {
-  return gather_record(go, go.x[i], go.y[i], go.z[i], go.rc[i]);
+  return gather_record(go, go.x[i], go.y[i], go.z[i], go.rc ? go.rc[i] : 0.0);
 }
 
 // GATHER: a particle of a small cell also writes its sorted record at its
@@ -473,7 +500,7 @@ __global__ __launch_bounds__(256) void k_cell_rank(const int32_t *__restrict__ c
       px = go.x[i];
       py = go.y[i];
       pz = go.z[i];
-      pr = go.rc[i];
+      pr = go.rc ? go.rc[i] : 0.0;
     }
     const int c = cell_of[i];
     const int a = cell_start[c], b = cell_start[c + 1];
