@@ -1253,10 +1253,8 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
                         n, c, dt, box.L);
       timer_end(ctx, "verlet", ev);
     }
-    if (!ctx->have_field || (step0 + st + 1) % redetect_every == 0)
-      DCM_TRY(detect());
-    else
-      DCM_TRY(prebuild());
+    // (a step without detection builds its cells in line: nothing to overlap)
+    if (!ctx->have_field || (step0 + st + 1) % redetect_every == 0) DCM_TRY(detect());
     DCM_TRY(forces(energy_series ? energy_series + 2 * (int64_t)st : nullptr));
     timer_begin(ctx, "verlet", &ev);
     // without an energy series to record in between, the closing kick and
