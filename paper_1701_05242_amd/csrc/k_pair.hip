@@ -759,6 +759,61 @@ __device__ __forceinline__ void block_partials(const Acc<PREC> &acc, int64_t cnt
   }
 }
 
+// Lane order of a workgroup's particles for the own-cutoff walk on compact
+// records.  A particle's walk grows with the cube of its cutoff, and near an
+// interface the cutoffs of neighbouring cells differ by up to the whole
+// ramp, so the 64 consecutive slots of a wavefront hold walks of very
+// different lengths and the short ones idle until the longest ends.  The
+// workgroup's particles are ranked by cutoff bin (kRcBins bins of rc_bound /
+// kRcBins, the largest first; slot order within a bin; empty slots last) and
+// lane t takes the particle of rank t, so each wavefront holds similar
+// cutoffs.  The rank depends only on the workgroup's records: the same
+// particles in the same slots give the same lanes in every kernel using it.
+// scratch: kPairBlock + (kPairBlock / 64) * (kRcBins + 1) ints of LDS, free
+// on entry and on return.  Returns the slot offset (0 .. kPairBlock - 1)
+// this lane takes.
+constexpr int kRcBins = 8;
+static_assert((kNearCap + 1) * kPairBlock >= kPairBlock + (kPairBlock / 64) * (kRcBins + 1),
+              "the lane order borrows the close-pair queue's LDS");
+__device__ __forceinline__ int rc_lane_order(const double4 *pos, int64_t base, int64_t count,
+                                             double rc_bound, int32_t *scratch) {
+  constexpr int kKeys = kRcBins + 1;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  int key = kRcBins;  // empty slot
+  if (t < count) {
+    const double r = pos[base + t].w;
+    const double q = rc_bound > 0.0 ? r * ((double)kRcBins / rc_bound) : 0.0;
+    int b = q >= 0.0 ? (int)q : 0;  // NaN: bin 0
+    b = b > kRcBins - 1 ? kRcBins - 1 : b;
+    key = kRcBins - 1 - b;
+  }
+  int32_t *start = scratch + kPairBlock;  // [wave][key]
+  unsigned long long mine = 0;
+#pragma unroll
+  for (int k = 0; k < kKeys; ++k) {
+    const unsigned long long m = __ballot(key == k);
+    mine = key == k ? m : mine;
+    if (lane == 0) start[wave * kKeys + k] = __popcll(m);
+  }
+  __syncthreads();
+  if (t == 0) {  // exclusive prefix over (key, wave)
+    int acc = 0;
+    for (int k = 0; k < kKeys; ++k)
+      for (int w = 0; w < kPairBlock / 64; ++w) {
+        const int c = start[w * kKeys + k];
+        start[w * kKeys + k] = acc;
+        acc += c;
+      }
+  }
+  __syncthreads();
+  const int rank = start[wave * kKeys + key] + __popcll(mine & ((1ull << lane) - 1ull));
+  scratch[rank] = t;
+  __syncthreads();
+  const int mine_t = scratch[t];
+  __syncthreads();
+  return mine_t;
+}
+
 // Forces of the lane's particle to caller order (24 eps applied), its pair
 // count, and the block's deterministic partial sums E, W[6], pair count.
 template <int PREC>
@@ -950,7 +1005,10 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(PairArgs a) {
   __shared__ int32_t nearq[REL ? kNearCap + 1 : 1][kPairBlock];
   __shared__ double red[kPairBlock / 64][kPartialSlots];
   const int64_t lblock = xcd_block(blockIdx.x, gridDim.x, kXcdGroup);
-  const int64_t s = lblock * kPairBlock + threadIdx.x;
+  int64_t s = lblock * kPairBlock + threadIdx.x;
+  if constexpr (REL)
+    s = lblock * kPairBlock + rc_lane_order(a.pos, lblock * kPairBlock,
+                                            a.n - lblock * kPairBlock, a.rc_bound, &nearq[0][0]);
   PairView v;
   v.pos = a.pos;
   v.cell_start = a.cell_start;
@@ -1128,7 +1186,9 @@ __global__ __launch_bounds__(kPairBlock) void k_pair_batched(BatchPairArgs a) {
     v.ext_src = nullptr;
     v.n3_f = nullptr;
     v.n3_cnt = nullptr;
-    const int64_t local = first + threadIdx.x;
+    int64_t local = first + threadIdx.x;
+    if constexpr (REL)
+      local = first + rc_lane_order(a.pos, g.p0 + first, g.n - first, g.rc_cap, &nearq[0][0]);
     pair_block<RULE, PREC, EVM, REL, CAP>(v, g.p0 + local, local < g.n, a.eps, sig2, segs, nearq,
                                           red,
                                      a.status,
