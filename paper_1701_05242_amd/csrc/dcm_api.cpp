@@ -1168,13 +1168,15 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     // take the cutoffs
     if (prebuilt && hipStreamWaitEvent(s, ctx->join_ev, 0) != hipSuccess)
       return fail(ctx, DCM_ERR_HIP, "dcm_step: stream join failed");
-    {  // cutoffs (Section 2.2) from the field in the sweep's buffers
+    {  // cutoffs (Section 2.2) from the field in the sweep's buffers; the
+       // distances are kept only when the caller asks for them
       hipEvent_t cev;
       timer_begin(ctx, "cutoffs", &cev);
       launch_assign_cutoffs_sweep(s, W[WX], W[WY], W[WZ], n, box.L, grid.n, vsc,
                                   ptr<double>(ctx->dA), ptr<double>(ctx->dB),
                                   ptr<uint32_t>(ctx->fsm_flags), ctx->field_waves,
-                                  ctx->field_rc_grid, rule, W[WDELTA], W[WRC], ctx->d_status,
+                                  ctx->field_rc_grid, rule, delta ? W[WDELTA] : nullptr, W[WRC],
+                                  ctx->d_status,
                                   prebuilt ? ptr<int32_t>(ctx->perm) : nullptr,
                                   ptr<double4>(ctx->sorted), ctx->rc_bound);
       timer_end(ctx, "cutoffs", cev);
