@@ -382,11 +382,14 @@ __device__ __forceinline__ void interact_rel(Acc<DCM_FP32_MIXED> &acc, float dx,
   const float r2i = inc ? __builtin_amdgcn_rcpf(r2) : 0.0f;
   const float s2 = sig2 * r2i;
   const float s6 = s2 * s2 * s2;
-  const float fp = s6 * fmaf(2.0f, s6, -1.0f) * r2i;
+  // the pair energy's s6^2 - s6 and the force factor's 2 s6^2 - s6 share
+  // one product: two fused ops where the energy would take a third
+  const float e = fmaf(s6, s6, -s6);
+  const float fp = fmaf(s6, s6, e) * r2i;
   acc.px = fmaf(fp, dx, acc.px);
   acc.py = fmaf(fp, dy, acc.py);
   acc.pz = fmaf(fp, dz, acc.pz);
-  if constexpr ((EVM & 1) != 0) acc.e += fmaf(s6, s6, -s6);
+  if constexpr ((EVM & 1) != 0) acc.e += e;
   if constexpr ((EVM & 2) != 0) {
     const float fdx = fp * dx, fdy = fp * dy, fdz = fp * dz;
     acc.w[0] = fmaf(fdx, dx, acc.w[0]);
