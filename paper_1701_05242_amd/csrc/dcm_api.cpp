@@ -25,9 +25,13 @@ dcm_status ensure(dcm_ctx *ctx, DevBuf &b, size_t bytes) {
   if (bytes < 256) bytes = 256;
   if (b.cap >= bytes) return DCM_OK;
   if (b.p) {
-    // work queued on the stream may still use the old buffer (with dcm_step's
-    // second stream in use, work on either stream: the whole device waits)
-    const hipError_t e = ctx->side ? hipDeviceSynchronize() : hipStreamSynchronize(ctx->stream);
+    // work queued on the context's streams may still use the old buffer:
+    // its stream, dcm_step's second stream, and the stream that one was
+    // forked from while it builds cells
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess && ctx->side && ctx->side != ctx->stream)
+      e = hipStreamSynchronize(ctx->side);
+    if (e == hipSuccess && ctx->forked_from) e = hipStreamSynchronize(ctx->forked_from);
     if (e != hipSuccess)
       return fail(ctx, DCM_ERR_HIP, "buffer growth: stream synchronisation failed");
     (void)hipFree(b.p);
@@ -1216,22 +1220,28 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
         hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
       return DCM_OK;
     if (!ctx->side) {
-      if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) {
-        ctx->side = nullptr;
-        return fail(ctx, DCM_ERR_HIP, "dcm_step: stream creation failed");
-      }
-      if (hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess)
-        return fail(ctx, DCM_ERR_HIP, "dcm_step: event creation failed");
+      // on the context's device, whichever is current
+      int cur = ctx->device;
+      if (hipGetDevice(&cur) != hipSuccess ||
+          (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess))
+        return fail(ctx, DCM_ERR_HIP, "dcm_step: device selection failed");
+      hipError_t e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+      if (e != hipSuccess) ctx->side = nullptr;
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
+      if (cur != ctx->device) (void)hipSetDevice(cur);
+      if (e != hipSuccess) return fail(ctx, DCM_ERR_HIP, "dcm_step: stream creation failed");
     }
     if (hipEventRecord(ctx->fork_ev, s) != hipSuccess ||
         hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0) != hipSuccess)
       return fail(ctx, DCM_ERR_HIP, "dcm_step: stream fork failed");
     ctx->stream = ctx->side;
+    ctx->forked_from = s;
     ctx->build_no_rc = true;
     const dcm_status st = dcm_build_cells(ctx, W[WX], W[WY], W[WZ], W[WRC], n, box,
                                           step_cell_edge, rule.rc_max, prec, nullptr, nullptr);
     ctx->stream = s;
+    ctx->forked_from = nullptr;
     ctx->build_no_rc = false;
     if (st != DCM_OK) return st;
     if (hipEventRecord(ctx->join_ev, ctx->side) != hipSuccess)

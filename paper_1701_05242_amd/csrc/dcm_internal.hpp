@@ -192,9 +192,11 @@ struct dcm_ctx {
   dcm::BatchState *batch = nullptr;
   int batch_queues = 0;  // work-queue layout asked for (0: tuned)
   // dcm_step: a second stream on which the cell build of a step runs beside
-  // detection, sweep and cutoffs, with its fork and join events
+  // the sweep, with its fork and join events; while that build is enqueued,
+  // stream is the second stream and forked_from the context's own
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipStream_t forked_from = nullptr;
   // set for the next cell build: build without the cutoffs (the sorted
   // records' rc comes later, from the cutoff assignment); consumed by that build
   bool build_no_rc = false;
