@@ -353,7 +353,13 @@ dcm_status dcm_forces_list(dcm_ctx *ctx, dcm_lj lj, int prec, int ev_flags, doub
  * distances and cutoffs.  The context keeps the last distance field between
  * calls; a call with nsteps > 0 reuses it until its first re-detection only
  * when n, box, grid and rc_grid equal those it was computed for (continue a
- * run with step0 = the steps done so far). */
+ * run with step0 = the steps done so far).
+ * On a step with re-detection, for DCM_PAIR_OWN and a cell edge already
+ * chosen, the cell build runs on a second stream that the context creates
+ * (non-blocking, default priority) beside the distance sweep, and the
+ * context's stream waits for it before the cutoffs are assigned; every
+ * launch of the call is complete once the context's stream is.  A stream
+ * being captured into a graph keeps the build on the context's stream. */
 dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, double *vy,
                     double *vz, double *fx, double *fy, double *fz, int64_t n, double mass,
                     dcm_box box, dcm_lj lj, dcm_rule rule, dcm_grid grid, double rc_grid,
