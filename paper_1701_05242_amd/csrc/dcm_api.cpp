@@ -110,15 +110,17 @@ dcm_status detect_check(dcm_ctx *ctx, const double *x, const double *y, const do
 dcm_status detect_enqueue(dcm_ctx *ctx, const double *x, const double *y, const double *z,
                           int64_t n, const dcm_box &box, const dcm_grid &grid,
                           const dcm_detect_opts &opts, const DetectScratch &sc, uint8_t *seg,
-                          uint8_t *iface, int32_t *threshold_out, bool timed) {
+                          uint8_t *iface, int32_t *threshold_out, bool timed, bool binned) {
   const int64_t nvox = (int64_t)grid.n[0] * grid.n[1] * grid.n[2];
   const double sc3[3] = {(double)grid.n[0] / box.L[0], (double)grid.n[1] / box.L[1],
                          (double)grid.n[2] / box.L[2]};
   hipStream_t s = ctx->stream;
   hipEvent_t ev = nullptr;
   if (timed) timer_begin(ctx, "detect", &ev);
-  launch_zero2_u32(s, sc.counts, nvox, sc.hist, (int64_t)kHistCopies * kHistBins);
-  launch_bin_density(s, x, y, z, n, box.L, grid.n, sc3, sc.counts, ctx->d_status);
+  if (!binned) {
+    launch_zero2_u32(s, sc.counts, nvox, sc.hist, (int64_t)kHistCopies * kHistBins);
+    launch_bin_density(s, x, y, z, n, box.L, grid.n, sc3, sc.counts, ctx->d_status);
+  }
   launch_gray_hist(s, sc.counts, sc.gray, grid.n, sc.hist, ctx->d_status);
   if (opts.split <= 0.0) launch_otsu(s, sc.hist, nvox, ctx->ctl, threshold_out, ctx->d_status);
   launch_threshold(s, sc.gray, grid.n, opts.split, ctx->ctl, sc.seg_a, threshold_out);
@@ -1125,6 +1127,8 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
   const dcm_detect_opts dopts = {0.0, -1.0, 0};
   // the cell build beside the sweep (set below; a no-op where it does not apply)
   std::function<dcm_status()> build_beside;
+  // the previous step's integrator pass binned the density counts already
+  bool binned = false;
   auto detect = [&]() -> dcm_status {
     // detection (Section 2.1) without the byte maps: the sweep takes its
     // sources from the phase maps, and the field stays in the sweep's
@@ -1132,7 +1136,8 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
     DetectScratch sc;
     DCM_TRY(detect_scratch(ctx, grid, nvox, dopts, nullptr, &sc));
     DCM_TRY(detect_enqueue(ctx, W[WX], W[WY], W[WZ], n, box, grid, dopts, sc, nullptr, nullptr,
-                           nullptr, true));
+                           nullptr, true, binned));
+    binned = false;
     const uint32_t *const maps[2] = {sc.seg_a, sc.seg_b};
     if (build_beside) DCM_TRY(build_beside());
     DCM_TRY(sweep_enqueue(ctx, nullptr, nullptr, grid, nvox, rc_grid, max_waves, nullptr, nullptr,
@@ -1266,17 +1271,31 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
       timer_end(ctx, "verlet", ev);
     }
     // (a step without detection builds its cells in line: nothing to overlap)
-    if (!ctx->have_field || (step0 + st + 1) % redetect_every == 0) DCM_TRY(detect());
+    if (!ctx->have_field || (step0 + st + 1) % redetect_every == 0)
+      DCM_TRY(detect());
+    else
+      binned = false;  // (never set for such a step)
     DCM_TRY(forces(energy_series ? energy_series + 2 * (int64_t)st : nullptr));
     timer_begin(ctx, "verlet", &ev);
     // without an energy series to record in between, the closing kick and
     // the next step's opening kick and drift share one pass
     drifted = !energy_series && st + 1 < nsteps;
-    if (drifted)
+    // a next step with detection has its density counts binned here, from
+    // the new positions (the field exists from this step on)
+    const bool bin_next = drifted && (step0 + st + 2) % redetect_every == 0;
+    if (bin_next) {
+      DetectScratch sc;
+      DCM_TRY(detect_scratch(ctx, grid, nvox, dopts, nullptr, &sc));
+      launch_zero2_u32(s, sc.counts, nvox, sc.hist, (int64_t)kHistCopies * kHistBins);
+      launch_kick_kick_drift_bin(s, W[WX], W[WY], W[WZ], W[WVX], W[WVY], W[WVZ], W[WFX], W[WFY],
+                                 W[WFZ], n, c, dt, box.L, grid.n, vsc, sc.counts, ctx->d_status);
+      binned = true;
+    } else if (drifted) {
       launch_kick_kick_drift(s, W[WX], W[WY], W[WZ], W[WVX], W[WVY], W[WVZ], W[WFX], W[WFY],
                              W[WFZ], n, c, dt, box.L);
-    else
+    } else {
       launch_kick(s, W[WVX], W[WVY], W[WVZ], W[WFX], W[WFY], W[WFZ], n, c);
+    }
     timer_end(ctx, "verlet", ev);
     if (energy_series)
       launch_kinetic(s, W[WVX], W[WVY], W[WVZ], n, mass, ptr<double>(ctx->ke), kinetic_blocks(n),

@@ -226,10 +226,12 @@ dcm_status detect_check(dcm_ctx *ctx, const double *x, const double *y, const do
                         int64_t n, const dcm_box &box, const dcm_grid &grid,
                         const dcm_detect_opts *opts, const uint8_t *seg, const uint8_t *iface,
                         int64_t *nvox);
+// binned: the counts (and the zeroed histogram) are in sc already
 dcm_status detect_enqueue(dcm_ctx *ctx, const double *x, const double *y, const double *z,
                           int64_t n, const dcm_box &box, const dcm_grid &grid,
                           const dcm_detect_opts &opts, const DetectScratch &sc, uint8_t *seg,
-                          uint8_t *iface, int32_t *threshold_out, bool timed);
+                          uint8_t *iface, int32_t *threshold_out, bool timed,
+                          bool binned = false);
 // dcm_noalloc.hip: look up (once per device) the device address of the
 // static scratch array of dcm_detect_interface_noalloc
 dcm_status noalloc_scratch_setup(int device, std::string *err);
@@ -530,6 +532,13 @@ void launch_kick_kick_drift(hipStream_t s, double *x, double *y, double *z, doub
 void launch_kick_drift(hipStream_t s, double *x, double *y, double *z, double *vx, double *vy,
                        double *vz, const double *fx, const double *fy, const double *fz,
                        int64_t n, double c, double dt, const double L[3]);
+// the same as launch_kick_kick_drift, and the next detection's density
+// counts of the new positions (counts zeroed beforehand)
+void launch_kick_kick_drift_bin(hipStream_t s, double *x, double *y, double *z, double *vx,
+                                double *vy, double *vz, const double *fx, const double *fy,
+                                const double *fz, int64_t n, double c, double dt,
+                                const double L[3], const int32_t nv[3], const double sc[3],
+                                uint32_t *counts, uint32_t *status);
 void launch_kinetic(hipStream_t s, const double *vx, const double *vy, const double *vz,
                     int64_t n, double mass, double *partials, int64_t blocks, double *out);
 int64_t kinetic_blocks(int64_t n);
