@@ -1230,12 +1230,21 @@ dcm_status dcm_step(dcm_ctx *ctx, double *x, double *y, double *z, double *vx, d
       if (hipGetDevice(&cur) != hipSuccess ||
           (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess))
         return fail(ctx, DCM_ERR_HIP, "dcm_step: device selection failed");
-      hipError_t e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
-      if (e != hipSuccess) ctx->side = nullptr;
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
+      hipStream_t side = nullptr;
+      hipEvent_t fork = nullptr, join = nullptr;
+      hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+      if (e != hipSuccess) {  // nothing is kept: a later step tries again
+        if (join) (void)hipEventDestroy(join);
+        if (fork) (void)hipEventDestroy(fork);
+        if (side) (void)hipStreamDestroy(side);
+      }
       if (cur != ctx->device) (void)hipSetDevice(cur);
       if (e != hipSuccess) return fail(ctx, DCM_ERR_HIP, "dcm_step: stream creation failed");
+      ctx->side = side;
+      ctx->fork_ev = fork;
+      ctx->join_ev = join;
     }
     if (hipEventRecord(ctx->fork_ev, s) != hipSuccess ||
         hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0) != hipSuccess)
