@@ -709,8 +709,9 @@ def test_verlet_trajectory_tracks_oracle():
 @pytest.mark.parametrize("prec", [dcm.DCM_FP64, dcm.DCM_FP32_MIXED])
 def test_step_without_energy_series_repeats_the_recorded_run(prec):
     """Without an energy series dcm_step fuses the closing and opening kicks
-    and keeps fewer fields in step between its reorderings; with one it runs
-    every kick on its own.  Both perform the same arithmetic, so 20 steps
+    (and, before a detection step, the density binning) and keeps fewer
+    fields in step between its reorderings; with one it runs every kick and
+    the binning on its own.  Both perform the same arithmetic, so 20 steps
     (reorderings after steps 1, 8 and 16) must give the same state bit for
     bit: positions, velocities, forces, cutoffs and distances."""
     print(f"[gpu] dcm_step with and without an energy series prec={prec}", flush=True)
